@@ -1,0 +1,121 @@
+/*
+ * pthr_oracle.h -- plain, sequential CPU reference of one PTHR elementary Monte
+ * Carlo step (EMCS) for the 3D Edwards-Anderson spin glass with Gaussian
+ * couplings.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This library exists to check the GPU library
+ * against an obviously correct implementation of the method.  Only the test
+ * suite, the smoke check and the CPU-baseline leg of the benchmark may load it;
+ * the product path never does.  It shares no code, header, table or constant
+ * generator with the HIP implementation.
+ *
+ * Method (paper, Sec. 2 "Model and observables" and Sec. 3 "Description of the
+ * algorithm"):
+ *   H = -sum_<ij> J_ij s_i s_j on an L^3 simple-cubic lattice with periodic
+ *   boundaries (Eq. 1), J_ij ~ N(0,1).  N_r replica groups, each with N_T
+ *   clones on a uniform temperature grid.  One EMCS = local Metropolis sweeps,
+ *   one all-cluster Houdayer update (ACU) on replica pairs at T < t_acu, one
+ *   parallel-tempering (PT) step inside every replica group and one
+ *   entropic-reservoir (ER) step.  The ER holds n_reservoir extra clones per
+ *   replica group at T_max; they are swept er_sweeps_per_emcs times per EMCS
+ *   and the oldest one is exchanged with the PT clone at T_max.
+ *
+ * Conventions fixed here where the paper is silent (each is listed with its
+ * reason in the design notes of the repository):
+ *   site i = x + L*(y + L*z); neighbour order +x,-x,+y,-y,+z,-z;
+ *   bond J[s][d][i] joins i and i + e_d (d = 0,1,2 for x,y,z);
+ *   checkerboard sweep: all sites with (x+y+z) even in increasing i, then odd;
+ *   random numbers: Philox4x32-10 (Salmon et al., SC'11) with counter
+ *   (site | m<<16 | purpose<<24, t, slot, sample) and key (seed lo, seed hi).
+ *
+ * Precision: ORACLE_FP64 computes local fields and the Metropolis exponent in
+ * double.  ORACLE_FP32 computes couplings, local fields and the Metropolis
+ * exponent in float, as the paper's FP32 form of the GPU path; energies, the PT
+ * exponent and all observable sums stay double in both forms.
+ */
+#ifndef PTHR_ORACLE_H
+#define PTHR_ORACLE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { ORACLE_FP64 = 0, ORACLE_FP32 = 1 };
+enum { ORACLE_ACU = 0, ORACLE_SINGLE_NEG = 1 };
+enum { ORACLE_SWEEP_PT = 1, ORACLE_SWEEP_ER = 2 };
+enum { ORACLE_NOBS = 6 }; /* sum e, sum e^2, sum q^2, sum q^4, sum q_l, sum S */
+
+typedef struct oracle_params {
+  int32_t L;
+  int32_t n_samples;          /* samples held by this context                  */
+  int32_t first_sample;       /* global id of sample 0 (Philox counter word 3) */
+  int32_t n_replicas;         /* N_r, even, <= 64                              */
+  int32_t n_temps;            /* N_T >= 2                                      */
+  int32_t n_reservoir;        /* ER clones per replica group (0 = no ER)       */
+  int32_t sweeps_per_emcs;    /* PT clones' sweeps per EMCS (paper: 10)        */
+  int32_t er_sweeps_per_emcs; /* ER clones' sweeps per EMCS (paper: 960/4)     */
+  int32_t precision;          /* ORACLE_FP64 or ORACLE_FP32                    */
+  int32_t houdayer_mode;      /* ORACLE_ACU or ORACLE_SINGLE_NEG               */
+  double t_acu;               /* Houdayer moves at T_k < t_acu (paper: 1.0)    */
+  uint64_t seed;
+} oracle_params;
+
+typedef struct oracle_ctx oracle_ctx;
+
+/* Returns NULL and writes a message to err (if non-NULL, err_len bytes) when a
+ * parameter is out of range.  Odd L is allowed here (sequential sweeps). */
+oracle_ctx *oracle_create(const oracle_params *p, char *err, size_t err_len);
+void oracle_destroy(oracle_ctx *c);
+
+/* J: [n_samples][3][V] doubles, T: [n_temps] strictly increasing.  Draws the
+ * initial spins and resets t, the sweep counters, permutations and ER FIFOs. */
+int oracle_init_samples(oracle_ctx *c, const double *J, const double *T);
+
+/* n sweeps of the PT clones (which & 1) and/or the ER clones (which & 2), each
+ * class continuing its own sweep counter m inside the current EMCS. */
+int oracle_sweep(oracle_ctx *c, int n, int which);
+/* One Houdayer step: every pair (2p, 2p+1) at every T_k < t_acu. */
+int oracle_houdayer(oracle_ctx *c);
+/* Energies, PT swaps, round-trip bookkeeping, then (if do_reservoir and
+ * n_reservoir > 0) the ER exchange.  Closes the EMCS: t += 1, m := 0. */
+int oracle_pt_swap(oracle_ctx *c, int do_reservoir);
+/* Adds this moment's observables into acc [S][N_T][ORACLE_NOBS] and the
+ * pooled overlap histogram hist [N_T][V+1]; n_meas += 1. */
+int oracle_measure(oracle_ctx *c, double *acc, uint64_t *hist, uint64_t *n_meas);
+/* Full EMCS loop: sweeps, Houdayer, PT (+ER), and measure if acc != NULL. */
+int oracle_run(oracle_ctx *c, int64_t n_emcs, double *acc, uint64_t *hist, uint64_t *n_meas);
+
+/* Canonical cluster labels (root = minimum site index of the component) of the
+ * Houdayer graph of pair p at temperature index k in sample s, current state. */
+int oracle_cluster_labels(const oracle_ctx *c, int s, int p, int k, int32_t *labels);
+
+/* State views (owned by the context; valid until oracle_destroy). */
+int8_t *oracle_spins(oracle_ctx *c);      /* [S][C][V], +1/-1                */
+int32_t *oracle_clone_at(oracle_ctx *c);  /* [S][N_r][N_T]                   */
+int32_t *oracle_er_head(oracle_ctx *c);   /* [S][N_r]                        */
+uint8_t *oracle_pt_last(oracle_ctx *c);   /* [S][N_r][N_T-1] last EMCS accepts */
+uint32_t *oracle_pt_count(oracle_ctx *c); /* [S][N_r][N_T-1] cumulative      */
+double *oracle_pt_energy(oracle_ctx *c);  /* [S][N_r*N_T] E per PT clone at the last PT step */
+uint8_t *oracle_rt_state(oracle_ctx *c);  /* [S][N_r*N_T] round-trip state    */
+uint64_t *oracle_rt_count(oracle_ctx *c); /* [S] completed round trips       */
+int64_t oracle_t(const oracle_ctx *c);
+int oracle_m(const oracle_ctx *c, int cls);
+int oracle_n_clones(const oracle_ctx *c);
+
+/* Building blocks exposed for the pin tests. */
+void oracle_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+double oracle_pexp(double x);
+double oracle_uniform53(uint32_t lo, uint32_t hi);
+float oracle_uniform32(uint32_t w);
+float oracle_pexp32(float x);
+double oracle_energy(const oracle_ctx *c, int s, int clone);
+double oracle_delta_e(const oracle_ctx *c, int s, int clone, int site);
+int oracle_num_threads(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
