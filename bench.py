@@ -1,0 +1,209 @@
+"""Throughput of the PTHR hot path on one MI355X.
+
+One step = one elementary Monte Carlo step (EMCS) of the whole batch: the
+Metropolis sweeps of every PT clone (10) and reservoir clone (240), the
+Houdayer step on every replica pair below T = 1, the PT and reservoir
+exchanges, and the observables.  Default workload: L=16, 1024 samples of
+Gaussian couplings, 4 replica groups x 36 temperatures on [0.2, 1.6], 4
+reservoir clones per group, FP32 form.  Prints one JSON line.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload l16_fp32]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+from paper_2605_25872_amd import inputs  # noqa: E402
+
+METRIC = "spin-flip attempts/ns + Houdayer moves/s, batched 3D EA L=16, one MI355X"
+# MI355X: 256 compute units x 4 SIMD x 16 lanes at 2.4 GHz -> one 32-bit (or
+# FP64) VALU operation per lane per cycle.
+VALU_PEAK_OPS = 256 * 64 * 2.4e9
+# EMCS needed to equilibrate one L=16 sample (paper, App. A.2 table).
+T_EQ_EMCS = {12: 2 ** 17, 14: 6.4e6, 16: 3.84e7, 18: 3.48e7}
+
+# Algorithmic VALU operations per Metropolis attempt: Philox
+# block shared by 4 (FP32) or 2 (FP64) attempts, local field, exponent, test.
+OPS_PER_ATTEMPT = {"fp32": 69, "fp64": 106}
+
+
+def log(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def attempts_per_emcs(w) -> float:
+    npt = w.n_replicas * w.n_temps
+    ner = w.n_replicas * w.n_reservoir
+    return float(w.V * (w.sweeps_per_emcs * npt + w.er_sweeps_per_emcs * ner)) * w.n_samples
+
+
+def moves_per_emcs(w, T) -> int:
+    k_acu = int(np.sum(T < w.t_acu))
+    return w.n_samples * (w.n_replicas // 2) * k_acu
+
+
+def cpu_baseline(w, n_samples: int, mode: str) -> dict:
+    """The CPU oracle on a bounded sample of the same workload (all host cores)."""
+    import oracle
+
+    T = w.temperatures()
+    prec = oracle.FP64 if w.precision == "fp64" else oracle.FP32
+    o = oracle.Oracle(w.L, n_samples, w.n_replicas, w.n_temps, w.n_reservoir, w.sweeps_per_emcs,
+                      w.er_sweeps_per_emcs, prec, oracle.ACU if mode == "acu" else oracle.SINGLE_NEG,
+                      w.t_acu, w.seed)
+    o.init(w.couplings(n_samples), T)
+    t0 = time.perf_counter()
+    o.run(1)
+    dt = time.perf_counter() - t0
+    sub = inputs.Workload(**{**w.__dict__, "n_samples": n_samples})
+    att = attempts_per_emcs(sub)
+    return {"value": att / (dt * 1e9), "unit": "spin-flip attempts/ns", "cores": oracle_threads(),
+            "kind": "oracle", "seconds": dt,
+            "houdayer_moves_per_s": moves_per_emcs(sub, T) / dt,
+            "sample": f"{n_samples} of {w.n_samples} samples, 1 EMCS, {w.precision} oracle"}
+
+
+def oracle_threads() -> int:
+    import oracle
+    return int(oracle._lib().oracle_num_threads())
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="l16_fp32", choices=sorted(inputs.WORKLOADS))
+    ap.add_argument("--mode", default="acu", choices=["acu", "single"])
+    ap.add_argument("--cpu-samples", type=int, default=32)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--compare-fp64-samples", type=int, default=16,
+                    help="samples for the unbatched FP64 one-sample-per-launch comparison (0 = skip)")
+    ap.add_argument("--autotune", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: samples are independent, a multi-GPU run "
+              "shards them with no exchange (see DESIGN.md); use --gpus 1", file=sys.stderr)
+        return 2
+
+    import torch
+    from paper_2605_25872_amd import pthr
+
+    w = inputs.WORKLOADS[args.workload]
+    T = w.temperatures()
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    log(f"workload {w.name}: L={w.L} S={w.n_samples} NR={w.n_replicas} NT={w.n_temps} "
+        f"NER={w.n_reservoir} {w.precision} {args.mode}")
+    g = pthr.Pthr(w.L, w.n_samples, w.n_replicas, w.n_temps, w.n_reservoir, w.sweeps_per_emcs,
+                  w.er_sweeps_per_emcs, w.precision, args.mode, w.t_acu, w.seed)
+    g.init_samples(w.couplings(), T)
+    obs = g.new_obs()
+    if args.autotune:
+        best = g.autotune(1)
+        log(f"autotune: {best:.2f} ms/EMCS with {g.schedule().threads_per_sample} work-items")
+    stream = torch.cuda.current_stream(dev)
+    n_er = w.er_sweeps_per_emcs if w.n_reservoir else 0
+
+    def step(ev_a=None, ev_b=None):
+        if ev_a is not None:
+            ev_a.record(stream)
+        g.sweep(w.sweeps_per_emcs, n_er)
+        if ev_b is not None:
+            ev_b.record(stream)
+        g.houdayer()
+        g.pt_swap(True)
+        g.measure(obs)
+
+    for i in range(args.warmup):
+        step()
+        torch.cuda.synchronize()
+        log(f"warmup step {i + 1}/{args.warmup} done")
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for a, b in evs:
+        step(a, b)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    g.check()
+    sweep_ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+    log(f"timed {args.steps} steps in {elapsed:.3f} s; sweep kernel {sweep_ms:.2f} ms per launch")
+
+    att = attempts_per_emcs(w)
+    moves = moves_per_emcs(w, T)
+    ms_per_step = elapsed / args.steps * 1e3
+    value = att * args.steps / (elapsed * 1e9)
+    ops = OPS_PER_ATTEMPT[w.precision] * att
+    achieved = ops / (sweep_ms * 1e-3)
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "spin-flip attempts/ns",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if w.precision == "fp32" else "f64",
+        "data": "synthetic",
+        "config": {"workload": w.name, "L": w.L, "samples": w.n_samples, "replicas": w.n_replicas,
+                   "temperatures": w.n_temps, "t_range": [w.t_min, w.t_max],
+                   "reservoir_clones": w.n_reservoir, "sweeps_per_emcs": w.sweeps_per_emcs,
+                   "reservoir_sweeps_per_emcs": w.er_sweeps_per_emcs, "houdayer": args.mode,
+                   "threads_per_sample": g.schedule().threads_per_sample},
+        "houdayer_moves_per_s": moves * args.steps / elapsed,
+        "attempts_per_emcs": att,
+        "wall_time_per_equilibrated_sample_s":
+            (elapsed / args.steps) / w.n_samples * T_EQ_EMCS.get(w.L, float("nan")),
+        "roofline": {"bound": "alu", "kernel": "sweep_kernel", "achieved": achieved / 1e12,
+                     "peak": VALU_PEAK_OPS / 1e12, "unit": "TOP/s", "frac": achieved / VALU_PEAK_OPS,
+                     "traffic": None, "ops_per_attempt": OPS_PER_ATTEMPT[w.precision],
+                     "sweep_ms_per_launch": sweep_ms},
+    }
+
+    if args.compare_fp64_samples > 0:
+        n = min(args.compare_fp64_samples, w.n_samples)
+        sub = inputs.Workload(**{**w.__dict__, "n_samples": n, "precision": "fp64"})
+        h = pthr.Pthr(w.L, n, w.n_replicas, w.n_temps, w.n_reservoir, w.sweeps_per_emcs,
+                      w.er_sweeps_per_emcs, "fp64", args.mode, w.t_acu, w.seed)
+        h.init_samples(sub.couplings(), T)
+        h.set_schedule(samples_per_launch=1)
+        hobs = h.new_obs()
+        h.run(1, hobs)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        h.run(1, hobs)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t1
+        out["fp64_one_sample_per_launch"] = {
+            "value": attempts_per_emcs(sub) / (dt * 1e9), "unit": "spin-flip attempts/ns",
+            "samples": n, "emcs": 1,
+            "houdayer_moves_per_s": moves_per_emcs(sub, T) / dt}
+        out["speedup_vs_fp64_one_sample_per_launch"] = value / out["fp64_one_sample_per_launch"]["value"]
+        log(f"fp64 one-sample-per-launch: {out['fp64_one_sample_per_launch']['value']:.2f} attempts/ns")
+
+    if not args.no_cpu_baseline:
+        log(f"cpu baseline: oracle on {args.cpu_samples} samples x 1 EMCS")
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_samples, args.mode)
+        log(f"cpu baseline: {out['cpu_baseline']['value']:.4f} attempts/ns "
+            f"on {out['cpu_baseline']['cores']} threads")
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,193 @@
+/*
+ * pthr.h -- C ABI of the MI355X (gfx950) PTHR library: Parallel Tempering with
+ * Houdayer all-cluster moves and an entropic Reservoir for the 3D
+ * Edwards-Anderson Ising spin glass with Gaussian couplings.
+ *
+ * The method is the one of the paper (arXiv 2605.25872), Sec. 3 "Description
+ * of the algorithm": one elementary Monte Carlo step (EMCS) of a sample is
+ *   (i)   sweeps_per_emcs Metropolis sweeps of every PT clone at its own
+ *         temperature, while every entropic-reservoir (ER) clone does
+ *         er_sweeps_per_emcs sweeps at T_max            -> pthr_sweep
+ *   (ii)  one Houdayer step on every replica pair (2p, 2p+1) at every
+ *         temperature T_k < t_acu (all-cluster update by default)
+ *                                                        -> pthr_houdayer
+ *   (iii) one parallel-tempering step in every replica group, then
+ *   (iv)  one ER step: the configuration at T_max and the oldest reservoir
+ *         configuration of the group trade places       -> pthr_pt_swap
+ *   and observables are accumulated                      -> pthr_measure
+ * pthr_run performs whole EMCS in one persistent launch per window.
+ *
+ * Problem statement (paper Sec. 2, Eq. 1; App. A.2): L^3 simple-cubic lattice
+ * with periodic boundaries, couplings J_ij ~ N(0,1) per sample, N_T
+ * temperatures (strictly increasing), N_r replica groups of N_T clones.
+ *
+ * Conventions
+ *   site i = x + L*(y + L*z); J[s][d][i] (d = 0,1,2 for x,y,z) is the bond
+ *   between i and i + e_d.  A PT clone id is r*N_T + k for the clone that
+ *   starts at temperature k of group r; ER clone ids follow, N_r*N_T +
+ *   r*n_reservoir + e.  Spins read back as int8 +1/-1.
+ *
+ * Numerics (PTHR_FP64): bit-exact with the independent CPU reference built
+ * from the same definitions: Philox4x32-10 counter-based random numbers keyed
+ * by (seed, sample, clone, EMCS, sweep, site), a specified double-precision
+ * exp, checkerboard sweeps (sites with even x+y+z, then odd), energies summed
+ * by a fixed pairwise tree.  PTHR_FP32: couplings, local fields and the
+ * Metropolis exponent in float (couplings rounded to float once, also for the
+ * energies); PT exponents, energies and all observable sums stay double.
+ *
+ * Memory and ownership
+ *   The library never allocates device memory.  The caller allocates the state
+ *   buffer (pthr_state_bytes) and observable buffers (pthr_obs_bytes) on the
+ *   device, e.g. as torch tensors, and passes raw device pointers and a HIP
+ *   stream (hipStream_t passed as void*, NULL = default stream).  Host arrays
+ *   passed in are copied before the call returns; the caller keeps them.
+ *   All device work is enqueued on the given stream; functions that return
+ *   host data synchronize that stream first.
+ *
+ * Errors: every function returns PTHR_OK (0) or a negative code; the message
+ * of the last failure on a context is available from pthr_last_error.  No
+ * function aborts the process.
+ */
+#ifndef PTHR_H
+#define PTHR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  PTHR_OK = 0,
+  PTHR_EINVAL = -1,      /* bad argument or parameter                        */
+  PTHR_EUNSUPPORTED = -2,/* valid but not supported here (odd L, LDS too small) */
+  PTHR_EHIP = -3,        /* a HIP runtime call failed                         */
+  PTHR_ESTATE = -4,      /* call out of order (not initialised, counters full) */
+  PTHR_EDEVICE = -5      /* a kernel reported an internal bound violation     */
+};
+enum { PTHR_FP64 = 0, PTHR_FP32 = 1 };
+enum { PTHR_ACU = 0, PTHR_SINGLE_NEG = 1 };
+enum { PTHR_NOBS = 6 }; /* per (sample, T): sum e, sum e^2, sum q^2, sum q^4, sum q_l, sum S */
+
+typedef struct pthr_params {
+  int32_t L;                  /* even, 2..32                                   */
+  int32_t n_samples;          /* >= 1                                          */
+  int32_t n_replicas;         /* N_r: even, 2..64 (pairs (0,1), (2,3), ...)    */
+  int32_t n_temps;            /* N_T: 2..1024                                  */
+  int32_t n_reservoir;        /* ER clones per replica group (paper: 4); 0 = no ER */
+  int32_t sweeps_per_emcs;    /* PT sweeps per EMCS (paper: 10), 0..256        */
+  int32_t er_sweeps_per_emcs; /* ER sweeps per EMCS (paper: 960/4 = 240), 0..256 */
+  int32_t precision;          /* PTHR_FP64 or PTHR_FP32                        */
+  int32_t houdayer_mode;      /* PTHR_ACU (paper) or PTHR_SINGLE_NEG (Houdayer's original) */
+  int32_t reserved;           /* must be 0                                     */
+  double t_acu;               /* Houdayer moves at T_k < t_acu (paper: 1.0)    */
+  uint64_t seed;              /* Philox key                                    */
+} pthr_params;
+
+typedef struct pthr_ctx pthr_ctx;
+
+/* Opaque context.  pthr_create validates the parameters (PTHR_EINVAL /
+ * PTHR_EUNSUPPORTED with no context created) and picks a default launch
+ * shape; it enqueues nothing.  *out is set to NULL on failure. */
+int pthr_create(const pthr_params *p, pthr_ctx **out);
+int pthr_destroy(pthr_ctx *ctx);
+const char *pthr_last_error(const pthr_ctx *ctx); /* "" if none; valid until the next call */
+/* Message of the last pthr_create failure on this thread. */
+const char *pthr_create_error(void);
+
+/* Bytes of device memory the caller must provide (0 if p is invalid). */
+size_t pthr_state_bytes(const pthr_params *p);
+/* Observable buffer: uint64 n_meas at offset 0; double acc[S][N_T][PTHR_NOBS]
+ * at offset 256; then uint64 hist[N_T][V+1], hist[k][(Q+V)/2] counting the
+ * overlaps Q of every replica pair a < b at temperature k, pooled over
+ * samples (paper Sec. 2, Eqs. 2-5). */
+size_t pthr_obs_bytes(const pthr_params *p);
+size_t pthr_obs_acc_offset(const pthr_params *p);
+size_t pthr_obs_hist_offset(const pthr_params *p);
+
+/* Binds the state buffer d_state (pthr_state_bytes, device, 256-byte aligned,
+ * owned by the caller, must outlive its use) and initialises it: copies J_host
+ * [S][3][V] (double; rounded to float for PTHR_FP32) and T_host [N_T] (double,
+ * strictly increasing, > 0; beta_k = 1/T_k), draws the initial spins, sets
+ * every clone at its starting temperature and every reservoir FIFO to slot 0,
+ * and resets the EMCS counter t and the sweep counters.  PTHR_EINVAL on
+ * non-finite J or a bad grid. */
+int pthr_init_samples(pthr_ctx *ctx, const double *J_host, const double *T_host, void *d_state,
+                      void *stream);
+
+/* Step (i), one launch: n_pt sweeps of every PT clone at its temperature and
+ * n_er sweeps of every ER clone at T_max (paper Sec. 3: 10 and 960/4 per EMCS),
+ * each class continuing its own sweep counter inside the current EMCS
+ * (PTHR_ESTATE if a counter would pass 256). */
+int pthr_sweep(pthr_ctx *ctx, int n_pt, int n_er, void *stream);
+/* Step (ii): one Houdayer move for every pair p and every k with T_k < t_acu:
+ * clusters of equal site overlap q_i = s_i^a s_i^b (paper Eq. 2) joined over
+ * nearest-neighbour links; ACU flips each cluster in both replicas with
+ * probability 1/2; SINGLE_NEG flips the q = -1 cluster of a uniformly chosen
+ * q = -1 site. */
+int pthr_houdayer(pthr_ctx *ctx, void *stream);
+/* Steps (iii)+(iv): energies, PT swaps for k = 0..N_T-2 ascending, each
+ * accepted with probability min{1, exp((b_k - b_{k+1})(E_k - E_{k+1}))},
+ * round-trip bookkeeping, then the ER exchange if do_reservoir and
+ * n_reservoir > 0.  Closes the EMCS: t += 1, sweep counters reset. */
+int pthr_pt_swap(pthr_ctx *ctx, int do_reservoir, void *stream);
+/* Adds the current observables to d_obs (device, pthr_obs_bytes). */
+int pthr_measure(pthr_ctx *ctx, void *d_obs, void *stream);
+/* Zero-fills d_obs with a kernel. */
+int pthr_obs_clear(pthr_ctx *ctx, void *d_obs, void *stream);
+/* n_emcs complete EMCS (sweeps, Houdayer, PT, ER, and measure if d_obs is not
+ * NULL), bit-identical to the step-wise calls.  Requires the sweep counters
+ * at 0 (PTHR_ESTATE otherwise). */
+int pthr_run(pthr_ctx *ctx, int64_t n_emcs, void *d_obs, void *stream);
+
+/* Canonical cluster labels of every Houdayer pair at the current state:
+ * d_labels int32 [S][N_r/2][K][V] with K = #{k : T_k < t_acu}; each site holds
+ * the smallest site index of its cluster. */
+int pthr_cluster_labels(pthr_ctx *ctx, void *d_labels, void *stream);
+
+/* Read-back into host arrays (NULL pointers are skipped); synchronizes. */
+int pthr_read_spins(pthr_ctx *ctx, int8_t *spins /* [S][C][V] */, void *stream);
+int pthr_read_pt(pthr_ctx *ctx, int32_t *clone_at /* [S][N_r][N_T] */,
+                 int32_t *er_head /* [S][N_r] */, uint8_t *pt_last /* [S][N_r][N_T-1] */,
+                 uint32_t *pt_count /* [S][N_r][N_T-1] */, double *pt_energy /* [S][N_r*N_T] */,
+                 uint8_t *rt_state /* [S][N_r*N_T] */, uint64_t *rt_count /* [S] */, void *stream);
+/* EMCS counter and the sweep counters of the current EMCS. */
+int pthr_counters(const pthr_ctx *ctx, int64_t *t, int32_t *m_pt, int32_t *m_er);
+/* Checks the device-side status words (synchronizes): PTHR_EDEVICE if any
+ * kernel hit an internal iteration bound. */
+int pthr_check(pthr_ctx *ctx, void *stream);
+
+/* Checkpoint / resume: the blob holds the counters and the whole state
+ * buffer; pthr_set_state on a context with the same parameters and a bound
+ * state buffer continues bit-identically. */
+size_t pthr_blob_bytes(const pthr_ctx *ctx);
+int pthr_get_state(pthr_ctx *ctx, void *blob, size_t bytes, void *stream);
+int pthr_set_state(pthr_ctx *ctx, const void *blob, size_t bytes, void *stream);
+
+/* Launch schedule.  threads_per_sample: work-items per sample workgroup (each
+ * owns V/threads sites; power-of-two site chunks of 2..32); samples_per_launch:
+ * 0 = all samples in one launch, 1 = one sample per launch (the unbatched
+ * form); exp_early_out: decide most Metropolis tests from the binade of
+ * exp(x) before evaluating the polynomial.  Every schedule produces identical
+ * bits. */
+typedef struct pthr_schedule {
+  int32_t threads_per_sample;
+  int32_t samples_per_launch;
+  int32_t exp_early_out;
+  int32_t reserved;
+} pthr_schedule;
+int pthr_get_schedule(const pthr_ctx *ctx, pthr_schedule *out);
+int pthr_set_schedule(pthr_ctx *ctx, const pthr_schedule *sch);
+/* Times candidate schedules with pthr_run on a scratch copy of the state
+ * (d_scratch: pthr_state_bytes bytes, device) for n_emcs EMCS each, keeps the
+ * fastest, restores nothing else.  best_ms (may be NULL) gets its time. */
+int pthr_autotune(pthr_ctx *ctx, void *d_scratch, int n_emcs, double *best_ms, void *stream);
+
+/* Dynamic LDS bytes one sample workgroup needs (0 if invalid). */
+size_t pthr_lds_bytes(const pthr_params *p);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

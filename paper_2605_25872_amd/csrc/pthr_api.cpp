@@ -1,0 +1,644 @@
+// C ABI of the PTHR library (declared in include/pthr.h): validation, the
+// device state layout, step-wise and fused EMCS launches, read-back,
+// checkpointing and the launch-shape autotuner.  All device memory belongs to
+// the caller; nothing here calls hipMalloc.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "pthr.h"
+#include "pthr_internal.h"
+
+namespace {
+
+constexpr size_t kLdsLimit = 160 * 1024;  // gfx950 LDS per workgroup
+constexpr uint64_t kBlobMagic = 0x5054485253544154ull;  // "PTHRSTAT"
+
+size_t align256(size_t v) { return (v + 255) / 256 * 256; }
+
+// Byte offsets of every region of the caller's state buffer.
+struct Layout {
+  size_t beta64, beta32, spins, J, clone_at, er_head, pt_last, pt_count, pt_energy, rt_state, rt_count,
+      status, total;
+};
+
+struct Derived {
+  int V, NPT, NER, C, NW, NWPT;
+};
+
+Derived derive(const pthr_params& p) {
+  Derived d{};
+  d.V = p.L * p.L * p.L;
+  d.NPT = p.n_replicas * p.n_temps;
+  d.NER = p.n_replicas * p.n_reservoir;
+  d.C = d.NPT + d.NER;
+  d.NWPT = (d.NPT + 31) / 32;
+  d.NW = d.NWPT + (d.NER + 31) / 32;
+  return d;
+}
+
+Layout layout_of(const pthr_params& p) {
+  const Derived d = derive(p);
+  const size_t S = p.n_samples, NR = p.n_replicas, NT = p.n_temps;
+  const size_t fp = p.precision == PTHR_FP64 ? 8 : 4;
+  Layout l{};
+  size_t o = 256;  // reserved header
+  l.beta64 = o;    o = align256(o + 8 * NT);
+  l.beta32 = o;    o = align256(o + 4 * NT);
+  l.spins = o;     o = align256(o + 4 * S * d.NW * d.V);
+  l.J = o;         o = align256(o + fp * S * 3 * d.V);
+  l.clone_at = o;  o = align256(o + 4 * S * NR * NT);
+  l.er_head = o;   o = align256(o + 4 * S * NR);
+  l.pt_last = o;   o = align256(o + S * NR * (NT - 1));
+  l.pt_count = o;  o = align256(o + 4 * S * NR * (NT - 1));
+  l.pt_energy = o; o = align256(o + 8 * S * d.NPT);
+  l.rt_state = o;  o = align256(o + S * d.NPT);
+  l.rt_count = o;  o = align256(o + 8 * S);
+  l.status = o;    o = align256(o + 4 * S);
+  l.total = o;
+  return l;
+}
+
+pthr::Geo geo_of(const pthr_params& p, int K_acu) {
+  const Derived d = derive(p);
+  pthr::Geo g{};
+  g.L = p.L;
+  g.V = d.V;
+  g.Vh = d.V / 2;
+  g.S = p.n_samples;
+  g.NR = p.n_replicas;
+  g.NT = p.n_temps;
+  g.NERG = p.n_reservoir;
+  g.NPT = d.NPT;
+  g.NER = d.NER;
+  g.C = d.C;
+  g.NW = d.NW;
+  g.NWPT = d.NWPT;
+  g.K_acu = K_acu;
+  g.mode = p.houdayer_mode;
+  g.key0 = static_cast<uint32_t>(p.seed);
+  g.key1 = static_cast<uint32_t>(p.seed >> 32);
+  return g;
+}
+
+int threads_for(int V, int chunk) { return (V / chunk + 63) / 64 * 64; }
+// Chunk sizes with a compiled kernel: FP64 keeps 12 doubles per pair of sites
+// in registers, so it stops at 4 sites per work-item.
+bool chunk_ok(int precision, int V, int chunk) {
+  if (precision == PTHR_FP64 && chunk > 4) return false;
+  return threads_for(V, chunk) <= 1024 && V / chunk >= 1;
+}
+// Smallest chunk (most work-items per sample) with a compiled kernel; 0 if none.
+int default_chunk(int precision, int V) {
+  for (int ch = 2; ch <= 8; ch *= 2)
+    if (chunk_ok(precision, V, ch)) return ch;
+  return 0;
+}
+
+thread_local std::string g_create_error;
+
+const char* validate(const pthr_params& p) {
+  if (p.L < 2 || p.L > 32) return "L must be in [2, 32]";
+  if (p.L % 2) return "odd L is not supported on the GPU (the checkerboard is not a bipartition)";
+  if (p.n_samples < 1 || p.n_samples > (1 << 24)) return "n_samples must be in [1, 2^24]";
+  if (p.n_replicas < 2 || p.n_replicas > 64 || p.n_replicas % 2) return "n_replicas must be even, in [2, 64]";
+  if (p.n_temps < 2 || p.n_temps > 1024) return "n_temps must be in [2, 1024]";
+  if (p.n_reservoir < 0 || p.n_reservoir > 64) return "n_reservoir must be in [0, 64]";
+  if (p.sweeps_per_emcs < 0 || p.sweeps_per_emcs > 256) return "sweeps_per_emcs must be in [0, 256]";
+  if (p.er_sweeps_per_emcs < 0 || p.er_sweeps_per_emcs > 256) return "er_sweeps_per_emcs must be in [0, 256]";
+  if (p.precision != PTHR_FP64 && p.precision != PTHR_FP32) return "precision must be PTHR_FP64 or PTHR_FP32";
+  if (p.houdayer_mode != PTHR_ACU && p.houdayer_mode != PTHR_SINGLE_NEG) return "houdayer_mode must be PTHR_ACU or PTHR_SINGLE_NEG";
+  if (p.reserved != 0) return "reserved must be 0";
+  if (std::isnan(p.t_acu)) return "t_acu must not be NaN";
+  return nullptr;
+}
+
+}  // namespace
+
+struct pthr_ctx {
+  pthr_params p{};
+  Derived d{};
+  Layout lay{};
+  pthr::Geo g{};
+  unsigned char* d_state = nullptr;
+  bool ready = false;
+  int64_t t = 0;
+  int m_pt = 0, m_er = 0;
+  int K_acu = 0;
+  std::vector<double> T;
+  pthr_schedule sch{};
+  std::string err;
+
+  int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    err = buf;
+    return code;
+  }
+  int hip_fail(hipError_t e, const char* what) {
+    return fail(PTHR_EHIP, "%s: %s", what, hipGetErrorString(e));
+  }
+  pthr::State state() const {
+    pthr::State st{};
+    unsigned char* b = d_state;
+    st.spins = reinterpret_cast<uint32_t*>(b + lay.spins);
+    st.J = b + lay.J;
+    st.clone_at = reinterpret_cast<int32_t*>(b + lay.clone_at);
+    st.er_head = reinterpret_cast<int32_t*>(b + lay.er_head);
+    st.pt_last = b + lay.pt_last;
+    st.pt_count = reinterpret_cast<uint32_t*>(b + lay.pt_count);
+    st.pt_energy = reinterpret_cast<double*>(b + lay.pt_energy);
+    st.rt_state = b + lay.rt_state;
+    st.rt_count = reinterpret_cast<uint64_t*>(b + lay.rt_count);
+    st.status = reinterpret_cast<uint32_t*>(b + lay.status);
+    st.beta64 = reinterpret_cast<const double*>(b + lay.beta64);
+    st.beta32 = reinterpret_cast<const float*>(b + lay.beta32);
+    return st;
+  }
+  pthr::Obs obs(void* d_obs) const {
+    pthr::Obs o{};
+    if (d_obs) {
+      unsigned char* b = static_cast<unsigned char*>(d_obs);
+      o.n_meas = reinterpret_cast<uint64_t*>(b);
+      o.acc = reinterpret_cast<double*>(b + pthr_obs_acc_offset(&p));
+      o.hist = reinterpret_cast<uint64_t*>(b + pthr_obs_hist_offset(&p));
+    }
+    return o;
+  }
+  pthr::Shape shape() const {
+    pthr::Shape sh{};
+    sh.threads = sch.threads_per_sample;
+    sh.chunk = 2;  // smallest chunk giving this many work-items (checked by set_schedule)
+    while (threads_for(d.V, sh.chunk) != sch.threads_per_sample && sh.chunk < 8) sh.chunk *= 2;
+    sh.early_out = sch.exp_early_out != 0;
+    return sh;
+  }
+  // Launches `run` over all samples, split by samples_per_launch.
+  int launch(pthr::Run run, void* d_obs, hipStream_t stream) {
+    const pthr::State st = state();
+    const pthr::Obs ob = obs(d_obs);
+    const int per = sch.samples_per_launch > 0 ? sch.samples_per_launch : p.n_samples;
+    for (int s0 = 0; s0 < p.n_samples; s0 += per) {
+      run.sample_begin = s0;
+      const int nb = std::min(per, p.n_samples - s0);
+      hipError_t e = pthr::launch_emcs(p.precision, g, st, ob, run, shape(), nb, stream);
+      if (e != hipSuccess) return hip_fail(e, "EMCS kernel launch");
+    }
+    return PTHR_OK;
+  }
+  int need_ready() {
+    if (!ready) return fail(PTHR_ESTATE, "state buffer not initialised (call pthr_init_samples)");
+    return PTHR_OK;
+  }
+};
+
+extern "C" {
+
+const char* pthr_create_error(void) { return g_create_error.c_str(); }
+
+size_t pthr_state_bytes(const pthr_params* p) {
+  if (!p || validate(*p)) return 0;
+  return layout_of(*p).total;
+}
+
+size_t pthr_lds_bytes(const pthr_params* p) {
+  if (!p || validate(*p)) return 0;
+  return pthr::lds_bytes(geo_of(*p, 0), p->precision == PTHR_FP64 ? 8 : 4);
+}
+
+size_t pthr_obs_acc_offset(const pthr_params* p) { return p ? 256 : 0; }
+size_t pthr_obs_hist_offset(const pthr_params* p) {
+  if (!p) return 0;
+  return align256(256 + sizeof(double) * size_t(p->n_samples) * p->n_temps * PTHR_NOBS);
+}
+size_t pthr_obs_bytes(const pthr_params* p) {
+  if (!p || validate(*p)) return 0;
+  const size_t V = size_t(p->L) * p->L * p->L;
+  return align256(pthr_obs_hist_offset(p) + sizeof(uint64_t) * size_t(p->n_temps) * (V + 1));
+}
+
+int pthr_create(const pthr_params* p, pthr_ctx** out) {
+  if (!out) {
+    g_create_error = "out must not be NULL";
+    return PTHR_EINVAL;
+  }
+  *out = nullptr;
+  if (!p) {
+    g_create_error = "params must not be NULL";
+    return PTHR_EINVAL;
+  }
+  if (const char* msg = validate(*p)) {
+    g_create_error = msg;
+    return (p->L % 2 && p->L >= 2 && p->L <= 32) ? PTHR_EUNSUPPORTED : PTHR_EINVAL;
+  }
+  const Derived d = derive(*p);
+  if (default_chunk(p->precision, d.V) == 0) {
+    g_create_error = "lattice too large for one workgroup per sample (V > 8192, or V > 4096 in FP64)";
+    return PTHR_EUNSUPPORTED;
+  }
+  const size_t lds = pthr::lds_bytes(geo_of(*p, 0), p->precision == PTHR_FP64 ? 8 : 4);
+  if (lds > kLdsLimit) {
+    char buf[256];
+    snprintf(buf, sizeof buf, "sample does not fit in LDS: needs %zu bytes, limit %zu", lds, kLdsLimit);
+    g_create_error = buf;
+    return PTHR_EUNSUPPORTED;
+  }
+  pthr_ctx* c = new pthr_ctx();
+  c->p = *p;
+  c->d = d;
+  c->lay = layout_of(*p);
+  c->g = geo_of(*p, 0);
+  const int ch = default_chunk(p->precision, d.V);
+  c->sch.threads_per_sample = threads_for(d.V, ch);
+  c->sch.samples_per_launch = 0;
+  c->sch.exp_early_out = 1;
+  *out = c;
+  g_create_error.clear();
+  return PTHR_OK;
+}
+
+int pthr_destroy(pthr_ctx* ctx) {
+  delete ctx;
+  return PTHR_OK;
+}
+
+const char* pthr_last_error(const pthr_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+int pthr_init_samples(pthr_ctx* ctx, const double* J_host, const double* T_host, void* d_state, void* stream) {
+  if (!ctx) return PTHR_EINVAL;
+  ctx->err.clear();
+  if (!J_host || !T_host || !d_state) return ctx->fail(PTHR_EINVAL, "J, T and d_state must not be NULL");
+  if (reinterpret_cast<uintptr_t>(d_state) % 256) return ctx->fail(PTHR_EINVAL, "d_state must be 256-byte aligned");
+  const pthr_params& p = ctx->p;
+  const int NT = p.n_temps;
+  for (int k = 0; k < NT; ++k) {
+    if (!(T_host[k] > 0.0) || !std::isfinite(T_host[k]))
+      return ctx->fail(PTHR_EINVAL, "T[%d] must be finite and > 0", k);
+    if (k > 0 && !(T_host[k] > T_host[k - 1])) return ctx->fail(PTHR_EINVAL, "T must be strictly increasing");
+  }
+  const size_t nJ = size_t(p.n_samples) * 3 * ctx->d.V;
+  for (size_t n = 0; n < nJ; ++n)
+    if (!std::isfinite(J_host[n])) return ctx->fail(PTHR_EINVAL, "J[%zu] is not finite", n);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  // host image of the small regions and the couplings
+  std::vector<double> b64(NT);
+  std::vector<float> b32(NT);
+  for (int k = 0; k < NT; ++k) {
+    b64[k] = 1.0 / T_host[k];
+    b32[k] = static_cast<float>(b64[k]);
+  }
+  int K = 0;
+  while (K < NT && T_host[K] < p.t_acu) ++K;
+  ctx->K_acu = K;
+  ctx->g = geo_of(p, K);
+  ctx->T.assign(T_host, T_host + NT);
+  ctx->d_state = static_cast<unsigned char*>(d_state);
+  const Layout& l = ctx->lay;
+  hipError_t e;
+  e = hipMemcpyAsync(ctx->d_state + l.beta64, b64.data(), 8 * NT, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(ctx->d_state + l.beta32, b32.data(), 4 * NT, hipMemcpyHostToDevice, s);
+  std::vector<float> J32;
+  if (e == hipSuccess) {
+    if (p.precision == PTHR_FP64) {
+      e = hipMemcpyAsync(ctx->d_state + l.J, J_host, 8 * nJ, hipMemcpyHostToDevice, s);
+    } else {
+      J32.resize(nJ);
+      for (size_t n = 0; n < nJ; ++n) J32[n] = static_cast<float>(J_host[n]);
+      e = hipMemcpyAsync(ctx->d_state + l.J, J32.data(), 4 * nJ, hipMemcpyHostToDevice, s);
+    }
+  }
+  const size_t S = p.n_samples, NR = p.n_replicas;
+  std::vector<int32_t> cat(S * NR * NT);
+  for (size_t x = 0; x < cat.size(); ++x) cat[x] = static_cast<int32_t>(x % (NR * NT));
+  if (e == hipSuccess) e = hipMemcpyAsync(ctx->d_state + l.clone_at, cat.data(), 4 * cat.size(), hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return ctx->hip_fail(e, "copy to the state buffer");
+  // zero the counters and bookkeeping regions with a kernel
+  const size_t zero_from = l.er_head, zero_to = l.total;
+  e = pthr::launch_zero(ctx->d_state + zero_from, zero_to - zero_from, s);
+  if (e == hipSuccess) e = pthr::launch_init(ctx->g, ctx->state(), s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);  // host staging buffers go out of scope
+  if (e != hipSuccess) return ctx->hip_fail(e, "state initialisation");
+  ctx->t = 0;
+  ctx->m_pt = ctx->m_er = 0;
+  ctx->ready = true;
+  return PTHR_OK;
+}
+
+int pthr_sweep(pthr_ctx* ctx, int n_pt, int n_er, void* stream) {
+  if (!ctx) return PTHR_EINVAL;
+  ctx->err.clear();
+  if (int rc = ctx->need_ready()) return rc;
+  if (n_pt < 0 || n_er < 0) return ctx->fail(PTHR_EINVAL, "sweep counts must be >= 0");
+  if (ctx->d.NER == 0) n_er = 0;
+  if (ctx->m_pt + n_pt > 256 || ctx->m_er + n_er > 256)
+    return ctx->fail(PTHR_ESTATE, "more than 256 sweeps in one EMCS (sweep counter field is 8 bits)");
+  if (n_pt == 0 && n_er == 0) return PTHR_OK;
+  pthr::Run run{};
+  run.t0 = static_cast<uint32_t>(ctx->t);
+  run.phases = pthr::kPhaseSweep;
+  run.m_pt0 = ctx->m_pt;
+  run.n_pt = n_pt;
+  run.m_er0 = ctx->m_er;
+  run.n_er = n_er;
+  if (int rc = ctx->launch(run, nullptr, static_cast<hipStream_t>(stream))) return rc;
+  ctx->m_pt += n_pt;
+  ctx->m_er += n_er;
+  return PTHR_OK;
+}
+
+int pthr_houdayer(pthr_ctx* ctx, void* stream) {
+  if (!ctx) return PTHR_EINVAL;
+  ctx->err.clear();
+  if (int rc = ctx->need_ready()) return rc;
+  if (ctx->K_acu == 0) return PTHR_OK;
+  pthr::Run run{};
+  run.t0 = static_cast<uint32_t>(ctx->t);
+  run.phases = pthr::kPhaseHoudayer;
+  return ctx->launch(run, nullptr, static_cast<hipStream_t>(stream));
+}
+
+int pthr_pt_swap(pthr_ctx* ctx, int do_reservoir, void* stream) {
+  if (!ctx) return PTHR_EINVAL;
+  ctx->err.clear();
+  if (int rc = ctx->need_ready()) return rc;
+  if (ctx->t >= 0xFFFFFFFFll) return ctx->fail(PTHR_ESTATE, "EMCS counter exhausted (2^32)");
+  pthr::Run run{};
+  run.t0 = static_cast<uint32_t>(ctx->t);
+  run.phases = pthr::kPhasePT;
+  run.do_reservoir = do_reservoir ? 1 : 0;
+  if (int rc = ctx->launch(run, nullptr, static_cast<hipStream_t>(stream))) return rc;
+  ctx->t += 1;
+  ctx->m_pt = ctx->m_er = 0;
+  return PTHR_OK;
+}
+
+int pthr_measure(pthr_ctx* ctx, void* d_obs, void* stream) {
+  if (!ctx) return PTHR_EINVAL;
+  ctx->err.clear();
+  if (int rc = ctx->need_ready()) return rc;
+  if (!d_obs) return ctx->fail(PTHR_EINVAL, "d_obs must not be NULL");
+  pthr::Run run{};
+  run.t0 = static_cast<uint32_t>(ctx->t);
+  run.phases = pthr::kPhaseMeasure;
+  return ctx->launch(run, d_obs, static_cast<hipStream_t>(stream));
+}
+
+int pthr_obs_clear(pthr_ctx* ctx, void* d_obs, void* stream) {
+  if (!ctx) return PTHR_EINVAL;
+  ctx->err.clear();
+  if (!d_obs) return ctx->fail(PTHR_EINVAL, "d_obs must not be NULL");
+  hipError_t e = pthr::launch_zero(d_obs, pthr_obs_bytes(&ctx->p), static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? PTHR_OK : ctx->hip_fail(e, "obs clear");
+}
+
+int pthr_run(pthr_ctx* ctx, int64_t n_emcs, void* d_obs, void* stream) {
+  if (!ctx) return PTHR_EINVAL;
+  ctx->err.clear();
+  if (int rc = ctx->need_ready()) return rc;
+  if (n_emcs < 0) return ctx->fail(PTHR_EINVAL, "n_emcs must be >= 0");
+  if (ctx->m_pt || ctx->m_er) return ctx->fail(PTHR_ESTATE, "an EMCS is in progress (sweep counters not at 0)");
+  if (ctx->t + n_emcs > 0xFFFFFFFFll) return ctx->fail(PTHR_ESTATE, "EMCS counter would pass 2^32");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  for (int64_t e = 0; e < n_emcs; ++e) {
+    // one EMCS: sweep kernel, Houdayer kernel, PT/ER kernel, measure kernel
+    pthr::Run run{};
+    run.t0 = static_cast<uint32_t>(ctx->t);
+      run.phases = pthr::kPhaseSweep | (ctx->K_acu ? pthr::kPhaseHoudayer : 0u) | pthr::kPhasePT |
+                 (d_obs ? pthr::kPhaseMeasure : 0u);
+    run.m_pt0 = 0;
+    run.n_pt = ctx->p.sweeps_per_emcs;
+    run.m_er0 = 0;
+    run.n_er = ctx->d.NER > 0 ? ctx->p.er_sweeps_per_emcs : 0;
+    run.do_reservoir = 1;
+    if (int rc = ctx->launch(run, d_obs, s)) return rc;
+    ctx->t += 1;
+  }
+  return PTHR_OK;
+}
+
+int pthr_cluster_labels(pthr_ctx* ctx, void* d_labels, void* stream) {
+  if (!ctx) return PTHR_EINVAL;
+  ctx->err.clear();
+  if (int rc = ctx->need_ready()) return rc;
+  if (!d_labels) return ctx->fail(PTHR_EINVAL, "d_labels must not be NULL");
+  if (ctx->K_acu == 0) return PTHR_OK;
+  pthr::Run run{};
+  run.t0 = static_cast<uint32_t>(ctx->t);
+  run.phases = pthr::kPhaseLabels;
+  run.labels = static_cast<int32_t*>(d_labels);
+  return ctx->launch(run, nullptr, static_cast<hipStream_t>(stream));
+}
+
+int pthr_read_spins(pthr_ctx* ctx, int8_t* spins, void* stream) {
+  if (!ctx) return PTHR_EINVAL;
+  ctx->err.clear();
+  if (int rc = ctx->need_ready()) return rc;
+  if (!spins) return ctx->fail(PTHR_EINVAL, "spins must not be NULL");
+  const Derived& d = ctx->d;
+  const size_t S = ctx->p.n_samples;
+  std::vector<uint32_t> words(S * d.NW * d.V);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = hipMemcpyAsync(words.data(), ctx->d_state + ctx->lay.spins, 4 * words.size(), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return ctx->hip_fail(e, "read spins");
+  const int L = ctx->p.L, Vh = d.V / 2;
+  for (size_t smp = 0; smp < S; ++smp)
+    for (int c = 0; c < d.C; ++c) {
+      const int w = c < d.NPT ? c / 32 : d.NWPT + (c - d.NPT) / 32;
+      const int b = c < d.NPT ? c % 32 : (c - d.NPT) % 32;
+      const uint32_t* plane = words.data() + (smp * d.NW + w) * d.V;
+      int8_t* out = spins + (smp * d.C + c) * d.V;
+      for (int i = 0; i < d.V; ++i) {
+        const int x = i % L, y = (i / L) % L, z = i / (L * L);
+        const int j = ((x + y + z) & 1) * Vh + (i >> 1);
+        out[i] = ((plane[j] >> b) & 1u) ? -1 : 1;
+      }
+    }
+  return PTHR_OK;
+}
+
+int pthr_read_pt(pthr_ctx* ctx, int32_t* clone_at, int32_t* er_head, uint8_t* pt_last, uint32_t* pt_count,
+                 double* pt_energy, uint8_t* rt_state, uint64_t* rt_count, void* stream) {
+  if (!ctx) return PTHR_EINVAL;
+  ctx->err.clear();
+  if (int rc = ctx->need_ready()) return rc;
+  const size_t S = ctx->p.n_samples, NR = ctx->p.n_replicas, NT = ctx->p.n_temps;
+  const Layout& l = ctx->lay;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  struct Item {
+    void* dst;
+    size_t off, bytes;
+  } items[] = {{clone_at, l.clone_at, 4 * S * NR * NT}, {er_head, l.er_head, 4 * S * NR},
+               {pt_last, l.pt_last, S * NR * (NT - 1)},  {pt_count, l.pt_count, 4 * S * NR * (NT - 1)},
+               {pt_energy, l.pt_energy, 8 * S * ctx->d.NPT}, {rt_state, l.rt_state, S * ctx->d.NPT},
+               {rt_count, l.rt_count, 8 * S}};
+  for (const Item& it : items) {
+    if (!it.dst) continue;
+    hipError_t e = hipMemcpyAsync(it.dst, ctx->d_state + it.off, it.bytes, hipMemcpyDeviceToHost, s);
+    if (e != hipSuccess) return ctx->hip_fail(e, "read PT state");
+  }
+  hipError_t e = hipStreamSynchronize(s);
+  return e == hipSuccess ? PTHR_OK : ctx->hip_fail(e, "read PT state");
+}
+
+int pthr_counters(const pthr_ctx* ctx, int64_t* t, int32_t* m_pt, int32_t* m_er) {
+  if (!ctx) return PTHR_EINVAL;
+  if (t) *t = ctx->t;
+  if (m_pt) *m_pt = ctx->m_pt;
+  if (m_er) *m_er = ctx->m_er;
+  return PTHR_OK;
+}
+
+int pthr_check(pthr_ctx* ctx, void* stream) {
+  if (!ctx) return PTHR_EINVAL;
+  ctx->err.clear();
+  if (int rc = ctx->need_ready()) return rc;
+  std::vector<uint32_t> st(ctx->p.n_samples);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = hipMemcpyAsync(st.data(), ctx->d_state + ctx->lay.status, 4 * st.size(), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return ctx->hip_fail(e, "read status");
+  for (size_t i = 0; i < st.size(); ++i)
+    if (st[i]) return ctx->fail(PTHR_EDEVICE, "sample %zu: status 0x%x (union-find iteration bound hit)", i, st[i]);
+  return PTHR_OK;
+}
+
+namespace {
+struct BlobHeader {
+  uint64_t magic;
+  pthr_params p;
+  int64_t t;
+  int32_t m_pt, m_er;
+  uint64_t state_bytes;
+};
+}  // namespace
+
+size_t pthr_blob_bytes(const pthr_ctx* ctx) { return ctx ? sizeof(BlobHeader) + ctx->lay.total : 0; }
+
+int pthr_get_state(pthr_ctx* ctx, void* blob, size_t bytes, void* stream) {
+  if (!ctx) return PTHR_EINVAL;
+  ctx->err.clear();
+  if (int rc = ctx->need_ready()) return rc;
+  if (!blob || bytes < pthr_blob_bytes(ctx)) return ctx->fail(PTHR_EINVAL, "blob too small");
+  BlobHeader h{};
+  h.magic = kBlobMagic;
+  h.p = ctx->p;
+  h.t = ctx->t;
+  h.m_pt = ctx->m_pt;
+  h.m_er = ctx->m_er;
+  h.state_bytes = ctx->lay.total;
+  std::memcpy(blob, &h, sizeof h);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = hipMemcpyAsync(static_cast<unsigned char*>(blob) + sizeof h, ctx->d_state, ctx->lay.total,
+                                hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  return e == hipSuccess ? PTHR_OK : ctx->hip_fail(e, "get state");
+}
+
+int pthr_set_state(pthr_ctx* ctx, const void* blob, size_t bytes, void* stream) {
+  if (!ctx) return PTHR_EINVAL;
+  ctx->err.clear();
+  if (int rc = ctx->need_ready()) return rc;
+  if (!blob || bytes < sizeof(BlobHeader)) return ctx->fail(PTHR_EINVAL, "blob too small");
+  BlobHeader h{};
+  std::memcpy(&h, blob, sizeof h);
+  if (h.magic != kBlobMagic || std::memcmp(&h.p, &ctx->p, sizeof h.p) != 0 || h.state_bytes != ctx->lay.total ||
+      bytes < sizeof h + h.state_bytes)
+    return ctx->fail(PTHR_EINVAL, "blob does not belong to a context with these parameters");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = hipMemcpyAsync(ctx->d_state, static_cast<const unsigned char*>(blob) + sizeof h, h.state_bytes,
+                                hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return ctx->hip_fail(e, "set state");
+  ctx->t = h.t;
+  ctx->m_pt = h.m_pt;
+  ctx->m_er = h.m_er;
+  return PTHR_OK;
+}
+
+int pthr_get_schedule(const pthr_ctx* ctx, pthr_schedule* out) {
+  if (!ctx || !out) return PTHR_EINVAL;
+  *out = ctx->sch;
+  return PTHR_OK;
+}
+
+int pthr_set_schedule(pthr_ctx* ctx, const pthr_schedule* sch) {
+  if (!ctx || !sch) return PTHR_EINVAL;
+  ctx->err.clear();
+  bool ok = false;
+  for (int ch = 2; ch <= 8; ch *= 2)
+    if (chunk_ok(ctx->p.precision, ctx->d.V, ch) && threads_for(ctx->d.V, ch) == sch->threads_per_sample) ok = true;
+  if (!ok)
+    return ctx->fail(PTHR_EINVAL,
+                     "threads_per_sample must be ceil(V/chunk / 64)*64 for chunk in {2,4,8} (FP64: {2,4}) and <= 1024");
+  if (sch->samples_per_launch < 0 || sch->reserved != 0) return ctx->fail(PTHR_EINVAL, "bad samples_per_launch");
+  ctx->sch = *sch;
+  ctx->sch.exp_early_out = sch->exp_early_out ? 1 : 0;
+  return PTHR_OK;
+}
+
+int pthr_autotune(pthr_ctx* ctx, void* d_scratch, int n_emcs, double* best_ms, void* stream) {
+  if (!ctx) return PTHR_EINVAL;
+  ctx->err.clear();
+  if (int rc = ctx->need_ready()) return rc;
+  if (!d_scratch || n_emcs < 1) return ctx->fail(PTHR_EINVAL, "need a scratch buffer and n_emcs >= 1");
+  if (ctx->m_pt || ctx->m_er) return ctx->fail(PTHR_ESTATE, "an EMCS is in progress");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  unsigned char* real = ctx->d_state;
+  const int64_t t_saved = ctx->t;
+  const pthr_schedule saved = ctx->sch;
+  pthr_schedule best = saved;
+  double best_t = 1e300;
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    return ctx->fail(PTHR_EHIP, "event creation failed");
+  int rc = PTHR_OK;
+  for (int ch = 2; ch <= 8 && rc == PTHR_OK; ch *= 2) {
+    if (!chunk_ok(ctx->p.precision, ctx->d.V, ch)) continue;
+    if (ch > 2 && threads_for(ctx->d.V, ch) == threads_for(ctx->d.V, ch / 2)) continue;
+    for (int early = 0; early <= 1 && rc == PTHR_OK; ++early) {
+      pthr_schedule cand = saved;
+      cand.threads_per_sample = threads_for(ctx->d.V, ch);
+      cand.exp_early_out = early;
+      ctx->sch = cand;
+      hipError_t e = hipMemcpyAsync(d_scratch, real, ctx->lay.total, hipMemcpyDeviceToDevice, s);
+      if (e != hipSuccess) {
+        rc = ctx->hip_fail(e, "autotune copy");
+        break;
+      }
+      ctx->d_state = static_cast<unsigned char*>(d_scratch);
+      ctx->t = t_saved;
+      float ms = 0.f;
+      if (hipEventRecord(e0, s) != hipSuccess) rc = ctx->fail(PTHR_EHIP, "autotune event");
+      if (rc == PTHR_OK) rc = pthr_run(ctx, n_emcs, nullptr, stream);
+      if (rc == PTHR_OK && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                            hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+        rc = ctx->fail(PTHR_EHIP, "autotune timing");
+      if (rc == PTHR_OK && ms < best_t) {
+        best_t = ms;
+        best = cand;
+      }
+      ctx->d_state = real;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  ctx->d_state = real;
+  ctx->t = t_saved;
+  ctx->sch = rc == PTHR_OK ? best : saved;
+  if (best_ms) *best_ms = best_t;
+  return rc;
+}
+
+}  // extern "C"

@@ -1,0 +1,84 @@
+// Internal interface between the C ABI (pthr_api.cpp) and the kernels
+// (pthr_kernels.hip).  Not installed; the public interface is include/pthr.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace pthr {
+
+// Counter word 0 of every Philox block: site | sweep << 16 | purpose << 24.
+enum Purpose : uint32_t { kInit = 1, kMetro = 2, kAcu = 3, kHseed = 4, kPt = 5 };
+
+enum Phase : uint32_t {
+  kPhaseSweep = 1u,     // Metropolis sweeps of PT and/or ER clones
+  kPhaseHoudayer = 2u,  // one Houdayer move per pair and T_k < t_acu
+  kPhasePT = 4u,        // energies, PT chain, round trips, ER exchange
+  kPhaseMeasure = 8u,   // observables into the obs buffer
+  kPhaseLabels = 16u,   // canonical cluster labels into a caller buffer
+};
+
+// Problem geometry, identical for every sample of a context.
+struct Geo {
+  int L, V, Vh;      // lattice side, sites, sites per checkerboard colour
+  int S;             // samples
+  int NR, NT;        // replica groups, temperatures
+  int NERG;          // reservoir clones per group
+  int NPT, NER, C;   // PT clones (NR*NT), ER clones (NR*NERG), all clones
+  int NW, NWPT;      // 32-clone spin words per site: all, PT only
+  int K_acu;         // number of temperatures with T_k < t_acu (a prefix)
+  int mode;          // 0 all-cluster, 1 single negative cluster
+  uint32_t key0, key1;
+};
+
+// Device pointers into the caller's state buffer (layout in pthr_api.cpp).
+struct State {
+  uint32_t* spins;     // [S][NW][V] words; bit b of word w at site index j is
+                       // clone 32w+b (PT) or NPT+32(w-NWPT)+b (ER); j = colour*Vh + i/2
+  void* J;             // [S][3][V] double (FP64) or float (FP32), natural site order
+  int32_t* clone_at;   // [S][NR][NT]
+  int32_t* er_head;    // [S][NR]
+  uint8_t* pt_last;    // [S][NR][NT-1]
+  uint32_t* pt_count;  // [S][NR][NT-1]
+  double* pt_energy;   // [S][NPT]
+  uint8_t* rt_state;   // [S][NPT]
+  uint64_t* rt_count;  // [S]
+  uint32_t* status;    // [S]
+  const double* beta64;  // [NT]
+  const float* beta32;   // [NT]
+};
+
+struct Obs {
+  uint64_t* n_meas;
+  double* acc;    // [S][NT][6]
+  uint64_t* hist; // [NT][V+1]
+};
+
+struct Run {
+  uint32_t t0;        // EMCS index of the first EMCS in this launch
+  uint32_t phases;    // Phase bits
+  int m_pt0, n_pt;    // PT sweep counter start and number of PT sweeps
+  int m_er0, n_er;    // same for ER clones
+  int do_reservoir;
+  int sample_begin;   // first sample of this launch
+  int32_t* labels;    // kPhaseLabels output [S][NR/2][K_acu][V]
+};
+
+// Device status bits (per sample).
+enum : uint32_t { kStatusUnionBound = 1u, kStatusFindBound = 2u };
+
+struct Shape {
+  int chunk;       // sites per work-item: 2, 4 or 8
+  int threads;     // work-items per sample workgroup (multiple of 64, <= 1024)
+  bool early_out;  // decide Metropolis tests from the binade of exp(x) first
+};
+
+size_t lds_bytes(const Geo& g, int fp_bytes);
+hipError_t launch_emcs(int precision, const Geo& g, const State& st, const Obs& ob, const Run& run,
+                       const Shape& sh, int n_blocks, hipStream_t stream);
+hipError_t launch_init(const Geo& g, const State& st, hipStream_t stream);
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t stream);
+
+}  // namespace pthr

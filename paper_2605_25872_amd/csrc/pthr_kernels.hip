@@ -1,0 +1,1002 @@
+// PTHR kernels for gfx950 (CDNA4).
+//
+// One workgroup owns one disorder sample for the whole launch.  Its LDS holds
+// every clone's spins bit-packed 32 clones per word: word w of site j is a
+// 32-bit mask whose bit b is clone 32w+b (1 = spin down).  Sites are split by
+// checkerboard colour, j = colour*V/2 + i/2, so the sites one colour updates
+// are contiguous and their neighbours are all in the other half.  Each
+// work-item owns `CH` consecutive natural sites (CH/2 of each colour) and keeps
+// their six couplings in registers for the whole launch; one 32-bit LDS load of
+// a neighbour word serves the 32 clones that share that site and those
+// couplings (the paper's multispin idea, App. A.1, carried to 32 clones per
+// word).  A launch runs `n_emcs` elementary Monte Carlo steps (paper Sec. 3)
+// with the state resident in LDS; step-wise API calls run one phase.
+//
+// Exactness: every random number is a Philox4x32-10 block keyed by
+// (seed; site | sweep<<16 | purpose<<24, EMCS, slot, sample), and every
+// floating-point result is produced by a fixed sequence of correctly rounded
+// operations (explicit fma, no contraction), so any launch shape gives the
+// same bits.
+
+#include <hip/hip_runtime.h>
+
+#include "pthr_internal.h"
+
+namespace pthr {
+namespace {
+
+constexpr int kWave = 64;
+constexpr int kMaxThreads = 1024;
+constexpr int kMaxWaves = kMaxThreads / kWave;
+
+// ---------------------------------------------------------------- random bits
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11).
+struct Block {
+  uint32_t w0, w1, w2, w3;
+};
+
+__device__ __forceinline__ Block philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                          uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int round = 0; round < 10; ++round) {
+    const uint64_t pa = static_cast<uint64_t>(0xD2511F53u) * c0;
+    const uint64_t pb = static_cast<uint64_t>(0xCD9E8D57u) * c2;
+    const uint32_t n0 = static_cast<uint32_t>(pb >> 32) ^ c1 ^ k0;
+    const uint32_t n2 = static_cast<uint32_t>(pa >> 32) ^ c3 ^ k1;
+    c1 = static_cast<uint32_t>(pb);
+    c3 = static_cast<uint32_t>(pa);
+    c0 = n0;
+    c2 = n2;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  return Block{c0, c1, c2, c3};
+}
+
+__device__ __forceinline__ uint32_t ctr_word(uint32_t site, uint32_t m, uint32_t purpose) {
+  return site | (m << 16) | (purpose << 24);
+}
+
+// [0,1) with 53 random bits: exact.
+__device__ __forceinline__ double uniform53(uint32_t lo, uint32_t hi) {
+  const uint64_t bits = ((static_cast<uint64_t>(hi) << 32) | lo) >> 11;
+  return static_cast<double>(bits) * 0x1p-53;
+}
+// [0,1] from one word rounded to float (FP32 form).
+__device__ __forceinline__ float uniform32(uint32_t w) {
+  return static_cast<float>(w) * 0x1p-32f;
+}
+
+// ---------------------------------------------------------------- exp(x), x <= 0
+// Cody-Waite: x = k ln2 + r with ln2 split in a 32-bit head and a tail, then
+// sum_{n<=13} r^n/n! by Horner with fused multiply-adds (1/n! rounded to
+// double), scaled by 2^k.  The result lies strictly inside (2^(k-1), 2^(k+1)).
+__device__ __forceinline__ double exp_poly64(double x, double k) {
+  double r = __builtin_fma(-k, 0x1.62e42feep-1, x);
+  r = __builtin_fma(-k, 0x1.a39ef35793c76p-33, r);
+  double p = 0x1.6124613a86d09p-33;             // 1/13!
+  p = __builtin_fma(p, r, 0x1.1eed8eff8d898p-29); // 1/12!
+  p = __builtin_fma(p, r, 0x1.ae64567f544e4p-26); // 1/11!
+  p = __builtin_fma(p, r, 0x1.27e4fb7789f5cp-22); // 1/10!
+  p = __builtin_fma(p, r, 0x1.71de3a556c734p-19); // 1/9!
+  p = __builtin_fma(p, r, 0x1.a01a01a01a01ap-16); // 1/8!
+  p = __builtin_fma(p, r, 0x1.a01a01a01a01ap-13); // 1/7!
+  p = __builtin_fma(p, r, 0x1.6c16c16c16c17p-10); // 1/6!
+  p = __builtin_fma(p, r, 0x1.1111111111111p-7);  // 1/5!
+  p = __builtin_fma(p, r, 0x1.5555555555555p-5);  // 1/4!
+  p = __builtin_fma(p, r, 0x1.5555555555555p-3);  // 1/3!
+  p = __builtin_fma(p, r, 0x1p-1);                // 1/2!
+  p = __builtin_fma(p, r, 1.0);                   // 1/1!
+  p = __builtin_fma(p, r, 1.0);                   // 1/0!
+  return __builtin_ldexp(p, static_cast<int>(k));
+}
+__device__ __forceinline__ double exp_neg64(double x) {
+  if (x < -708.0) return 0.0;
+  return exp_poly64(x, __builtin_rint(x * 0x1.71547652b82fep+0));
+}
+
+// FP32 form: same reduction with a 16-bit head, degree-7 polynomial.
+__device__ __forceinline__ float exp_poly32(float x, float k) {
+  float r = __builtin_fmaf(-k, 0x1.62e4p-1f, x);
+  r = __builtin_fmaf(-k, 0x1.7f7d1cp-20f, r);
+  float p = 0x1.a01a02p-13f;              // 1/7!
+  p = __builtin_fmaf(p, r, 0x1.6c16c2p-10f); // 1/6!
+  p = __builtin_fmaf(p, r, 0x1.111112p-7f);  // 1/5!
+  p = __builtin_fmaf(p, r, 0x1.555556p-5f);  // 1/4!
+  p = __builtin_fmaf(p, r, 0x1.555556p-3f);  // 1/3!
+  p = __builtin_fmaf(p, r, 0x1p-1f);         // 1/2!
+  p = __builtin_fmaf(p, r, 1.0f);            // 1/1!
+  p = __builtin_fmaf(p, r, 1.0f);            // 1/0!
+  return __builtin_ldexpf(p, static_cast<int>(k));
+}
+__device__ __forceinline__ float exp_neg32(float x) {
+  if (x < -86.0f) return 0.0f;
+  return exp_poly32(x, __builtin_rintf(x * 0x1.715476p+0f));
+}
+
+// Metropolis test "u < exp(x)" for x = -beta*dE < 0.  With kEarly the binade
+// bracket decides it without the polynomial unless u falls within a factor 2
+// of exp(x); both forms return the same decision.
+template <typename FP>
+struct Prec;
+template <>
+struct Prec<double> {
+  static __device__ __forceinline__ double u(const Block& b, int word_pair) {
+    return word_pair ? uniform53(b.w2, b.w3) : uniform53(b.w0, b.w1);
+  }
+  template <bool kEarly>
+  static __device__ __forceinline__ bool accept(double u, double x) {
+    if (x < -708.0) return false;
+    const double k = __builtin_rint(x * 0x1.71547652b82fep+0);
+    if (kEarly) {
+      const int ki = static_cast<int>(k);
+      if (u < __builtin_ldexp(1.0, ki - 1)) return true;
+      if (!(u < __builtin_ldexp(1.0, ki + 1))) return false;
+    }
+    return u < exp_poly64(x, k);
+  }
+  static __device__ __forceinline__ double neg_if(double v, uint32_t bit) {
+    const unsigned long long sign = static_cast<unsigned long long>(bit) << 63;
+    return __longlong_as_double(static_cast<long long>(static_cast<unsigned long long>(__double_as_longlong(v)) ^ sign));
+  }
+};
+template <>
+struct Prec<float> {
+  template <bool kEarly>
+  static __device__ __forceinline__ bool accept(float u, float x) {
+    if (x < -86.0f) return false;
+    const float k = __builtin_rintf(x * 0x1.715476p+0f);
+    if (kEarly) {
+      const int ki = static_cast<int>(k);
+      if (u < __builtin_ldexpf(1.0f, ki - 1)) return true;
+      if (!(u < __builtin_ldexpf(1.0f, ki + 1))) return false;
+    }
+    return u < exp_poly32(x, k);
+  }
+  static __device__ __forceinline__ float neg_if(float v, uint32_t bit) {
+    return __int_as_float(__float_as_int(v) ^ static_cast<int>(bit << 31));
+  }
+};
+
+// ---------------------------------------------------------------- lattice helpers
+struct Site {
+  int i, x, y, z;
+};
+__device__ __forceinline__ Site site_of(int i, int L) {
+  const int x = i % L, yz = i / L;
+  return Site{i, x, yz % L, yz / L};
+}
+// Natural index of the neighbour in direction d (+x,-x,+y,-y,+z,-z).
+__device__ __forceinline__ int neighbour(const Site& s, int d, int L) {
+  const int L2 = L * L;
+  switch (d) {
+    case 0: return s.x + 1 < L ? s.i + 1 : s.i - (L - 1);
+    case 1: return s.x > 0 ? s.i - 1 : s.i + (L - 1);
+    case 2: return s.y + 1 < L ? s.i + L : s.i - L * (L - 1);
+    case 3: return s.y > 0 ? s.i - L : s.i + L * (L - 1);
+    case 4: return s.z + 1 < L ? s.i + L2 : s.i - L2 * (L - 1);
+    default: return s.z > 0 ? s.i - L2 : s.i + L2 * (L - 1);
+  }
+}
+// Word index (within one clone-word plane) of natural site i.
+__device__ __forceinline__ int plane_idx(int i, int colour, int Vh) { return colour * Vh + (i >> 1); }
+__device__ __forceinline__ int colour_of(const Site& s) { return (s.x + s.y + s.z) & 1; }
+
+__device__ __forceinline__ int word_of(const Geo& g, int clone) {
+  return clone < g.NPT ? (clone >> 5) : g.NWPT + ((clone - g.NPT) >> 5);
+}
+__device__ __forceinline__ int bit_of(const Geo& g, int clone) {
+  return clone < g.NPT ? (clone & 31) : ((clone - g.NPT) & 31);
+}
+
+// ---------------------------------------------------------------- LDS layout
+struct Lds {
+  uint32_t* sp;   // [NW][V]
+  uint32_t* lab;  // [max(V, 2*16*NPT)] labels; reused for energy partials
+  uint8_t* qb;    // [V] site overlap bits
+  uint32_t* eta;  // [ceil(V/32)] ACU flip flags per root
+  int32_t* cat;   // [NR][NT]
+  int32_t* head;  // [NR]
+  double* E;      // [NPT]
+  void* bcl;      // [C] beta per clone (FP)
+  uint8_t* rt;    // [NPT]
+  int32_t* qacc;  // [NT][npairs][2]
+  int32_t* misc;  // [64]
+};
+
+__host__ __device__ inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+struct LdsPlan {
+  size_t sp, lab, qb, eta, cat, head, E, bcl, rt, qacc, misc, total;
+};
+__host__ __device__ inline LdsPlan plan_lds(const Geo& g, int fp_bytes) {
+  LdsPlan p{};
+  size_t o = 0;
+  const int npairs = g.NR * (g.NR - 1) / 2;
+  p.sp = o;   o = align_up(o + sizeof(uint32_t) * size_t(g.NW) * g.V, 16);
+  size_t lab_words = size_t(g.V);
+  const size_t red_words = size_t(2) * kMaxWaves * g.NPT;
+  if (red_words > lab_words) lab_words = red_words;
+  p.lab = o;  o = align_up(o + sizeof(uint32_t) * lab_words, 16);
+  p.qb = o;   o = align_up(o + size_t(g.V), 16);
+  p.eta = o;  o = align_up(o + sizeof(uint32_t) * ((g.V + 31) / 32), 16);
+  p.cat = o;  o = align_up(o + sizeof(int32_t) * size_t(g.NR) * g.NT, 16);
+  p.head = o; o = align_up(o + sizeof(int32_t) * size_t(g.NR), 16);
+  p.E = o;    o = align_up(o + sizeof(double) * size_t(g.NPT), 16);
+  p.bcl = o;  o = align_up(o + size_t(fp_bytes) * g.C, 16);
+  p.rt = o;   o = align_up(o + size_t(g.NPT), 16);
+  p.qacc = o; o = align_up(o + sizeof(int32_t) * 2 * size_t(g.NT) * (npairs > 0 ? npairs : 1), 16);
+  p.misc = o; o = align_up(o + sizeof(int32_t) * 64, 16);
+  p.total = o;
+  return p;
+}
+
+extern __shared__ __align__(16) unsigned char lds_raw[];
+
+// Views into the dynamic LDS allocation; every phase rebuilds its own (a few
+// integer operations) instead of receiving a struct by reference.
+__device__ __forceinline__ Lds lds_view(const Geo& g, int fp_bytes) {
+  const LdsPlan plan = plan_lds(g, fp_bytes);
+  Lds s;
+  s.sp = reinterpret_cast<uint32_t*>(lds_raw + plan.sp);
+  s.lab = reinterpret_cast<uint32_t*>(lds_raw + plan.lab);
+  s.qb = lds_raw + plan.qb;
+  s.eta = reinterpret_cast<uint32_t*>(lds_raw + plan.eta);
+  s.cat = reinterpret_cast<int32_t*>(lds_raw + plan.cat);
+  s.head = reinterpret_cast<int32_t*>(lds_raw + plan.head);
+  s.E = reinterpret_cast<double*>(lds_raw + plan.E);
+  s.bcl = lds_raw + plan.bcl;
+  s.rt = lds_raw + plan.rt;
+  s.qacc = reinterpret_cast<int32_t*>(lds_raw + plan.qacc);
+  s.misc = reinterpret_cast<int32_t*>(lds_raw + plan.misc);
+  return s;
+}
+
+// ---------------------------------------------------------------- reductions
+__device__ __forceinline__ int lane_id() { return threadIdx.x & (kWave - 1); }
+__device__ __forceinline__ int wave_id() { return threadIdx.x / kWave; }
+
+__device__ __forceinline__ int wave_sum_int(int v) {
+#pragma unroll
+  for (int off = 1; off < kWave; off <<= 1) v += __shfl_xor(v, off, kWave);
+  return v;
+}
+__device__ __forceinline__ int wave_incl_scan(int v) {
+#pragma unroll
+  for (int off = 1; off < kWave; off <<= 1) {
+    const int o = __shfl_up(v, off, kWave);
+    if (lane_id() >= off) v += o;
+  }
+  return v;
+}
+
+// Exclusive prefix over the workgroup; *total gets the sum.  Uses misc[0..31].
+__device__ int block_exclusive_scan(int v, int32_t* misc, int* total) {
+  const int incl = wave_incl_scan(v);
+  const int nw = (blockDim.x + kWave - 1) / kWave;
+  if (lane_id() == kWave - 1) misc[wave_id()] = incl;
+  __syncthreads();
+  int before = 0, all = 0;
+  for (int w = 0; w < nw; ++w) {
+    const int m = misc[w];
+    if (w < wave_id()) before += m;
+    all += m;
+  }
+  __syncthreads();
+  *total = all;
+  return before + incl - v;
+}
+
+// ---------------------------------------------------------------- union-find
+// Lock-free union-find in LDS with atomicMin links towards the smaller index:
+// every label points to a smaller-or-equal site of the same cluster, so the
+// final root of a cluster is its smallest site.
+__device__ __forceinline__ int find_root(const uint32_t* lab, int x, int V, bool* bad) {
+  int n = 0;
+  int y = static_cast<int>(lab[x]);
+  while (y != x) {
+    x = y;
+    y = static_cast<int>(lab[x]);
+    if (++n > V) {
+      *bad = true;
+      break;
+    }
+  }
+  return x;
+}
+__device__ __forceinline__ void unite(uint32_t* lab, int a, int b, int V, bool* bad) {
+  for (int n = 0; n < 4 * V + 8; ++n) {
+    a = find_root(lab, a, V, bad);
+    b = find_root(lab, b, V, bad);
+    if (a == b) return;
+    if (a < b) {
+      const int old = static_cast<int>(atomicMin(&lab[b], static_cast<uint32_t>(a)));
+      if (old == b) return;
+      b = old;
+    } else {
+      const int old = static_cast<int>(atomicMin(&lab[a], static_cast<uint32_t>(b)));
+      if (old == a) return;
+      a = old;
+    }
+  }
+  *bad = true;
+}
+
+// ---------------------------------------------------------------- the kernel
+// Own sites of a work-item: the CH consecutive natural sites starting at
+// threadIdx.x * CH (CH/2 of each colour, since L is even).
+template <int CH>
+struct Own {
+  int first;
+  bool owns;
+  __device__ __forceinline__ Own(int V) : first(static_cast<int>(threadIdx.x) * CH), owns(first < V) {}
+};
+
+// Flip clones a and b at plane index j (both replicas of a Houdayer pair).
+__device__ __forceinline__ void flip_pair(const Geo& g, const Lds& s, int a, int b, int j) {
+  const int wa = word_of(g, a), wb = word_of(g, b);
+  const uint32_t ma = 1u << bit_of(g, a), mb = 1u << bit_of(g, b);
+  if (wa == wb) {
+    s.sp[size_t(wa) * g.V + j] ^= (ma | mb);
+  } else {
+    s.sp[size_t(wa) * g.V + j] ^= ma;
+    s.sp[size_t(wb) * g.V + j] ^= mb;
+  }
+}
+__device__ __forceinline__ uint32_t spin_bit(const Geo& g, const Lds& s, int clone, int j) {
+  return (s.sp[size_t(word_of(g, clone)) * g.V + j] >> bit_of(g, clone)) & 1u;
+}
+
+template <typename FP>
+__device__ void rebuild_beta(const Geo& g, const Lds& s, const FP* beta) {
+  FP* bc = static_cast<FP*>(s.bcl);
+  for (int x = threadIdx.x; x < g.NPT; x += blockDim.x) {
+    const int r = x / g.NT, k = x % g.NT;
+    bc[s.cat[r * g.NT + k]] = beta[k];
+  }
+  for (int x = threadIdx.x; x < g.NER; x += blockDim.x) bc[g.NPT + x] = beta[g.NT - 1];
+}
+
+// ------------------------------------------------------------------ Metropolis
+// All attempts of one 32-clone word at one site: bit b of x[d] set means
+// s_i s_j = -1 on bond d, so the local term is -J_d.  dE = 2 sum_d (+-J_d) in
+// neighbour order; accept iff dE <= 0 or u < exp(-beta dE).
+template <typename FP, bool kEarly>
+__device__ __forceinline__ void update_word(const Geo& g, const FP* bc, uint32_t* plane, int self_idx,
+                                            const int (&nb)[6], const FP (&Jd)[6], uint32_t c0w, uint32_t t,
+                                            int sample, int clone0, int nbits) {
+  constexpr int G = sizeof(FP) == 8 ? 2 : 4;  // clones per Philox block
+  const uint32_t self = plane[self_idx];
+  uint32_t x[6];
+#pragma unroll
+  for (int d = 0; d < 6; ++d) x[d] = self ^ plane[nb[d]];
+  uint32_t flips = 0;
+  int c = clone0;
+  const int cend = clone0 + nbits;
+  while (c < cend) {
+    const int grp = c / G;
+    const Block blk = philox10(c0w, t, static_cast<uint32_t>(grp), static_cast<uint32_t>(sample), g.key0, g.key1);
+#pragma unroll
+    for (int j = 0; j < G; ++j) {
+      const int cc = grp * G + j;
+      if (cc < c || cc >= cend) continue;
+      const int b = cc - clone0;
+      FP h = Prec<FP>::neg_if(Jd[0], (x[0] >> b) & 1u);
+#pragma unroll
+      for (int d = 1; d < 6; ++d) h = h + Prec<FP>::neg_if(Jd[d], (x[d] >> b) & 1u);
+      const FP dE = FP(2) * h;
+      bool acc = dE <= FP(0);
+      if (!acc) {
+        FP u;
+        if constexpr (sizeof(FP) == 8) {
+          u = Prec<double>::u(blk, j & 1);
+        } else {
+          const uint32_t wj = j == 0 ? blk.w0 : j == 1 ? blk.w1 : j == 2 ? blk.w2 : blk.w3;
+          u = uniform32(wj);
+        }
+        acc = Prec<FP>::template accept<kEarly>(u, -(bc[cc] * dE));
+      }
+      flips |= static_cast<uint32_t>(acc) << b;
+    }
+    c = grp * G + G;
+  }
+  plane[self_idx] = self ^ flips;
+}
+
+// n_pt sweeps of the PT clones and n_er sweeps of the ER clones, interleaved
+// sweep by sweep (the classes are independent).  Jc[colour][q] are the six
+// couplings of this work-item's colour-`colour` site in pair q.
+template <typename FP, int CH, bool kEarly>
+__device__ __forceinline__ void sweep_phase(const Geo& g, const Lds& s, const FP* Js, int sample, uint32_t t,
+                                            int m_pt0, int n_pt, int m_er0, int n_er) {
+  const Own<CH> own(g.V);
+  // couplings of own sites, by colour, held in registers for all sweeps of this phase
+  FP Jc[2][CH / 2][6];
+  int pq[CH / 2];
+#pragma unroll
+  for (int q = 0; q < CH / 2; ++q) {
+    const int i0 = own.owns ? own.first + 2 * q : 0;
+    const Site s0 = site_of(i0, g.L);
+    pq[q] = s0.x | (s0.y << 10) | (s0.z << 20);
+#pragma unroll
+    for (int colour = 0; colour < 2; ++colour) {
+      const int sel = (s0.y + s0.z + colour) & 1;
+      const Site sc{i0 + sel, s0.x + sel, s0.y, s0.z};
+#pragma unroll
+      for (int d = 0; d < 6; ++d) {
+        const int owner = (d & 1) ? neighbour(sc, d, g.L) : sc.i;
+        Jc[colour][q][d] = own.owns ? Js[size_t(d >> 1) * g.V + owner] : FP(0);
+      }
+    }
+  }
+  const int n_m = n_pt > n_er ? n_pt : n_er;
+  const FP* bc = static_cast<const FP*>(s.bcl);
+  for (int mm = 0; mm < n_m; ++mm) {
+    const bool pt_on = mm < n_pt, er_on = mm < n_er && g.NER > 0;
+    const uint32_t c0pt = ctr_word(0, static_cast<uint32_t>(m_pt0 + mm), kMetro);
+    const uint32_t c0er = ctr_word(0, static_cast<uint32_t>(m_er0 + mm), kMetro);
+#pragma unroll
+    for (int colour = 0; colour < 2; ++colour) {
+      if (own.owns) {
+#pragma unroll
+        for (int q = 0; q < CH / 2; ++q) {
+          const int i0 = own.first + 2 * q;  // x even
+          const int x0 = pq[q] & 1023, y = (pq[q] >> 10) & 1023, z = pq[q] >> 20;
+          const int sel = (y + z + colour) & 1;
+          const Site st{i0 + sel, x0 + sel, y, z};
+          int nb[6];
+#pragma unroll
+          for (int d = 0; d < 6; ++d) nb[d] = plane_idx(neighbour(st, d, g.L), colour ^ 1, g.Vh);
+          const int self_idx = colour * g.Vh + (i0 >> 1);
+          if (pt_on)
+            for (int w = 0; w < g.NWPT; ++w)
+              update_word<FP, kEarly>(g, bc, s.sp + size_t(w) * g.V, self_idx, nb, Jc[colour][q],
+                                      c0pt | static_cast<uint32_t>(st.i), t, sample, 32 * w,
+                                      min(32, g.NPT - 32 * w));
+          if (er_on)
+            for (int w = g.NWPT; w < g.NW; ++w) {
+              const int e0 = 32 * (w - g.NWPT);
+              update_word<FP, kEarly>(g, bc, s.sp + size_t(w) * g.V, self_idx, nb, Jc[colour][q],
+                                      c0er | static_cast<uint32_t>(st.i), t, sample, g.NPT + e0,
+                                      min(32, g.NER - e0));
+            }
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// ------------------------------------------------------------------ clusters
+// Canonical labels of the Houdayer graph of clones a, b into s.lab: sites are
+// joined across a bond iff their site overlaps q = s^a s^b are equal.
+template <int CH>
+__device__ __forceinline__ bool label_phase(const Geo& g, int a, int b) {
+  const Lds s = lds_view(g, 4);
+  const Own<CH> own(g.V);
+  bool bad = false;
+  if (own.owns) {
+#pragma unroll
+    for (int j = 0; j < CH; ++j) {
+      const int i = own.first + j;
+      const Site st = site_of(i, g.L);
+      const int jj = plane_idx(i, colour_of(st), g.Vh);
+      s.qb[i] = static_cast<uint8_t>(spin_bit(g, s, a, jj) ^ spin_bit(g, s, b, jj));
+      s.lab[i] = static_cast<uint32_t>(i);
+    }
+  }
+  __syncthreads();
+  if (own.owns) {
+#pragma unroll
+    for (int j = 0; j < CH; ++j) {
+      const int i = own.first + j;
+      const Site st = site_of(i, g.L);
+      const uint8_t qi = s.qb[i];
+#pragma unroll
+      for (int d = 0; d < 6; d += 2) {
+        const int n = neighbour(st, d, g.L);
+        if (s.qb[n] == qi) unite(s.lab, i, n, g.V, &bad);
+      }
+    }
+  }
+  __syncthreads();
+  if (own.owns) {
+#pragma unroll
+    for (int j = 0; j < CH; ++j) {
+      const int i = own.first + j;
+      s.lab[i] = static_cast<uint32_t>(find_root(s.lab, i, g.V, &bad));
+    }
+  }
+  __syncthreads();
+  return bad;
+}
+
+// One Houdayer move for every pair p and every k < K_acu.
+template <int CH>
+__device__ __forceinline__ bool houdayer_phase(const Geo& g, int sample, uint32_t t) {
+  const Lds s = lds_view(g, 4);
+  const Own<CH> own(g.V);
+  bool bad = false;
+  for (int p = 0; p < g.NR / 2; ++p) {
+    for (int k = 0; k < g.K_acu; ++k) {
+      const int a = s.cat[(2 * p) * g.NT + k], b = s.cat[(2 * p + 1) * g.NT + k];
+      const uint32_t slot = static_cast<uint32_t>(p * g.NT + k);
+      if (g.mode == 0)
+        for (int x = threadIdx.x; x < (g.V + 31) / 32; x += blockDim.x) s.eta[x] = 0u;
+      bad |= label_phase<CH>(g, a, b);
+      if (g.mode == 0) {
+        // all-cluster update: every root draws its cluster's sign
+        if (own.owns) {
+#pragma unroll
+          for (int j = 0; j < CH; ++j) {
+            const int i = own.first + j;
+            if (static_cast<int>(s.lab[i]) == i) {
+              const Block blk = philox10(ctr_word(i, 0, kAcu), t, slot, sample, g.key0, g.key1);
+              if (blk.w0 >> 31) atomicOr(&s.eta[i >> 5], 1u << (i & 31));
+            }
+          }
+        }
+        __syncthreads();
+        if (own.owns) {
+#pragma unroll
+          for (int j = 0; j < CH; ++j) {
+            const int i = own.first + j;
+            const int r = static_cast<int>(s.lab[i]);
+            if ((s.eta[r >> 5] >> (r & 31)) & 1u) flip_pair(g, s, a, b, plane_idx(i, colour_of(site_of(i, g.L)), g.Vh));
+          }
+        }
+      } else {
+        // single cluster: the q = -1 cluster of a uniformly chosen q = -1 site
+        int mine = 0;
+        if (own.owns) {
+#pragma unroll
+          for (int j = 0; j < CH; ++j) mine += s.qb[own.first + j];
+        }
+        int n_minus = 0;
+        const int before = block_exclusive_scan(mine, s.misc, &n_minus);
+        if (n_minus > 0) {
+          const Block blk = philox10(ctr_word(0, 0, kHseed), t, slot, sample, g.key0, g.key1);
+          const int target = static_cast<int>((static_cast<uint64_t>(blk.w0) * static_cast<uint32_t>(n_minus)) >> 32);
+          if (own.owns && target >= before && target < before + mine) {
+            int seen = before;
+#pragma unroll
+            for (int j = 0; j < CH; ++j) {
+              const int i = own.first + j;
+              if (s.qb[i]) {
+                if (seen == target) s.misc[32] = static_cast<int32_t>(s.lab[i]);
+                ++seen;
+              }
+            }
+          }
+          __syncthreads();
+          const int root = s.misc[32];
+          if (own.owns) {
+#pragma unroll
+            for (int j = 0; j < CH; ++j) {
+              const int i = own.first + j;
+              if (static_cast<int>(s.lab[i]) == root) flip_pair(g, s, a, b, plane_idx(i, colour_of(site_of(i, g.L)), g.Vh));
+            }
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  return bad;
+}
+
+template <int CH>
+__device__ __forceinline__ bool labels_out_phase(const Geo& g, int sample, int32_t* labels) {
+  const Lds s = lds_view(g, 4);
+  bool bad = false;
+  for (int p = 0; p < g.NR / 2; ++p)
+    for (int k = 0; k < g.K_acu; ++k) {
+      bad |= label_phase<CH>(g, s.cat[(2 * p) * g.NT + k], s.cat[(2 * p + 1) * g.NT + k]);
+      int32_t* out = labels + ((size_t(sample) * (g.NR / 2) + p) * g.K_acu + k) * g.V;
+      for (int x = threadIdx.x; x < g.V; x += blockDim.x) out[x] = static_cast<int32_t>(s.lab[x]);
+      __syncthreads();
+    }
+  return bad;
+}
+
+// ------------------------------------------------------------------ energies
+// E(c) = -sum_i a_i, a_i = (J_x[i] s_i s_{i+x} + J_y[i] s_i s_{i+y}) + J_z[i] s_i s_{i+z}
+// in double, summed by a pairwise tree in natural site order (own chunk, then
+// a butterfly across the wave, then across the waves), padded with +0.0 to a
+// power of two.  Writes s.E[0..NPT).
+template <typename FP, int CH>
+__device__ __forceinline__ void energy_phase(const Geo& g, const FP* Js) {
+  const Lds s = lds_view(g, sizeof(FP));
+  const Own<CH> own(g.V);
+  double jf[CH][3];
+  int self[CH], fn[CH][3];
+#pragma unroll
+  for (int j = 0; j < CH; ++j) {
+    const int i = own.owns ? own.first + j : 0;
+    const Site st = site_of(i, g.L);
+    const int col = colour_of(st);
+    self[j] = plane_idx(i, col, g.Vh);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      jf[j][d] = own.owns ? static_cast<double>(Js[size_t(d) * g.V + i]) : 0.0;
+      fn[j][d] = plane_idx(neighbour(st, 2 * d, g.L), col ^ 1, g.Vh);
+    }
+  }
+  double* red = reinterpret_cast<double*>(s.lab);
+  const int nwave = (blockDim.x + kWave - 1) / kWave;
+  int nwp = 1;
+  while (nwp < nwave) nwp <<= 1;
+  for (int c = 0; c < g.NPT; ++c) {
+    const uint32_t* plane = s.sp + size_t(c >> 5) * g.V;
+    const int b = c & 31;
+    double a[CH];
+#pragma unroll
+    for (int j = 0; j < CH; ++j) {
+      a[j] = 0.0;
+      if (own.owns) {
+        const uint32_t si = plane[self[j]] >> b;
+        const double tx = Prec<double>::neg_if(jf[j][0], (si ^ (plane[fn[j][0]] >> b)) & 1u);
+        const double ty = Prec<double>::neg_if(jf[j][1], (si ^ (plane[fn[j][1]] >> b)) & 1u);
+        const double tz = Prec<double>::neg_if(jf[j][2], (si ^ (plane[fn[j][2]] >> b)) & 1u);
+        a[j] = (tx + ty) + tz;
+      }
+    }
+#pragma unroll
+    for (int w = CH; w > 1; w >>= 1) {
+#pragma unroll
+      for (int j = 0; j < w / 2; ++j) a[j] = a[2 * j] + a[2 * j + 1];
+    }
+    double v = a[0];
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) v = v + __shfl_xor(v, off, kWave);
+    if (lane_id() == 0) red[wave_id() * g.NPT + c] = v;
+  }
+  __syncthreads();
+  for (int c = threadIdx.x; c < g.NPT; c += blockDim.x) {
+    for (int q = nwave; q < nwp; ++q) red[q * g.NPT + c] = 0.0;
+    for (int width = nwp; width > 1; width >>= 1)
+      for (int q = 0; q < width / 2; ++q)
+        red[q * g.NPT + c] = red[(2 * q) * g.NPT + c] + red[(2 * q + 1) * g.NPT + c];
+    s.E[c] = -red[c];
+  }
+  __syncthreads();
+}
+
+// ------------------------------------------------------------------ PT + ER
+template <typename FP, int CH>
+__device__ __forceinline__ void pt_phase(const Geo& g, const State& st, int sample, uint32_t t, int do_reservoir,
+                                      const FP* beta_fp) {
+  const Lds s = lds_view(g, sizeof(FP));
+  energy_phase<FP, CH>(g, static_cast<const FP*>(st.J) + size_t(sample) * 3 * g.V);
+  const Own<CH> own(g.V);
+  const int NT = g.NT;
+  if (static_cast<int>(threadIdx.x) < g.NR) {
+    const int r = threadIdx.x;
+    int32_t* at = s.cat + r * NT;
+    const size_t base = (size_t(sample) * g.NR + r) * (NT - 1);
+    for (int k = 0; k < NT - 1; ++k) {
+      const double x = (st.beta64[k] - st.beta64[k + 1]) * (s.E[at[k]] - s.E[at[k + 1]]);
+      const Block blk = philox10(ctr_word(k, 0, kPt), t, r, sample, g.key0, g.key1);
+      const bool acc = (x >= 0.0) || (uniform53(blk.w0, blk.w1) < exp_neg64(x));
+      st.pt_last[base + k] = static_cast<uint8_t>(acc);
+      st.pt_count[base + k] += static_cast<uint32_t>(acc);
+      if (acc) {
+        const int32_t tmp = at[k];
+        at[k] = at[k + 1];
+        at[k + 1] = tmp;
+      }
+    }
+    // round trips: left T_max -> touched T_min -> back at T_max
+    if (s.rt[at[0]] == 1) s.rt[at[0]] = 2;
+    if (s.rt[at[NT - 1]] == 2)  // groups finish concurrently: count atomically
+      atomicAdd(reinterpret_cast<unsigned long long*>(&st.rt_count[sample]), 1ull);
+    s.rt[at[NT - 1]] = 1;
+  }
+  for (int c = threadIdx.x; c < g.NPT; c += blockDim.x) st.pt_energy[size_t(sample) * g.NPT + c] = s.E[c];
+  __syncthreads();
+  if (do_reservoir && g.NERG > 0) {
+    // the configuration at T_max and the oldest reservoir configuration trade places
+    for (int r = 0; r < g.NR; ++r) {
+      const int a = s.cat[r * NT + NT - 1];
+      const int b = g.NPT + r * g.NERG + s.head[r];
+      if (own.owns) {
+        const int wa = word_of(g, a), wb = word_of(g, b), ba = bit_of(g, a), bb = bit_of(g, b);
+#pragma unroll
+        for (int j = 0; j < CH; ++j) {
+          const int i = own.first + j;
+          const int jj = plane_idx(i, colour_of(site_of(i, g.L)), g.Vh);
+          const uint32_t va = (s.sp[size_t(wa) * g.V + jj] >> ba) & 1u;
+          const uint32_t vb = (s.sp[size_t(wb) * g.V + jj] >> bb) & 1u;
+          if (va != vb) {
+            s.sp[size_t(wa) * g.V + jj] ^= 1u << ba;
+            s.sp[size_t(wb) * g.V + jj] ^= 1u << bb;
+          }
+        }
+      }
+    }
+    __syncthreads();
+    if (static_cast<int>(threadIdx.x) < g.NR) s.head[threadIdx.x] = (s.head[threadIdx.x] + 1) % g.NERG;
+  }
+  __syncthreads();
+  rebuild_beta<FP>(g, s, beta_fp);
+  __syncthreads();
+}
+
+// ------------------------------------------------------------------ observables
+template <typename FP, int CH>
+__device__ __forceinline__ void measure_phase(const Geo& g, const State& st, const Obs& ob, int sample) {
+  const Lds s = lds_view(g, sizeof(FP));
+  energy_phase<FP, CH>(g, static_cast<const FP*>(st.J) + size_t(sample) * 3 * g.V);
+  const Own<CH> own(g.V);
+  const int NT = g.NT, NR = g.NR, npairs = NR * (NR - 1) / 2;
+  for (int x = threadIdx.x; x < 2 * NT * npairs; x += blockDim.x) s.qacc[x] = 0;
+  __syncthreads();
+  for (int k = 0; k < NT; ++k) {
+    int pair = 0;
+    for (int a = 0; a < NR; ++a)
+      for (int b = a + 1; b < NR; ++b, ++pair) {
+        const int ca = s.cat[a * NT + k], cb = s.cat[b * NT + k];
+        int Q = 0, QL = 0;
+        if (own.owns) {
+#pragma unroll
+          for (int j = 0; j < CH; ++j) {
+            const Site sti = site_of(own.first + j, g.L);
+            const int col = colour_of(sti);
+            const int ji = plane_idx(sti.i, col, g.Vh);
+            const uint32_t qi = spin_bit(g, s, ca, ji) ^ spin_bit(g, s, cb, ji);
+            Q += qi ? -1 : 1;
+#pragma unroll
+            for (int d = 0; d < 6; d += 2) {
+              const int jn = plane_idx(neighbour(sti, d, g.L), col ^ 1, g.Vh);
+              const uint32_t qn = spin_bit(g, s, ca, jn) ^ spin_bit(g, s, cb, jn);
+              QL += (qi ^ qn) ? -1 : 1;
+            }
+          }
+        }
+        Q = wave_sum_int(Q);
+        QL = wave_sum_int(QL);
+        if (lane_id() == 0 && (Q != 0 || QL != 0)) {
+          atomicAdd(&s.qacc[2 * (k * npairs + pair)], Q);
+          atomicAdd(&s.qacc[2 * (k * npairs + pair) + 1], QL);
+        }
+      }
+  }
+  __syncthreads();
+  const double V = static_cast<double>(g.V);
+  for (int k = threadIdx.x; k < NT; k += blockDim.x) {
+    double esum = 0.0, e2sum = 0.0, q2sum = 0.0, q4sum = 0.0, qlsum = 0.0, ssum = 0.0;
+    for (int r = 0; r < NR; ++r) {
+      const double er = s.E[s.cat[r * NT + k]] / V;
+      esum += er;
+      e2sum += er * er;
+    }
+    int pair = 0;
+    for (int a = 0; a < NR; ++a)
+      for (int b = a + 1; b < NR; ++b, ++pair) {
+        const int Q = s.qacc[2 * (k * npairs + pair)];
+        const int QL = s.qacc[2 * (k * npairs + pair) + 1];
+        const double q = static_cast<double>(Q) / V;
+        const double ql = static_cast<double>(QL) / (3.0 * V);
+        const double q2 = q * q;
+        q2sum += q2;
+        q4sum += q2 * q2;
+        qlsum += ql;
+        const double ea = s.E[s.cat[a * NT + k]] / V, eb = s.E[s.cat[b * NT + k]] / V;
+        ssum += (ea + eb) / 6.0 + (1.0 - ql) * st.beta64[k];
+        atomicAdd(reinterpret_cast<unsigned long long*>(&ob.hist[size_t(k) * (g.V + 1) + (Q + g.V) / 2]), 1ull);
+      }
+    double* o = ob.acc + (size_t(sample) * NT + k) * 6;
+    o[0] += esum;
+    o[1] += e2sum;
+    o[2] += q2sum;
+    o[3] += q4sum;
+    o[4] += qlsum;
+    o[5] += ssum;
+  }
+  if (threadIdx.x == 0 && sample == 0) atomicAdd(reinterpret_cast<unsigned long long*>(ob.n_meas), 1ull);
+  __syncthreads();
+}
+
+// ------------------------------------------------------------------ kernels
+// Every phase is its own kernel with its own register budget; each loads the
+// parts of the sample it needs from HBM into LDS and writes back what it
+// changed.  One workgroup per sample; run.sample_begin offsets the grid.
+
+// Load every spin word and the permutation into LDS.
+__device__ __forceinline__ void load_spins(const Geo& g, const Lds& s, const State& st, int sample) {
+  const size_t words = size_t(g.NW) * g.V;
+  const uint4* src = reinterpret_cast<const uint4*>(st.spins + size_t(sample) * words);
+  uint4* dst = reinterpret_cast<uint4*>(s.sp);
+  if (words % 4 == 0) {
+    for (size_t x = threadIdx.x; x < words / 4; x += blockDim.x) dst[x] = src[x];
+  } else {
+    const uint32_t* gsp = st.spins + size_t(sample) * words;
+    for (size_t x = threadIdx.x; x < words; x += blockDim.x) s.sp[x] = gsp[x];
+  }
+  for (int x = threadIdx.x; x < g.NR * g.NT; x += blockDim.x) s.cat[x] = st.clone_at[size_t(sample) * g.NR * g.NT + x];
+}
+__device__ __forceinline__ void store_spins(const Geo& g, const Lds& s, const State& st, int sample) {
+  const size_t words = size_t(g.NW) * g.V;
+  if (words % 4 == 0) {
+    uint4* dst = reinterpret_cast<uint4*>(st.spins + size_t(sample) * words);
+    const uint4* src = reinterpret_cast<const uint4*>(s.sp);
+    for (size_t x = threadIdx.x; x < words / 4; x += blockDim.x) dst[x] = src[x];
+  } else {
+    uint32_t* osp = st.spins + size_t(sample) * words;
+    for (size_t x = threadIdx.x; x < words; x += blockDim.x) osp[x] = s.sp[x];
+  }
+}
+
+template <typename FP, int CH, bool kEarly>
+__global__ __launch_bounds__(kMaxThreads) void sweep_kernel(Geo g, State st, Run run) {
+  const int sample = run.sample_begin + blockIdx.x;
+  if (sample >= g.S) return;  // the whole workgroup leaves together
+  const Lds s = lds_view(g, sizeof(FP));
+  load_spins(g, s, st, sample);
+  __syncthreads();
+  const FP* beta_fp;
+  if constexpr (sizeof(FP) == 8) beta_fp = reinterpret_cast<const FP*>(st.beta64);
+  else beta_fp = reinterpret_cast<const FP*>(st.beta32);
+  rebuild_beta<FP>(g, s, beta_fp);
+  __syncthreads();
+  const FP* Js = static_cast<const FP*>(st.J) + size_t(sample) * 3 * g.V;
+  sweep_phase<FP, CH, kEarly>(g, s, Js, sample, run.t0, run.m_pt0, run.n_pt, run.m_er0, run.n_er);
+  store_spins(g, s, st, sample);
+}
+
+template <int CH>
+__global__ __launch_bounds__(kMaxThreads) void houdayer_kernel(Geo g, State st, Run run) {
+  const int sample = run.sample_begin + blockIdx.x;
+  if (sample >= g.S) return;
+  const Lds s = lds_view(g, 4);
+  load_spins(g, s, st, sample);
+  __syncthreads();
+  const bool bad = (run.phases & kPhaseLabels) ? labels_out_phase<CH>(g, sample, run.labels)
+                                                : houdayer_phase<CH>(g, sample, run.t0);
+  if (!(run.phases & kPhaseLabels)) store_spins(g, s, st, sample);
+  if (bad && threadIdx.x == 0) atomicOr(&st.status[sample], kStatusUnionBound);
+}
+
+template <typename FP, int CH>
+__global__ __launch_bounds__(kMaxThreads) void pt_kernel(Geo g, State st, Run run) {
+  const int sample = run.sample_begin + blockIdx.x;
+  if (sample >= g.S) return;
+  const Lds s = lds_view(g, sizeof(FP));
+  load_spins(g, s, st, sample);
+  for (int x = threadIdx.x; x < g.NR; x += blockDim.x) s.head[x] = st.er_head[size_t(sample) * g.NR + x];
+  for (int x = threadIdx.x; x < g.NPT; x += blockDim.x) s.rt[x] = st.rt_state[size_t(sample) * g.NPT + x];
+  __syncthreads();
+  const FP* beta_fp;
+  if constexpr (sizeof(FP) == 8) beta_fp = reinterpret_cast<const FP*>(st.beta64);
+  else beta_fp = reinterpret_cast<const FP*>(st.beta32);
+  pt_phase<FP, CH>(g, st, sample, run.t0, run.do_reservoir, beta_fp);
+  if (run.do_reservoir && g.NERG > 0) store_spins(g, s, st, sample);
+  for (int x = threadIdx.x; x < g.NR * g.NT; x += blockDim.x) st.clone_at[size_t(sample) * g.NR * g.NT + x] = s.cat[x];
+  for (int x = threadIdx.x; x < g.NR; x += blockDim.x) st.er_head[size_t(sample) * g.NR + x] = s.head[x];
+  for (int x = threadIdx.x; x < g.NPT; x += blockDim.x) st.rt_state[size_t(sample) * g.NPT + x] = s.rt[x];
+}
+
+template <typename FP, int CH>
+__global__ __launch_bounds__(kMaxThreads) void measure_kernel(Geo g, State st, Obs ob, Run run) {
+  const int sample = run.sample_begin + blockIdx.x;
+  if (sample >= g.S) return;
+  load_spins(g, lds_view(g, sizeof(FP)), st, sample);
+  __syncthreads();
+  measure_phase<FP, CH>(g, st, ob, sample);
+}
+
+// Initial spins: bit = sign bit of word 0 of the INIT block of (site, clone).
+__global__ void init_kernel(Geo g, State st) {
+  const size_t total = size_t(g.S) * g.NW * g.V;
+  for (size_t x = blockIdx.x * size_t(blockDim.x) + threadIdx.x; x < total; x += size_t(gridDim.x) * blockDim.x) {
+    const int j = static_cast<int>(x % g.V);
+    const int w = static_cast<int>((x / g.V) % g.NW);
+    const int sample = static_cast<int>(x / (size_t(g.V) * g.NW));
+    const int colour = j >= g.Vh;
+    const int i0 = 2 * (j - colour * g.Vh);
+    const Site s0 = site_of(i0, g.L);
+    const int i = i0 + ((s0.y + s0.z + colour) & 1);
+    int clone0, nbits;
+    if (w < g.NWPT) {
+      clone0 = 32 * w;
+      nbits = min(32, g.NPT - clone0);
+    } else {
+      clone0 = g.NPT + 32 * (w - g.NWPT);
+      nbits = min(32, g.NPT + g.NER - clone0);
+    }
+    uint32_t word = 0;
+    for (int b = 0; b < nbits; ++b) {
+      const Block blk = philox10(ctr_word(i, 0, kInit), 0u, static_cast<uint32_t>(clone0 + b),
+                                 static_cast<uint32_t>(sample), g.key0, g.key1);
+      word |= (blk.w0 >> 31) << b;
+    }
+    st.spins[x] = word;
+  }
+}
+
+__global__ void zero_kernel(uint32_t* p, size_t n) {
+  for (size_t x = blockIdx.x * size_t(blockDim.x) + threadIdx.x; x < n; x += size_t(gridDim.x) * blockDim.x) p[x] = 0u;
+}
+
+template <typename K>
+hipError_t set_lds(K kern, size_t lds) {
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
+                             static_cast<int>(lds));
+}
+
+template <typename FP, int CH, bool kEarly>
+hipError_t launch_t(const Geo& g, const State& st, const Obs& ob, const Run& run, int threads, int n_blocks,
+                    hipStream_t stream) {
+  const size_t lds = plan_lds(g, sizeof(FP)).total;
+  hipError_t e = hipSuccess;
+  if (run.phases & kPhaseSweep) {
+    auto k = sweep_kernel<FP, CH, kEarly>;
+    if ((e = set_lds(k, lds)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k, dim3(n_blocks), dim3(threads), lds, stream, g, st, run);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  if (run.phases & (kPhaseHoudayer | kPhaseLabels)) {
+    auto k = houdayer_kernel<CH>;
+    const size_t l4 = plan_lds(g, 4).total;
+    if ((e = set_lds(k, l4)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k, dim3(n_blocks), dim3(threads), l4, stream, g, st, run);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  if (run.phases & kPhasePT) {
+    auto k = pt_kernel<FP, CH>;
+    if ((e = set_lds(k, lds)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k, dim3(n_blocks), dim3(threads), lds, stream, g, st, run);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  if (run.phases & kPhaseMeasure) {
+    auto k = measure_kernel<FP, CH>;
+    if ((e = set_lds(k, lds)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k, dim3(n_blocks), dim3(threads), lds, stream, g, st, ob, run);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  return e;
+}
+
+}  // namespace
+
+size_t lds_bytes(const Geo& g, int fp_bytes) { return plan_lds(g, fp_bytes).total; }
+
+hipError_t launch_emcs(int precision, const Geo& g, const State& st, const Obs& ob, const Run& run,
+                       const Shape& sh, int n_blocks, hipStream_t stream) {
+#define PTHR_LAUNCH(FP, CH)                                                                         \
+  return sh.early_out ? launch_t<FP, CH, true>(g, st, ob, run, sh.threads, n_blocks, stream)        \
+                      : launch_t<FP, CH, false>(g, st, ob, run, sh.threads, n_blocks, stream)
+  if (precision == 0) {
+    switch (sh.chunk) {
+      case 2: PTHR_LAUNCH(double, 2);
+      case 4: PTHR_LAUNCH(double, 4);
+    }
+  } else {
+    switch (sh.chunk) {
+      case 2: PTHR_LAUNCH(float, 2);
+      case 4: PTHR_LAUNCH(float, 4);
+      case 8: PTHR_LAUNCH(float, 8);
+    }
+  }
+#undef PTHR_LAUNCH
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_init(const Geo& g, const State& st, hipStream_t stream) {
+  const size_t total = size_t(g.S) * g.NW * g.V;
+  const int threads = 256;
+  const int blocks = static_cast<int>((total + threads - 1) / threads < 65536 ? (total + threads - 1) / threads : 65536);
+  hipLaunchKernelGGL(init_kernel, dim3(blocks), dim3(threads), 0, stream, g, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t stream) {
+  const size_t n = bytes / 4;
+  if (n == 0) return hipSuccess;
+  const int threads = 256;
+  const int blocks = static_cast<int>((n + threads - 1) / threads < 4096 ? (n + threads - 1) / threads : 4096);
+  hipLaunchKernelGGL(zero_kernel, dim3(blocks), dim3(threads), 0, stream, static_cast<uint32_t*>(p), n);
+  return hipGetLastError();
+}
+
+}  // namespace pthr

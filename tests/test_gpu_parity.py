@@ -1,0 +1,277 @@
+"""Parity of the HIP library (through its C ABI) with the CPU oracle on the same
+seeded inputs.  FP64 and FP32 forms are both compared bit for bit: spins,
+permutations, reservoir FIFOs, swap decisions and counts, energies, round
+trips, cluster labels and accumulated observables.  Small cases cover several
+workgroup tiles and ragged shapes; the full workloads are checked on sampled
+samples that the oracle recomputes one by one."""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2605_25872_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def step(msg: str) -> None:
+    print(f"[gpu-parity] {msg}", file=sys.stderr, flush=True)
+
+
+def _pthr():
+    from paper_2605_25872_amd import pthr
+    return pthr
+
+
+def make_pair(L, S, NR, NT, NER, precision="fp64", mode="acu", t_acu=1.0, sweeps=10, er_sweeps=240,
+              seed=1, jseed=1, T=None, t_range=(0.3, 1.6)):
+    pthr = _pthr()
+    J = inputs.couplings(L, S, seed=jseed)
+    T = inputs.temperatures(*t_range, NT) if T is None else np.asarray(T, dtype=np.float64)
+    prec_o = oracle.FP64 if precision == "fp64" else oracle.FP32
+    mode_o = oracle.ACU if mode == "acu" else oracle.SINGLE_NEG
+    o = oracle.Oracle(L, S, NR, NT, NER, sweeps, er_sweeps, prec_o, mode_o, t_acu, seed)
+    g = pthr.Pthr(L, S, NR, NT, NER, sweeps, er_sweeps, precision, mode, t_acu, seed)
+    o.init(J, T)
+    g.init_samples(J, T)
+    return o, g
+
+
+def assert_same_state(o, g, what=""):
+    spins = g.read_spins()
+    if not np.array_equal(spins, o.spins):
+        bad = np.argwhere(spins != o.spins)
+        raise AssertionError(f"{what}: spins differ at {len(bad)} places, first (sample, clone, site) {bad[:5].tolist()}")
+    pt = g.read_pt()
+    assert np.array_equal(pt["clone_at"], o.clone_at), what
+    assert np.array_equal(pt["er_head"], o.er_head), what
+    assert np.array_equal(pt["pt_last"], o.pt_last), what
+    assert np.array_equal(pt["pt_count"], o.pt_count), what
+    assert np.array_equal(pt["pt_energy"].view(np.uint64), o.pt_energy.view(np.uint64)), what
+    assert np.array_equal(pt["rt_state"], o.rt_state), what
+    assert np.array_equal(pt["rt_count"], o.rt_count), what
+    t, mp, me = g.counters()
+    assert (t, mp, me) == (o.t, o.m(oracle.SWEEP_PT), o.m(oracle.SWEEP_ER)), what
+
+
+def assert_same_obs(o_obs, g, g_obs):
+    arr = g.obs_arrays(g_obs)
+    assert arr["n_meas"] == int(o_obs.n_meas[0])
+    assert np.array_equal(arr["hist"], o_obs.hist)
+    assert np.array_equal(arr["acc"].view(np.uint64), o_obs.acc.view(np.uint64))
+
+
+def stepwise(o, g, n_emcs, with_obs=True, check_each=True):
+    oo = o.new_observables() if with_obs else None
+    go = g.new_obs() if with_obs else None
+    for e in range(n_emcs):
+        o.sweep(o.params.sweeps_per_emcs, oracle.SWEEP_PT)
+        g.sweep(o.params.sweeps_per_emcs, 0)
+        if check_each:
+            assert_same_state(o, g, f"EMCS {e} after PT sweeps")
+        if o.NER:
+            # the ER sweeps in two launches, continuing the sweep counter
+            half = o.params.er_sweeps_per_emcs // 2
+            o.sweep(o.params.er_sweeps_per_emcs, oracle.SWEEP_ER)
+            g.sweep(0, half)
+            g.sweep(0, o.params.er_sweeps_per_emcs - half)
+            if check_each:
+                assert_same_state(o, g, f"EMCS {e} after ER sweeps")
+        o.houdayer()
+        g.houdayer()
+        if check_each:
+            assert_same_state(o, g, f"EMCS {e} after Houdayer")
+        o.pt_swap(True)
+        g.pt_swap(True)
+        assert_same_state(o, g, f"EMCS {e} after PT/ER step")
+        if with_obs:
+            o.measure(oo)
+            g.measure(go)
+    g.check()
+    if with_obs:
+        assert_same_obs(oo, g, go)
+
+
+# ----------------------------------------------------------------------------- small cases
+def test_l4_single_sample_workload_fp64():
+    """L=4, one sample, 2 replicas x 8 temperatures on [0.5, 1.6], no
+    reservoir: Metropolis + PT + Houdayer, FP64."""
+    step("l4 single sample fp64")
+    o, g = make_pair(4, 1, 2, 8, 0, t_range=(0.5, 1.6))
+    stepwise(o, g, 6)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_l4_with_reservoir_every_substep(precision):
+    step(f"l4 reservoir {precision}")
+    o, g = make_pair(4, 3, 4, 6, 4, precision=precision, er_sweeps=24, t_range=(0.3, 1.6))
+    stepwise(o, g, 5)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_l8_several_tiles(precision):
+    """L=8 (512 sites, 4 waves per sample), 4 replicas x 20 temperatures, 4
+    reservoir clones: the shape of the L=8 FP64 workload on a few samples."""
+    step(f"l8 {precision}")
+    o, g = make_pair(8, 4, 4, 20, 4, precision=precision, er_sweeps=40)
+    stepwise(o, g, 2)
+
+
+def test_l6_ragged_words_and_single_cluster():
+    """Clone counts that leave partial 32-clone words (2*7=14 PT clones, 6 ER
+    clones) and Houdayer's single-cluster mode."""
+    step("l6 ragged single")
+    o, g = make_pair(6, 3, 2, 7, 3, mode="single", er_sweeps=12, t_range=(0.2, 1.4))
+    stepwise(o, g, 4)
+
+
+def test_l2_smallest_lattice_and_two_temperatures():
+    step("l2")
+    o, g = make_pair(2, 5, 2, 2, 1, sweeps=3, er_sweeps=5, t_acu=5.0, t_range=(0.4, 1.0))
+    stepwise(o, g, 6)
+
+
+def test_no_houdayer_no_reservoir():
+    step("plain PT")
+    o, g = make_pair(4, 2, 2, 5, 0, t_acu=0.0)
+    stepwise(o, g, 4)
+
+
+def test_many_replicas_cross_word_pairs():
+    """8 replica groups x 9 temperatures: Houdayer pairs and measured pairs
+    whose clones sit in different 32-clone words."""
+    step("many replicas")
+    o, g = make_pair(4, 2, 8, 9, 2, er_sweeps=8, t_range=(0.3, 1.5))
+    stepwise(o, g, 3)
+
+
+# ----------------------------------------------------------------------------- labels, run, schedules
+def test_cluster_labels_match_oracle():
+    step("labels")
+    o, g = make_pair(6, 3, 4, 5, 0, t_range=(0.3, 0.9))
+    o.run(2)
+    g.run(2)
+    lab = g.labels()
+    for s in range(3):
+        for p in range(2):
+            for k in range(g.K_acu):
+                assert np.array_equal(lab[s, p, k], o.labels(s, p, k))
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_fused_run_equals_stepwise_and_oracle(precision):
+    step(f"run vs stepwise {precision}")
+    o, g = make_pair(8, 3, 4, 10, 4, precision=precision, er_sweeps=30)
+    oo, go = o.new_observables(), g.new_obs()
+    o.run(3, oo)
+    g.run(3, go)
+    assert_same_state(o, g, "after pthr_run")
+    assert_same_obs(oo, g, go)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_every_schedule_gives_the_same_bits(precision):
+    step(f"schedules {precision}")
+    pthr = _pthr()
+    ref = None
+    for threads, early, per in ((256, 1, 0), (128, 1, 0), (256, 0, 1), (128, 0, 2)):
+        _, g = make_pair(8, 3, 4, 10, 4, precision=precision, er_sweeps=20)
+        g.set_schedule(threads_per_sample=threads, exp_early_out=early, samples_per_launch=per)
+        go = g.new_obs()
+        g.run(2, go)
+        got = (g.read_spins(), g.read_pt(), g.obs_arrays(go))
+        if ref is None:
+            ref = got
+            continue
+        assert np.array_equal(got[0], ref[0])
+        for k in ref[1]:
+            assert np.array_equal(got[1][k], ref[1][k]), k
+        assert np.array_equal(got[2]["acc"], ref[2]["acc"])
+        assert np.array_equal(got[2]["hist"], ref[2]["hist"])
+    del pthr
+
+
+def test_checkpoint_resume_is_bit_identical():
+    step("checkpoint")
+    pthr = _pthr()
+    _, a = make_pair(4, 2, 2, 6, 2, er_sweeps=10)
+    a.run(2)
+    blob = a.get_state()
+    a.run(3)
+    _, b = make_pair(4, 2, 2, 6, 2, er_sweeps=10)
+    b.set_state(blob)
+    b.run(3)
+    assert np.array_equal(a.read_spins(), b.read_spins())
+    assert a.counters() == b.counters()
+    with pytest.raises(pthr.PthrError):
+        _, c = make_pair(4, 2, 2, 7, 2, er_sweeps=10)
+        c.set_state(blob)
+
+
+def test_autotune_keeps_the_state_and_picks_a_valid_schedule():
+    step("autotune")
+    o, g = make_pair(8, 4, 4, 10, 4, er_sweeps=20)
+    ms = g.autotune(1)
+    assert ms > 0
+    stepwise(o, g, 1, with_obs=False, check_each=False)
+
+
+def test_errors_are_reported_not_raised_on_device():
+    pthr = _pthr()
+    _, g = make_pair(4, 1, 2, 4, 0)
+    with pytest.raises(pthr.PthrError):
+        g.sweep(300)
+    g.sweep(200)
+    with pytest.raises(pthr.PthrError):
+        g.sweep(100)  # counter field full
+    with pytest.raises(pthr.PthrError):
+        g.run(1)  # EMCS in progress
+    with pytest.raises(pthr.PthrError):
+        g.init_samples(inputs.couplings(4, 1), np.array([1.0, 0.5, 2.0, 3.0]))
+
+
+# ----------------------------------------------------------------------------- full workloads, sampled
+def sampled_check(name, samples, n_emcs, mode="acu"):
+    """Run the whole workload on the GPU; recompute the chosen samples with the
+    oracle (same global sample ids) and compare them bit for bit."""
+    pthr = _pthr()
+    w = inputs.WORKLOADS[name]
+    T = w.temperatures()
+    step(f"full {name}: {w.n_samples} samples, {n_emcs} EMCS on the GPU")
+    g = pthr.Pthr(w.L, w.n_samples, w.n_replicas, w.n_temps, w.n_reservoir, w.sweeps_per_emcs,
+                  w.er_sweeps_per_emcs, w.precision, mode, w.t_acu, w.seed)
+    g.init_samples(w.couplings(), T)
+    go = g.new_obs()
+    g.run(n_emcs, go)
+    g.check()
+    spins = g.read_spins()
+    pt = g.read_pt()
+    acc = g.obs_arrays(go)["acc"]
+    prec = oracle.FP64 if w.precision == "fp64" else oracle.FP32
+    for s in samples:
+        step(f"  oracle sample {s}")
+        o1 = oracle.Oracle(w.L, 1, w.n_replicas, w.n_temps, w.n_reservoir, w.sweeps_per_emcs,
+                           w.er_sweeps_per_emcs, prec, oracle.ACU if mode == "acu" else oracle.SINGLE_NEG,
+                           w.t_acu, w.seed, first_sample=s)
+        o1.init(w.couplings(1, first_sample=s), T)
+        oo = o1.new_observables()
+        o1.run(n_emcs, oo)
+        assert np.array_equal(spins[s], o1.spins[0]), f"sample {s}"
+        assert np.array_equal(pt["clone_at"][s], o1.clone_at[0])
+        assert np.array_equal(pt["pt_energy"][s].view(np.uint64), o1.pt_energy[0].view(np.uint64))
+        assert np.array_equal(acc[s].view(np.uint64), oo.acc[0].view(np.uint64))
+
+
+def test_full_l8_fp64_workload_sampled():
+    sampled_check("l8_fp64", [0, 137, 255], 2)
+
+
+def test_full_l16_fp32_workload_sampled():
+    sampled_check("l16_fp32", [0, 1023], 1)
+
+
+def test_full_l16_fp32_single_cluster_sampled():
+    sampled_check("l16_fp32", [511], 1, mode="single")

@@ -1,0 +1,86 @@
+"""Host-side checks of the HIP library that need no GPU: the shared library
+loads, exports every entry point declared in include/pthr.h, and validates
+parameters (no compute calls)."""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2605_25872_amd import pthr
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    text = open(os.path.join(ROOT, "include", "pthr.h")).read()
+    return sorted(set(re.findall(r"\b(pthr_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(pthr.LIB_PATH):
+        from paper_2605_25872_amd import build
+        build.build()
+    return pthr.library()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    declared = _declared()
+    assert len(declared) >= 25
+    assert sorted(pthr.EXPORTED) == declared
+    for name in declared:
+        assert getattr(lib, name) is not None
+
+
+def _create(lib, **kw):
+    args = dict(L=8, n_samples=4, n_replicas=4, n_temps=20, n_reservoir=4)
+    args.update(kw)
+    p = pthr.make_params(**args)
+    ctx = ctypes.c_void_p()
+    rc = lib.pthr_create(ctypes.byref(p), ctypes.byref(ctx))
+    msg = lib.pthr_create_error().decode()
+    if rc == 0:
+        lib.pthr_destroy(ctx)
+    return rc, msg, p
+
+
+def test_validation(lib):
+    assert _create(lib)[0] == pthr.PTHR_OK
+    rc, msg, _ = _create(lib, L=3)
+    assert rc == pthr.PTHR_EUNSUPPORTED and "odd L" in msg
+    assert _create(lib, n_replicas=3)[0] == pthr.PTHR_EINVAL
+    assert _create(lib, n_temps=1)[0] == pthr.PTHR_EINVAL
+    assert _create(lib, n_samples=0)[0] == pthr.PTHR_EINVAL
+    assert _create(lib, L=40)[0] == pthr.PTHR_EINVAL
+    assert _create(lib, sweeps_per_emcs=257)[0] == pthr.PTHR_EINVAL
+    rc, msg, _ = _create(lib, L=16, n_temps=64, precision="fp32")
+    assert rc == pthr.PTHR_EUNSUPPORTED and "LDS" in msg
+    bad = pthr.make_params(8, 4, 4, 20, 4)
+    bad.reserved = 1
+    ctx = ctypes.c_void_p()
+    assert lib.pthr_create(ctypes.byref(bad), ctypes.byref(ctx)) == pthr.PTHR_EINVAL
+    assert lib.pthr_state_bytes(ctypes.byref(bad)) == 0
+
+
+def test_sizes_of_the_headline_workload(lib):
+    p = pthr.make_params(16, 1024, 4, 36, 4, precision="fp32")
+    # 6 spin words of 32 clones per site, float couplings: ~154 MB for 1024 samples
+    assert 150e6 < lib.pthr_state_bytes(ctypes.byref(p)) < 160e6
+    assert lib.pthr_lds_bytes(ctypes.byref(p)) <= 160 * 1024
+    V = 16 ** 3
+    assert lib.pthr_obs_bytes(ctypes.byref(p)) >= 256 + 8 * 1024 * 36 * 6 + 8 * 36 * (V + 1)
+
+
+def test_calls_before_init_fail_cleanly(lib):
+    p = pthr.make_params(4, 1, 2, 8, 0)
+    ctx = ctypes.c_void_p()
+    assert lib.pthr_create(ctypes.byref(p), ctypes.byref(ctx)) == 0
+    try:
+        assert lib.pthr_sweep(ctx, 1, 0, None) == pthr.PTHR_ESTATE
+        assert b"not initialised" in lib.pthr_last_error(ctx)
+        assert lib.pthr_run(ctx, 1, None, None) == pthr.PTHR_ESTATE
+    finally:
+        lib.pthr_destroy(ctx)
