@@ -31,9 +31,13 @@ VALU_PEAK_OPS = 256 * 64 * 2.4e9
 # EMCS needed to equilibrate one L=16 sample (paper, App. A.2 table).
 T_EQ_EMCS = {12: 2 ** 17, 14: 6.4e6, 16: 3.84e7, 18: 3.48e7}
 
-# Algorithmic VALU operations per Metropolis attempt: Philox
-# block shared by 4 (FP32) or 2 (FP64) attempts, local field, exponent, test.
-OPS_PER_ATTEMPT = {"fp32": 69, "fp64": 106}
+# Algorithmic VALU operations every Metropolis attempt must perform (see
+# the design doc): its share of a Philox4x32-10 block (80 32-bit operations, shared
+# by 4 FP32 or 2 FP64 attempts), 6 sign applications (2 each) and 5 additions
+# for the local field, dE, -beta*dE, the dE <= 0 test, the uniform (2), the
+# comparison and the flip bit.  The exponential, needed only when dE > 0 and
+# u falls within a factor 2 of exp(-beta dE), is not counted.
+OPS_PER_ATTEMPT = {"fp32": 80 // 4 + 17 + 3 + 3 + 1, "fp64": 80 // 2 + 17 + 3 + 3 + 1}
 
 
 def log(msg: str) -> None:
@@ -89,7 +93,20 @@ def main() -> int:
     ap.add_argument("--compare-fp64-samples", type=int, default=16,
                     help="samples for the unbatched FP64 one-sample-per-launch comparison (0 = skip)")
     ap.add_argument("--autotune", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only copy a MIB-MiB device buffer 3 times (HBM counter calibration)")
     args = ap.parse_args()
+
+    if args.copy_calibration:
+        import torch
+        n = args.copy_calibration << 20
+        src = torch.empty(n, dtype=torch.uint8, device="cuda:0").fill_(1)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes_per_copy": n, "copies": 3}), flush=True)
+        return 0
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: samples are independent, a multi-GPU run "

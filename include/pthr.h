@@ -15,7 +15,7 @@
  *   (iv)  one ER step: the configuration at T_max and the oldest reservoir
  *         configuration of the group trade places       -> pthr_pt_swap
  *   and observables are accumulated                      -> pthr_measure
- * pthr_run performs whole EMCS in one persistent launch per window.
+ * pthr_run performs whole EMCS (one launch per phase, samples batched).
  *
  * Problem statement (paper Sec. 2, Eq. 1; App. A.2): L^3 simple-cubic lattice
  * with periodic boundaries, couplings J_ij ~ N(0,1) per sample, N_T

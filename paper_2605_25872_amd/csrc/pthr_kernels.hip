@@ -9,8 +9,8 @@
 // their six couplings in registers for the whole launch; one 32-bit LDS load of
 // a neighbour word serves the 32 clones that share that site and those
 // couplings (the paper's multispin idea, App. A.1, carried to 32 clones per
-// word).  A launch runs `n_emcs` elementary Monte Carlo steps (paper Sec. 3)
-// with the state resident in LDS; step-wise API calls run one phase.
+// word).  Each phase of an elementary Monte Carlo step (paper Sec. 3) is its
+// own kernel: it loads the sample into LDS, runs, and writes back.
 //
 // Exactness: every random number is a Philox4x32-10 block keyed by
 // (seed; site | sweep<<16 | purpose<<24, EMCS, slot, sample), and every
