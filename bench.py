@@ -128,7 +128,9 @@ def main() -> int:
     obs = g.new_obs()
     if args.autotune:
         best = g.autotune(1)
-        log(f"autotune: {best:.2f} ms/EMCS with {g.schedule().threads_per_sample} work-items")
+        sch = g.schedule()
+        log(f"autotune: {best:.2f} ms/EMCS with {sch.threads_per_sample} work-items per sample, "
+            f"exp early-out below T = {sch.exp_early_out / 1000:g}")
     stream = torch.cuda.current_stream(dev)
     n_er = w.er_sweeps_per_emcs if w.n_reservoir else 0
 
@@ -181,7 +183,8 @@ def main() -> int:
                    "temperatures": w.n_temps, "t_range": [w.t_min, w.t_max],
                    "reservoir_clones": w.n_reservoir, "sweeps_per_emcs": w.sweeps_per_emcs,
                    "reservoir_sweeps_per_emcs": w.er_sweeps_per_emcs, "houdayer": args.mode,
-                   "threads_per_sample": g.schedule().threads_per_sample},
+                   "threads_per_sample": g.schedule().threads_per_sample,
+                   "exp_early_out_below_T": g.schedule().exp_early_out / 1000},
         "houdayer_moves_per_s": moves * args.steps / elapsed,
         "attempts_per_emcs": att,
         "wall_time_per_equilibrated_sample_s":

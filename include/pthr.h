@@ -73,7 +73,7 @@ enum { PTHR_NOBS = 6 }; /* per (sample, T): sum e, sum e^2, sum q^2, sum q^4, su
 typedef struct pthr_params {
   int32_t L;                  /* even, 2..32                                   */
   int32_t n_samples;          /* >= 1                                          */
-  int32_t n_replicas;         /* N_r: even, 2..64 (pairs (0,1), (2,3), ...)    */
+  int32_t n_replicas;         /* N_r: even, 2..32 (pairs (0,1), (2,3), ...)    */
   int32_t n_temps;            /* N_T: 2..1024                                  */
   int32_t n_reservoir;        /* ER clones per replica group (paper: 4); 0 = no ER */
   int32_t sweeps_per_emcs;    /* PT sweeps per EMCS (paper: 10), 0..256        */
@@ -166,11 +166,12 @@ int pthr_get_state(pthr_ctx *ctx, void *blob, size_t bytes, void *stream);
 int pthr_set_state(pthr_ctx *ctx, const void *blob, size_t bytes, void *stream);
 
 /* Launch schedule.  threads_per_sample: work-items per sample workgroup (each
- * owns V/threads sites; power-of-two site chunks of 2..32); samples_per_launch:
+ * owns V/threads consecutive sites: 2, 4 or 8 of them); samples_per_launch:
  * 0 = all samples in one launch, 1 = one sample per launch (the unbatched
- * form); exp_early_out: decide most Metropolis tests from the binade of
- * exp(x) before evaluating the polynomial.  Every schedule produces identical
- * bits. */
+ * form); exp_early_out: clones with 1000/T above this value (i.e. colder than
+ * T = exp_early_out/1000) decide a Metropolis test from the binade of exp(x)
+ * before evaluating the polynomial; 0 = never.  Every schedule produces
+ * identical bits. */
 typedef struct pthr_schedule {
   int32_t threads_per_sample;
   int32_t samples_per_launch;

@@ -26,8 +26,8 @@ size_t align256(size_t v) { return (v + 255) / 256 * 256; }
 
 // Byte offsets of every region of the caller's state buffer.
 struct Layout {
-  size_t beta64, beta32, spins, J, clone_at, er_head, pt_last, pt_count, pt_energy, rt_state, rt_count,
-      status, total;
+  size_t beta64, beta32, spins, J, beta_clone, clone_at, er_head, pt_last, pt_count, pt_energy, rt_state,
+      rt_count, status, total;
 };
 
 struct Derived {
@@ -55,6 +55,7 @@ Layout layout_of(const pthr_params& p) {
   l.beta32 = o;    o = align256(o + 4 * NT);
   l.spins = o;     o = align256(o + 4 * S * d.NW * d.V);
   l.J = o;         o = align256(o + fp * S * 3 * d.V);
+  l.beta_clone = o; o = align256(o + fp * S * d.C);
   l.clone_at = o;  o = align256(o + 4 * S * NR * NT);
   l.er_head = o;   o = align256(o + 4 * S * NR);
   l.pt_last = o;   o = align256(o + S * NR * (NT - 1));
@@ -109,7 +110,7 @@ const char* validate(const pthr_params& p) {
   if (p.L < 2 || p.L > 32) return "L must be in [2, 32]";
   if (p.L % 2) return "odd L is not supported on the GPU (the checkerboard is not a bipartition)";
   if (p.n_samples < 1 || p.n_samples > (1 << 24)) return "n_samples must be in [1, 2^24]";
-  if (p.n_replicas < 2 || p.n_replicas > 64 || p.n_replicas % 2) return "n_replicas must be even, in [2, 64]";
+  if (p.n_replicas < 2 || p.n_replicas > 32 || p.n_replicas % 2) return "n_replicas must be even, in [2, 32]";
   if (p.n_temps < 2 || p.n_temps > 1024) return "n_temps must be in [2, 1024]";
   if (p.n_reservoir < 0 || p.n_reservoir > 64) return "n_reservoir must be in [0, 64]";
   if (p.sweeps_per_emcs < 0 || p.sweeps_per_emcs > 256) return "sweeps_per_emcs must be in [0, 256]";
@@ -164,6 +165,7 @@ struct pthr_ctx {
     st.status = reinterpret_cast<uint32_t*>(b + lay.status);
     st.beta64 = reinterpret_cast<const double*>(b + lay.beta64);
     st.beta32 = reinterpret_cast<const float*>(b + lay.beta32);
+    st.beta_clone = b + lay.beta_clone;
     return st;
   }
   pthr::Obs obs(void* d_obs) const {
@@ -181,7 +183,6 @@ struct pthr_ctx {
     sh.threads = sch.threads_per_sample;
     sh.chunk = 2;  // smallest chunk giving this many work-items (checked by set_schedule)
     while (threads_for(d.V, sh.chunk) != sch.threads_per_sample && sh.chunk < 8) sh.chunk *= 2;
-    sh.early_out = sch.exp_early_out != 0;
     return sh;
   }
   // Launches `run` over all samples, split by samples_per_launch.
@@ -189,6 +190,8 @@ struct pthr_ctx {
     const pthr::State st = state();
     const pthr::Obs ob = obs(d_obs);
     const int per = sch.samples_per_launch > 0 ? sch.samples_per_launch : p.n_samples;
+    // exp early-out for clones colder than exp_early_out/1000 (0 = never)
+    run.early_beta = sch.exp_early_out > 0 ? static_cast<float>(1000.0 / sch.exp_early_out) : 3.0e38f;
     for (int s0 = 0; s0 < p.n_samples; s0 += per) {
       run.sample_begin = s0;
       const int nb = std::min(per, p.n_samples - s0);
@@ -262,7 +265,7 @@ int pthr_create(const pthr_params* p, pthr_ctx** out) {
   const int ch = default_chunk(p->precision, d.V);
   c->sch.threads_per_sample = threads_for(d.V, ch);
   c->sch.samples_per_launch = 0;
-  c->sch.exp_early_out = 1;
+  c->sch.exp_early_out = 700;  // early-out below T = 0.7
   *out = c;
   g_create_error.clear();
   return PTHR_OK;
@@ -319,6 +322,19 @@ int pthr_init_samples(pthr_ctx* ctx, const double* J_host, const double* T_host,
     }
   }
   const size_t S = p.n_samples, NR = p.n_replicas;
+  // every clone starts at its own temperature; reservoir clones are at T_max
+  std::vector<double> bc64(S * ctx->d.C);
+  std::vector<float> bc32(S * ctx->d.C);
+  for (size_t smp = 0; smp < S; ++smp)
+    for (int c = 0; c < ctx->d.C; ++c) {
+      const int k = c < ctx->d.NPT ? c % NT : NT - 1;
+      bc64[smp * ctx->d.C + c] = b64[k];
+      bc32[smp * ctx->d.C + c] = b32[k];
+    }
+  if (e == hipSuccess)
+    e = p.precision == PTHR_FP64
+            ? hipMemcpyAsync(ctx->d_state + l.beta_clone, bc64.data(), 8 * bc64.size(), hipMemcpyHostToDevice, s)
+            : hipMemcpyAsync(ctx->d_state + l.beta_clone, bc32.data(), 4 * bc32.size(), hipMemcpyHostToDevice, s);
   std::vector<int32_t> cat(S * NR * NT);
   for (size_t x = 0; x < cat.size(); ++x) cat[x] = static_cast<int32_t>(x % (NR * NT));
   if (e == hipSuccess) e = hipMemcpyAsync(ctx->d_state + l.clone_at, cat.data(), 4 * cat.size(), hipMemcpyHostToDevice, s);
@@ -583,8 +599,8 @@ int pthr_set_schedule(pthr_ctx* ctx, const pthr_schedule* sch) {
     return ctx->fail(PTHR_EINVAL,
                      "threads_per_sample must be ceil(V/chunk / 64)*64 for chunk in {2,4,8} (FP64: {2,4}) and <= 1024");
   if (sch->samples_per_launch < 0 || sch->reserved != 0) return ctx->fail(PTHR_EINVAL, "bad samples_per_launch");
+  if (sch->exp_early_out < 0) return ctx->fail(PTHR_EINVAL, "exp_early_out must be >= 0");
   ctx->sch = *sch;
-  ctx->sch.exp_early_out = sch->exp_early_out ? 1 : 0;
   return PTHR_OK;
 }
 
@@ -607,7 +623,8 @@ int pthr_autotune(pthr_ctx* ctx, void* d_scratch, int n_emcs, double* best_ms, v
   for (int ch = 2; ch <= 8 && rc == PTHR_OK; ch *= 2) {
     if (!chunk_ok(ctx->p.precision, ctx->d.V, ch)) continue;
     if (ch > 2 && threads_for(ctx->d.V, ch) == threads_for(ctx->d.V, ch / 2)) continue;
-    for (int early = 0; early <= 1 && rc == PTHR_OK; ++early) {
+    for (int early : {0, 500, 700, 1000, 100000}) {
+      if (rc != PTHR_OK) break;
       pthr_schedule cand = saved;
       cand.threads_per_sample = threads_for(ctx->d.V, ch);
       cand.exp_early_out = early;

@@ -48,6 +48,7 @@ struct State {
   uint32_t* status;    // [S]
   const double* beta64;  // [NT]
   const float* beta32;   // [NT]
+  void* beta_clone;      // [S][C] inverse temperature of every clone (FP), kept by the PT kernel
 };
 
 struct Obs {
@@ -63,6 +64,7 @@ struct Run {
   int m_er0, n_er;    // same for ER clones
   int do_reservoir;
   int sample_begin;   // first sample of this launch
+  float early_beta;   // Metropolis tests of clones with beta >= early_beta use the exp early-out
   int32_t* labels;    // kPhaseLabels output [S][NR/2][K_acu][V]
 };
 
@@ -72,7 +74,6 @@ enum : uint32_t { kStatusUnionBound = 1u, kStatusFindBound = 2u };
 struct Shape {
   int chunk;       // sites per work-item: 2, 4 or 8
   int threads;     // work-items per sample workgroup (multiple of 64, <= 1024)
-  bool early_out;  // decide Metropolis tests from the binade of exp(x) first
 };
 
 size_t lds_bytes(const Geo& g, int fp_bytes);

@@ -114,9 +114,10 @@ __device__ __forceinline__ float exp_neg32(float x) {
   return exp_poly32(x, __builtin_rintf(x * 0x1.715476p+0f));
 }
 
-// Metropolis test "u < exp(x)" for x = -beta*dE < 0.  With kEarly the binade
-// bracket decides it without the polynomial unless u falls within a factor 2
-// of exp(x); both forms return the same decision.
+// Metropolis test "u < exp(x)" for x = -beta*dE < 0.  With `early` the binade
+// bracket 2^(k-1) < exp(x) < 2^(k+1) decides it without the polynomial unless
+// u falls inside the bracket; both forms return the same decision.
+// with_sign(J, s) is |J| carrying the sign bit of s (bit 31): one v_bfi_b32.
 template <typename FP>
 struct Prec;
 template <>
@@ -124,39 +125,50 @@ struct Prec<double> {
   static __device__ __forceinline__ double u(const Block& b, int word_pair) {
     return word_pair ? uniform53(b.w2, b.w3) : uniform53(b.w0, b.w1);
   }
-  template <bool kEarly>
-  static __device__ __forceinline__ bool accept(double u, double x) {
+  static __device__ __forceinline__ bool accept(double u, double x, bool early) {
     if (x < -708.0) return false;
     const double k = __builtin_rint(x * 0x1.71547652b82fep+0);
-    if (kEarly) {
+    if (early) {
       const int ki = static_cast<int>(k);
       if (u < __builtin_ldexp(1.0, ki - 1)) return true;
       if (!(u < __builtin_ldexp(1.0, ki + 1))) return false;
     }
     return u < exp_poly64(x, k);
   }
-  static __device__ __forceinline__ double neg_if(double v, uint32_t bit) {
-    const unsigned long long sign = static_cast<unsigned long long>(bit) << 63;
-    return __longlong_as_double(static_cast<long long>(static_cast<unsigned long long>(__double_as_longlong(v)) ^ sign));
+  static __device__ __forceinline__ bool negative(double J) { return __double2hiint(J) < 0; }
+  static __device__ __forceinline__ double magnitude(double J) {
+    return __hiloint2double(__double2hiint(J) & 0x7FFFFFFF, __double2loint(J));
+  }
+  // |J| (sign bit clear) with the sign bit of s
+  static __device__ __forceinline__ double with_sign(double Jabs, uint32_t s) {
+    return __hiloint2double(static_cast<int>((s & 0x80000000u) | static_cast<uint32_t>(__double2hiint(Jabs))),
+                            __double2loint(Jabs));
   }
 };
 template <>
 struct Prec<float> {
-  template <bool kEarly>
-  static __device__ __forceinline__ bool accept(float u, float x) {
+  static __device__ __forceinline__ bool accept(float u, float x, bool early) {
     if (x < -86.0f) return false;
     const float k = __builtin_rintf(x * 0x1.715476p+0f);
-    if (kEarly) {
+    if (early) {
       const int ki = static_cast<int>(k);
       if (u < __builtin_ldexpf(1.0f, ki - 1)) return true;
       if (!(u < __builtin_ldexpf(1.0f, ki + 1))) return false;
     }
     return u < exp_poly32(x, k);
   }
-  static __device__ __forceinline__ float neg_if(float v, uint32_t bit) {
-    return __int_as_float(__float_as_int(v) ^ static_cast<int>(bit << 31));
+  static __device__ __forceinline__ bool negative(float J) { return __float_as_int(J) < 0; }
+  static __device__ __forceinline__ float magnitude(float J) { return __uint_as_float(__float_as_uint(J) & 0x7FFFFFFFu); }
+  // |J| (sign bit clear) with the sign bit of s
+  static __device__ __forceinline__ float with_sign(float Jabs, uint32_t s) {
+    return __uint_as_float((s & 0x80000000u) | __float_as_uint(Jabs));
   }
 };
+
+__device__ __forceinline__ double neg_if64(double v, uint32_t bit) {
+  const unsigned long long sign = static_cast<unsigned long long>(bit) << 63;
+  return __longlong_as_double(static_cast<long long>(static_cast<unsigned long long>(__double_as_longlong(v)) ^ sign));
+}
 
 // ---------------------------------------------------------------- lattice helpers
 struct Site {
@@ -200,7 +212,7 @@ struct Lds {
   double* E;      // [NPT]
   void* bcl;      // [C] beta per clone (FP)
   uint8_t* rt;    // [NPT]
-  int32_t* qacc;  // [NT][npairs][2]
+  int32_t* qacc;  // [NT][npairs] packed Q' | Q_l' << 16
   int32_t* misc;  // [64]
 };
 
@@ -288,15 +300,20 @@ __device__ int block_exclusive_scan(int v, int32_t* misc, int* total) {
 }
 
 // ---------------------------------------------------------------- union-find
-// Lock-free union-find in LDS with atomicMin links towards the smaller index:
-// every label points to a smaller-or-equal site of the same cluster, so the
-// final root of a cluster is its smallest site.
-__device__ __forceinline__ int find_root(const uint32_t* lab, int x, int V, bool* bad) {
+// Lock-free union-find in LDS.  Links always point from a root to a smaller
+// site of the same cluster (atomicMin), so lab[x] <= x for every x, chains
+// strictly decrease, and the surviving root of a cluster is its smallest
+// site.  find() halves paths as it walks (lab[x] := lab[lab[x]]); a racing
+// store can only replace a parent by another ancestor-or-relinked site that
+// is smaller and in the same cluster, which keeps both properties.
+__device__ __forceinline__ int find_root(uint32_t* lab, int x, int V, bool* bad) {
   int n = 0;
-  int y = static_cast<int>(lab[x]);
-  while (y != x) {
-    x = y;
-    y = static_cast<int>(lab[x]);
+  int p = static_cast<int>(lab[x]);
+  while (p != x) {
+    const int gp = static_cast<int>(lab[p]);
+    if (gp != p) lab[x] = static_cast<uint32_t>(gp);  // path halving
+    x = gp;
+    p = static_cast<int>(lab[x]);
     if (++n > V) {
       *bad = true;
       break;
@@ -358,35 +375,39 @@ __device__ void rebuild_beta(const Geo& g, const Lds& s, const FP* beta) {
 }
 
 // ------------------------------------------------------------------ Metropolis
-// All attempts of one 32-clone word at one site: bit b of x[d] set means
-// s_i s_j = -1 on bond d, so the local term is -J_d.  dE = 2 sum_d (+-J_d) in
-// neighbour order; accept iff dE <= 0 or u < exp(-beta dE).
-template <typename FP, bool kEarly>
-__device__ __forceinline__ void update_word(const Geo& g, const FP* bc, uint32_t* plane, int self_idx,
-                                            const int (&nb)[6], const FP (&Jd)[6], uint32_t c0w, uint32_t t,
-                                            int sample, int clone0, int nbits) {
+// All attempts of one 32-clone word at one site.  Bit b of x[d] is the sign
+// bit of the local term J_d s_i s_j (s_i s_j = -1 flips the sign of J_d), so
+// the term is |J_d| with that sign.  dE = 2 sum_d term_d in neighbour order;
+// accept iff dE <= 0 or u < exp(-beta dE).  beta per clone comes from a
+// uniform (scalar) load.
+template <typename FP>
+__device__ __forceinline__ void update_word(const Geo& g, const FP* __restrict__ bc, uint32_t* plane, int self_idx,
+                                            const int (&nb)[6], const FP (&Jd)[6], uint32_t sgn, uint32_t c0w,
+                                            uint32_t t, int sample, int clone0, int nbits, int early_beta_bits) {
   constexpr int G = sizeof(FP) == 8 ? 2 : 4;  // clones per Philox block
   const uint32_t self = plane[self_idx];
-  uint32_t x[6];
+  uint32_t x[6];  // bit b: sign bit of the local term of clone clone0+b
 #pragma unroll
-  for (int d = 0; d < 6; ++d) x[d] = self ^ plane[nb[d]];
+  for (int d = 0; d < 6; ++d) x[d] = self ^ plane[nb[d]] ^ (0u - ((sgn >> d) & 1u));
   uint32_t flips = 0;
   int c = clone0;
   const int cend = clone0 + nbits;
   while (c < cend) {
-    const int grp = c / G;
+    const int grp = static_cast<int>(static_cast<uint32_t>(c) / G);
     const Block blk = philox10(c0w, t, static_cast<uint32_t>(grp), static_cast<uint32_t>(sample), g.key0, g.key1);
 #pragma unroll
     for (int j = 0; j < G; ++j) {
       const int cc = grp * G + j;
       if (cc < c || cc >= cend) continue;
       const int b = cc - clone0;
-      FP h = Prec<FP>::neg_if(Jd[0], (x[0] >> b) & 1u);
+      const uint32_t sh = 31u - static_cast<uint32_t>(b);
+      FP h = Prec<FP>::with_sign(Jd[0], x[0] << sh);
 #pragma unroll
-      for (int d = 1; d < 6; ++d) h = h + Prec<FP>::neg_if(Jd[d], (x[d] >> b) & 1u);
+      for (int d = 1; d < 6; ++d) h = h + Prec<FP>::with_sign(Jd[d], x[d] << sh);
       const FP dE = FP(2) * h;
       bool acc = dE <= FP(0);
       if (!acc) {
+        const FP beta = bc[cc];
         FP u;
         if constexpr (sizeof(FP) == 8) {
           u = Prec<double>::u(blk, j & 1);
@@ -394,7 +415,8 @@ __device__ __forceinline__ void update_word(const Geo& g, const FP* bc, uint32_t
           const uint32_t wj = j == 0 ? blk.w0 : j == 1 ? blk.w1 : j == 2 ? blk.w2 : blk.w3;
           u = uniform32(wj);
         }
-        acc = Prec<FP>::template accept<kEarly>(u, -(bc[cc] * dE));
+        // beta > 0: comparing the float bit patterns as integers orders them
+        acc = Prec<FP>::accept(u, -(beta * dE), __float_as_int(static_cast<float>(beta)) >= early_beta_bits);
       }
       flips |= static_cast<uint32_t>(acc) << b;
     }
@@ -404,39 +426,59 @@ __device__ __forceinline__ void update_word(const Geo& g, const FP* bc, uint32_t
 }
 
 // n_pt sweeps of the PT clones and n_er sweeps of the ER clones, interleaved
-// sweep by sweep (the classes are independent).  Jc[colour][q] are the six
-// couplings of this work-item's colour-`colour` site in pair q.
-template <typename FP, int CH, bool kEarly>
-__device__ __forceinline__ void sweep_phase(const Geo& g, const Lds& s, const FP* Js, int sample, uint32_t t,
-                                            int m_pt0, int n_pt, int m_er0, int n_er) {
+// sweep by sweep (the classes are independent).
+template <typename FP, int CH>
+__device__ __forceinline__ void sweep_phase(const Geo& g, const Lds& s, const FP* Js, const FP* __restrict__ bc,
+                                            int sample, uint32_t t, int m_pt0, int n_pt, int m_er0, int n_er,
+                                            float early_beta) {
   const Own<CH> own(g.V);
-  // couplings of own sites, by colour, held in registers for all sweeps of this phase
-  FP Jc[2][CH / 2][6];
+  // Couplings of own sites: magnitudes, plus the six sign bits packed in one
+  // word.  FP32 (and FP64 with 2 sites per work-item) keeps both colours in
+  // registers for all sweeps of the phase; FP64 with 4 sites reloads the
+  // current colour's couplings (L2-resident) at every half-sweep to stay
+  // within 128 VGPRs.
+  constexpr bool kAllInRegs = sizeof(FP) == 4 || CH == 2;
+  constexpr int NC = kAllInRegs ? 2 : 1;
+  FP Jc[NC][CH / 2][6];
+  uint32_t sg[NC][CH / 2];
   int pq[CH / 2];
 #pragma unroll
   for (int q = 0; q < CH / 2; ++q) {
-    const int i0 = own.owns ? own.first + 2 * q : 0;
-    const Site s0 = site_of(i0, g.L);
+    const Site s0 = site_of(own.owns ? own.first + 2 * q : 0, g.L);
     pq[q] = s0.x | (s0.y << 10) | (s0.z << 20);
+  }
+  auto load_couplings = [&](int slot, int colour) {
 #pragma unroll
-    for (int colour = 0; colour < 2; ++colour) {
-      const int sel = (s0.y + s0.z + colour) & 1;
-      const Site sc{i0 + sel, s0.x + sel, s0.y, s0.z};
+    for (int q = 0; q < CH / 2; ++q) {
+      const int i0 = own.owns ? own.first + 2 * q : 0;
+      const int x0 = pq[q] & 1023, y = (pq[q] >> 10) & 1023, z = pq[q] >> 20;
+      const int sel = (y + z + colour) & 1;
+      const Site sc{i0 + sel, x0 + sel, y, z};
+      uint32_t bits = 0;
 #pragma unroll
       for (int d = 0; d < 6; ++d) {
         const int owner = (d & 1) ? neighbour(sc, d, g.L) : sc.i;
-        Jc[colour][q][d] = own.owns ? Js[size_t(d >> 1) * g.V + owner] : FP(0);
+        const FP J = own.owns ? Js[size_t(d >> 1) * g.V + owner] : FP(0);
+        Jc[slot][q][d] = Prec<FP>::magnitude(J);
+        bits |= static_cast<uint32_t>(Prec<FP>::negative(J)) << d;
       }
+      sg[slot][q] = bits;
     }
+  };
+  if constexpr (kAllInRegs) {
+    load_couplings(0, 0);
+    load_couplings(NC - 1, 1);
   }
+  const int early_bits = __float_as_int(early_beta);
   const int n_m = n_pt > n_er ? n_pt : n_er;
-  const FP* bc = static_cast<const FP*>(s.bcl);
   for (int mm = 0; mm < n_m; ++mm) {
     const bool pt_on = mm < n_pt, er_on = mm < n_er && g.NER > 0;
     const uint32_t c0pt = ctr_word(0, static_cast<uint32_t>(m_pt0 + mm), kMetro);
     const uint32_t c0er = ctr_word(0, static_cast<uint32_t>(m_er0 + mm), kMetro);
 #pragma unroll
     for (int colour = 0; colour < 2; ++colour) {
+      const int slot = kAllInRegs ? colour : 0;
+      if constexpr (!kAllInRegs) load_couplings(0, colour);
       if (own.owns) {
 #pragma unroll
         for (int q = 0; q < CH / 2; ++q) {
@@ -450,15 +492,15 @@ __device__ __forceinline__ void sweep_phase(const Geo& g, const Lds& s, const FP
           const int self_idx = colour * g.Vh + (i0 >> 1);
           if (pt_on)
             for (int w = 0; w < g.NWPT; ++w)
-              update_word<FP, kEarly>(g, bc, s.sp + size_t(w) * g.V, self_idx, nb, Jc[colour][q],
-                                      c0pt | static_cast<uint32_t>(st.i), t, sample, 32 * w,
-                                      min(32, g.NPT - 32 * w));
+              update_word<FP>(g, bc, s.sp + size_t(w) * g.V, self_idx, nb, Jc[slot][q], sg[slot][q],
+                              c0pt | static_cast<uint32_t>(st.i), t, sample, 32 * w, min(32, g.NPT - 32 * w),
+                              early_bits);
           if (er_on)
             for (int w = g.NWPT; w < g.NW; ++w) {
               const int e0 = 32 * (w - g.NWPT);
-              update_word<FP, kEarly>(g, bc, s.sp + size_t(w) * g.V, self_idx, nb, Jc[colour][q],
-                                      c0er | static_cast<uint32_t>(st.i), t, sample, g.NPT + e0,
-                                      min(32, g.NER - e0));
+              update_word<FP>(g, bc, s.sp + size_t(w) * g.V, self_idx, nb, Jc[slot][q], sg[slot][q],
+                              c0er | static_cast<uint32_t>(st.i), t, sample, g.NPT + e0, min(32, g.NER - e0),
+                              early_bits);
             }
         }
       }
@@ -470,8 +512,11 @@ __device__ __forceinline__ void sweep_phase(const Geo& g, const Lds& s, const FP
 // ------------------------------------------------------------------ clusters
 // Canonical labels of the Houdayer graph of clones a, b into s.lab: sites are
 // joined across a bond iff their site overlaps q = s^a s^b are equal.
+// With draw_eta (all-cluster update), each cluster root also draws its sign
+// eta from the Philox block (ACU, site=root, slot) and marks flips in s.eta.
 template <int CH>
-__device__ __forceinline__ bool label_phase(const Geo& g, int a, int b) {
+__device__ __forceinline__ bool label_phase(const Geo& g, int a, int b, bool draw_eta = false, uint32_t t = 0,
+                                            uint32_t slot = 0, int sample = 0) {
   const Lds s = lds_view(g, 4);
   const Own<CH> own(g.V);
   bool bad = false;
@@ -504,7 +549,12 @@ __device__ __forceinline__ bool label_phase(const Geo& g, int a, int b) {
 #pragma unroll
     for (int j = 0; j < CH; ++j) {
       const int i = own.first + j;
-      s.lab[i] = static_cast<uint32_t>(find_root(s.lab, i, g.V, &bad));
+      const int r = find_root(s.lab, i, g.V, &bad);
+      s.lab[i] = static_cast<uint32_t>(r);
+      if (draw_eta && r == i) {
+        const Block blk = philox10(ctr_word(i, 0, kAcu), t, slot, sample, g.key0, g.key1);
+        if (blk.w0 >> 31) atomicOr(&s.eta[i >> 5], 1u << (i & 31));
+      }
     }
   }
   __syncthreads();
@@ -523,20 +573,9 @@ __device__ __forceinline__ bool houdayer_phase(const Geo& g, int sample, uint32_
       const uint32_t slot = static_cast<uint32_t>(p * g.NT + k);
       if (g.mode == 0)
         for (int x = threadIdx.x; x < (g.V + 31) / 32; x += blockDim.x) s.eta[x] = 0u;
-      bad |= label_phase<CH>(g, a, b);
+      bad |= label_phase<CH>(g, a, b, g.mode == 0, t, slot, sample);
       if (g.mode == 0) {
-        // all-cluster update: every root draws its cluster's sign
-        if (own.owns) {
-#pragma unroll
-          for (int j = 0; j < CH; ++j) {
-            const int i = own.first + j;
-            if (static_cast<int>(s.lab[i]) == i) {
-              const Block blk = philox10(ctr_word(i, 0, kAcu), t, slot, sample, g.key0, g.key1);
-              if (blk.w0 >> 31) atomicOr(&s.eta[i >> 5], 1u << (i & 31));
-            }
-          }
-        }
-        __syncthreads();
+        // all-cluster update: flip both replicas on clusters whose root drew eta = -1
         if (own.owns) {
 #pragma unroll
           for (int j = 0; j < CH; ++j) {
@@ -635,9 +674,9 @@ __device__ __forceinline__ void energy_phase(const Geo& g, const FP* Js) {
       a[j] = 0.0;
       if (own.owns) {
         const uint32_t si = plane[self[j]] >> b;
-        const double tx = Prec<double>::neg_if(jf[j][0], (si ^ (plane[fn[j][0]] >> b)) & 1u);
-        const double ty = Prec<double>::neg_if(jf[j][1], (si ^ (plane[fn[j][1]] >> b)) & 1u);
-        const double tz = Prec<double>::neg_if(jf[j][2], (si ^ (plane[fn[j][2]] >> b)) & 1u);
+        const double tx = neg_if64(jf[j][0], (si ^ (plane[fn[j][0]] >> b)) & 1u);
+        const double ty = neg_if64(jf[j][1], (si ^ (plane[fn[j][1]] >> b)) & 1u);
+        const double tz = neg_if64(jf[j][2], (si ^ (plane[fn[j][2]] >> b)) & 1u);
         a[j] = (tx + ty) + tz;
       }
     }
@@ -729,36 +768,53 @@ __device__ __forceinline__ void measure_phase(const Geo& g, const State& st, con
   energy_phase<FP, CH>(g, static_cast<const FP*>(st.J) + size_t(sample) * 3 * g.V);
   const Own<CH> own(g.V);
   const int NT = g.NT, NR = g.NR, npairs = NR * (NR - 1) / 2;
-  for (int x = threadIdx.x; x < 2 * NT * npairs; x += blockDim.x) s.qacc[x] = 0;
+  for (int x = threadIdx.x; x < NT * npairs; x += blockDim.x) s.qacc[x] = 0;
   __syncthreads();
+  // Per site and temperature, the spins of the N_r clones there (bit r) and of
+  // their three forward neighbours.  Each site adds q_i + 1 in {0, 2} to Q' and
+  // sum_d (q_i q_j + 1) in {0..6} to Q_l', packed as Q' | Q_l' << 16 (both
+  // fields stay below 2^16 for V <= 8192); Q = Q' - V, Q_l = Q_l' - 3V.
   for (int k = 0; k < NT; ++k) {
+    uint32_t m[CH], mn[CH][3];
+#pragma unroll
+    for (int j = 0; j < CH; ++j) {
+      m[j] = 0;
+      mn[j][0] = mn[j][1] = mn[j][2] = 0;
+      if (own.owns) {
+        const Site sti = site_of(own.first + j, g.L);
+        const int col = colour_of(sti);
+        const int ji = plane_idx(sti.i, col, g.Vh);
+        int jn[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) jn[d] = plane_idx(neighbour(sti, 2 * d, g.L), col ^ 1, g.Vh);
+        for (int r = 0; r < NR; ++r) {
+          const int c = s.cat[r * NT + k];
+          const uint32_t* plane = s.sp + size_t(word_of(g, c)) * g.V;
+          const int b = bit_of(g, c);
+          m[j] |= ((plane[ji] >> b) & 1u) << r;
+#pragma unroll
+          for (int d = 0; d < 3; ++d) mn[j][d] |= ((plane[jn[d]] >> b) & 1u) << r;
+        }
+      }
+    }
     int pair = 0;
     for (int a = 0; a < NR; ++a)
       for (int b = a + 1; b < NR; ++b, ++pair) {
-        const int ca = s.cat[a * NT + k], cb = s.cat[b * NT + k];
-        int Q = 0, QL = 0;
+        uint32_t packed = 0;
         if (own.owns) {
 #pragma unroll
           for (int j = 0; j < CH; ++j) {
-            const Site sti = site_of(own.first + j, g.L);
-            const int col = colour_of(sti);
-            const int ji = plane_idx(sti.i, col, g.Vh);
-            const uint32_t qi = spin_bit(g, s, ca, ji) ^ spin_bit(g, s, cb, ji);
-            Q += qi ? -1 : 1;
+            const uint32_t qi = ((m[j] >> a) ^ (m[j] >> b)) & 1u;  // 1: q_i = -1
+            packed += 2u - 2u * qi;
 #pragma unroll
-            for (int d = 0; d < 6; d += 2) {
-              const int jn = plane_idx(neighbour(sti, d, g.L), col ^ 1, g.Vh);
-              const uint32_t qn = spin_bit(g, s, ca, jn) ^ spin_bit(g, s, cb, jn);
-              QL += (qi ^ qn) ? -1 : 1;
+            for (int d = 0; d < 3; ++d) {
+              const uint32_t qn = ((mn[j][d] >> a) ^ (mn[j][d] >> b)) & 1u;
+              packed += (2u - 2u * (qi ^ qn)) << 16;
             }
           }
         }
-        Q = wave_sum_int(Q);
-        QL = wave_sum_int(QL);
-        if (lane_id() == 0 && (Q != 0 || QL != 0)) {
-          atomicAdd(&s.qacc[2 * (k * npairs + pair)], Q);
-          atomicAdd(&s.qacc[2 * (k * npairs + pair) + 1], QL);
-        }
+        packed = static_cast<uint32_t>(wave_sum_int(static_cast<int>(packed)));
+        if (lane_id() == 0 && packed != 0) atomicAdd(reinterpret_cast<uint32_t*>(&s.qacc[k * npairs + pair]), packed);
       }
   }
   __syncthreads();
@@ -773,8 +829,9 @@ __device__ __forceinline__ void measure_phase(const Geo& g, const State& st, con
     int pair = 0;
     for (int a = 0; a < NR; ++a)
       for (int b = a + 1; b < NR; ++b, ++pair) {
-        const int Q = s.qacc[2 * (k * npairs + pair)];
-        const int QL = s.qacc[2 * (k * npairs + pair) + 1];
+        const uint32_t packed = static_cast<uint32_t>(s.qacc[k * npairs + pair]);
+        const int Q = static_cast<int>(packed & 0xFFFFu) - g.V;
+        const int QL = static_cast<int>(packed >> 16) - 3 * g.V;
         const double q = static_cast<double>(Q) / V;
         const double ql = static_cast<double>(QL) / (3.0 * V);
         const double q2 = q * q;
@@ -827,20 +884,16 @@ __device__ __forceinline__ void store_spins(const Geo& g, const Lds& s, const St
   }
 }
 
-template <typename FP, int CH, bool kEarly>
+template <typename FP, int CH>
 __global__ __launch_bounds__(kMaxThreads) void sweep_kernel(Geo g, State st, Run run) {
   const int sample = run.sample_begin + blockIdx.x;
   if (sample >= g.S) return;  // the whole workgroup leaves together
   const Lds s = lds_view(g, sizeof(FP));
   load_spins(g, s, st, sample);
   __syncthreads();
-  const FP* beta_fp;
-  if constexpr (sizeof(FP) == 8) beta_fp = reinterpret_cast<const FP*>(st.beta64);
-  else beta_fp = reinterpret_cast<const FP*>(st.beta32);
-  rebuild_beta<FP>(g, s, beta_fp);
-  __syncthreads();
   const FP* Js = static_cast<const FP*>(st.J) + size_t(sample) * 3 * g.V;
-  sweep_phase<FP, CH, kEarly>(g, s, Js, sample, run.t0, run.m_pt0, run.n_pt, run.m_er0, run.n_er);
+  const FP* bc = static_cast<const FP*>(st.beta_clone) + size_t(sample) * g.C;
+  sweep_phase<FP, CH>(g, s, Js, bc, sample, run.t0, run.m_pt0, run.n_pt, run.m_er0, run.n_er, run.early_beta);
   store_spins(g, s, st, sample);
 }
 
@@ -871,6 +924,9 @@ __global__ __launch_bounds__(kMaxThreads) void pt_kernel(Geo g, State st, Run ru
   else beta_fp = reinterpret_cast<const FP*>(st.beta32);
   pt_phase<FP, CH>(g, st, sample, run.t0, run.do_reservoir, beta_fp);
   if (run.do_reservoir && g.NERG > 0) store_spins(g, s, st, sample);
+  FP* bcg = static_cast<FP*>(st.beta_clone) + size_t(sample) * g.C;
+  const FP* bcl = static_cast<const FP*>(s.bcl);
+  for (int x = threadIdx.x; x < g.C; x += blockDim.x) bcg[x] = bcl[x];
   for (int x = threadIdx.x; x < g.NR * g.NT; x += blockDim.x) st.clone_at[size_t(sample) * g.NR * g.NT + x] = s.cat[x];
   for (int x = threadIdx.x; x < g.NR; x += blockDim.x) st.er_head[size_t(sample) * g.NR + x] = s.head[x];
   for (int x = threadIdx.x; x < g.NPT; x += blockDim.x) st.rt_state[size_t(sample) * g.NPT + x] = s.rt[x];
@@ -924,13 +980,13 @@ hipError_t set_lds(K kern, size_t lds) {
                              static_cast<int>(lds));
 }
 
-template <typename FP, int CH, bool kEarly>
+template <typename FP, int CH>
 hipError_t launch_t(const Geo& g, const State& st, const Obs& ob, const Run& run, int threads, int n_blocks,
                     hipStream_t stream) {
   const size_t lds = plan_lds(g, sizeof(FP)).total;
   hipError_t e = hipSuccess;
   if (run.phases & kPhaseSweep) {
-    auto k = sweep_kernel<FP, CH, kEarly>;
+    auto k = sweep_kernel<FP, CH>;
     if ((e = set_lds(k, lds)) != hipSuccess) return e;
     hipLaunchKernelGGL(k, dim3(n_blocks), dim3(threads), lds, stream, g, st, run);
     if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -963,9 +1019,7 @@ size_t lds_bytes(const Geo& g, int fp_bytes) { return plan_lds(g, fp_bytes).tota
 
 hipError_t launch_emcs(int precision, const Geo& g, const State& st, const Obs& ob, const Run& run,
                        const Shape& sh, int n_blocks, hipStream_t stream) {
-#define PTHR_LAUNCH(FP, CH)                                                                         \
-  return sh.early_out ? launch_t<FP, CH, true>(g, st, ob, run, sh.threads, n_blocks, stream)        \
-                      : launch_t<FP, CH, false>(g, st, ob, run, sh.threads, n_blocks, stream)
+#define PTHR_LAUNCH(FP, CH) return launch_t<FP, CH>(g, st, ob, run, sh.threads, n_blocks, stream)
   if (precision == 0) {
     switch (sh.chunk) {
       case 2: PTHR_LAUNCH(double, 2);
