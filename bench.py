@@ -76,6 +76,56 @@ def cpu_baseline(w, n_samples: int, mode: str) -> dict:
             "sample": f"{n_samples} of {w.n_samples} samples, 1 EMCS, {w.precision} oracle"}
 
 
+def precision_check(args) -> dict:
+    """FP32 form against the FP64 form (bit-identical to the FP64 oracle) on
+    the same samples: per-temperature mean energy per spin, paired over
+    samples, and the total-variation distance between the pooled overlap
+    histograms, set against the distance between two FP64 runs with different
+    seeds.  Measurements are taken over the second half of the run."""
+    import torch
+    from paper_2605_25872_amd import pthr
+
+    w = inputs.WORKLOADS["l8_fp64"]
+    S, n = args.samples, args.emcs
+    T = w.temperatures()
+    J = w.couplings(S)
+    res = {}
+    for label, prec, seed in (("fp64", "fp64", 1), ("fp32", "fp32", 1), ("fp64_seed2", "fp64", 2)):
+        g = pthr.Pthr(w.L, S, w.n_replicas, w.n_temps, w.n_reservoir, w.sweeps_per_emcs,
+                      w.er_sweeps_per_emcs, prec, "acu", w.t_acu, seed)
+        g.init_samples(J, T)
+        obs = g.new_obs()
+        t0 = time.perf_counter()
+        half = n // 2
+        for done in range(0, half, 256):
+            g.run(min(256, half - done))
+            torch.cuda.synchronize()
+        for done in range(0, n - half, 256):
+            g.run(min(256, n - half - done), obs)
+            torch.cuda.synchronize()
+            log(f"precision check {label}: {half + done + min(256, n - half - done)}/{n} EMCS")
+        g.check()
+        arr = g.obs_arrays(obs)
+        m = arr["n_meas"]
+        res[label] = {"e": arr["acc"][:, :, 0] / (m * w.n_replicas), "hist": arr["hist"].astype(float),
+                      "seconds": time.perf_counter() - t0}
+    d = res["fp32"]["e"] - res["fp64"]["e"]            # [S][N_T], paired on samples
+    diff = d.mean(axis=0)
+    sigma = d.std(axis=0, ddof=1) / np.sqrt(S)
+    tv = lambda a, b: 0.5 * np.abs(a / a.sum(1, keepdims=True) - b / b.sum(1, keepdims=True)).sum(1)
+    tv32 = tv(res["fp32"]["hist"], res["fp64"]["hist"])
+    tv64 = tv(res["fp64_seed2"]["hist"], res["fp64"]["hist"])
+    return {"mode": "fp32_vs_fp64", "workload": f"L=8, {S} samples, 4x20 temperatures on [0.3, 1.6], "
+            f"4 reservoir clones, {n} EMCS, second half measured",
+            "T": T.tolist(), "e_fp64": res["fp64"]["e"].mean(0).tolist(),
+            "e_diff_fp32_minus_fp64": diff.tolist(), "e_diff_sigma": sigma.tolist(),
+            "max_abs_diff": float(np.abs(diff).max()), "max_abs_z": float(np.abs(diff / sigma).max()),
+            "within_1e-4": bool(np.all(np.abs(diff) <= 1e-4)),
+            "within_3_sigma": bool(np.all(np.abs(diff) <= 3 * sigma)),
+            "pq_tv_fp32_vs_fp64": tv32.tolist(), "pq_tv_fp64_vs_fp64_other_seed": tv64.tolist(),
+            "seconds": {k: v["seconds"] for k, v in res.items()}}
+
+
 def oracle_threads() -> int:
     import oracle
     return int(oracle._lib().oracle_num_threads())
@@ -95,7 +145,15 @@ def main() -> int:
     ap.add_argument("--autotune", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy a MIB-MiB device buffer 3 times (HBM counter calibration)")
+    ap.add_argument("--fp32-vs-fp64", action="store_true",
+                    help="only compare the FP32 form with the FP64 form statistically")
+    ap.add_argument("--samples", type=int, default=256)
+    ap.add_argument("--emcs", type=int, default=4096)
     args = ap.parse_args()
+
+    if args.fp32_vs_fp64:
+        print(json.dumps(precision_check(args)), flush=True)
+        return 0
 
     if args.copy_calibration:
         import torch

@@ -176,7 +176,7 @@ typedef struct pthr_schedule {
   int32_t threads_per_sample;
   int32_t samples_per_launch;
   int32_t exp_early_out;
-  int32_t reserved;
+  int32_t graph_window; /* pthr_run replays a captured HIP graph of this many EMCS (0 = plain launches) */
 } pthr_schedule;
 int pthr_get_schedule(const pthr_ctx *ctx, pthr_schedule *out);
 int pthr_set_schedule(pthr_ctx *ctx, const pthr_schedule *sch);

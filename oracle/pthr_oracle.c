@@ -285,25 +285,22 @@ int oracle_init_samples(oracle_ctx *c, const double *J, const double *T) {
 }
 
 /* ------------------------------------------------------------------------- */
-/* Local energy change of flipping site i: dE = 2 s_i sum_j J_ij s_j, the sum
- * taken in the fixed neighbour order +x,-x,+y,-y,+z,-z. */
+/* Local energy change of flipping site i: dE = 2 s_i h with h = sum_j J_ij s_j
+ * over the six neighbours, summed axis by axis:
+ *   h = ((t[+x] + t[-x]) + (t[+y] + t[-y])) + (t[+z] + t[-z]),  t[d] = J_d s_j(d). */
 double oracle_delta_e(const oracle_ctx *c, int s, int clone, int i) {
   const int8_t *sp = clone_spins(c, s, clone);
-  double h = 0.0;
-  for (int d = 0; d < 6; ++d) {
-    double term = bond(c, s, i, d) * (double)sp[c->nbr[6 * i + d]];
-    h = (d == 0) ? term : h + term;
-  }
+  double t[6];
+  for (int d = 0; d < 6; ++d) t[d] = bond(c, s, i, d) * (double)sp[c->nbr[6 * i + d]];
+  double h = ((t[0] + t[1]) + (t[2] + t[3])) + (t[4] + t[5]);
   return 2.0 * (double)sp[i] * h;
 }
 
 static float delta_e32(const oracle_ctx *c, int s, int clone, int i) {
   const int8_t *sp = clone_spins(c, s, clone);
-  float h = 0.0f;
-  for (int d = 0; d < 6; ++d) {
-    float term = bond32(c, s, i, d) * (float)sp[c->nbr[6 * i + d]];
-    h = (d == 0) ? term : h + term;
-  }
+  float t[6];
+  for (int d = 0; d < 6; ++d) t[d] = bond32(c, s, i, d) * (float)sp[c->nbr[6 * i + d]];
+  float h = ((t[0] + t[1]) + (t[2] + t[3])) + (t[4] + t[5]);
   return 2.0f * (float)sp[i] * h;
 }
 

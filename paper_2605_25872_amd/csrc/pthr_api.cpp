@@ -11,6 +11,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -50,7 +51,7 @@ Layout layout_of(const pthr_params& p) {
   const size_t S = p.n_samples, NR = p.n_replicas, NT = p.n_temps;
   const size_t fp = p.precision == PTHR_FP64 ? 8 : 4;
   Layout l{};
-  size_t o = 256;  // reserved header
+  size_t o = 256;  // header: the EMCS counter t (uint32) at offset 0
   l.beta64 = o;    o = align256(o + 8 * NT);
   l.beta32 = o;    o = align256(o + 4 * NT);
   l.spins = o;     o = align256(o + 4 * S * d.NW * d.V);
@@ -137,6 +138,20 @@ struct pthr_ctx {
   std::vector<double> T;
   pthr_schedule sch{};
   std::string err;
+  // captured EMCS window for pthr_run
+  hipStream_t cap_stream = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  int g_window = 0;
+  void* g_obs = nullptr;
+  unsigned char* g_state = nullptr;
+  pthr_schedule g_sch{};
+
+  ~pthr_ctx() { drop_graph(); if (cap_stream) (void)hipStreamDestroy(cap_stream); }
+  void drop_graph() {
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    gexec = nullptr;
+    g_window = 0;
+  }
 
   int fail(int code, const char* fmt, ...) {
     char buf[512];
@@ -153,6 +168,7 @@ struct pthr_ctx {
   pthr::State state() const {
     pthr::State st{};
     unsigned char* b = d_state;
+    st.t_dev = reinterpret_cast<uint32_t*>(b);  // first word of the reserved header
     st.spins = reinterpret_cast<uint32_t*>(b + lay.spins);
     st.J = b + lay.J;
     st.clone_at = reinterpret_cast<int32_t*>(b + lay.clone_at);
@@ -198,6 +214,72 @@ struct pthr_ctx {
       hipError_t e = pthr::launch_emcs(p.precision, g, st, ob, run, shape(), nb, stream);
       if (e != hipSuccess) return hip_fail(e, "EMCS kernel launch");
     }
+    return PTHR_OK;
+  }
+  // Raises the kernels' dynamic-LDS limit, once per device and process.
+  int prepare() {
+    static std::mutex mu;
+    static bool done[64] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "get device");
+    std::lock_guard<std::mutex> lock(mu);
+    if (dev >= 0 && dev < 64 && done[dev]) return PTHR_OK;
+    e = pthr::prepare_kernels(kLdsLimit);
+    if (e != hipSuccess) return hip_fail(e, "kernel attributes");
+    if (dev >= 0 && dev < 64) done[dev] = true;
+    return PTHR_OK;
+  }
+  // One whole EMCS on `stream`: sweeps, Houdayer, PT + reservoir (all
+  // samples), t += 1, then the observables if d_obs is set.
+  int emcs(void* d_obs, hipStream_t stream) {
+    pthr::Run run{};
+    run.phases = pthr::kPhaseSweep | (K_acu ? pthr::kPhaseHoudayer : 0u) | pthr::kPhasePT;
+    run.n_pt = p.sweeps_per_emcs;
+    run.n_er = d.NER > 0 ? p.er_sweeps_per_emcs : 0;
+    run.do_reservoir = 1;
+    if (int rc = launch(run, nullptr, stream)) return rc;
+    hipError_t e = pthr::launch_advance_t(state(), stream);
+    if (e != hipSuccess) return hip_fail(e, "advance t");
+    if (d_obs) {
+      pthr::Run m{};
+      m.phases = pthr::kPhaseMeasure;
+      if (int rc = launch(m, d_obs, stream)) return rc;
+    }
+    return PTHR_OK;
+  }
+  // Instantiates (or reuses) a graph of `window` EMCS for the current buffers
+  // and schedule.  The graph reads t from the state buffer, so it can be
+  // replayed any number of times.
+  int graph(int window, void* d_obs) {
+    if (gexec && g_window == window && g_obs == d_obs && g_state == d_state &&
+        std::memcmp(&g_sch, &sch, sizeof sch) == 0)
+      return PTHR_OK;
+    drop_graph();
+    hipError_t e = hipSuccess;
+    if (!cap_stream) e = hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking);
+    if (e != hipSuccess) return hip_fail(e, "capture stream");
+    if ((e = hipStreamBeginCapture(cap_stream, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+      return hip_fail(e, "begin capture");
+    int rc = PTHR_OK;
+    for (int w = 0; w < window && rc == PTHR_OK; ++w) rc = emcs(d_obs, cap_stream);
+    hipGraph_t gr = nullptr;
+    e = hipStreamEndCapture(cap_stream, &gr);
+    if (rc != PTHR_OK) {
+      if (gr) (void)hipGraphDestroy(gr);
+      return rc;
+    }
+    if (e != hipSuccess) return hip_fail(e, "end capture");
+    e = hipGraphInstantiate(&gexec, gr, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(gr);
+    if (e != hipSuccess) {
+      gexec = nullptr;
+      return hip_fail(e, "graph instantiation");
+    }
+    g_window = window;
+    g_obs = d_obs;
+    g_state = d_state;
+    g_sch = sch;
     return PTHR_OK;
   }
   int need_ready() {
@@ -266,6 +348,7 @@ int pthr_create(const pthr_params* p, pthr_ctx** out) {
   c->sch.threads_per_sample = threads_for(d.V, ch);
   c->sch.samples_per_launch = 0;
   c->sch.exp_early_out = 700;  // early-out below T = 0.7
+  c->sch.graph_window = 16;
   *out = c;
   g_create_error.clear();
   return PTHR_OK;
@@ -282,6 +365,8 @@ int pthr_init_samples(pthr_ctx* ctx, const double* J_host, const double* T_host,
   if (!ctx) return PTHR_EINVAL;
   ctx->err.clear();
   if (!J_host || !T_host || !d_state) return ctx->fail(PTHR_EINVAL, "J, T and d_state must not be NULL");
+  if (int rc = ctx->prepare()) return rc;
+  ctx->drop_graph();
   if (reinterpret_cast<uintptr_t>(d_state) % 256) return ctx->fail(PTHR_EINVAL, "d_state must be 256-byte aligned");
   const pthr_params& p = ctx->p;
   const int NT = p.n_temps;
@@ -339,9 +424,10 @@ int pthr_init_samples(pthr_ctx* ctx, const double* J_host, const double* T_host,
   for (size_t x = 0; x < cat.size(); ++x) cat[x] = static_cast<int32_t>(x % (NR * NT));
   if (e == hipSuccess) e = hipMemcpyAsync(ctx->d_state + l.clone_at, cat.data(), 4 * cat.size(), hipMemcpyHostToDevice, s);
   if (e != hipSuccess) return ctx->hip_fail(e, "copy to the state buffer");
-  // zero the counters and bookkeeping regions with a kernel
+  // zero the header (t) and the counters and bookkeeping regions with a kernel
   const size_t zero_from = l.er_head, zero_to = l.total;
-  e = pthr::launch_zero(ctx->d_state + zero_from, zero_to - zero_from, s);
+  e = pthr::launch_zero(ctx->d_state, 256, s);
+  if (e == hipSuccess) e = pthr::launch_zero(ctx->d_state + zero_from, zero_to - zero_from, s);
   if (e == hipSuccess) e = pthr::launch_init(ctx->g, ctx->state(), s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);  // host staging buffers go out of scope
   if (e != hipSuccess) return ctx->hip_fail(e, "state initialisation");
@@ -361,7 +447,6 @@ int pthr_sweep(pthr_ctx* ctx, int n_pt, int n_er, void* stream) {
     return ctx->fail(PTHR_ESTATE, "more than 256 sweeps in one EMCS (sweep counter field is 8 bits)");
   if (n_pt == 0 && n_er == 0) return PTHR_OK;
   pthr::Run run{};
-  run.t0 = static_cast<uint32_t>(ctx->t);
   run.phases = pthr::kPhaseSweep;
   run.m_pt0 = ctx->m_pt;
   run.n_pt = n_pt;
@@ -379,7 +464,6 @@ int pthr_houdayer(pthr_ctx* ctx, void* stream) {
   if (int rc = ctx->need_ready()) return rc;
   if (ctx->K_acu == 0) return PTHR_OK;
   pthr::Run run{};
-  run.t0 = static_cast<uint32_t>(ctx->t);
   run.phases = pthr::kPhaseHoudayer;
   return ctx->launch(run, nullptr, static_cast<hipStream_t>(stream));
 }
@@ -390,10 +474,11 @@ int pthr_pt_swap(pthr_ctx* ctx, int do_reservoir, void* stream) {
   if (int rc = ctx->need_ready()) return rc;
   if (ctx->t >= 0xFFFFFFFFll) return ctx->fail(PTHR_ESTATE, "EMCS counter exhausted (2^32)");
   pthr::Run run{};
-  run.t0 = static_cast<uint32_t>(ctx->t);
   run.phases = pthr::kPhasePT;
   run.do_reservoir = do_reservoir ? 1 : 0;
   if (int rc = ctx->launch(run, nullptr, static_cast<hipStream_t>(stream))) return rc;
+  hipError_t e = pthr::launch_advance_t(ctx->state(), static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return ctx->hip_fail(e, "advance t");
   ctx->t += 1;
   ctx->m_pt = ctx->m_er = 0;
   return PTHR_OK;
@@ -405,7 +490,6 @@ int pthr_measure(pthr_ctx* ctx, void* d_obs, void* stream) {
   if (int rc = ctx->need_ready()) return rc;
   if (!d_obs) return ctx->fail(PTHR_EINVAL, "d_obs must not be NULL");
   pthr::Run run{};
-  run.t0 = static_cast<uint32_t>(ctx->t);
   run.phases = pthr::kPhaseMeasure;
   return ctx->launch(run, d_obs, static_cast<hipStream_t>(stream));
 }
@@ -426,18 +510,18 @@ int pthr_run(pthr_ctx* ctx, int64_t n_emcs, void* d_obs, void* stream) {
   if (ctx->m_pt || ctx->m_er) return ctx->fail(PTHR_ESTATE, "an EMCS is in progress (sweep counters not at 0)");
   if (ctx->t + n_emcs > 0xFFFFFFFFll) return ctx->fail(PTHR_ESTATE, "EMCS counter would pass 2^32");
   hipStream_t s = static_cast<hipStream_t>(stream);
-  for (int64_t e = 0; e < n_emcs; ++e) {
-    // one EMCS: sweep kernel, Houdayer kernel, PT/ER kernel, measure kernel
-    pthr::Run run{};
-    run.t0 = static_cast<uint32_t>(ctx->t);
-      run.phases = pthr::kPhaseSweep | (ctx->K_acu ? pthr::kPhaseHoudayer : 0u) | pthr::kPhasePT |
-                 (d_obs ? pthr::kPhaseMeasure : 0u);
-    run.m_pt0 = 0;
-    run.n_pt = ctx->p.sweeps_per_emcs;
-    run.m_er0 = 0;
-    run.n_er = ctx->d.NER > 0 ? ctx->p.er_sweeps_per_emcs : 0;
-    run.do_reservoir = 1;
-    if (int rc = ctx->launch(run, d_obs, s)) return rc;
+  const int W = ctx->sch.graph_window;
+  int64_t done = 0;
+  if (W > 0 && n_emcs >= W) {
+    if (int rc = ctx->graph(W, d_obs)) return rc;
+    for (; done + W <= n_emcs; done += W) {
+      hipError_t e = hipGraphLaunch(ctx->gexec, s);
+      if (e != hipSuccess) return ctx->hip_fail(e, "graph launch");
+      ctx->t += W;
+    }
+  }
+  for (; done < n_emcs; ++done) {
+    if (int rc = ctx->emcs(d_obs, s)) return rc;
     ctx->t += 1;
   }
   return PTHR_OK;
@@ -450,7 +534,6 @@ int pthr_cluster_labels(pthr_ctx* ctx, void* d_labels, void* stream) {
   if (!d_labels) return ctx->fail(PTHR_EINVAL, "d_labels must not be NULL");
   if (ctx->K_acu == 0) return PTHR_OK;
   pthr::Run run{};
-  run.t0 = static_cast<uint32_t>(ctx->t);
   run.phases = pthr::kPhaseLabels;
   run.labels = static_cast<int32_t*>(d_labels);
   return ctx->launch(run, nullptr, static_cast<hipStream_t>(stream));
@@ -598,7 +681,8 @@ int pthr_set_schedule(pthr_ctx* ctx, const pthr_schedule* sch) {
   if (!ok)
     return ctx->fail(PTHR_EINVAL,
                      "threads_per_sample must be ceil(V/chunk / 64)*64 for chunk in {2,4,8} (FP64: {2,4}) and <= 1024");
-  if (sch->samples_per_launch < 0 || sch->reserved != 0) return ctx->fail(PTHR_EINVAL, "bad samples_per_launch");
+  if (sch->samples_per_launch < 0) return ctx->fail(PTHR_EINVAL, "bad samples_per_launch");
+  if (sch->graph_window < 0 || sch->graph_window > 4096) return ctx->fail(PTHR_EINVAL, "graph_window must be in [0, 4096]");
   if (sch->exp_early_out < 0) return ctx->fail(PTHR_EINVAL, "exp_early_out must be >= 0");
   ctx->sch = *sch;
   return PTHR_OK;

@@ -35,6 +35,7 @@ struct Geo {
 
 // Device pointers into the caller's state buffer (layout in pthr_api.cpp).
 struct State {
+  uint32_t* t_dev;     // EMCS counter t (device-resident so captured graphs can be replayed)
   uint32_t* spins;     // [S][NW][V] words; bit b of word w at site index j is
                        // clone 32w+b (PT) or NPT+32(w-NWPT)+b (ER); j = colour*Vh + i/2
   void* J;             // [S][3][V] double (FP64) or float (FP32), natural site order
@@ -58,7 +59,6 @@ struct Obs {
 };
 
 struct Run {
-  uint32_t t0;        // EMCS index of the first EMCS in this launch
   uint32_t phases;    // Phase bits
   int m_pt0, n_pt;    // PT sweep counter start and number of PT sweeps
   int m_er0, n_er;    // same for ER clones
@@ -81,5 +81,8 @@ hipError_t launch_emcs(int precision, const Geo& g, const State& st, const Obs& 
                        const Shape& sh, int n_blocks, hipStream_t stream);
 hipError_t launch_init(const Geo& g, const State& st, hipStream_t stream);
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t stream);
+hipError_t launch_advance_t(const State& st, hipStream_t stream);
+// Raises the dynamic-LDS limit of every kernel instantiation once per process.
+hipError_t prepare_kernels(size_t lds_bytes);
 
 }  // namespace pthr

@@ -109,9 +109,34 @@ __device__ __forceinline__ float exp_poly32(float x, float k) {
   p = __builtin_fmaf(p, r, 1.0f);            // 1/0!
   return __builtin_ldexpf(p, static_cast<int>(k));
 }
+// exp(x) * 2^32 with the same rounding steps as exp_poly32: every Horner
+// coefficient is scaled by 2^32, which commutes with each rounding (no
+// overflow or underflow on this range), so float(w) < exp_poly32_x2p32(x, k)
+// decides exactly as float(w) * 2^-32 < exp_poly32(x, k).
+__device__ __forceinline__ float exp_poly32_x2p32(float x, float k) {
+  float r = __builtin_fmaf(-k, 0x1.62e4p-1f, x);
+  r = __builtin_fmaf(-k, 0x1.7f7d1cp-20f, r);
+  float p = 0x1.a01a02p+19f;                 // 2^32/7!
+  p = __builtin_fmaf(p, r, 0x1.6c16c2p+22f); // 2^32/6!
+  p = __builtin_fmaf(p, r, 0x1.111112p+25f); // 2^32/5!
+  p = __builtin_fmaf(p, r, 0x1.555556p+27f); // 2^32/4!
+  p = __builtin_fmaf(p, r, 0x1.555556p+29f); // 2^32/3!
+  p = __builtin_fmaf(p, r, 0x1p+31f);        // 2^32/2!
+  p = __builtin_fmaf(p, r, 0x1p+32f);        // 2^32/1!
+  p = __builtin_fmaf(p, r, 0x1p+32f);        // 2^32/0!
+  return __builtin_ldexpf(p, static_cast<int>(k));
+}
+
 __device__ __forceinline__ float exp_neg32(float x) {
   if (x < -86.0f) return 0.0f;
   return exp_poly32(x, __builtin_rintf(x * 0x1.715476p+0f));
+}
+
+// (a & mask) | (b & ~mask) as one v_bfi_b32.
+__device__ __forceinline__ uint32_t bitfield_insert(uint32_t mask, uint32_t a, uint32_t b) {
+  uint32_t r;
+  asm("v_bfi_b32 %0, %1, %2, %3" : "=v"(r) : "v"(mask), "v"(a), "v"(b));
+  return r;
 }
 
 // Metropolis test "u < exp(x)" for x = -beta*dE < 0.  With `early` the binade
@@ -135,6 +160,11 @@ struct Prec<double> {
     }
     return u < exp_poly64(x, k);
   }
+  // Same decision as accept(u, x, false) for x <= 0, without branches.
+  static __device__ __forceinline__ bool accept_always(double u, double x) {
+    const double p = exp_poly64(x, __builtin_rint(x * 0x1.71547652b82fep+0));
+    return (x >= -708.0) & (u < p);
+  }
   static __device__ __forceinline__ bool negative(double J) { return __double2hiint(J) < 0; }
   static __device__ __forceinline__ double magnitude(double J) {
     return __hiloint2double(__double2hiint(J) & 0x7FFFFFFF, __double2loint(J));
@@ -156,6 +186,12 @@ struct Prec<float> {
       if (!(u < __builtin_ldexpf(1.0f, ki + 1))) return false;
     }
     return u < exp_poly32(x, k);
+  }
+  // Same decision as accept(uniform32(w), x, false) for x <= 0, branch-free,
+  // comparing float(w) with exp(x) * 2^32.
+  static __device__ __forceinline__ bool accept_always_w(uint32_t w, float x) {
+    const float p = exp_poly32_x2p32(x, __builtin_rintf(x * 0x1.715476p+0f));
+    return (x >= -86.0f) & (static_cast<float>(w) < p);
   }
   static __device__ __forceinline__ bool negative(float J) { return __float_as_int(J) < 0; }
   static __device__ __forceinline__ float magnitude(float J) { return __uint_as_float(__float_as_uint(J) & 0x7FFFFFFFu); }
@@ -375,20 +411,62 @@ __device__ void rebuild_beta(const Geo& g, const Lds& s, const FP* beta) {
 }
 
 // ------------------------------------------------------------------ Metropolis
-// All attempts of one 32-clone word at one site.  Bit b of x[d] is the sign
-// bit of the local term J_d s_i s_j (s_i s_j = -1 flips the sign of J_d), so
-// the term is |J_d| with that sign.  dE = 2 sum_d term_d in neighbour order;
-// accept iff dE <= 0 or u < exp(-beta dE).  beta per clone comes from a
-// uniform (scalar) load.
+// Couplings of one site as the sweep uses them.  The local field is summed
+// axis by axis, h = ((t[+x] + t[-x]) + (t[+y] + t[-y])) + (t[+z] + t[-z]) with
+// t[d] = J_d s_i s_j(d) (the s_i factor makes dE = 2h).  For an axis with
+// couplings A = J[+], B = J[-]: if the two terms have the same sign their sum
+// is that sign times P = |A| + |B|, otherwise it is the sign of the + term times
+// M = |A| - |B|; both are rounded once, exactly like the sum of the two signed
+// terms.  FP32 stores P and |M| per axis; FP64 stores |J| per direction.
 template <typename FP>
+struct SiteJ {
+  FP v[6];        // FP32: P_x, |M_x|, P_y, |M_y|, P_z, |M_z|; FP64: |J_d| for d = 0..5
+  uint32_t sign;  // bits 0..5: J_d < 0; bits 8..10: M_axis < 0 (FP32)
+};
+
+template <typename FP>
+__device__ __forceinline__ SiteJ<FP> make_site_j(const FP (&J)[6]) {
+  SiteJ<FP> r;
+  r.sign = 0;
+#pragma unroll
+  for (int d = 0; d < 6; ++d) r.sign |= static_cast<uint32_t>(Prec<FP>::negative(J[d])) << d;
+  if constexpr (sizeof(FP) == 4) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const float A = Prec<float>::magnitude(J[2 * a]), B = Prec<float>::magnitude(J[2 * a + 1]);
+      const float M = A - B;
+      r.v[2 * a] = A + B;
+      r.v[2 * a + 1] = Prec<float>::magnitude(M);
+      r.sign |= static_cast<uint32_t>(Prec<float>::negative(M)) << (8 + a);
+    }
+  } else {
+#pragma unroll
+    for (int d = 0; d < 6; ++d) r.v[d] = Prec<FP>::magnitude(J[d]);
+  }
+  return r;
+}
+
+// All attempts of one 32-clone word at one site.  Bit b of x[d] is the sign
+// bit of t[d] for clone clone0+b.  Accept iff dE <= 0 or u < exp(-beta dE);
+// beta per clone comes from a uniform (scalar) load.  kMaybeEarly: clones
+// colder than the early-out threshold may decide from the binade of exp(x).
+template <typename FP, bool kMaybeEarly>
 __device__ __forceinline__ void update_word(const Geo& g, const FP* __restrict__ bc, uint32_t* plane, int self_idx,
-                                            const int (&nb)[6], const FP (&Jd)[6], uint32_t sgn, uint32_t c0w,
-                                            uint32_t t, int sample, int clone0, int nbits, int early_beta_bits) {
+                                            const int (&nb)[6], const SiteJ<FP>& sj, uint32_t c0w, uint32_t t,
+                                            int sample, int clone0, int nbits, int early_beta_bits) {
   constexpr int G = sizeof(FP) == 8 ? 2 : 4;  // clones per Philox block
   const uint32_t self = plane[self_idx];
-  uint32_t x[6];  // bit b: sign bit of the local term of clone clone0+b
+  uint32_t x[6];  // bit b: sign bit of t[d] of clone clone0+b
 #pragma unroll
-  for (int d = 0; d < 6; ++d) x[d] = self ^ plane[nb[d]] ^ (0u - ((sgn >> d) & 1u));
+  for (int d = 0; d < 6; ++d) x[d] = self ^ plane[nb[d]] ^ (0u - ((sj.sign >> d) & 1u));
+  uint32_t y[3], z[3];  // FP32: axis terms of unlike sign; sign bit of the axis sum
+  if constexpr (sizeof(FP) == 4) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      y[a] = x[2 * a] ^ x[2 * a + 1];
+      z[a] = x[2 * a] ^ (y[a] & (0u - ((sj.sign >> (8 + a)) & 1u)));
+    }
+  }
   uint32_t flips = 0;
   int c = clone0;
   const int cend = clone0 + nbits;
@@ -401,22 +479,50 @@ __device__ __forceinline__ void update_word(const Geo& g, const FP* __restrict__
       if (cc < c || cc >= cend) continue;
       const int b = cc - clone0;
       const uint32_t sh = 31u - static_cast<uint32_t>(b);
-      FP h = Prec<FP>::with_sign(Jd[0], x[0] << sh);
+      FP h;
+      if constexpr (sizeof(FP) == 4) {
+        float ax[3];
 #pragma unroll
-      for (int d = 1; d < 6; ++d) h = h + Prec<FP>::with_sign(Jd[d], x[d] << sh);
+        for (int a = 0; a < 3; ++a) {
+          // all ones where the axis' two terms have unlike signs: take |M|, else P
+          const uint32_t pick = static_cast<uint32_t>(__builtin_amdgcn_sbfe(static_cast<int>(y[a]), b, 1));
+          ax[a] = Prec<float>::with_sign(__uint_as_float(bitfield_insert(pick, __float_as_uint(sj.v[2 * a + 1]),
+                                                                         __float_as_uint(sj.v[2 * a]))),
+                                         z[a] << sh);
+        }
+        h = (ax[0] + ax[1]) + ax[2];
+      } else {
+        FP tt[6];
+#pragma unroll
+        for (int d = 0; d < 6; ++d) tt[d] = Prec<FP>::with_sign(sj.v[d], x[d] << sh);
+        h = ((tt[0] + tt[1]) + (tt[2] + tt[3])) + (tt[4] + tt[5]);
+      }
       const FP dE = FP(2) * h;
-      bool acc = dE <= FP(0);
-      if (!acc) {
-        const FP beta = bc[cc];
-        FP u;
+      const FP beta = bc[cc];
+      // beta > 0: comparing the float bit patterns as integers orders them
+      const bool early = kMaybeEarly && __float_as_int(static_cast<float>(beta)) >= early_beta_bits;
+      bool acc;
+      if (early) {
+        // cold clone (uniform branch): most tests are decided by the binade
+        acc = dE <= FP(0);
+        if (!acc) {
+          FP u;
+          if constexpr (sizeof(FP) == 8) {
+            u = Prec<double>::u(blk, j & 1);
+          } else {
+            u = uniform32(j == 0 ? blk.w0 : j == 1 ? blk.w1 : j == 2 ? blk.w2 : blk.w3);
+          }
+          acc = Prec<FP>::accept(u, -(beta * dE), true);
+        }
+      } else {
+        // branch-free: the polynomial is evaluated for every lane (dE <= 0
+        // lanes take the test's first clause; their exp value is unused)
         if constexpr (sizeof(FP) == 8) {
-          u = Prec<double>::u(blk, j & 1);
+          acc = (dE <= FP(0)) | Prec<double>::accept_always(Prec<double>::u(blk, j & 1), -(beta * dE));
         } else {
           const uint32_t wj = j == 0 ? blk.w0 : j == 1 ? blk.w1 : j == 2 ? blk.w2 : blk.w3;
-          u = uniform32(wj);
+          acc = (dE <= FP(0)) | Prec<float>::accept_always_w(wj, -(beta * dE));
         }
-        // beta > 0: comparing the float bit patterns as integers orders them
-        acc = Prec<FP>::accept(u, -(beta * dE), __float_as_int(static_cast<float>(beta)) >= early_beta_bits);
       }
       flips |= static_cast<uint32_t>(acc) << b;
     }
@@ -432,15 +538,13 @@ __device__ __forceinline__ void sweep_phase(const Geo& g, const Lds& s, const FP
                                             int sample, uint32_t t, int m_pt0, int n_pt, int m_er0, int n_er,
                                             float early_beta) {
   const Own<CH> own(g.V);
-  // Couplings of own sites: magnitudes, plus the six sign bits packed in one
-  // word.  FP32 (and FP64 with 2 sites per work-item) keeps both colours in
-  // registers for all sweeps of the phase; FP64 with 4 sites reloads the
-  // current colour's couplings (L2-resident) at every half-sweep to stay
-  // within 128 VGPRs.
+  // Couplings of own sites in the form the field uses (SiteJ).  FP32 (and
+  // FP64 with 2 sites per work-item) keeps both colours in registers for all
+  // sweeps of the phase; FP64 with 4 sites reloads the current colour's
+  // couplings (L2-resident) at every half-sweep to stay within 128 VGPRs.
   constexpr bool kAllInRegs = sizeof(FP) == 4 || CH == 2;
   constexpr int NC = kAllInRegs ? 2 : 1;
-  FP Jc[NC][CH / 2][6];
-  uint32_t sg[NC][CH / 2];
+  SiteJ<FP> sj[NC][CH / 2];
   int pq[CH / 2];
 #pragma unroll
   for (int q = 0; q < CH / 2; ++q) {
@@ -454,15 +558,13 @@ __device__ __forceinline__ void sweep_phase(const Geo& g, const Lds& s, const FP
       const int x0 = pq[q] & 1023, y = (pq[q] >> 10) & 1023, z = pq[q] >> 20;
       const int sel = (y + z + colour) & 1;
       const Site sc{i0 + sel, x0 + sel, y, z};
-      uint32_t bits = 0;
+      FP J[6];
 #pragma unroll
       for (int d = 0; d < 6; ++d) {
         const int owner = (d & 1) ? neighbour(sc, d, g.L) : sc.i;
-        const FP J = own.owns ? Js[size_t(d >> 1) * g.V + owner] : FP(0);
-        Jc[slot][q][d] = Prec<FP>::magnitude(J);
-        bits |= static_cast<uint32_t>(Prec<FP>::negative(J)) << d;
+        J[d] = own.owns ? Js[size_t(d >> 1) * g.V + owner] : FP(0);
       }
-      sg[slot][q] = bits;
+      sj[slot][q] = make_site_j<FP>(J);
     }
   };
   if constexpr (kAllInRegs) {
@@ -470,6 +572,7 @@ __device__ __forceinline__ void sweep_phase(const Geo& g, const Lds& s, const FP
     load_couplings(NC - 1, 1);
   }
   const int early_bits = __float_as_int(early_beta);
+  const bool er_early = g.NER > 0 && __float_as_int(static_cast<float>(bc[g.NPT])) >= early_bits;
   const int n_m = n_pt > n_er ? n_pt : n_er;
   for (int mm = 0; mm < n_m; ++mm) {
     const bool pt_on = mm < n_pt, er_on = mm < n_er && g.NER > 0;
@@ -492,15 +595,21 @@ __device__ __forceinline__ void sweep_phase(const Geo& g, const Lds& s, const FP
           const int self_idx = colour * g.Vh + (i0 >> 1);
           if (pt_on)
             for (int w = 0; w < g.NWPT; ++w)
-              update_word<FP>(g, bc, s.sp + size_t(w) * g.V, self_idx, nb, Jc[slot][q], sg[slot][q],
-                              c0pt | static_cast<uint32_t>(st.i), t, sample, 32 * w, min(32, g.NPT - 32 * w),
-                              early_bits);
+              update_word<FP, true>(g, bc, s.sp + size_t(w) * g.V, self_idx, nb, sj[slot][q],
+                                    c0pt | static_cast<uint32_t>(st.i), t, sample, 32 * w, min(32, g.NPT - 32 * w),
+                                    early_bits);
           if (er_on)
             for (int w = g.NWPT; w < g.NW; ++w) {
               const int e0 = 32 * (w - g.NWPT);
-              update_word<FP>(g, bc, s.sp + size_t(w) * g.V, self_idx, nb, Jc[slot][q], sg[slot][q],
-                              c0er | static_cast<uint32_t>(st.i), t, sample, g.NPT + e0, min(32, g.NER - e0),
-                              early_bits);
+              // every reservoir clone sits at T_max: one uniform choice of path per word
+              if (er_early)
+                update_word<FP, true>(g, bc, s.sp + size_t(w) * g.V, self_idx, nb, sj[slot][q],
+                                      c0er | static_cast<uint32_t>(st.i), t, sample, g.NPT + e0,
+                                      min(32, g.NER - e0), early_bits);
+              else
+                update_word<FP, false>(g, bc, s.sp + size_t(w) * g.V, self_idx, nb, sj[slot][q],
+                                       c0er | static_cast<uint32_t>(st.i), t, sample, g.NPT + e0,
+                                       min(32, g.NER - e0), early_bits);
             }
         }
       }
@@ -893,7 +1002,8 @@ __global__ __launch_bounds__(kMaxThreads) void sweep_kernel(Geo g, State st, Run
   __syncthreads();
   const FP* Js = static_cast<const FP*>(st.J) + size_t(sample) * 3 * g.V;
   const FP* bc = static_cast<const FP*>(st.beta_clone) + size_t(sample) * g.C;
-  sweep_phase<FP, CH>(g, s, Js, bc, sample, run.t0, run.m_pt0, run.n_pt, run.m_er0, run.n_er, run.early_beta);
+  const uint32_t t = *st.t_dev;
+  sweep_phase<FP, CH>(g, s, Js, bc, sample, t, run.m_pt0, run.n_pt, run.m_er0, run.n_er, run.early_beta);
   store_spins(g, s, st, sample);
 }
 
@@ -905,7 +1015,7 @@ __global__ __launch_bounds__(kMaxThreads) void houdayer_kernel(Geo g, State st, 
   load_spins(g, s, st, sample);
   __syncthreads();
   const bool bad = (run.phases & kPhaseLabels) ? labels_out_phase<CH>(g, sample, run.labels)
-                                                : houdayer_phase<CH>(g, sample, run.t0);
+                                                : houdayer_phase<CH>(g, sample, *st.t_dev);
   if (!(run.phases & kPhaseLabels)) store_spins(g, s, st, sample);
   if (bad && threadIdx.x == 0) atomicOr(&st.status[sample], kStatusUnionBound);
 }
@@ -922,7 +1032,7 @@ __global__ __launch_bounds__(kMaxThreads) void pt_kernel(Geo g, State st, Run ru
   const FP* beta_fp;
   if constexpr (sizeof(FP) == 8) beta_fp = reinterpret_cast<const FP*>(st.beta64);
   else beta_fp = reinterpret_cast<const FP*>(st.beta32);
-  pt_phase<FP, CH>(g, st, sample, run.t0, run.do_reservoir, beta_fp);
+  pt_phase<FP, CH>(g, st, sample, *st.t_dev, run.do_reservoir, beta_fp);
   if (run.do_reservoir && g.NERG > 0) store_spins(g, s, st, sample);
   FP* bcg = static_cast<FP*>(st.beta_clone) + size_t(sample) * g.C;
   const FP* bcl = static_cast<const FP*>(s.bcl);
@@ -970,6 +1080,9 @@ __global__ void init_kernel(Geo g, State st) {
   }
 }
 
+// Closes an EMCS: t += 1 (one work-item).
+__global__ void advance_t_kernel(uint32_t* t) { *t += 1u; }
+
 __global__ void zero_kernel(uint32_t* p, size_t n) {
   for (size_t x = blockIdx.x * size_t(blockDim.x) + threadIdx.x; x < n; x += size_t(gridDim.x) * blockDim.x) p[x] = 0u;
 }
@@ -981,32 +1094,37 @@ hipError_t set_lds(K kern, size_t lds) {
 }
 
 template <typename FP, int CH>
+hipError_t prepare_t(size_t lds) {
+  hipError_t e;
+  if ((e = set_lds(sweep_kernel<FP, CH>, lds)) != hipSuccess) return e;
+  if ((e = set_lds(houdayer_kernel<CH>, lds)) != hipSuccess) return e;
+  if ((e = set_lds(pt_kernel<FP, CH>, lds)) != hipSuccess) return e;
+  return set_lds(measure_kernel<FP, CH>, lds);
+}
+
+template <typename FP, int CH>
 hipError_t launch_t(const Geo& g, const State& st, const Obs& ob, const Run& run, int threads, int n_blocks,
                     hipStream_t stream) {
   const size_t lds = plan_lds(g, sizeof(FP)).total;
   hipError_t e = hipSuccess;
   if (run.phases & kPhaseSweep) {
     auto k = sweep_kernel<FP, CH>;
-    if ((e = set_lds(k, lds)) != hipSuccess) return e;
     hipLaunchKernelGGL(k, dim3(n_blocks), dim3(threads), lds, stream, g, st, run);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   if (run.phases & (kPhaseHoudayer | kPhaseLabels)) {
     auto k = houdayer_kernel<CH>;
     const size_t l4 = plan_lds(g, 4).total;
-    if ((e = set_lds(k, l4)) != hipSuccess) return e;
     hipLaunchKernelGGL(k, dim3(n_blocks), dim3(threads), l4, stream, g, st, run);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   if (run.phases & kPhasePT) {
     auto k = pt_kernel<FP, CH>;
-    if ((e = set_lds(k, lds)) != hipSuccess) return e;
     hipLaunchKernelGGL(k, dim3(n_blocks), dim3(threads), lds, stream, g, st, run);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   if (run.phases & kPhaseMeasure) {
     auto k = measure_kernel<FP, CH>;
-    if ((e = set_lds(k, lds)) != hipSuccess) return e;
     hipLaunchKernelGGL(k, dim3(n_blocks), dim3(threads), lds, stream, g, st, ob, run);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
@@ -1034,6 +1152,20 @@ hipError_t launch_emcs(int precision, const Geo& g, const State& st, const Obs& 
   }
 #undef PTHR_LAUNCH
   return hipErrorInvalidValue;
+}
+
+hipError_t prepare_kernels(size_t lds) {
+  hipError_t e;
+  if ((e = prepare_t<double, 2>(lds)) != hipSuccess) return e;
+  if ((e = prepare_t<double, 4>(lds)) != hipSuccess) return e;
+  if ((e = prepare_t<float, 2>(lds)) != hipSuccess) return e;
+  if ((e = prepare_t<float, 4>(lds)) != hipSuccess) return e;
+  return prepare_t<float, 8>(lds);
+}
+
+hipError_t launch_advance_t(const State& st, hipStream_t stream) {
+  hipLaunchKernelGGL(advance_t_kernel, dim3(1), dim3(1), 0, stream, st.t_dev);
+  return hipGetLastError();
 }
 
 hipError_t launch_init(const Geo& g, const State& st, hipStream_t stream) {

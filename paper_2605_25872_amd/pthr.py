@@ -48,7 +48,7 @@ class Params(ctypes.Structure):
 
 class Schedule(ctypes.Structure):
     _fields_ = [("threads_per_sample", ctypes.c_int32), ("samples_per_launch", ctypes.c_int32),
-                ("exp_early_out", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("exp_early_out", ctypes.c_int32), ("graph_window", ctypes.c_int32)]
 
 
 _lib = None
@@ -59,6 +59,9 @@ def library() -> ctypes.CDLL:
     global _lib
     if _lib is not None:
         return _lib
+    # torch ships its own HIP runtime; load it first so that libpthr.so binds to
+    # the same runtime instance as the tensors and streams it is handed
+    import torch  # noqa: F401
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} not found: build it with `python -m paper_2605_25872_amd.build`")
     lib = ctypes.CDLL(LIB_PATH)
@@ -261,8 +264,11 @@ class Pthr:
         self._check(self.lib.pthr_get_schedule(self.ctx, ctypes.byref(sch)))
         return sch
 
-    def set_schedule(self, threads_per_sample=None, samples_per_launch=None, exp_early_out=None) -> None:
+    def set_schedule(self, threads_per_sample=None, samples_per_launch=None, exp_early_out=None,
+                     graph_window=None) -> None:
         sch = self.schedule()
+        if graph_window is not None:
+            sch.graph_window = graph_window
         if threads_per_sample is not None:
             sch.threads_per_sample = threads_per_sample
         if samples_per_launch is not None:

@@ -173,6 +173,25 @@ def test_fused_run_equals_stepwise_and_oracle(precision):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_graph_replays_match_oracle(precision):
+    """pthr_run replays a captured graph of 8 EMCS (t is read from the state
+    buffer); replays are interleaved with eager calls and read-backs, and the
+    state is checked against the oracle after every stretch."""
+    step(f"graph replays {precision}")
+    o, g = make_pair(4, 3, 2, 6, 2, precision=precision, er_sweeps=12)
+    g.set_schedule(graph_window=8)
+    oo, go = o.new_observables(), g.new_obs()
+    for stretch in (8, 19, 3, 16):  # 1 replay; 2 replays + 3 eager; eager; 2 replays
+        o.run(stretch, oo)
+        g.run(stretch, go)
+        assert_same_state(o, g, f"after a stretch of {stretch}")
+        o.emcs(oo)  # step-wise EMCS between the replays
+        g.emcs(go)
+        assert_same_state(o, g, "after a step-wise EMCS")
+    assert_same_obs(oo, g, go)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_every_schedule_gives_the_same_bits(precision):
     step(f"schedules {precision}")
     pthr = _pthr()

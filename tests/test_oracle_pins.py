@@ -406,7 +406,8 @@ def test_metropolis_decisions_follow_the_documented_random_stream():
     and the exp routine (pinned above): clone c at site i in sweep m of EMCS t
     uses block (site | m<<16 | 2<<24, t, c//2, sample), words (0,1) for even c
     and (2,3) for odd c, u = ((hi<<32 | lo) >> 11) * 2^-53; FP32 uses word c%4
-    of block c//4, u = float(w) * 2^-32; accept iff dE <= 0 or u < exp(-beta dE).
+    of block c//4, u = float(w) * 2^-32; accept iff dE <= 0 or u < exp(-beta dE),
+    with the local field summed axis by axis ((+x,-x) + (+y,-y)) + (+z,-z).
     A flip then changes the recorded spin.  Pins the stream plumbing and the
     resolution of the uniforms to their definition."""
     for precision in (oracle.FP64, oracle.FP32):
@@ -438,13 +439,12 @@ def test_metropolis_decisions_follow_the_documented_random_stream():
                                         [seed & 0xFFFFFFFF, seed >> 32])
                     u = np.float32(np.float32(blk[c % 4]) * np.float32(2.0 ** -32))
                     sp = before[c]
-                    h = np.float32(0)
-                    # dE in float from the float couplings (same order as the oracle)
+                    # dE in float from the float couplings, summed axis by axis
                     nb = [(1, 0, 0), (1, 0, 1), (2, 1, 0), (2, 1, 1), (4, 2, 0), (4, 2, 1)]
-                    for d, (j, axis, back) in enumerate(nb):
-                        owner = j if back else 0
-                        term = np.float32(J32[axis][owner]) * np.float32(sp[j])
-                        h = term if d == 0 else np.float32(h + term)
+                    t = [np.float32(J32[axis][j if back else 0]) * np.float32(sp[j])
+                         for j, axis, back in nb]
+                    h = np.float32(np.float32(np.float32(t[0] + t[1]) + np.float32(t[2] + t[3]))
+                                   + np.float32(t[4] + t[5]))
                     dE32 = np.float32(np.float32(2.0) * np.float32(sp[0])) * h
                     acc = dE32 <= 0 or u < oracle.pexp32(-(np.float32(beta) * dE32))
                 predictions[c] = acc
