@@ -29,7 +29,9 @@
  *
  * Numerics (PTHR_FP64): bit-exact with the independent CPU reference built
  * from the same definitions: Philox4x32-10 counter-based random numbers keyed
- * by (seed, sample, clone, EMCS, sweep, site), a specified double-precision
+ * by (seed, sample, clone, EMCS, sweep, site) -- a Metropolis block serves 2
+ * (FP64) or 4 (FP32) consecutive clone indices, reservoir clones counted from
+ * the first multiple of 4 at or above N_r*N_T -- a specified double-precision
  * exp, checkerboard sweeps (sites with even x+y+z, then odd), energies summed
  * by a fixed pairwise tree.  PTHR_FP32: couplings, local fields and the
  * Metropolis exponent in float (couplings rounded to float once, also for the

@@ -304,22 +304,30 @@ static float delta_e32(const oracle_ctx *c, int s, int clone, int i) {
   return 2.0f * (float)sp[i] * h;
 }
 
+/* Random-number index of a clone in the Metropolis draws: PT clones use their
+ * id; reservoir clones follow from the first multiple of 4 at or above N_PT,
+ * so that the two classes never share a Philox block. */
+static int metro_index(const oracle_ctx *c, int clone) {
+  return clone < c->NPT ? clone : (c->NPT + 3) / 4 * 4 + (clone - c->NPT);
+}
+
 /* One Metropolis attempt on site i of a clone at inverse temperature index k:
- * accept with probability min{1, exp(-beta dE)}.  FP64: the uniform takes
- * words (0,1) of the block for even clones and (2,3) for odd clones, whose
- * slot is clone/2.  FP32: word clone%4 of the block of slot clone/4. */
+ * accept with probability min{1, exp(-beta dE)}.  With n = metro_index(clone):
+ * FP64: the uniform takes words (0,1) of block n/2 for even n and (2,3) for
+ * odd n.  FP32: word n%4 of block n/4. */
 static void metropolis_attempt(oracle_ctx *c, int s, int clone, int i, int k, int m) {
   int8_t *sp = clone_spins(c, s, clone);
+  const int n = metro_index(c, clone);
   uint32_t w[4];
   int accept;
   if (c->p.precision == ORACLE_FP64) {
-    draw(c, PURPOSE_METRO, (uint32_t)i, (uint32_t)m, (uint32_t)c->t, (uint32_t)(clone / 2), s, w);
-    double u = (clone % 2 == 0) ? oracle_uniform53(w[0], w[1]) : oracle_uniform53(w[2], w[3]);
+    draw(c, PURPOSE_METRO, (uint32_t)i, (uint32_t)m, (uint32_t)c->t, (uint32_t)(n / 2), s, w);
+    double u = (n % 2 == 0) ? oracle_uniform53(w[0], w[1]) : oracle_uniform53(w[2], w[3]);
     double dE = oracle_delta_e(c, s, clone, i);
     accept = (dE <= 0.0) || (u < oracle_pexp(-(c->beta[k] * dE)));
   } else {
-    draw(c, PURPOSE_METRO, (uint32_t)i, (uint32_t)m, (uint32_t)c->t, (uint32_t)(clone / 4), s, w);
-    float u = oracle_uniform32(w[clone % 4]);
+    draw(c, PURPOSE_METRO, (uint32_t)i, (uint32_t)m, (uint32_t)c->t, (uint32_t)(n / 4), s, w);
+    float u = oracle_uniform32(w[n % 4]);
     float dE = delta_e32(c, s, clone, i);
     accept = (dE <= 0.0f) || (u < oracle_pexp32(-(c->beta32[k] * dE)));
   }

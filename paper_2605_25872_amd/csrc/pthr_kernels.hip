@@ -20,6 +20,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "pthr_internal.h"
 
 namespace pthr {
@@ -35,14 +37,33 @@ struct Block {
   uint32_t w0, w1, w2, w3;
 };
 
+// a ^ b ^ k in one VALU operation (three-input bitwise function, truth table
+// 0x96); k is wave-uniform and read from a scalar register.
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t k) {
+  uint32_t r;
+  asm("v_bitop3_b32 %0, %1, %2, %3 bitop3:0x96" : "=v"(r) : "v"(a), "v"(b), "s"(k));
+  return r;
+}
+
 __device__ __forceinline__ Block philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                                           uint32_t k0, uint32_t k1) {
 #pragma unroll
   for (int round = 0; round < 10; ++round) {
     const uint64_t pa = static_cast<uint64_t>(0xD2511F53u) * c0;
     const uint64_t pb = static_cast<uint64_t>(0xCD9E8D57u) * c2;
-    const uint32_t n0 = static_cast<uint32_t>(pb >> 32) ^ c1 ^ k0;
-    const uint32_t n2 = static_cast<uint32_t>(pa >> 32) ^ c3 ^ k1;
+    uint32_t n0, n2;
+    // The first rounds often see wave-uniform counter words: their XORs are
+    // left to the compiler, which keeps uniform parts on the scalar unit.
+    if (round < 2) {
+      n0 = static_cast<uint32_t>(pb >> 32) ^ c1 ^ k0;
+    } else {
+      n0 = xor3(static_cast<uint32_t>(pb >> 32), c1, k0);
+    }
+    if (round < 3) {
+      n2 = static_cast<uint32_t>(pa >> 32) ^ c3 ^ k1;
+    } else {
+      n2 = xor3(static_cast<uint32_t>(pa >> 32), c3, k1);
+    }
     c1 = static_cast<uint32_t>(pb);
     c3 = static_cast<uint32_t>(pa);
     c0 = n0;
@@ -127,15 +148,19 @@ __device__ __forceinline__ float exp_poly32_x2p32(float x, float k) {
   return __builtin_ldexpf(p, static_cast<int>(k));
 }
 
-__device__ __forceinline__ float exp_neg32(float x) {
-  if (x < -86.0f) return 0.0f;
-  return exp_poly32(x, __builtin_rintf(x * 0x1.715476p+0f));
-}
-
 // (a & mask) | (b & ~mask) as one v_bfi_b32.
 __device__ __forceinline__ uint32_t bitfield_insert(uint32_t mask, uint32_t a, uint32_t b) {
   uint32_t r;
   asm("v_bfi_b32 %0, %1, %2, %3" : "=v"(r) : "v"(mask), "v"(a), "v"(b));
+  return r;
+}
+
+// (f << 1) | bit, bit = this lane's bit of the wave mask `lanes`, as one
+// v_addc_co_u32 (f + f + carry-in).
+__device__ __forceinline__ uint32_t shift_in(uint32_t f, uint64_t lanes) {
+  uint32_t r;
+  uint64_t carry_out;
+  asm("v_addc_co_u32_e64 %0, %1, %2, %2, %3" : "=v"(r), "=s"(carry_out) : "v"(f), "s"(lanes));
   return r;
 }
 
@@ -160,10 +185,11 @@ struct Prec<double> {
     }
     return u < exp_poly64(x, k);
   }
-  // Same decision as accept(u, x, false) for x <= 0, without branches.
-  static __device__ __forceinline__ bool accept_always(double u, double x) {
+  // Same decision as accept(u, x, false) for x <= 0, without branches, as a
+  // mask over the wave's lanes (each clause is its own compare).
+  static __device__ __forceinline__ uint64_t accept_lanes(double u, double x) {
     const double p = exp_poly64(x, __builtin_rint(x * 0x1.71547652b82fep+0));
-    return (x >= -708.0) & (u < p);
+    return __builtin_amdgcn_ballot_w64(x >= -708.0) & __builtin_amdgcn_ballot_w64(u < p);
   }
   static __device__ __forceinline__ bool negative(double J) { return __double2hiint(J) < 0; }
   static __device__ __forceinline__ double magnitude(double J) {
@@ -188,10 +214,10 @@ struct Prec<float> {
     return u < exp_poly32(x, k);
   }
   // Same decision as accept(uniform32(w), x, false) for x <= 0, branch-free,
-  // comparing float(w) with exp(x) * 2^32.
-  static __device__ __forceinline__ bool accept_always_w(uint32_t w, float x) {
+  // comparing float(w) with exp(x) * 2^32; a mask over the wave's lanes.
+  static __device__ __forceinline__ uint64_t accept_lanes_w(uint32_t w, float x) {
     const float p = exp_poly32_x2p32(x, __builtin_rintf(x * 0x1.715476p+0f));
-    return (x >= -86.0f) & (static_cast<float>(w) < p);
+    return __builtin_amdgcn_ballot_w64(x >= -86.0f) & __builtin_amdgcn_ballot_w64(static_cast<float>(w) < p);
   }
   static __device__ __forceinline__ bool negative(float J) { return __float_as_int(J) < 0; }
   static __device__ __forceinline__ float magnitude(float J) { return __uint_as_float(__float_as_uint(J) & 0x7FFFFFFFu); }
@@ -418,9 +444,11 @@ __device__ void rebuild_beta(const Geo& g, const Lds& s, const FP* beta) {
 // is that sign times P = |A| + |B|, otherwise it is the sign of the + term times
 // M = |A| - |B|; both are rounded once, exactly like the sum of the two signed
 // terms.  FP32 stores P and |M| per axis; FP64 stores |J| per direction.
+// Every stored magnitude is doubled (exact), so the same sum yields dE = 2h
+// with identical rounding.
 template <typename FP>
 struct SiteJ {
-  FP v[6];        // FP32: P_x, |M_x|, P_y, |M_y|, P_z, |M_z|; FP64: |J_d| for d = 0..5
+  FP v[6];        // FP32: 2P_x, 2|M_x|, 2P_y, ...; FP64: 2|J_d| for d = 0..5
   uint32_t sign;  // bits 0..5: J_d < 0; bits 8..10: M_axis < 0 (FP32)
 };
 
@@ -435,99 +463,121 @@ __device__ __forceinline__ SiteJ<FP> make_site_j(const FP (&J)[6]) {
     for (int a = 0; a < 3; ++a) {
       const float A = Prec<float>::magnitude(J[2 * a]), B = Prec<float>::magnitude(J[2 * a + 1]);
       const float M = A - B;
-      r.v[2 * a] = A + B;
-      r.v[2 * a + 1] = Prec<float>::magnitude(M);
+      r.v[2 * a] = 2.0f * (A + B);
+      r.v[2 * a + 1] = 2.0f * Prec<float>::magnitude(M);
       r.sign |= static_cast<uint32_t>(Prec<float>::negative(M)) << (8 + a);
     }
   } else {
 #pragma unroll
-    for (int d = 0; d < 6; ++d) r.v[d] = Prec<FP>::magnitude(J[d]);
+    for (int d = 0; d < 6; ++d) r.v[d] = FP(2) * Prec<FP>::magnitude(J[d]);
   }
   return r;
 }
 
-// All attempts of one 32-clone word at one site.  Bit b of x[d] is the sign
-// bit of t[d] for clone clone0+b.  Accept iff dE <= 0 or u < exp(-beta dE);
-// beta per clone comes from a uniform (scalar) load.  kMaybeEarly: clones
-// colder than the early-out threshold may decide from the binade of exp(x).
+// Sign words of one 32-clone word at one site: bit b of x[d] is the sign bit
+// of t[d] for clone clone0+b; FP32 also keeps, per axis, y (the two terms have
+// unlike signs) and z (sign bit of the axis sum).
+struct WordSigns {
+  uint32_t x[6], y[3], z[3];
+};
+
+// The Metropolis attempts of random-number indices n = grp*G + j (j from G-1
+// down to 0) of one word, all drawing on Philox block grp.  The word's clones
+// are clone0 + (n - n0), n0 = the index of clone0 (a multiple of G); indices
+// past the word's last clone (a partial last block) run on that clone's beta
+// and are discarded by the caller.  Accept iff dE <= 0 or u < exp(-beta dE).
+// kMaybeEarly: clones colder than the early-out threshold may decide from the
+// binade of exp(x).  Each decision is shifted in at bit 0 of `flips`.
+template <typename FP, bool kMaybeEarly>
+__device__ __forceinline__ void attempt_group(const Geo& g, const FP* __restrict__ bc, const WordSigns& ws,
+                                              const SiteJ<FP>& sj, uint32_t c0w, uint32_t t, int sample, int grp,
+                                              int n0, int clone0, int nbits, int early_beta_bits,
+                                              uint32_t& flips) {
+  constexpr int G = sizeof(FP) == 8 ? 2 : 4;  // clones per Philox block
+  FP beta[G];
+#pragma unroll
+  for (int j = 0; j < G; ++j) beta[j] = bc[clone0 + min(grp * G + j - n0, nbits - 1)];
+  const Block blk = philox10(c0w, t, static_cast<uint32_t>(grp), static_cast<uint32_t>(sample), g.key0, g.key1);
+#pragma unroll
+  for (int j = G - 1; j >= 0; --j) {
+    const int b = grp * G + j - n0;
+    const uint32_t sh = 31u - static_cast<uint32_t>(b);
+    FP dE;  // the couplings carry the factor 2: the sum is dE = 2h
+    if constexpr (sizeof(FP) == 4) {
+      float ax[3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        // all ones where the axis' two terms have unlike signs: take |M|, else P
+        const uint32_t pick = static_cast<uint32_t>(__builtin_amdgcn_sbfe(static_cast<int>(ws.y[a]), b, 1));
+        ax[a] = Prec<float>::with_sign(__uint_as_float(bitfield_insert(pick, __float_as_uint(sj.v[2 * a + 1]),
+                                                                       __float_as_uint(sj.v[2 * a]))),
+                                       ws.z[a] << sh);
+      }
+      dE = (ax[0] + ax[1]) + ax[2];
+    } else {
+      FP tt[6];
+#pragma unroll
+      for (int d = 0; d < 6; ++d) tt[d] = Prec<FP>::with_sign(sj.v[d], ws.x[d] << sh);
+      dE = ((tt[0] + tt[1]) + (tt[2] + tt[3])) + (tt[4] + tt[5]);
+    }
+    // beta > 0: comparing the float bit patterns as integers orders them
+    const bool early = kMaybeEarly && __float_as_int(static_cast<float>(beta[j])) >= early_beta_bits;
+    uint64_t acc_lanes;
+    if (early) {
+      // cold clone (uniform branch): most tests are decided by the binade
+      bool acc = dE <= FP(0);
+      if (!acc) {
+        FP u;
+        if constexpr (sizeof(FP) == 8) {
+          u = Prec<double>::u(blk, j & 1);
+        } else {
+          u = uniform32(j == 0 ? blk.w0 : j == 1 ? blk.w1 : j == 2 ? blk.w2 : blk.w3);
+        }
+        acc = Prec<FP>::accept(u, -(beta[j] * dE), true);
+      }
+      acc_lanes = __builtin_amdgcn_ballot_w64(acc);
+    } else {
+      // branch-free: the polynomial is evaluated for every lane (dE <= 0
+      // lanes take the test's first clause; their exp value is unused)
+      uint64_t by_exp;
+      if constexpr (sizeof(FP) == 8) {
+        by_exp = Prec<double>::accept_lanes(Prec<double>::u(blk, j & 1), -(beta[j] * dE));
+      } else {
+        const uint32_t wj = j == 0 ? blk.w0 : j == 1 ? blk.w1 : j == 2 ? blk.w2 : blk.w3;
+        by_exp = Prec<float>::accept_lanes_w(wj, -(beta[j] * dE));
+      }
+      acc_lanes = __builtin_amdgcn_ballot_w64(dE <= FP(0)) | by_exp;
+    }
+    flips = shift_in(flips, acc_lanes);
+  }
+}
+
+// All attempts of one word (clones clone0 .. clone0+nbits-1, random-number
+// indices n0 .. n0+nbits-1 with n0 a multiple of 4) at one site.  beta per
+// clone comes from uniform (scalar) loads.  Blocks are visited from the last
+// to the first, so clone clone0+b ends at bit b of the flip mask; the bits of
+// a partial last block's surplus indices land above bit nbits-1 and are
+// masked off.
 template <typename FP, bool kMaybeEarly>
 __device__ __forceinline__ void update_word(const Geo& g, const FP* __restrict__ bc, uint32_t* plane, int self_idx,
                                             const int (&nb)[6], const SiteJ<FP>& sj, uint32_t c0w, uint32_t t,
-                                            int sample, int clone0, int nbits, int early_beta_bits) {
-  constexpr int G = sizeof(FP) == 8 ? 2 : 4;  // clones per Philox block
+                                            int sample, int clone0, int n0, int nbits, int early_beta_bits) {
+  constexpr int G = sizeof(FP) == 8 ? 2 : 4;
   const uint32_t self = plane[self_idx];
-  uint32_t x[6];  // bit b: sign bit of t[d] of clone clone0+b
+  WordSigns ws;
 #pragma unroll
-  for (int d = 0; d < 6; ++d) x[d] = self ^ plane[nb[d]] ^ (0u - ((sj.sign >> d) & 1u));
-  uint32_t y[3], z[3];  // FP32: axis terms of unlike sign; sign bit of the axis sum
+  for (int d = 0; d < 6; ++d) ws.x[d] = self ^ plane[nb[d]] ^ (0u - ((sj.sign >> d) & 1u));
   if constexpr (sizeof(FP) == 4) {
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-      y[a] = x[2 * a] ^ x[2 * a + 1];
-      z[a] = x[2 * a] ^ (y[a] & (0u - ((sj.sign >> (8 + a)) & 1u)));
+      ws.y[a] = ws.x[2 * a] ^ ws.x[2 * a + 1];
+      ws.z[a] = ws.x[2 * a] ^ (ws.y[a] & (0u - ((sj.sign >> (8 + a)) & 1u)));
     }
   }
   uint32_t flips = 0;
-  int c = clone0;
-  const int cend = clone0 + nbits;
-  while (c < cend) {
-    const int grp = static_cast<int>(static_cast<uint32_t>(c) / G);
-    const Block blk = philox10(c0w, t, static_cast<uint32_t>(grp), static_cast<uint32_t>(sample), g.key0, g.key1);
-#pragma unroll
-    for (int j = 0; j < G; ++j) {
-      const int cc = grp * G + j;
-      if (cc < c || cc >= cend) continue;
-      const int b = cc - clone0;
-      const uint32_t sh = 31u - static_cast<uint32_t>(b);
-      FP h;
-      if constexpr (sizeof(FP) == 4) {
-        float ax[3];
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-          // all ones where the axis' two terms have unlike signs: take |M|, else P
-          const uint32_t pick = static_cast<uint32_t>(__builtin_amdgcn_sbfe(static_cast<int>(y[a]), b, 1));
-          ax[a] = Prec<float>::with_sign(__uint_as_float(bitfield_insert(pick, __float_as_uint(sj.v[2 * a + 1]),
-                                                                         __float_as_uint(sj.v[2 * a]))),
-                                         z[a] << sh);
-        }
-        h = (ax[0] + ax[1]) + ax[2];
-      } else {
-        FP tt[6];
-#pragma unroll
-        for (int d = 0; d < 6; ++d) tt[d] = Prec<FP>::with_sign(sj.v[d], x[d] << sh);
-        h = ((tt[0] + tt[1]) + (tt[2] + tt[3])) + (tt[4] + tt[5]);
-      }
-      const FP dE = FP(2) * h;
-      const FP beta = bc[cc];
-      // beta > 0: comparing the float bit patterns as integers orders them
-      const bool early = kMaybeEarly && __float_as_int(static_cast<float>(beta)) >= early_beta_bits;
-      bool acc;
-      if (early) {
-        // cold clone (uniform branch): most tests are decided by the binade
-        acc = dE <= FP(0);
-        if (!acc) {
-          FP u;
-          if constexpr (sizeof(FP) == 8) {
-            u = Prec<double>::u(blk, j & 1);
-          } else {
-            u = uniform32(j == 0 ? blk.w0 : j == 1 ? blk.w1 : j == 2 ? blk.w2 : blk.w3);
-          }
-          acc = Prec<FP>::accept(u, -(beta * dE), true);
-        }
-      } else {
-        // branch-free: the polynomial is evaluated for every lane (dE <= 0
-        // lanes take the test's first clause; their exp value is unused)
-        if constexpr (sizeof(FP) == 8) {
-          acc = (dE <= FP(0)) | Prec<double>::accept_always(Prec<double>::u(blk, j & 1), -(beta * dE));
-        } else {
-          const uint32_t wj = j == 0 ? blk.w0 : j == 1 ? blk.w1 : j == 2 ? blk.w2 : blk.w3;
-          acc = (dE <= FP(0)) | Prec<float>::accept_always_w(wj, -(beta * dE));
-        }
-      }
-      flips |= static_cast<uint32_t>(acc) << b;
-    }
-    c = grp * G + G;
-  }
+  for (int grp = (n0 + nbits - 1) / G; grp >= n0 / G; --grp)
+    attempt_group<FP, kMaybeEarly>(g, bc, ws, sj, c0w, t, sample, grp, n0, clone0, nbits, early_beta_bits, flips);
+  if (nbits < 32) flips &= (1u << nbits) - 1u;
   plane[self_idx] = self ^ flips;
 }
 
@@ -574,13 +624,18 @@ __device__ __forceinline__ void sweep_phase(const Geo& g, const Lds& s, const FP
   const int early_bits = __float_as_int(early_beta);
   const bool er_early = g.NER > 0 && __float_as_int(static_cast<float>(bc[g.NPT])) >= early_bits;
   const int n_m = n_pt > n_er ? n_pt : n_er;
+  // random-number index of the first reservoir clone: the first multiple of 4
+  // at or above N_PT (PT clones use their own ids)
+  const int n_er0 = (g.NPT + 3) / 4 * 4;
   for (int mm = 0; mm < n_m; ++mm) {
     const bool pt_on = mm < n_pt, er_on = mm < n_er && g.NER > 0;
     const uint32_t c0pt = ctr_word(0, static_cast<uint32_t>(m_pt0 + mm), kMetro);
     const uint32_t c0er = ctr_word(0, static_cast<uint32_t>(m_er0 + mm), kMetro);
-#pragma unroll
-    for (int colour = 0; colour < 2; ++colour) {
-      const int slot = kAllInRegs ? colour : 0;
+    // one checkerboard half-sweep; the colour is a compile-time constant so
+    // that the couplings of both colours stay in registers
+    auto half_sweep = [&](auto colour_tag) {
+      constexpr int colour = decltype(colour_tag)::value;
+      constexpr int slot = kAllInRegs ? colour : 0;
       if constexpr (!kAllInRegs) load_couplings(0, colour);
       if (own.owns) {
 #pragma unroll
@@ -596,25 +651,28 @@ __device__ __forceinline__ void sweep_phase(const Geo& g, const Lds& s, const FP
           if (pt_on)
             for (int w = 0; w < g.NWPT; ++w)
               update_word<FP, true>(g, bc, s.sp + size_t(w) * g.V, self_idx, nb, sj[slot][q],
-                                    c0pt | static_cast<uint32_t>(st.i), t, sample, 32 * w, min(32, g.NPT - 32 * w),
-                                    early_bits);
+                                    c0pt | static_cast<uint32_t>(st.i), t, sample, 32 * w, 32 * w,
+                                    min(32, g.NPT - 32 * w), early_bits);
           if (er_on)
             for (int w = g.NWPT; w < g.NW; ++w) {
               const int e0 = 32 * (w - g.NWPT);
               // every reservoir clone sits at T_max: one uniform choice of path per word
               if (er_early)
                 update_word<FP, true>(g, bc, s.sp + size_t(w) * g.V, self_idx, nb, sj[slot][q],
-                                      c0er | static_cast<uint32_t>(st.i), t, sample, g.NPT + e0,
+                                      c0er | static_cast<uint32_t>(st.i), t, sample, g.NPT + e0, n_er0 + e0,
                                       min(32, g.NER - e0), early_bits);
               else
                 update_word<FP, false>(g, bc, s.sp + size_t(w) * g.V, self_idx, nb, sj[slot][q],
-                                       c0er | static_cast<uint32_t>(st.i), t, sample, g.NPT + e0,
+                                       c0er | static_cast<uint32_t>(st.i), t, sample, g.NPT + e0, n_er0 + e0,
                                        min(32, g.NER - e0), early_bits);
             }
         }
       }
-      __syncthreads();
-    }
+    };
+    half_sweep(std::integral_constant<int, 0>{});
+    __syncthreads();
+    half_sweep(std::integral_constant<int, 1>{});
+    __syncthreads();
   }
 }
 

@@ -120,11 +120,13 @@ def test_l8_several_tiles(precision):
     stepwise(o, g, 2)
 
 
-def test_l6_ragged_words_and_single_cluster():
-    """Clone counts that leave partial 32-clone words (2*7=14 PT clones, 6 ER
-    clones) and Houdayer's single-cluster mode."""
-    step("l6 ragged single")
-    o, g = make_pair(6, 3, 2, 7, 3, mode="single", er_sweeps=12, t_range=(0.2, 1.4))
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_l6_ragged_words_and_single_cluster(precision):
+    """Clone counts that leave partial 32-clone words and partial Philox blocks
+    (2*7=14 PT clones, so the reservoir clones' random-number indices start at
+    16; 6 ER clones) and Houdayer's single-cluster mode."""
+    step(f"l6 ragged single {precision}")
+    o, g = make_pair(6, 3, 2, 7, 3, precision=precision, mode="single", er_sweeps=12, t_range=(0.2, 1.4))
     stepwise(o, g, 4)
 
 
