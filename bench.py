@@ -126,6 +126,74 @@ def precision_check(args) -> dict:
             "seconds": {k: v["seconds"] for k, v in res.items()}}
 
 
+def bench_mixed(args) -> dict:
+    """Five lattice sizes (L = 8, 10, 12, 14, 16; FP32) advanced together: one
+    graph launch per EMCS with a branch per size, against the same contexts
+    run one after the other."""
+    import torch
+    from paper_2605_25872_amd import pthr
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    members = []
+    for w in inputs.MIXED_BATCH:
+        g = pthr.Pthr(w.L, w.n_samples, w.n_replicas, w.n_temps, w.n_reservoir, w.sweeps_per_emcs,
+                      w.er_sweeps_per_emcs, w.precision, args.mode, w.t_acu, w.seed)
+        g.init_samples(w.couplings(), w.temperatures())
+        if args.autotune:
+            best = g.autotune(1)
+            log(f"autotune L={w.L}: {best:.2f} ms/EMCS, {g.schedule().threads_per_sample} work-items, "
+                f"early-out below T = {g.schedule().exp_early_out / 1000:g}")
+        members.append(g)
+    group = pthr.Group(members)
+    obs = [g.new_obs() for g in members]
+    group.run(max(args.warmup, 1), obs, graph_window=1)
+    torch.cuda.synchronize()
+    log("mixed batch: warm-up done")
+    t0 = time.perf_counter()
+    group.run(args.steps, obs, graph_window=1)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    # the same contexts one after the other, each with its own graph
+    t1 = time.perf_counter()
+    for g, o in zip(members, obs):
+        g.set_schedule(graph_window=1)
+        g.run(args.steps, o)
+    torch.cuda.synchronize()
+    sequential = time.perf_counter() - t1
+    for g in members:
+        g.check()
+    att = sum(attempts_per_emcs(w) for w in inputs.MIXED_BATCH)
+    moves = sum(moves_per_emcs(w, w.temperatures()) for w in inputs.MIXED_BATCH)
+    value = att * args.steps / (elapsed * 1e9)
+    log(f"mixed batch: {value:.1f} attempts/ns together, "
+        f"{att * args.steps / (sequential * 1e9):.1f} one size after the other")
+    return {
+        "metric": METRIC.replace("L=16", "L=8..16 mixed"),
+        "value": value,
+        "unit": "spin-flip attempts/ns",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "mixed_l8_to_l16",
+                   "members": [{"L": w.L, "samples": w.n_samples, "temperatures": w.n_temps,
+                                "threads_per_sample": g.schedule().threads_per_sample,
+                                "exp_early_out_below_T": g.schedule().exp_early_out / 1000}
+                               for w, g in zip(inputs.MIXED_BATCH, members)],
+                   "replicas": 4, "reservoir_clones": 4, "houdayer": args.mode},
+        "attempts_per_emcs": att,
+        "houdayer_moves_per_s": moves * args.steps / elapsed,
+        "one_size_after_the_other": {"value": att * args.steps / (sequential * 1e9),
+                                     "ms_per_step": sequential / args.steps * 1e3},
+    }
+
+
 def oracle_threads() -> int:
     import oracle
     return int(oracle._lib().oracle_num_threads())
@@ -136,7 +204,8 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="l16_fp32", choices=sorted(inputs.WORKLOADS))
+    ap.add_argument("--workload", default="l16_fp32", choices=sorted(inputs.WORKLOADS) + ["mixed"],
+                    help="'mixed': L = 8..16 side by side, one graph launch per EMCS")
     ap.add_argument("--mode", default="acu", choices=["acu", "single"])
     ap.add_argument("--cpu-samples", type=int, default=32)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -170,6 +239,10 @@ def main() -> int:
         print("bench.py runs on one GPU only: samples are independent, a multi-GPU run "
               "shards them with no exchange (see DESIGN.md); use --gpus 1", file=sys.stderr)
         return 2
+
+    if args.workload == "mixed":
+        print(json.dumps(bench_mixed(args)), flush=True)
+        return 0
 
     import torch
     from paper_2605_25872_amd import pthr

@@ -190,6 +190,26 @@ int pthr_autotune(pthr_ctx *ctx, void *d_scratch, int n_emcs, double *best_ms, v
 /* Dynamic LDS bytes one sample workgroup needs (0 if invalid). */
 size_t pthr_lds_bytes(const pthr_params *p);
 
+/* Groups: several contexts advanced together, e.g. batches of different
+ * lattice sizes (the paper simulates L = 6 ... 18 side by side; Table A1).
+ * Every context keeps its own state buffer, schedule and counters; a group
+ * only owns HIP streams and events (pthr_group_create) and a cached graph.
+ * pthr_group_run performs n_emcs complete EMCS of every context, each exactly
+ * as pthr_run would (bit-identical), with each context's chain on a stream of
+ * its own, forked from and joined back into `stream`, so that the lattices
+ * share the GPU.  With graph_window > 0, windows of that many EMCS of all
+ * contexts are captured into one graph (one branch per context) and replayed;
+ * the remainder runs as plain launches.  d_obs: NULL (no observables) or an
+ * array of n_ctx observable buffers, entries may be NULL.  The contexts must
+ * stay alive while the group exists and must not be used from another thread
+ * during a run.  PTHR_ESTATE if a context is not initialised or inside an
+ * EMCS. */
+typedef struct pthr_group pthr_group;
+int pthr_group_create(pthr_ctx *const *ctxs, int n_ctx, pthr_group **out); /* 1 <= n_ctx <= 64 */
+int pthr_group_destroy(pthr_group *grp);
+const char *pthr_group_last_error(const pthr_group *grp);
+int pthr_group_run(pthr_group *grp, int64_t n_emcs, void *const *d_obs, int graph_window, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

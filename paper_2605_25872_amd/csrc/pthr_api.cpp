@@ -22,6 +22,7 @@ namespace {
 
 constexpr size_t kLdsLimit = 160 * 1024;  // gfx950 LDS per workgroup
 constexpr uint64_t kBlobMagic = 0x5054485253544154ull;  // "PTHRSTAT"
+constexpr int kMaxGroup = 64;  // contexts per group
 
 size_t align256(size_t v) { return (v + 255) / 256 * 256; }
 
@@ -740,6 +741,187 @@ int pthr_autotune(pthr_ctx* ctx, void* d_scratch, int n_emcs, double* best_ms, v
   ctx->sch = rc == PTHR_OK ? best : saved;
   if (best_ms) *best_ms = best_t;
   return rc;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ groups
+// Contexts advanced together: each context's EMCS chain runs on a side stream
+// of its own, forked from and joined back into the caller's stream, so the
+// chains of different lattices share the GPU.  Windows of EMCS are captured
+// once into a single graph with one parallel branch per context.
+struct pthr_group {
+  std::vector<pthr_ctx*> ctx;
+  std::vector<hipStream_t> side;
+  std::vector<hipEvent_t> join;
+  hipEvent_t fork = nullptr;
+  hipStream_t cap_stream = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  int g_window = 0;
+  std::vector<void*> g_obs;
+  std::vector<unsigned char*> g_state;
+  std::vector<pthr_schedule> g_sch;
+  std::string err;
+
+  ~pthr_group() {
+    drop_graph();
+    for (hipStream_t st : side)
+      if (st) (void)hipStreamDestroy(st);
+    for (hipEvent_t ev : join)
+      if (ev) (void)hipEventDestroy(ev);
+    if (fork) (void)hipEventDestroy(fork);
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
+  }
+  void drop_graph() {
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    gexec = nullptr;
+    g_window = 0;
+  }
+  int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    err = buf;
+    return code;
+  }
+  // n EMCS of every context, forked from `from` and joined back into it.
+  int chains(int n, void* const* d_obs, hipStream_t from) {
+    hipError_t e = hipEventRecord(fork, from);
+    if (e != hipSuccess) return fail(PTHR_EHIP, "fork: %s", hipGetErrorString(e));
+    for (size_t i = 0; i < ctx.size(); ++i) {
+      if ((e = hipStreamWaitEvent(side[i], fork, 0)) != hipSuccess)
+        return fail(PTHR_EHIP, "fork wait: %s", hipGetErrorString(e));
+      for (int w = 0; w < n; ++w)
+        if (int rc = ctx[i]->emcs(d_obs ? d_obs[i] : nullptr, side[i]))
+          return fail(rc, "context %zu: %s", i, ctx[i]->err.c_str());
+      if ((e = hipEventRecord(join[i], side[i])) != hipSuccess ||
+          (e = hipStreamWaitEvent(from, join[i], 0)) != hipSuccess)
+        return fail(PTHR_EHIP, "join: %s", hipGetErrorString(e));
+    }
+    return PTHR_OK;
+  }
+  bool graph_current(int window, void* const* d_obs) const {
+    if (!gexec || g_window != window) return false;
+    for (size_t i = 0; i < ctx.size(); ++i)
+      if (g_obs[i] != (d_obs ? d_obs[i] : nullptr) || g_state[i] != ctx[i]->d_state ||
+          std::memcmp(&g_sch[i], &ctx[i]->sch, sizeof(pthr_schedule)) != 0)
+        return false;
+    return true;
+  }
+  int graph(int window, void* const* d_obs) {
+    if (graph_current(window, d_obs)) return PTHR_OK;
+    drop_graph();
+    hipError_t e = hipSuccess;
+    if (!cap_stream) e = hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking);
+    if (e != hipSuccess) return fail(PTHR_EHIP, "capture stream: %s", hipGetErrorString(e));
+    if ((e = hipStreamBeginCapture(cap_stream, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+      return fail(PTHR_EHIP, "begin capture: %s", hipGetErrorString(e));
+    const int rc = chains(window, d_obs, cap_stream);
+    hipGraph_t gr = nullptr;
+    e = hipStreamEndCapture(cap_stream, &gr);
+    if (rc != PTHR_OK) {
+      if (gr) (void)hipGraphDestroy(gr);
+      return rc;
+    }
+    if (e != hipSuccess) return fail(PTHR_EHIP, "end capture: %s", hipGetErrorString(e));
+    e = hipGraphInstantiate(&gexec, gr, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(gr);
+    if (e != hipSuccess) {
+      gexec = nullptr;
+      return fail(PTHR_EHIP, "graph instantiation: %s", hipGetErrorString(e));
+    }
+    g_window = window;
+    g_obs.assign(ctx.size(), nullptr);
+    g_state.resize(ctx.size());
+    g_sch.resize(ctx.size());
+    for (size_t i = 0; i < ctx.size(); ++i) {
+      g_obs[i] = d_obs ? d_obs[i] : nullptr;
+      g_state[i] = ctx[i]->d_state;
+      g_sch[i] = ctx[i]->sch;
+    }
+    return PTHR_OK;
+  }
+};
+
+extern "C" {
+
+int pthr_group_create(pthr_ctx* const* ctxs, int n_ctx, pthr_group** out) {
+  if (!out) {
+    g_create_error = "out must not be NULL";
+    return PTHR_EINVAL;
+  }
+  *out = nullptr;
+  if (!ctxs || n_ctx < 1 || n_ctx > kMaxGroup) {
+    g_create_error = "need 1 to 64 contexts";
+    return PTHR_EINVAL;
+  }
+  for (int i = 0; i < n_ctx; ++i) {
+    if (!ctxs[i]) {
+      g_create_error = "context pointers must not be NULL";
+      return PTHR_EINVAL;
+    }
+    for (int j = 0; j < i; ++j)
+      if (ctxs[j] == ctxs[i]) {
+        g_create_error = "a context appears twice";
+        return PTHR_EINVAL;
+      }
+  }
+  pthr_group* grp = new pthr_group();
+  grp->ctx.assign(ctxs, ctxs + n_ctx);
+  grp->side.assign(n_ctx, nullptr);
+  grp->join.assign(n_ctx, nullptr);
+  hipError_t e = hipEventCreateWithFlags(&grp->fork, hipEventDisableTiming);
+  for (int i = 0; i < n_ctx && e == hipSuccess; ++i) {
+    e = hipStreamCreateWithFlags(&grp->side[i], hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&grp->join[i], hipEventDisableTiming);
+  }
+  if (e != hipSuccess) {
+    g_create_error = std::string("stream or event creation: ") + hipGetErrorString(e);
+    delete grp;
+    return PTHR_EHIP;
+  }
+  g_create_error.clear();
+  *out = grp;
+  return PTHR_OK;
+}
+
+int pthr_group_destroy(pthr_group* grp) {
+  delete grp;
+  return PTHR_OK;
+}
+
+const char* pthr_group_last_error(const pthr_group* grp) { return grp ? grp->err.c_str() : "null group"; }
+
+int pthr_group_run(pthr_group* grp, int64_t n_emcs, void* const* d_obs, int graph_window, void* stream) {
+  if (!grp) return PTHR_EINVAL;
+  grp->err.clear();
+  if (n_emcs < 0) return grp->fail(PTHR_EINVAL, "n_emcs must be >= 0");
+  if (graph_window < 0 || graph_window > 4096) return grp->fail(PTHR_EINVAL, "graph_window must be in [0, 4096]");
+  for (size_t i = 0; i < grp->ctx.size(); ++i) {
+    pthr_ctx* c = grp->ctx[i];
+    c->err.clear();
+    if (!c->ready) return grp->fail(PTHR_ESTATE, "context %zu: state buffer not initialised", i);
+    if (c->m_pt || c->m_er) return grp->fail(PTHR_ESTATE, "context %zu: an EMCS is in progress", i);
+    if (c->t + n_emcs > 0xFFFFFFFFll) return grp->fail(PTHR_ESTATE, "context %zu: EMCS counter would pass 2^32", i);
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  int64_t done = 0;
+  if (graph_window > 0 && n_emcs >= graph_window) {
+    if (int rc = grp->graph(graph_window, d_obs)) return rc;
+    for (; done + graph_window <= n_emcs; done += graph_window) {
+      hipError_t e = hipGraphLaunch(grp->gexec, s);
+      if (e != hipSuccess) return grp->fail(PTHR_EHIP, "graph launch: %s", hipGetErrorString(e));
+      for (pthr_ctx* c : grp->ctx) c->t += graph_window;
+    }
+  }
+  if (done < n_emcs) {
+    const int rest = static_cast<int>(n_emcs - done);
+    if (int rc = grp->chains(rest, d_obs, s)) return rc;
+    for (pthr_ctx* c : grp->ctx) c->t += rest;
+  }
+  return PTHR_OK;
 }
 
 }  // extern "C"

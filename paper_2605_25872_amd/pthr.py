@@ -27,7 +27,8 @@ EXPORTED = (
     "pthr_sweep", "pthr_houdayer", "pthr_pt_swap", "pthr_measure", "pthr_obs_clear", "pthr_run",
     "pthr_cluster_labels", "pthr_read_spins", "pthr_read_pt", "pthr_counters", "pthr_check",
     "pthr_blob_bytes", "pthr_get_state", "pthr_set_state", "pthr_get_schedule",
-    "pthr_set_schedule", "pthr_autotune", "pthr_lds_bytes",
+    "pthr_set_schedule", "pthr_autotune", "pthr_lds_bytes", "pthr_group_create",
+    "pthr_group_destroy", "pthr_group_last_error", "pthr_group_run",
 )
 
 
@@ -95,6 +96,10 @@ def library() -> ctypes.CDLL:
         "pthr_get_schedule": (i32, [vp, ctypes.POINTER(Schedule)]),
         "pthr_set_schedule": (i32, [vp, ctypes.POINTER(Schedule)]),
         "pthr_autotune": (i32, [vp, vp, i32, vp, vp]),
+        "pthr_group_create": (i32, [ctypes.POINTER(vp), i32, ctypes.POINTER(vp)]),
+        "pthr_group_destroy": (i32, [vp]),
+        "pthr_group_last_error": (ctypes.c_char_p, [vp]),
+        "pthr_group_run": (i32, [vp, i64, ctypes.POINTER(vp), i32, vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -283,3 +288,38 @@ class Pthr:
         self._check(self.lib.pthr_autotune(self.ctx, ctypes.c_void_p(scratch.data_ptr()), n_emcs,
                                            ctypes.byref(best), self._stream()))
         return best.value
+
+
+class Group:
+    """Several contexts (e.g. lattices of different sizes) advanced together:
+    each context's EMCS chain on its own HIP stream, windows of EMCS captured
+    into one graph with a branch per context."""
+
+    def __init__(self, members: list):
+        self.members = list(members)
+        self.lib = library()
+        self.torch = self.members[0].torch
+        arr = (ctypes.c_void_p * len(self.members))(*(m.ctx.value for m in self.members))
+        grp = ctypes.c_void_p()
+        rc = self.lib.pthr_group_create(arr, len(self.members), ctypes.byref(grp))
+        if rc != PTHR_OK:
+            raise PthrError(rc, self.lib.pthr_create_error().decode())
+        self.grp = grp
+
+    def __del__(self):
+        grp = getattr(self, "grp", None)
+        if grp is not None and grp.value:
+            self.lib.pthr_group_destroy(grp)
+            self.grp = None
+
+    def run(self, n_emcs: int, obs: list | None = None, graph_window: int = 16) -> None:
+        """n_emcs EMCS of every member; obs: None or one buffer (or None) per member."""
+        ptrs = None
+        if obs is not None:
+            if len(obs) != len(self.members):
+                raise ValueError("one observable buffer (or None) per member")
+            ptrs = (ctypes.c_void_p * len(obs))(*(o.data_ptr() if o is not None else None for o in obs))
+        stream = ctypes.c_void_p(self.torch.cuda.current_stream(self.members[0].device).cuda_stream)
+        rc = self.lib.pthr_group_run(self.grp, n_emcs, ptrs, graph_window, stream)
+        if rc != PTHR_OK:
+            raise PthrError(rc, self.lib.pthr_group_last_error(self.grp).decode())

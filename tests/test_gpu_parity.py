@@ -193,6 +193,32 @@ def test_graph_replays_match_oracle(precision):
     assert_same_obs(oo, g, go)
 
 
+def test_group_of_lattice_sizes_matches_oracle():
+    """A group of three lattices (L = 4, 6, 8; FP64 and FP32 members) advanced
+    together: one captured graph with a branch per context, replayed, then the
+    remainder as plain launches on forked streams.  Every member stays
+    bit-identical to its own oracle."""
+    step("group of lattice sizes")
+    pthr = _pthr()
+    cases = [(4, 3, 2, 6, 2, "fp64"), (6, 2, 2, 7, 3, "fp32"), (8, 2, 4, 5, 1, "fp32")]
+    pairs = [make_pair(L, S, NR, NT, NER, precision=prec, er_sweeps=12, jseed=10 + L, seed=3 + L)
+             for L, S, NR, NT, NER, prec in cases]
+    group = pthr.Group([g for _, g in pairs])
+    gobs = [g.new_obs() for _, g in pairs]
+    oobs = [o.new_observables() for o, _ in pairs]
+    for stretch, with_obs in ((9, True), (4, False), (8, True)):  # 2 replays + 1 eager; eager; 2 replays
+        for (o, _), oo in zip(pairs, oobs):
+            o.run(stretch, oo if with_obs else None)
+        group.run(stretch, gobs if with_obs else None, graph_window=4)
+        for i, (o, g) in enumerate(pairs):
+            assert_same_state(o, g, f"member {i} after a stretch of {stretch}")
+    for (o, g), oo, go in zip(pairs, oobs, gobs):
+        assert_same_obs(oo, g, go)
+    with pytest.raises(pthr.PthrError):
+        pairs[0][1].sweep(1, 0)  # a member inside an EMCS ...
+        group.run(1)             # ... cannot be advanced by the group
+
+
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_every_schedule_gives_the_same_bits(precision):
     step(f"schedules {precision}")

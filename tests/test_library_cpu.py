@@ -84,3 +84,25 @@ def test_calls_before_init_fail_cleanly(lib):
         assert lib.pthr_run(ctx, 1, None, None) == pthr.PTHR_ESTATE
     finally:
         lib.pthr_destroy(ctx)
+
+
+def test_group_argument_checks(lib):
+    """Group creation rejects bad arguments before touching the GPU."""
+    grp = ctypes.c_void_p()
+    assert lib.pthr_group_create(None, 1, ctypes.byref(grp)) == pthr.PTHR_EINVAL
+    p = pthr.make_params(4, 1, 2, 8, 0)
+    ctx = ctypes.c_void_p()
+    assert lib.pthr_create(ctypes.byref(p), ctypes.byref(ctx)) == 0
+    try:
+        one = (ctypes.c_void_p * 1)(ctx.value)
+        assert lib.pthr_group_create(one, 0, ctypes.byref(grp)) == pthr.PTHR_EINVAL
+        assert lib.pthr_group_create(one, 65, ctypes.byref(grp)) == pthr.PTHR_EINVAL
+        twice = (ctypes.c_void_p * 2)(ctx.value, ctx.value)
+        assert lib.pthr_group_create(twice, 2, ctypes.byref(grp)) == pthr.PTHR_EINVAL
+        assert b"twice" in lib.pthr_create_error()
+        holes = (ctypes.c_void_p * 2)(ctx.value, None)
+        assert lib.pthr_group_create(holes, 2, ctypes.byref(grp)) == pthr.PTHR_EINVAL
+        assert grp.value is None
+        assert lib.pthr_group_run(None, 1, None, 0, None) == pthr.PTHR_EINVAL
+    finally:
+        lib.pthr_destroy(ctx)
