@@ -40,6 +40,36 @@ T_EQ_EMCS = {12: 2 ** 17, 14: 6.4e6, 16: 3.84e7, 18: 3.48e7}
 OPS_PER_ATTEMPT = {"fp32": 80 // 4 + 17 + 3 + 3 + 1, "fp64": 80 // 2 + 17 + 3 + 3 + 1}
 
 
+# HBM bytes per sweep launch of the L=16 FP32 workload, from rocprofv3 counter
+# runs (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, the factors that make a 256 MiB
+# device copy read and write 256 MiB), valid for the kernel sources whose
+# SHA-256 is recorded here; any other source reports null.
+SWEEP_TRAFFIC = {
+    "workload": "l16_fp32",
+    "sources_sha256": "bd583e39ca4e4f79810c1485eaa30e8c269e13b77a417987720e306b5eee2519",
+    "fetch_kib": 74929.3,
+    "write_kib": 98304.0,
+}
+KERNEL_SOURCES = ("paper_2605_25872_amd/csrc/pthr_kernels.hip", "paper_2605_25872_amd/csrc/pthr_internal.h")
+
+
+def kernel_sources_sha256() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def sweep_traffic_bytes(workload: str):
+    """Counter-measured HBM bytes per sweep launch, or None if the kernel
+    sources changed since the counters were taken (or another workload)."""
+    if workload != SWEEP_TRAFFIC["workload"] or kernel_sources_sha256() != SWEEP_TRAFFIC["sources_sha256"]:
+        return None
+    return 1024.0 * (2.0 * SWEEP_TRAFFIC["fetch_kib"] + 1.0 * SWEEP_TRAFFIC["write_kib"])
+
+
 def log(msg: str) -> None:
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -207,7 +237,7 @@ def main() -> int:
     ap.add_argument("--workload", default="l16_fp32", choices=sorted(inputs.WORKLOADS) + ["mixed"],
                     help="'mixed': L = 8..16 side by side, one graph launch per EMCS")
     ap.add_argument("--mode", default="acu", choices=["acu", "single"])
-    ap.add_argument("--cpu-samples", type=int, default=32)
+    ap.add_argument("--cpu-samples", type=int, default=192)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--compare-fp64-samples", type=int, default=16,
                     help="samples for the unbatched FP64 one-sample-per-launch comparison (0 = skip)")
@@ -322,7 +352,8 @@ def main() -> int:
             (elapsed / args.steps) / w.n_samples * T_EQ_EMCS.get(w.L, float("nan")),
         "roofline": {"bound": "alu", "kernel": "sweep_kernel", "achieved": achieved / 1e12,
                      "peak": VALU_PEAK_OPS / 1e12, "unit": "TOP/s", "frac": achieved / VALU_PEAK_OPS,
-                     "traffic": None, "ops_per_attempt": OPS_PER_ATTEMPT[w.precision],
+                     "traffic": sweep_traffic_bytes(w.name), "traffic_unit": "HBM bytes per launch",
+                     "ops_per_attempt": OPS_PER_ATTEMPT[w.precision],
                      "sweep_ms_per_launch": sweep_ms},
     }
 

@@ -401,6 +401,28 @@ def test_uniforms_match_their_definition():
         assert oracle.uniform32(w) == np.float32(np.float32(w) * np.float32(2.0 ** -32))
 
 
+def _predict_site0(o, precision, seed, c, n, m, beta, before, J32):
+    """Decision of the first Metropolis attempt of a sweep (site 0) for clone c
+    with random-number index n, sweep m, from the documented stream."""
+    if precision == oracle.FP64:
+        dE = o.delta_e(0, c, 0)
+        blk = oracle.philox([0 | (m << 16) | (2 << 24), o.t, n // 2, 0], [seed & 0xFFFFFFFF, seed >> 32])
+        lo, hi = (blk[0], blk[1]) if n % 2 == 0 else (blk[2], blk[3])
+        u = float(((int(hi) << 32) | int(lo)) >> 11) * 2.0 ** -53
+        return dE <= 0 or u < oracle.pexp(-(beta * dE))
+    blk = oracle.philox([0 | (m << 16) | (2 << 24), o.t, n // 4, 0], [seed & 0xFFFFFFFF, seed >> 32])
+    u = np.float32(np.float32(blk[n % 4]) * np.float32(2.0 ** -32))
+    sp = before[c]
+    # dE in float from the float couplings, summed axis by axis (L = 2: both
+    # neighbours along an axis are site 1, 2 or 4)
+    nb = [(1, 0, 0), (1, 0, 1), (2, 1, 0), (2, 1, 1), (4, 2, 0), (4, 2, 1)]
+    terms = [np.float32(J32[axis][j if back else 0]) * np.float32(sp[j]) for j, axis, back in nb]
+    h = np.float32(np.float32(np.float32(terms[0] + terms[1]) + np.float32(terms[2] + terms[3]))
+                   + np.float32(terms[4] + terms[5]))
+    dE32 = np.float32(np.float32(2.0) * np.float32(sp[0])) * h
+    return dE32 <= 0 or u < oracle.pexp32(-(np.float32(beta) * dE32))
+
+
 def test_metropolis_decisions_follow_the_documented_random_stream():
     """Replays single Metropolis decisions from the Philox stream (pinned above)
     and the exp routine (pinned above): clone c at site i in sweep m of EMCS t
@@ -416,38 +438,16 @@ def test_metropolis_decisions_follow_the_documented_random_stream():
         J = inputs.couplings(L, 1, seed=3)
         T = np.array([0.05, 3.0])  # tiny acceptances at the low temperature
         o.init(J, T)
-        if precision == oracle.FP32:
-            J32 = J[0].astype(np.float32).astype(np.float64)
+        J32 = J[0].astype(np.float32).astype(np.float64)
         checked = 0
-        for t in range(300):
+        for _ in range(300):
             _reset_identity(o)
             before = o.spins[0].copy()
             # predict site 0 (parity 0, the first attempt of the sweep) for every clone
             predictions = {}
             for c in range(o.NPT):
-                dE = o.delta_e(0, c, 0)
                 k = list(o.clone_at[0].ravel()).index(c) % o.NT
-                beta = 1.0 / T[k]
-                if precision == oracle.FP64:
-                    blk = oracle.philox([0 | (0 << 16) | (2 << 24), o.t, c // 2, 0],
-                                        [seed & 0xFFFFFFFF, seed >> 32])
-                    lo, hi = (blk[0], blk[1]) if c % 2 == 0 else (blk[2], blk[3])
-                    u = float(((int(hi) << 32) | int(lo)) >> 11) * 2.0 ** -53
-                    acc = dE <= 0 or u < oracle.pexp(-(beta * dE))
-                else:
-                    blk = oracle.philox([0 | (0 << 16) | (2 << 24), o.t, c // 4, 0],
-                                        [seed & 0xFFFFFFFF, seed >> 32])
-                    u = np.float32(np.float32(blk[c % 4]) * np.float32(2.0 ** -32))
-                    sp = before[c]
-                    # dE in float from the float couplings, summed axis by axis
-                    nb = [(1, 0, 0), (1, 0, 1), (2, 1, 0), (2, 1, 1), (4, 2, 0), (4, 2, 1)]
-                    t = [np.float32(J32[axis][j if back else 0]) * np.float32(sp[j])
-                         for j, axis, back in nb]
-                    h = np.float32(np.float32(np.float32(t[0] + t[1]) + np.float32(t[2] + t[3]))
-                                   + np.float32(t[4] + t[5]))
-                    dE32 = np.float32(np.float32(2.0) * np.float32(sp[0])) * h
-                    acc = dE32 <= 0 or u < oracle.pexp32(-(np.float32(beta) * dE32))
-                predictions[c] = acc
+                predictions[c] = _predict_site0(o, precision, seed, c, c, 0, 1.0 / T[k], before, J32)
             o.sweep(1, oracle.SWEEP_PT)
             # site 0 is the first site updated, so its flip is decided on `before`
             for c, acc in predictions.items():
@@ -455,6 +455,36 @@ def test_metropolis_decisions_follow_the_documented_random_stream():
                 checked += 1
             o.pt_swap(False)
         assert checked == 300 * 4
+
+
+def test_reservoir_decisions_use_the_offset_random_index():
+    """Reservoir clone e (id N_PT + e) draws its Metropolis numbers with index
+    n = 4*ceil(N_PT/4) + e, at beta_max, on its own sweep counter.  With
+    N_r = 2, N_T = 3 (N_PT = 6) the indices start at 8, so a mistaken offset
+    (6, or none) changes the blocks and words used."""
+    for precision in (oracle.FP64, oracle.FP32):
+        L, seed = 2, 91
+        o = oracle.Oracle(L, 1, 2, 3, 2, precision=precision, t_acu=0.0, seed=seed)
+        J = inputs.couplings(L, 1, seed=5)
+        T = np.array([0.3, 0.5, 0.9])
+        o.init(J, T)
+        J32 = J[0].astype(np.float32).astype(np.float64)
+        checked = flips = 0
+        for _ in range(200):
+            for m in range(3):
+                before = o.spins[0].copy()
+                predictions = {c: _predict_site0(o, precision, seed, c, 8 + (c - o.NPT), m, 1.0 / T[-1],
+                                                 before, J32)
+                               for c in range(o.NPT, o.C)}
+                assert o.m(oracle.SWEEP_ER) == m
+                o.sweep(1, oracle.SWEEP_ER)
+                for c, acc in predictions.items():
+                    assert (o.spins[0, c, 0] != before[c, 0]) == acc
+                    checked += 1
+                    flips += int(acc)
+            o.pt_swap(True)
+        assert checked == 200 * 3 * 4
+        assert 0 < flips < checked
 
 
 # --------------------------------------------------------------------------- measure / ER / round trips
