@@ -20,7 +20,7 @@
 
 namespace {
 
-constexpr size_t kLdsLimit = 160 * 1024;  // gfx950 LDS per workgroup
+constexpr size_t kLdsLimit = pthr::kLdsMax;
 constexpr uint64_t kBlobMagic = 0x5054485253544154ull;  // "PTHRSTAT"
 constexpr int kMaxGroup = 64;  // contexts per group
 

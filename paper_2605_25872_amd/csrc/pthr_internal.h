@@ -66,6 +66,7 @@ struct Run {
   int sample_begin;   // first sample of this launch
   float early_beta;   // Metropolis tests of clones with beta >= early_beta use the exp early-out
   int32_t* labels;    // kPhaseLabels output [S][NR/2][K_acu][V]
+  int hou_moves;      // Houdayer moves labelled at once (set by the launcher)
 };
 
 // Device status bits (per sample).
@@ -76,7 +77,11 @@ struct Shape {
   int threads;     // work-items per sample workgroup (multiple of 64, <= 1024)
 };
 
+constexpr size_t kLdsMax = 160 * 1024;  // gfx950 LDS per workgroup
+constexpr int kMaxHouMoves = 16;        // Houdayer moves labelled at once, at most
+
 size_t lds_bytes(const Geo& g, int fp_bytes);
+int houdayer_moves_per_pass(const Geo& g, int threads);
 hipError_t launch_emcs(int precision, const Geo& g, const State& st, const Obs& ob, const Run& run,
                        const Shape& sh, int n_blocks, hipStream_t stream);
 hipError_t launch_init(const Geo& g, const State& st, hipStream_t stream);

@@ -266,9 +266,7 @@ __device__ __forceinline__ int bit_of(const Geo& g, int clone) {
 // ---------------------------------------------------------------- LDS layout
 struct Lds {
   uint32_t* sp;   // [NW][V]
-  uint32_t* lab;  // [max(V, 2*16*NPT)] labels; reused for energy partials
-  uint8_t* qb;    // [V] site overlap bits
-  uint32_t* eta;  // [ceil(V/32)] ACU flip flags per root
+  uint32_t* lab;  // [2*16*NPT] energy partials
   int32_t* cat;   // [NR][NT]
   int32_t* head;  // [NR]
   double* E;      // [NPT]
@@ -281,19 +279,15 @@ struct Lds {
 __host__ __device__ inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 struct LdsPlan {
-  size_t sp, lab, qb, eta, cat, head, E, bcl, rt, qacc, misc, total;
+  size_t sp, lab, cat, head, E, bcl, rt, qacc, misc, total;
 };
 __host__ __device__ inline LdsPlan plan_lds(const Geo& g, int fp_bytes) {
   LdsPlan p{};
   size_t o = 0;
   const int npairs = g.NR * (g.NR - 1) / 2;
   p.sp = o;   o = align_up(o + sizeof(uint32_t) * size_t(g.NW) * g.V, 16);
-  size_t lab_words = size_t(g.V);
   const size_t red_words = size_t(2) * kMaxWaves * g.NPT;
-  if (red_words > lab_words) lab_words = red_words;
-  p.lab = o;  o = align_up(o + sizeof(uint32_t) * lab_words, 16);
-  p.qb = o;   o = align_up(o + size_t(g.V), 16);
-  p.eta = o;  o = align_up(o + sizeof(uint32_t) * ((g.V + 31) / 32), 16);
+  p.lab = o;  o = align_up(o + sizeof(uint32_t) * red_words, 16);
   p.cat = o;  o = align_up(o + sizeof(int32_t) * size_t(g.NR) * g.NT, 16);
   p.head = o; o = align_up(o + sizeof(int32_t) * size_t(g.NR), 16);
   p.E = o;    o = align_up(o + sizeof(double) * size_t(g.NPT), 16);
@@ -314,8 +308,6 @@ __device__ __forceinline__ Lds lds_view(const Geo& g, int fp_bytes) {
   Lds s;
   s.sp = reinterpret_cast<uint32_t*>(lds_raw + plan.sp);
   s.lab = reinterpret_cast<uint32_t*>(lds_raw + plan.lab);
-  s.qb = lds_raw + plan.qb;
-  s.eta = reinterpret_cast<uint32_t*>(lds_raw + plan.eta);
   s.cat = reinterpret_cast<int32_t*>(lds_raw + plan.cat);
   s.head = reinterpret_cast<int32_t*>(lds_raw + plan.head);
   s.E = reinterpret_cast<double*>(lds_raw + plan.E);
@@ -410,21 +402,6 @@ struct Own {
   bool owns;
   __device__ __forceinline__ Own(int V) : first(static_cast<int>(threadIdx.x) * CH), owns(first < V) {}
 };
-
-// Flip clones a and b at plane index j (both replicas of a Houdayer pair).
-__device__ __forceinline__ void flip_pair(const Geo& g, const Lds& s, int a, int b, int j) {
-  const int wa = word_of(g, a), wb = word_of(g, b);
-  const uint32_t ma = 1u << bit_of(g, a), mb = 1u << bit_of(g, b);
-  if (wa == wb) {
-    s.sp[size_t(wa) * g.V + j] ^= (ma | mb);
-  } else {
-    s.sp[size_t(wa) * g.V + j] ^= ma;
-    s.sp[size_t(wb) * g.V + j] ^= mb;
-  }
-}
-__device__ __forceinline__ uint32_t spin_bit(const Geo& g, const Lds& s, int clone, int j) {
-  return (s.sp[size_t(word_of(g, clone)) * g.V + j] >> bit_of(g, clone)) & 1u;
-}
 
 template <typename FP>
 __device__ void rebuild_beta(const Geo& g, const Lds& s, const FP* beta) {
@@ -677,131 +654,216 @@ __device__ __forceinline__ void sweep_phase(const Geo& g, const Lds& s, const FP
 }
 
 // ------------------------------------------------------------------ clusters
-// Canonical labels of the Houdayer graph of clones a, b into s.lab: sites are
-// joined across a bond iff their site overlaps q = s^a s^b are equal.
-// With draw_eta (all-cluster update), each cluster root also draws its sign
-// eta from the Philox block (ACU, site=root, slot) and marks flips in s.eta.
-template <int CH>
-__device__ __forceinline__ bool label_phase(const Geo& g, int a, int b, bool draw_eta = false, uint32_t t = 0,
-                                            uint32_t slot = 0, int sample = 0) {
-  const Lds s = lds_view(g, 4);
-  const Own<CH> own(g.V);
-  bool bad = false;
-  if (own.owns) {
-#pragma unroll
-    for (int j = 0; j < CH; ++j) {
-      const int i = own.first + j;
-      const Site st = site_of(i, g.L);
-      const int jj = plane_idx(i, colour_of(st), g.Vh);
-      s.qb[i] = static_cast<uint8_t>(spin_bit(g, s, a, jj) ^ spin_bit(g, s, b, jj));
-      s.lab[i] = static_cast<uint32_t>(i);
-    }
-  }
-  __syncthreads();
-  if (own.owns) {
-#pragma unroll
-    for (int j = 0; j < CH; ++j) {
-      const int i = own.first + j;
-      const Site st = site_of(i, g.L);
-      const uint8_t qi = s.qb[i];
-#pragma unroll
-      for (int d = 0; d < 6; d += 2) {
-        const int n = neighbour(st, d, g.L);
-        if (s.qb[n] == qi) unite(s.lab, i, n, g.V, &bad);
-      }
-    }
-  }
-  __syncthreads();
-  if (own.owns) {
-#pragma unroll
-    for (int j = 0; j < CH; ++j) {
-      const int i = own.first + j;
-      const int r = find_root(s.lab, i, g.V, &bad);
-      s.lab[i] = static_cast<uint32_t>(r);
-      if (draw_eta && r == i) {
-        const Block blk = philox10(ctr_word(i, 0, kAcu), t, slot, sample, g.key0, g.key1);
-        if (blk.w0 >> 31) atomicOr(&s.eta[i >> 5], 1u << (i & 31));
-      }
-    }
-  }
-  __syncthreads();
-  return bad;
+// Houdayer moves, row-parallel.  A work-item owns one x-row (L <= 32 sites) of
+// one move (pair p, temperature k); hou_moves moves are labelled at once, each
+// in its own LDS label array.  Along a row the sites of equal overlap
+// q_i = s_i^a s_i^b (bit 1: q = -1) form runs, maximal intervals of equal q
+// with x = 0 always starting one.  Only run starts are union-find nodes: runs
+// are joined across the periodic +x bond of the row and across the +y and +z
+// bonds, once per pair of touching runs.  Unions link a root to a smaller site
+// (atomicMin), so the surviving root of a cluster is its smallest site, which
+// is always a run start: the canonical root.
+
+struct HouLds {
+  uint32_t* sp;    // [NW][V] spin words
+  int32_t* cat;    // [NR][NT]
+  uint32_t* lab;   // [M][V] union-find parents (entries of run starts only)
+  uint32_t* qrow;  // [M][L^2] overlap bits of every row
+  uint32_t* eta;   // [M][ceil(V/32)] ACU: the root drew eta = -1
+  int32_t* misc;   // [kHouMisc] scan scratch, per-move single-cluster data
+};
+constexpr int kHouMisc = 32 + 3 * kMaxHouMoves;
+
+__host__ __device__ inline size_t hou_lds_bytes(const Geo& g, int M) {
+  size_t o = 0;
+  o = align_up(o + sizeof(uint32_t) * size_t(g.NW) * g.V, 16);
+  o = align_up(o + sizeof(int32_t) * size_t(g.NR) * g.NT, 16);
+  o = align_up(o + sizeof(uint32_t) * size_t(M) * g.V, 16);
+  o = align_up(o + sizeof(uint32_t) * size_t(M) * g.L * g.L, 16);
+  o = align_up(o + sizeof(uint32_t) * size_t(M) * ((g.V + 31) / 32), 16);
+  o = align_up(o + sizeof(int32_t) * kHouMisc, 16);
+  return o;
+}
+__device__ __forceinline__ HouLds hou_view(const Geo& g, int M) {
+  HouLds s;
+  size_t o = 0;
+  s.sp = reinterpret_cast<uint32_t*>(lds_raw + o);
+  o = align_up(o + sizeof(uint32_t) * size_t(g.NW) * g.V, 16);
+  s.cat = reinterpret_cast<int32_t*>(lds_raw + o);
+  o = align_up(o + sizeof(int32_t) * size_t(g.NR) * g.NT, 16);
+  s.lab = reinterpret_cast<uint32_t*>(lds_raw + o);
+  o = align_up(o + sizeof(uint32_t) * size_t(M) * g.V, 16);
+  s.qrow = reinterpret_cast<uint32_t*>(lds_raw + o);
+  o = align_up(o + sizeof(uint32_t) * size_t(M) * g.L * g.L, 16);
+  s.eta = reinterpret_cast<uint32_t*>(lds_raw + o);
+  o = align_up(o + sizeof(uint32_t) * size_t(M) * ((g.V + 31) / 32), 16);
+  s.misc = reinterpret_cast<int32_t*>(lds_raw + o);
+  return s;
 }
 
-// One Houdayer move for every pair p and every k < K_acu.
-template <int CH>
-__device__ __forceinline__ bool houdayer_phase(const Geo& g, int sample, uint32_t t) {
-  const Lds s = lds_view(g, 4);
-  const Own<CH> own(g.V);
+// Bit x set where a run of the row mask q starts (x = 0 always).
+__device__ __forceinline__ uint32_t run_starts(uint32_t q, uint32_t full) { return ((q ^ (q << 1)) | 1u) & full; }
+// Position of the last run start at or below x.
+__device__ __forceinline__ int start_at(uint32_t rs, int x) {
+  return 31 - __builtin_clz(rs & ((2u << x) - 1u));  // 2u << 31 wraps to 0: all bits
+}
+
+// Overlap bits of the sites (x, y, z), x = 0..L-1, of row y + L z.
+__device__ __forceinline__ uint32_t row_overlap(const Geo& g, const uint32_t* sp, int a, int b, int row) {
+  const uint32_t* pa = sp + size_t(word_of(g, a)) * g.V;
+  const uint32_t* pb = sp + size_t(word_of(g, b)) * g.V;
+  const int ba = bit_of(g, a), bb = bit_of(g, b);
+  const int yz = row % g.L + row / g.L, i0 = row * g.L;
+  uint32_t q = 0;
+  for (int x = 0; x < g.L; ++x) {
+    const int j = plane_idx(i0 + x, (x + yz) & 1, g.Vh);
+    q |= (((pa[j] >> ba) ^ (pb[j] >> bb)) & 1u) << x;
+  }
+  return q;
+}
+
+// Joins the runs of row `row` (mask q, starts rs) with those of row `nrow`
+// (mask qn) wherever a bond between the rows has equal overlap at both ends:
+// one union per maximal interval in which both runs stay the same.
+__device__ __forceinline__ void join_rows(const Geo& g, uint32_t* lab, uint32_t q, uint32_t rs, int row, uint32_t qn,
+                                          int nrow, uint32_t full, bool* bad) {
+  const uint32_t rsn = run_starts(qn, full);
+  const uint32_t eq = ~(q ^ qn) & full;
+  uint32_t u = eq & (~(eq << 1) | rs | rsn);
+  while (u) {
+    const int x = __builtin_ctz(u);
+    u &= u - 1u;
+    unite(lab, start_at(rs, x) + g.L * row, start_at(rsn, x) + g.L * nrow, g.V, bad);
+  }
+}
+
+// Flips clones a and b at plane index j; several moves may touch one word at
+// the same time, so the update is atomic.
+__device__ __forceinline__ void flip_pair_atomic(const Geo& g, uint32_t* sp, int a, int b, int j) {
+  const int wa = word_of(g, a), wb = word_of(g, b);
+  const uint32_t ma = 1u << bit_of(g, a), mb = 1u << bit_of(g, b);
+  if (wa == wb) {
+    atomicXor(&sp[size_t(wa) * g.V + j], ma | mb);
+  } else {
+    atomicXor(&sp[size_t(wa) * g.V + j], ma);
+    atomicXor(&sp[size_t(wb) * g.V + j], mb);
+  }
+}
+
+// One Houdayer move for every pair p and every k < K_acu (or, with `labels`,
+// the canonical labels of every such pair into labels [S][NR/2][K_acu][V]),
+// hou_moves moves per pass.
+__device__ bool houdayer_moves(const Geo& g, const HouLds& s, int M, int sample, uint32_t t, int32_t* labels) {
+  const int L = g.L, L2 = L * L, V = g.V;
+  const uint32_t full = L == 32 ? 0xFFFFFFFFu : (1u << L) - 1u;
+  const int n_moves = (g.NR / 2) * g.K_acu;
+  const int eta_words = (V + 31) / 32;
+  const int m = threadIdx.x / L2, row = threadIdx.x % L2;
+  const int y = row % L, z = row / L, i0 = row * L;
   bool bad = false;
-  for (int p = 0; p < g.NR / 2; ++p) {
-    for (int k = 0; k < g.K_acu; ++k) {
-      const int a = s.cat[(2 * p) * g.NT + k], b = s.cat[(2 * p + 1) * g.NT + k];
-      const uint32_t slot = static_cast<uint32_t>(p * g.NT + k);
-      if (g.mode == 0)
-        for (int x = threadIdx.x; x < (g.V + 31) / 32; x += blockDim.x) s.eta[x] = 0u;
-      bad |= label_phase<CH>(g, a, b, g.mode == 0, t, slot, sample);
-      if (g.mode == 0) {
-        // all-cluster update: flip both replicas on clusters whose root drew eta = -1
-        if (own.owns) {
-#pragma unroll
-          for (int j = 0; j < CH; ++j) {
-            const int i = own.first + j;
-            const int r = static_cast<int>(s.lab[i]);
-            if ((s.eta[r >> 5] >> (r & 31)) & 1u) flip_pair(g, s, a, b, plane_idx(i, colour_of(site_of(i, g.L)), g.Vh));
-          }
+  for (int base = 0; base < n_moves; base += M) {
+    const int mv = base + m;
+    const bool active = m < M && mv < n_moves;
+    const int p = active ? mv / g.K_acu : 0, k = active ? mv % g.K_acu : 0;
+    const int a = s.cat[(2 * p) * g.NT + k], b = s.cat[(2 * p + 1) * g.NT + k];
+    const uint32_t slot = static_cast<uint32_t>(p * g.NT + k);
+    uint32_t* lab = s.lab + size_t(active ? m : 0) * V;
+    uint32_t* eta = s.eta + size_t(active ? m : 0) * eta_words;
+    // overlap bits of the row; run starts become singleton roots
+    for (int x = threadIdx.x; x < M * eta_words; x += blockDim.x) s.eta[x] = 0u;
+    uint32_t q = 0, rs = 0;
+    if (active) {
+      q = row_overlap(g, s.sp, a, b, row);
+      s.qrow[m * L2 + row] = q;
+      rs = run_starts(q, full);
+      for (uint32_t r = rs; r; r &= r - 1u) {
+        const int i = i0 + __builtin_ctz(r);
+        lab[i] = static_cast<uint32_t>(i);
+      }
+    }
+    __syncthreads();
+    // unions: the periodic +x bond of the row, then the +y and +z rows
+    if (active) {
+      const int xl = 31 - __builtin_clz(rs);
+      if (xl > 0 && ((q >> (L - 1)) & 1u) == (q & 1u)) unite(lab, i0, i0 + xl, V, &bad);
+      const int ry = (y + 1 == L ? 0 : y + 1) + L * z, rz = y + L * (z + 1 == L ? 0 : z + 1);
+      join_rows(g, lab, q, rs, row, s.qrow[m * L2 + ry], ry, full, &bad);
+      join_rows(g, lab, q, rs, row, s.qrow[m * L2 + rz], rz, full, &bad);
+    }
+    __syncthreads();
+    // roots; under ACU every root draws its eta from the block (ACU, root, slot)
+    if (active) {
+      for (uint32_t r = rs; r; r &= r - 1u) {
+        const int i = i0 + __builtin_ctz(r);
+        const int root = find_root(lab, i, V, &bad);
+        lab[i] = static_cast<uint32_t>(root);
+        if (!labels && g.mode == 0 && root == i) {
+          const Block blk = philox10(ctr_word(i, 0, kAcu), t, slot, sample, g.key0, g.key1);
+          if (blk.w0 >> 31) atomicOr(&eta[i >> 5], 1u << (i & 31));
         }
-      } else {
-        // single cluster: the q = -1 cluster of a uniformly chosen q = -1 site
-        int mine = 0;
-        if (own.owns) {
-#pragma unroll
-          for (int j = 0; j < CH; ++j) mine += s.qb[own.first + j];
-        }
-        int n_minus = 0;
-        const int before = block_exclusive_scan(mine, s.misc, &n_minus);
+      }
+    }
+    if (!labels && g.mode != 0) {
+      // single cluster: the q = -1 cluster of the target-th q = -1 site in
+      // site order, target uniform; per-move counts from one block scan
+      int total = 0;
+      const int cnt = active ? __builtin_popcount(q) : 0;
+      const int before = block_exclusive_scan(cnt, s.misc, &total);  // synchronizes
+      if (active && row == 0) s.misc[32 + m] = before;
+      if (threadIdx.x == 0) s.misc[32 + kMaxHouMoves] = total;
+      __syncthreads();
+      if (active) {
+        const int first = s.misc[32 + m];
+        const int last = (m + 1 < M && base + m + 1 < n_moves) ? s.misc[32 + m + 1] : s.misc[32 + kMaxHouMoves];
+        const int n_minus = last - first;
         if (n_minus > 0) {
           const Block blk = philox10(ctr_word(0, 0, kHseed), t, slot, sample, g.key0, g.key1);
           const int target = static_cast<int>((static_cast<uint64_t>(blk.w0) * static_cast<uint32_t>(n_minus)) >> 32);
-          if (own.owns && target >= before && target < before + mine) {
-            int seen = before;
-#pragma unroll
-            for (int j = 0; j < CH; ++j) {
-              const int i = own.first + j;
-              if (s.qb[i]) {
-                if (seen == target) s.misc[32] = static_cast<int32_t>(s.lab[i]);
-                ++seen;
-              }
-            }
-          }
-          __syncthreads();
-          const int root = s.misc[32];
-          if (own.owns) {
-#pragma unroll
-            for (int j = 0; j < CH; ++j) {
-              const int i = own.first + j;
-              if (static_cast<int>(s.lab[i]) == root) flip_pair(g, s, a, b, plane_idx(i, colour_of(site_of(i, g.L)), g.Vh));
-            }
+          int rank = target - (before - first);
+          if (rank >= 0 && rank < cnt) {
+            uint32_t bits = q;
+            for (; rank > 0; --rank) bits &= bits - 1u;
+            const int x = __builtin_ctz(bits);
+            s.misc[32 + kMaxHouMoves + 1 + m] = static_cast<int32_t>(lab[i0 + start_at(rs, x)]);
           }
         }
       }
       __syncthreads();
-    }
-  }
-  return bad;
-}
-
-template <int CH>
-__device__ __forceinline__ bool labels_out_phase(const Geo& g, int sample, int32_t* labels) {
-  const Lds s = lds_view(g, 4);
-  bool bad = false;
-  for (int p = 0; p < g.NR / 2; ++p)
-    for (int k = 0; k < g.K_acu; ++k) {
-      bad |= label_phase<CH>(g, s.cat[(2 * p) * g.NT + k], s.cat[(2 * p + 1) * g.NT + k]);
-      int32_t* out = labels + ((size_t(sample) * (g.NR / 2) + p) * g.K_acu + k) * g.V;
-      for (int x = threadIdx.x; x < g.V; x += blockDim.x) out[x] = static_cast<int32_t>(s.lab[x]);
+      if (active) {
+        const int first = s.misc[32 + m];
+        const int last = (m + 1 < M && base + m + 1 < n_moves) ? s.misc[32 + m + 1] : s.misc[32 + kMaxHouMoves];
+        if (last > first) {
+          const uint32_t root = static_cast<uint32_t>(s.misc[32 + kMaxHouMoves + 1 + m]);
+          for (uint32_t r = rs; r; r &= r - 1u) {
+            const int xs = __builtin_ctz(r);
+            if (lab[i0 + xs] != root) continue;
+            const uint32_t rest = r & (r - 1u);
+            const int xe = rest ? __builtin_ctz(rest) : L;
+            for (int x = xs; x < xe; ++x) flip_pair_atomic(g, s.sp, a, b, plane_idx(i0 + x, (x + y + z) & 1, g.Vh));
+          }
+        }
+      }
+    } else {
       __syncthreads();
+      if (active) {
+        if (labels) {
+          int32_t* out = labels + ((size_t(sample) * (g.NR / 2) + p) * g.K_acu + k) * V;
+          for (int x = 0; x < L; ++x) out[i0 + x] = static_cast<int32_t>(lab[i0 + start_at(rs, x)]);
+        } else {
+          // all-cluster update: flip both replicas on clusters whose root drew eta = -1
+          for (uint32_t r = rs; r; r &= r - 1u) {
+            const int xs = __builtin_ctz(r);
+            const uint32_t root = lab[i0 + xs];
+            if (!((eta[root >> 5] >> (root & 31)) & 1u)) continue;
+            const uint32_t rest = r & (r - 1u);
+            const int xe = rest ? __builtin_ctz(rest) : L;
+            for (int x = xs; x < xe; ++x) flip_pair_atomic(g, s.sp, a, b, plane_idx(i0 + x, (x + y + z) & 1, g.Vh));
+          }
+        }
+      }
     }
+    __syncthreads();
+  }
   return bad;
 }
 
@@ -1027,28 +1089,34 @@ __device__ __forceinline__ void measure_phase(const Geo& g, const State& st, con
 // changed.  One workgroup per sample; run.sample_begin offsets the grid.
 
 // Load every spin word and the permutation into LDS.
-__device__ __forceinline__ void load_spins(const Geo& g, const Lds& s, const State& st, int sample) {
+__device__ __forceinline__ void load_spins(const Geo& g, uint32_t* sp, int32_t* cat, const State& st, int sample) {
   const size_t words = size_t(g.NW) * g.V;
-  const uint4* src = reinterpret_cast<const uint4*>(st.spins + size_t(sample) * words);
-  uint4* dst = reinterpret_cast<uint4*>(s.sp);
   if (words % 4 == 0) {
+    const uint4* src = reinterpret_cast<const uint4*>(st.spins + size_t(sample) * words);
+    uint4* dst = reinterpret_cast<uint4*>(sp);
     for (size_t x = threadIdx.x; x < words / 4; x += blockDim.x) dst[x] = src[x];
   } else {
     const uint32_t* gsp = st.spins + size_t(sample) * words;
-    for (size_t x = threadIdx.x; x < words; x += blockDim.x) s.sp[x] = gsp[x];
+    for (size_t x = threadIdx.x; x < words; x += blockDim.x) sp[x] = gsp[x];
   }
-  for (int x = threadIdx.x; x < g.NR * g.NT; x += blockDim.x) s.cat[x] = st.clone_at[size_t(sample) * g.NR * g.NT + x];
+  for (int x = threadIdx.x; x < g.NR * g.NT; x += blockDim.x) cat[x] = st.clone_at[size_t(sample) * g.NR * g.NT + x];
 }
-__device__ __forceinline__ void store_spins(const Geo& g, const Lds& s, const State& st, int sample) {
+__device__ __forceinline__ void load_spins(const Geo& g, const Lds& s, const State& st, int sample) {
+  load_spins(g, s.sp, s.cat, st, sample);
+}
+__device__ __forceinline__ void store_spins(const Geo& g, const uint32_t* sp, const State& st, int sample) {
   const size_t words = size_t(g.NW) * g.V;
   if (words % 4 == 0) {
     uint4* dst = reinterpret_cast<uint4*>(st.spins + size_t(sample) * words);
-    const uint4* src = reinterpret_cast<const uint4*>(s.sp);
+    const uint4* src = reinterpret_cast<const uint4*>(sp);
     for (size_t x = threadIdx.x; x < words / 4; x += blockDim.x) dst[x] = src[x];
   } else {
     uint32_t* osp = st.spins + size_t(sample) * words;
-    for (size_t x = threadIdx.x; x < words; x += blockDim.x) osp[x] = s.sp[x];
+    for (size_t x = threadIdx.x; x < words; x += blockDim.x) osp[x] = sp[x];
   }
+}
+__device__ __forceinline__ void store_spins(const Geo& g, const Lds& s, const State& st, int sample) {
+  store_spins(g, s.sp, st, sample);
 }
 
 template <typename FP, int CH>
@@ -1065,17 +1133,18 @@ __global__ __launch_bounds__(kMaxThreads) void sweep_kernel(Geo g, State st, Run
   store_spins(g, s, st, sample);
 }
 
-template <int CH>
+// Houdayer moves (or cluster labels) of one sample per workgroup; the LDS
+// layout depends on run.hou_moves, the number of moves labelled at once.
 __global__ __launch_bounds__(kMaxThreads) void houdayer_kernel(Geo g, State st, Run run) {
   const int sample = run.sample_begin + blockIdx.x;
   if (sample >= g.S) return;
-  const Lds s = lds_view(g, 4);
-  load_spins(g, s, st, sample);
+  const HouLds s = hou_view(g, run.hou_moves);
+  load_spins(g, s.sp, s.cat, st, sample);
   __syncthreads();
-  const bool bad = (run.phases & kPhaseLabels) ? labels_out_phase<CH>(g, sample, run.labels)
-                                                : houdayer_phase<CH>(g, sample, *st.t_dev);
-  if (!(run.phases & kPhaseLabels)) store_spins(g, s, st, sample);
-  if (bad && threadIdx.x == 0) atomicOr(&st.status[sample], kStatusUnionBound);
+  const bool labels = (run.phases & kPhaseLabels) != 0;
+  const bool bad = houdayer_moves(g, s, run.hou_moves, sample, *st.t_dev, labels ? run.labels : nullptr);
+  if (!labels) store_spins(g, s.sp, st, sample);
+  if (bad) atomicOr(&st.status[sample], kStatusUnionBound);
 }
 
 template <typename FP, int CH>
@@ -1155,7 +1224,7 @@ template <typename FP, int CH>
 hipError_t prepare_t(size_t lds) {
   hipError_t e;
   if ((e = set_lds(sweep_kernel<FP, CH>, lds)) != hipSuccess) return e;
-  if ((e = set_lds(houdayer_kernel<CH>, lds)) != hipSuccess) return e;
+  if ((e = set_lds(houdayer_kernel, lds)) != hipSuccess) return e;
   if ((e = set_lds(pt_kernel<FP, CH>, lds)) != hipSuccess) return e;
   return set_lds(measure_kernel<FP, CH>, lds);
 }
@@ -1171,9 +1240,10 @@ hipError_t launch_t(const Geo& g, const State& st, const Obs& ob, const Run& run
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   if (run.phases & (kPhaseHoudayer | kPhaseLabels)) {
-    auto k = houdayer_kernel<CH>;
-    const size_t l4 = plan_lds(g, 4).total;
-    hipLaunchKernelGGL(k, dim3(n_blocks), dim3(threads), l4, stream, g, st, run);
+    Run r = run;
+    r.hou_moves = houdayer_moves_per_pass(g, threads);
+    if (r.hou_moves < 1) return hipErrorInvalidConfiguration;
+    hipLaunchKernelGGL(houdayer_kernel, dim3(n_blocks), dim3(threads), hou_lds_bytes(g, r.hou_moves), stream, g, st, r);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   if (run.phases & kPhasePT) {
@@ -1191,7 +1261,22 @@ hipError_t launch_t(const Geo& g, const State& st, const Obs& ob, const Run& run
 
 }  // namespace
 
-size_t lds_bytes(const Geo& g, int fp_bytes) { return plan_lds(g, fp_bytes).total; }
+size_t lds_bytes(const Geo& g, int fp_bytes) {
+  const size_t phases = plan_lds(g, fp_bytes).total, hou = hou_lds_bytes(g, 1);
+  return phases > hou ? phases : hou;
+}
+
+// Houdayer moves labelled at once: one x-row per work-item, as many moves as
+// the workgroup has rows for and LDS holds (at least one: a workgroup has at
+// least V/8 >= L^2 work-items, rounded up to whole waves).
+int houdayer_moves_per_pass(const Geo& g, int threads) {
+  const int n_moves = (g.NR / 2) * g.K_acu;
+  int M = threads / (g.L * g.L);
+  if (M > n_moves) M = n_moves;
+  if (M > kMaxHouMoves) M = kMaxHouMoves;
+  while (M > 1 && hou_lds_bytes(g, M) > kLdsMax) --M;
+  return M;
+}
 
 hipError_t launch_emcs(int precision, const Geo& g, const State& st, const Obs& ob, const Run& run,
                        const Shape& sh, int n_blocks, hipStream_t stream) {
