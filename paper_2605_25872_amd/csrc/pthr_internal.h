@@ -67,6 +67,7 @@ struct Run {
   float early_beta;   // Metropolis tests of clones with beta >= early_beta use the exp early-out
   int32_t* labels;    // kPhaseLabels output [S][NR/2][K_acu][V]
   int hou_moves;      // Houdayer moves labelled at once (set by the launcher)
+  int meas_k;         // temperatures per pass of the row-parallel overlaps (0: per-site form)
 };
 
 // Device status bits (per sample).
@@ -82,6 +83,7 @@ constexpr int kMaxHouMoves = 16;        // Houdayer moves labelled at once, at m
 
 size_t lds_bytes(const Geo& g, int fp_bytes);
 int houdayer_moves_per_pass(const Geo& g, int threads);
+int measure_rows_per_pass(const Geo& g, int threads, int fp_bytes);
 hipError_t launch_emcs(int precision, const Geo& g, const State& st, const Obs& ob, const Run& run,
                        const Shape& sh, int n_blocks, hipStream_t stream);
 hipError_t launch_init(const Geo& g, const State& st, hipStream_t stream);

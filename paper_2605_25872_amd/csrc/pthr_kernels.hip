@@ -708,18 +708,19 @@ __device__ __forceinline__ int start_at(uint32_t rs, int x) {
   return 31 - __builtin_clz(rs & ((2u << x) - 1u));  // 2u << 31 wraps to 0: all bits
 }
 
-// Overlap bits of the sites (x, y, z), x = 0..L-1, of row y + L z.
-__device__ __forceinline__ uint32_t row_overlap(const Geo& g, const uint32_t* sp, int a, int b, int row) {
-  const uint32_t* pa = sp + size_t(word_of(g, a)) * g.V;
-  const uint32_t* pb = sp + size_t(word_of(g, b)) * g.V;
-  const int ba = bit_of(g, a), bb = bit_of(g, b);
+// Spin bits of clone c at the sites (x, y, z), x = 0..L-1, of row y + L z
+// (bit x set: spin down).
+__device__ __forceinline__ uint32_t clone_row(const Geo& g, const uint32_t* sp, int c, int row) {
+  const uint32_t* pl = sp + size_t(word_of(g, c)) * g.V;
+  const int b = bit_of(g, c);
   const int yz = row % g.L + row / g.L, i0 = row * g.L;
-  uint32_t q = 0;
-  for (int x = 0; x < g.L; ++x) {
-    const int j = plane_idx(i0 + x, (x + yz) & 1, g.Vh);
-    q |= (((pa[j] >> ba) ^ (pb[j] >> bb)) & 1u) << x;
-  }
-  return q;
+  uint32_t m = 0;
+  for (int x = 0; x < g.L; ++x) m |= ((pl[plane_idx(i0 + x, (x + yz) & 1, g.Vh)] >> b) & 1u) << x;
+  return m;
+}
+// Overlap bits of a row: bit x set where q = s^a s^b = -1.
+__device__ __forceinline__ uint32_t row_overlap(const Geo& g, const uint32_t* sp, int a, int b, int row) {
+  return clone_row(g, sp, a, row) ^ clone_row(g, sp, b, row);
 }
 
 // Joins the runs of row `row` (mask q, starts rs) with those of row `nrow`
@@ -991,60 +992,109 @@ __device__ __forceinline__ void pt_phase(const Geo& g, const State& st, int samp
 }
 
 // ------------------------------------------------------------------ observables
+// Overlaps of every replica pair at every temperature, row-parallel: KC
+// temperatures at a time, one work-item per (temperature, x-row).  The row
+// masks of the N_r clones at each temperature go through LDS (cm,
+// [KC][NR][L^2]) so that every row meets its +y and +z neighbour rows.  Per
+// pair and row, with q the overlap bits (1: q_i = -1), the row adds
+// 2(L - |q|) to Q' and 2(3L - |q ^ q(+x)| - |q ^ q(+y)| - |q ^ q(+z)|) to Q_l'
+// (|.| = popcount), packed into s.qacc as in the per-site form.
+__device__ void overlaps_rows(const Geo& g, const Lds& s, uint32_t* cm, int KC) {
+  const int L = g.L, L2 = L * L, NR = g.NR, NT = g.NT, npairs = NR * (NR - 1) / 2;
+  const uint32_t full = L == 32 ? 0xFFFFFFFFu : (1u << L) - 1u;
+  const int kk = threadIdx.x / L2, row = threadIdx.x % L2;
+  const int y = row % L, z = row / L;
+  const int ry = (y + 1 == L ? 0 : y + 1) + L * z, rz = y + L * (z + 1 == L ? 0 : z + 1);
+  const bool wave_one_k = L2 % kWave == 0;  // every wave's work-items share kk
+  for (int k0 = 0; k0 < NT; k0 += KC) {
+    const int k = k0 + kk;
+    const bool active = kk < KC && k < NT;
+    if (active)
+      for (int r = 0; r < NR; ++r) cm[(kk * NR + r) * L2 + row] = clone_row(g, s.sp, s.cat[r * NT + k], row);
+    __syncthreads();
+    if (active) {
+      const uint32_t* c0 = cm + size_t(kk) * NR * L2;
+      int pair = 0;
+      for (int a = 0; a < NR; ++a) {
+        const uint32_t ma = c0[a * L2 + row], may = c0[a * L2 + ry], maz = c0[a * L2 + rz];
+        for (int b = a + 1; b < NR; ++b, ++pair) {
+          const uint32_t q = ma ^ c0[b * L2 + row];
+          const uint32_t qy = may ^ c0[b * L2 + ry], qz = maz ^ c0[b * L2 + rz];
+          const uint32_t qx = ((q >> 1) | (q << (L - 1))) & full;  // bit x: q at x + 1 (periodic)
+          const int nq = __builtin_popcount(q);
+          const int nd = __builtin_popcount(q ^ qx) + __builtin_popcount(q ^ qy) + __builtin_popcount(q ^ qz);
+          uint32_t packed = static_cast<uint32_t>(2 * (L - nq)) + (static_cast<uint32_t>(2 * (3 * L - nd)) << 16);
+          if (wave_one_k) {
+            packed = static_cast<uint32_t>(wave_sum_int(static_cast<int>(packed)));
+            if (lane_id() == 0) atomicAdd(reinterpret_cast<uint32_t*>(&s.qacc[k * npairs + pair]), packed);
+          } else {
+            atomicAdd(reinterpret_cast<uint32_t*>(&s.qacc[k * npairs + pair]), packed);
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
 template <typename FP, int CH>
-__device__ __forceinline__ void measure_phase(const Geo& g, const State& st, const Obs& ob, int sample) {
+__device__ __forceinline__ void measure_phase(const Geo& g, const State& st, const Obs& ob, int sample, int KC) {
   const Lds s = lds_view(g, sizeof(FP));
   energy_phase<FP, CH>(g, static_cast<const FP*>(st.J) + size_t(sample) * 3 * g.V);
   const Own<CH> own(g.V);
   const int NT = g.NT, NR = g.NR, npairs = NR * (NR - 1) / 2;
   for (int x = threadIdx.x; x < NT * npairs; x += blockDim.x) s.qacc[x] = 0;
   __syncthreads();
-  // Per site and temperature, the spins of the N_r clones there (bit r) and of
-  // their three forward neighbours.  Each site adds q_i + 1 in {0, 2} to Q' and
-  // sum_d (q_i q_j + 1) in {0..6} to Q_l', packed as Q' | Q_l' << 16 (both
-  // fields stay below 2^16 for V <= 8192); Q = Q' - V, Q_l = Q_l' - 3V.
-  for (int k = 0; k < NT; ++k) {
-    uint32_t m[CH], mn[CH][3];
+  if (KC > 0) {
+    overlaps_rows(g, s, reinterpret_cast<uint32_t*>(lds_raw + plan_lds(g, sizeof(FP)).total), KC);
+  } else {
+    // Per site and temperature, the spins of the N_r clones there (bit r) and of
+    // their three forward neighbours.  Each site adds q_i + 1 in {0, 2} to Q' and
+    // sum_d (q_i q_j + 1) in {0..6} to Q_l', packed as Q' | Q_l' << 16 (both
+    // fields stay below 2^16 for V <= 8192); Q = Q' - V, Q_l = Q_l' - 3V.
+    for (int k = 0; k < NT; ++k) {
+      uint32_t m[CH], mn[CH][3];
 #pragma unroll
-    for (int j = 0; j < CH; ++j) {
-      m[j] = 0;
-      mn[j][0] = mn[j][1] = mn[j][2] = 0;
-      if (own.owns) {
-        const Site sti = site_of(own.first + j, g.L);
-        const int col = colour_of(sti);
-        const int ji = plane_idx(sti.i, col, g.Vh);
-        int jn[3];
-#pragma unroll
-        for (int d = 0; d < 3; ++d) jn[d] = plane_idx(neighbour(sti, 2 * d, g.L), col ^ 1, g.Vh);
-        for (int r = 0; r < NR; ++r) {
-          const int c = s.cat[r * NT + k];
-          const uint32_t* plane = s.sp + size_t(word_of(g, c)) * g.V;
-          const int b = bit_of(g, c);
-          m[j] |= ((plane[ji] >> b) & 1u) << r;
-#pragma unroll
-          for (int d = 0; d < 3; ++d) mn[j][d] |= ((plane[jn[d]] >> b) & 1u) << r;
-        }
-      }
-    }
-    int pair = 0;
-    for (int a = 0; a < NR; ++a)
-      for (int b = a + 1; b < NR; ++b, ++pair) {
-        uint32_t packed = 0;
+      for (int j = 0; j < CH; ++j) {
+        m[j] = 0;
+        mn[j][0] = mn[j][1] = mn[j][2] = 0;
         if (own.owns) {
+          const Site sti = site_of(own.first + j, g.L);
+          const int col = colour_of(sti);
+          const int ji = plane_idx(sti.i, col, g.Vh);
+          int jn[3];
 #pragma unroll
-          for (int j = 0; j < CH; ++j) {
-            const uint32_t qi = ((m[j] >> a) ^ (m[j] >> b)) & 1u;  // 1: q_i = -1
-            packed += 2u - 2u * qi;
+          for (int d = 0; d < 3; ++d) jn[d] = plane_idx(neighbour(sti, 2 * d, g.L), col ^ 1, g.Vh);
+          for (int r = 0; r < NR; ++r) {
+            const int c = s.cat[r * NT + k];
+            const uint32_t* plane = s.sp + size_t(word_of(g, c)) * g.V;
+            const int b = bit_of(g, c);
+            m[j] |= ((plane[ji] >> b) & 1u) << r;
 #pragma unroll
-            for (int d = 0; d < 3; ++d) {
-              const uint32_t qn = ((mn[j][d] >> a) ^ (mn[j][d] >> b)) & 1u;
-              packed += (2u - 2u * (qi ^ qn)) << 16;
-            }
+            for (int d = 0; d < 3; ++d) mn[j][d] |= ((plane[jn[d]] >> b) & 1u) << r;
           }
         }
-        packed = static_cast<uint32_t>(wave_sum_int(static_cast<int>(packed)));
-        if (lane_id() == 0 && packed != 0) atomicAdd(reinterpret_cast<uint32_t*>(&s.qacc[k * npairs + pair]), packed);
       }
+      int pair = 0;
+      for (int a = 0; a < NR; ++a)
+        for (int b = a + 1; b < NR; ++b, ++pair) {
+          uint32_t packed = 0;
+          if (own.owns) {
+#pragma unroll
+            for (int j = 0; j < CH; ++j) {
+              const uint32_t qi = ((m[j] >> a) ^ (m[j] >> b)) & 1u;  // 1: q_i = -1
+              packed += 2u - 2u * qi;
+#pragma unroll
+              for (int d = 0; d < 3; ++d) {
+                const uint32_t qn = ((mn[j][d] >> a) ^ (mn[j][d] >> b)) & 1u;
+                packed += (2u - 2u * (qi ^ qn)) << 16;
+              }
+            }
+          }
+          packed = static_cast<uint32_t>(wave_sum_int(static_cast<int>(packed)));
+          if (lane_id() == 0 && packed != 0) atomicAdd(reinterpret_cast<uint32_t*>(&s.qacc[k * npairs + pair]), packed);
+        }
+    }
   }
   __syncthreads();
   const double V = static_cast<double>(g.V);
@@ -1175,7 +1225,7 @@ __global__ __launch_bounds__(kMaxThreads) void measure_kernel(Geo g, State st, O
   if (sample >= g.S) return;
   load_spins(g, lds_view(g, sizeof(FP)), st, sample);
   __syncthreads();
-  measure_phase<FP, CH>(g, st, ob, sample);
+  measure_phase<FP, CH>(g, st, ob, sample, run.meas_k);
 }
 
 // Initial spins: bit = sign bit of word 0 of the INIT block of (site, clone).
@@ -1253,7 +1303,10 @@ hipError_t launch_t(const Geo& g, const State& st, const Obs& ob, const Run& run
   }
   if (run.phases & kPhaseMeasure) {
     auto k = measure_kernel<FP, CH>;
-    hipLaunchKernelGGL(k, dim3(n_blocks), dim3(threads), lds, stream, g, st, ob, run);
+    Run r = run;
+    r.meas_k = measure_rows_per_pass(g, threads, sizeof(FP));
+    const size_t lm = lds + (r.meas_k > 0 ? sizeof(uint32_t) * size_t(r.meas_k) * g.NR * g.L * g.L : 0);
+    hipLaunchKernelGGL(k, dim3(n_blocks), dim3(threads), lm, stream, g, st, ob, r);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   return e;
@@ -1269,6 +1322,17 @@ size_t lds_bytes(const Geo& g, int fp_bytes) {
 // Houdayer moves labelled at once: one x-row per work-item, as many moves as
 // the workgroup has rows for and LDS holds (at least one: a workgroup has at
 // least V/8 >= L^2 work-items, rounded up to whole waves).
+// Temperatures whose overlaps are taken at once by the row-parallel form: one
+// x-row per work-item and the clones' row masks in LDS after the phase plan;
+// 0 selects the per-site form.
+int measure_rows_per_pass(const Geo& g, int threads, int fp_bytes) {
+  const size_t base = plan_lds(g, fp_bytes).total, per_k = sizeof(uint32_t) * size_t(g.NR) * g.L * g.L;
+  int KC = threads / (g.L * g.L);
+  if (KC > g.NT) KC = g.NT;
+  while (KC > 0 && base + per_k * KC > kLdsMax) --KC;
+  return KC;
+}
+
 int houdayer_moves_per_pass(const Geo& g, int threads) {
   const int n_moves = (g.NR / 2) * g.K_acu;
   int M = threads / (g.L * g.L);
