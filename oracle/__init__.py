@@ -87,8 +87,8 @@ def _lib() -> ctypes.CDLL:
     lib.oracle_uniform53.argtypes = [ctypes.c_uint32, ctypes.c_uint32]
     lib.oracle_uniform32.restype = ctypes.c_float
     lib.oracle_uniform32.argtypes = [ctypes.c_uint32]
-    lib.oracle_pexp32.restype = ctypes.c_float
-    lib.oracle_pexp32.argtypes = [ctypes.c_float]
+    lib.oracle_pexp2_32.restype = ctypes.c_float
+    lib.oracle_pexp2_32.argtypes = [ctypes.c_float]
     lib.oracle_energy.restype = ctypes.c_double
     lib.oracle_energy.argtypes = [vp, i32, i32]
     lib.oracle_delta_e.restype = ctypes.c_double
@@ -123,8 +123,9 @@ def uniform32(w: int) -> np.float32:
     return np.float32(_lib().oracle_uniform32(w))
 
 
-def pexp32(x: float) -> np.float32:
-    return np.float32(_lib().oracle_pexp32(float(np.float32(x))))
+def pexp2_32(t: float) -> np.float32:
+    """FP32 form of the Metropolis exponential: 2^t (0 below t = -124)."""
+    return np.float32(_lib().oracle_pexp2_32(float(np.float32(t))))
 
 
 class Observables:

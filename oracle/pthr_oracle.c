@@ -52,7 +52,7 @@ struct oracle_ctx {
   double *J;          /* [S][3][V]                                                       */
   float *J32;         /* [S][3][V] = (float)J, FP32 form only                            */
   double *T, *beta;   /* [N_T]                                                           */
-  float *beta32;      /* [N_T] = (float)beta                                             */
+  float *bl32;        /* [N_T] = (float)(beta log2 e), the FP32 form's Metropolis factor  */
   int8_t *spins;      /* [S][C][V]                                                       */
   int32_t *clone_at;  /* [S][N_r][N_T]: PT clone id at temperature k of group r          */
   int32_t *er_head;   /* [S][N_r]: oldest reservoir slot of group r                      */
@@ -117,9 +117,7 @@ float oracle_uniform32(uint32_t w) { return (float)w * 0x1p-32f; }
 static const double LOG2E = 0x1.71547652b82fep+0;   /* RN(1/ln 2)                      */
 static const double LN2_HI = 0x1.62e42feep-1;       /* ln 2 truncated to 32 bits       */
 static const double LN2_LO = 0x1.a39ef35793c76p-33; /* RN(ln 2 - LN2_HI)               */
-static const float LOG2E_F = 0x1.715476p+0f;        /* RN_f(1/ln 2)                    */
-static const float LN2_HI_F = 0x1.62e4p-1f;         /* ln 2 truncated to 16 bits       */
-static const float LN2_LO_F = 0x1.7f7d1cp-20f;      /* RN_f(ln 2 - LN2_HI_F)           */
+static const double LN2_D = 0x1.62e42fefa39efp-1;   /* RN(ln 2)                        */
 
 double oracle_pexp(double x) {
   if (x < -708.0) return 0.0;
@@ -136,17 +134,23 @@ double oracle_pexp(double x) {
   return ldexp(p, (int)k);
 }
 
-float oracle_pexp32(float x) {
-  if (x < -86.0f) return 0.0f;
-  float k = nearbyintf(x * LOG2E_F);
-  float r = fmaf(-k, LN2_HI_F, x);
-  r = fmaf(-k, LN2_LO_F, r);
-  float fact = 5040.0f; /* 7! */
-  float p = 1.0f / fact;
-  for (int n = 6; n >= 0; --n) {
-    fact /= (float)(n + 1);
-    p = fmaf(p, r, 1.0f / fact);
+/* FP32 form of the Metropolis exponential, in base 2: 2^t for
+ * t = -(beta log2(e)) dE.  t = k + f with k = rint(t) and f = t - k (exact,
+ * |f| <= 1/2); 2^f = e^(f ln 2) by its Taylor polynomial of degree 7, the
+ * coefficients (ln 2)^n / n! computed in double and rounded to float, Horner
+ * with fma; then 2^k.  0 below t = -124. */
+float oracle_pexp2_32(float t) {
+  if (t < -124.0f) return 0.0f;
+  float coef[8];
+  double v = 1.0;
+  for (int n = 0; n <= 7; ++n) {
+    if (n > 0) v *= LN2_D / n;
+    coef[n] = (float)v;
   }
+  float k = nearbyintf(t);
+  float f = t - k;
+  float p = coef[7];
+  for (int n = 6; n >= 0; --n) p = fmaf(p, f, coef[n]);
   return ldexpf(p, (int)k);
 }
 
@@ -217,7 +221,7 @@ oracle_ctx *oracle_create(const oracle_params *p, char *err, size_t err_len) {
   c->J32 = (float *)calloc((size_t)S * 3 * c->V, sizeof(float));
   c->T = (double *)calloc(NT, sizeof(double));
   c->beta = (double *)calloc(NT, sizeof(double));
-  c->beta32 = (float *)calloc(NT, sizeof(float));
+  c->bl32 = (float *)calloc(NT, sizeof(float));
   c->spins = (int8_t *)calloc((size_t)S * c->C * c->V, 1);
   c->clone_at = (int32_t *)calloc((size_t)S * NR * NT, sizeof(int32_t));
   c->er_head = (int32_t *)calloc((size_t)S * NR, sizeof(int32_t));
@@ -233,7 +237,7 @@ oracle_ctx *oracle_create(const oracle_params *p, char *err, size_t err_len) {
 void oracle_destroy(oracle_ctx *c) {
   if (!c) return;
   free(c->nbr); free(c->parity); free(c->J); free(c->J32); free(c->T); free(c->beta);
-  free(c->beta32); free(c->spins); free(c->clone_at); free(c->er_head); free(c->pt_last);
+  free(c->bl32); free(c->spins); free(c->clone_at); free(c->er_head); free(c->pt_last);
   free(c->pt_count); free(c->pt_energy); free(c->rt_state); free(c->rt_count);
   free(c);
 }
@@ -256,7 +260,7 @@ int oracle_init_samples(oracle_ctx *c, const double *J, const double *T) {
   for (int k = 0; k < NT; ++k) {
     c->T[k] = T[k];
     c->beta[k] = 1.0 / T[k];
-    c->beta32[k] = (float)c->beta[k];
+    c->bl32[k] = (float)(c->beta[k] * LOG2E); /* FP32 Metropolis: beta log2(e) */
   }
   /* Random initial spins: sign bit of the first word of the INIT block. */
   for (int s = 0; s < S; ++s)
@@ -329,7 +333,8 @@ static void metropolis_attempt(oracle_ctx *c, int s, int clone, int i, int k, in
     draw(c, PURPOSE_METRO, (uint32_t)i, (uint32_t)m, (uint32_t)c->t, (uint32_t)(n / 4), s, w);
     float u = oracle_uniform32(w[n % 4]);
     float dE = delta_e32(c, s, clone, i);
-    accept = (dE <= 0.0f) || (u < oracle_pexp32(-(c->beta32[k] * dE)));
+    float t = -(c->bl32[k] * dE);
+    accept = (t >= -124.0f) && (u <= oracle_pexp2_32(t));
   }
   if (accept) sp[i] = (int8_t)-sp[i];
 }

@@ -29,9 +29,12 @@
  *   (site | m<<16 | purpose<<24, t, slot, sample) and key (seed lo, seed hi).
  *
  * Precision: ORACLE_FP64 computes local fields and the Metropolis exponent in
- * double.  ORACLE_FP32 computes couplings, local fields and the Metropolis
- * exponent in float, as the paper's FP32 form of the GPU path; energies, the PT
- * exponent and all observable sums stay double in both forms.
+ * double: accept iff dE <= 0 or u < exp(-beta dE).  ORACLE_FP32 computes
+ * couplings, local fields and the Metropolis exponent in float, as the FP32
+ * form of the GPU path, with the exponent in base 2: t = -(beta log2 e) dE
+ * (beta log2 e rounded to float once per temperature), accept iff t >= -124
+ * and u <= 2^t, which accepts every dE <= 0.  Energies, the PT exponent and
+ * all observable sums stay double in both forms.
  */
 #ifndef PTHR_ORACLE_H
 #define PTHR_ORACLE_H
@@ -110,7 +113,7 @@ void oracle_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t
 double oracle_pexp(double x);
 double oracle_uniform53(uint32_t lo, uint32_t hi);
 float oracle_uniform32(uint32_t w);
-float oracle_pexp32(float x);
+float oracle_pexp2_32(float t); /* FP32 form: 2^t, 0 below t = -124 */
 double oracle_energy(const oracle_ctx *c, int s, int clone);
 double oracle_delta_e(const oracle_ctx *c, int s, int clone, int site);
 int oracle_num_threads(void);

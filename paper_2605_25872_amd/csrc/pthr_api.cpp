@@ -23,6 +23,7 @@ namespace {
 constexpr size_t kLdsLimit = pthr::kLdsMax;
 constexpr uint64_t kBlobMagic = 0x5054485253544154ull;  // "PTHRSTAT"
 constexpr int kMaxGroup = 64;  // contexts per group
+constexpr double kLog2e = 0x1.71547652b82fep+0;  // RN(log2 e)
 
 size_t align256(size_t v) { return (v + 255) / 256 * 256; }
 
@@ -208,7 +209,9 @@ struct pthr_ctx {
     const pthr::Obs ob = obs(d_obs);
     const int per = sch.samples_per_launch > 0 ? sch.samples_per_launch : p.n_samples;
     // exp early-out for clones colder than exp_early_out/1000 (0 = never)
-    run.early_beta = sch.exp_early_out > 0 ? static_cast<float>(1000.0 / sch.exp_early_out) : 3.0e38f;
+    // (the FP32 form keeps beta log2 e per clone)
+    const double unit = p.precision == PTHR_FP32 ? kLog2e : 1.0;
+    run.early_beta = sch.exp_early_out > 0 ? static_cast<float>(1000.0 / sch.exp_early_out * unit) : 3.0e38f;
     for (int s0 = 0; s0 < p.n_samples; s0 += per) {
       run.sample_begin = s0;
       const int nb = std::min(per, p.n_samples - s0);
@@ -385,7 +388,7 @@ int pthr_init_samples(pthr_ctx* ctx, const double* J_host, const double* T_host,
   std::vector<float> b32(NT);
   for (int k = 0; k < NT; ++k) {
     b64[k] = 1.0 / T_host[k];
-    b32[k] = static_cast<float>(b64[k]);
+    b32[k] = static_cast<float>(b64[k] * kLog2e);  // the FP32 form's Metropolis factor beta log2 e
   }
   int K = 0;
   while (K < NT && T_host[K] < p.t_acu) ++K;

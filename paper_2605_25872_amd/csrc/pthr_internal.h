@@ -48,8 +48,9 @@ struct State {
   uint64_t* rt_count;  // [S]
   uint32_t* status;    // [S]
   const double* beta64;  // [NT]
-  const float* beta32;   // [NT]
-  void* beta_clone;      // [S][C] inverse temperature of every clone (FP), kept by the PT kernel
+  const float* beta32;   // [NT] FP32 form's Metropolis factor (float)(beta log2 e)
+  void* beta_clone;      // [S][C] Metropolis factor of every clone (FP64: beta; FP32: beta log2 e),
+                         // kept by the PT kernel
 };
 
 struct Obs {

@@ -116,35 +116,35 @@ __device__ __forceinline__ double exp_neg64(double x) {
   return exp_poly64(x, __builtin_rint(x * 0x1.71547652b82fep+0));
 }
 
-// FP32 form: same reduction with a 16-bit head, degree-7 polynomial.
-__device__ __forceinline__ float exp_poly32(float x, float k) {
-  float r = __builtin_fmaf(-k, 0x1.62e4p-1f, x);
-  r = __builtin_fmaf(-k, 0x1.7f7d1cp-20f, r);
-  float p = 0x1.a01a02p-13f;              // 1/7!
-  p = __builtin_fmaf(p, r, 0x1.6c16c2p-10f); // 1/6!
-  p = __builtin_fmaf(p, r, 0x1.111112p-7f);  // 1/5!
-  p = __builtin_fmaf(p, r, 0x1.555556p-5f);  // 1/4!
-  p = __builtin_fmaf(p, r, 0x1.555556p-3f);  // 1/3!
-  p = __builtin_fmaf(p, r, 0x1p-1f);         // 1/2!
-  p = __builtin_fmaf(p, r, 1.0f);            // 1/1!
-  p = __builtin_fmaf(p, r, 1.0f);            // 1/0!
+// FP32 form, in base 2: 2^t for t = -(beta log2 e) dE.  t = k + f with
+// k = rint(t) and f = t - k (exact, |f| <= 1/2); 2^f = e^(f ln 2) by its
+// Taylor polynomial of degree 7 (coefficients (ln 2)^n / n! rounded to float),
+// Horner with fused multiply-adds, then 2^k.  The result lies strictly inside
+// (2^(k-1), 2^(k+1)).
+__device__ __forceinline__ float exp2_poly32(float f, float k) {
+  float p = 0x1.ffcbfcp-17f;                 // (ln 2)^7 / 7!
+  p = __builtin_fmaf(p, f, 0x1.430912p-13f); // (ln 2)^6 / 6!
+  p = __builtin_fmaf(p, f, 0x1.5d87fep-10f); // (ln 2)^5 / 5!
+  p = __builtin_fmaf(p, f, 0x1.3b2ab6p-7f);  // (ln 2)^4 / 4!
+  p = __builtin_fmaf(p, f, 0x1.c6b08ep-5f);  // (ln 2)^3 / 3!
+  p = __builtin_fmaf(p, f, 0x1.ebfbe0p-3f);  // (ln 2)^2 / 2!
+  p = __builtin_fmaf(p, f, 0x1.62e430p-1f);  // ln 2
+  p = __builtin_fmaf(p, f, 1.0f);
   return __builtin_ldexpf(p, static_cast<int>(k));
 }
-// exp(x) * 2^32 with the same rounding steps as exp_poly32: every Horner
+// 2^t * 2^32 with the same rounding steps as exp2_poly32: every Horner
 // coefficient is scaled by 2^32, which commutes with each rounding (no
-// overflow or underflow on this range), so float(w) < exp_poly32_x2p32(x, k)
-// decides exactly as float(w) * 2^-32 < exp_poly32(x, k).
-__device__ __forceinline__ float exp_poly32_x2p32(float x, float k) {
-  float r = __builtin_fmaf(-k, 0x1.62e4p-1f, x);
-  r = __builtin_fmaf(-k, 0x1.7f7d1cp-20f, r);
-  float p = 0x1.a01a02p+19f;                 // 2^32/7!
-  p = __builtin_fmaf(p, r, 0x1.6c16c2p+22f); // 2^32/6!
-  p = __builtin_fmaf(p, r, 0x1.111112p+25f); // 2^32/5!
-  p = __builtin_fmaf(p, r, 0x1.555556p+27f); // 2^32/4!
-  p = __builtin_fmaf(p, r, 0x1.555556p+29f); // 2^32/3!
-  p = __builtin_fmaf(p, r, 0x1p+31f);        // 2^32/2!
-  p = __builtin_fmaf(p, r, 0x1p+32f);        // 2^32/1!
-  p = __builtin_fmaf(p, r, 0x1p+32f);        // 2^32/0!
+// overflow or underflow for t >= -124), so float(w) <= exp2_poly32_x2p32(f, k)
+// decides exactly as float(w) * 2^-32 <= exp2_poly32(f, k).
+__device__ __forceinline__ float exp2_poly32_x2p32(float f, float k) {
+  float p = 0x1.ffcbfcp+15f;
+  p = __builtin_fmaf(p, f, 0x1.430912p+19f);
+  p = __builtin_fmaf(p, f, 0x1.5d87fep+22f);
+  p = __builtin_fmaf(p, f, 0x1.3b2ab6p+25f);
+  p = __builtin_fmaf(p, f, 0x1.c6b08ep+27f);
+  p = __builtin_fmaf(p, f, 0x1.ebfbe0p+29f);
+  p = __builtin_fmaf(p, f, 0x1.62e430p+31f);
+  p = __builtin_fmaf(p, f, 0x1p+32f);
   return __builtin_ldexpf(p, static_cast<int>(k));
 }
 
@@ -164,9 +164,10 @@ __device__ __forceinline__ uint32_t shift_in(uint32_t f, uint64_t lanes) {
   return r;
 }
 
-// Metropolis test "u < exp(x)" for x = -beta*dE < 0.  With `early` the binade
-// bracket 2^(k-1) < exp(x) < 2^(k+1) decides it without the polynomial unless
-// u falls inside the bracket; both forms return the same decision.
+// Metropolis test for dE > 0: FP64 "u < exp(x)", x = -beta dE; FP32
+// "u <= 2^t", t = -(beta log2 e) dE.  With `early` the binade bracket
+// 2^(k-1) < value < 2^(k+1) decides it without the polynomial unless u falls
+// inside the bracket; both forms return the same decision.
 // with_sign(J, s) is |J| carrying the sign bit of s (bit 31): one v_bfi_b32.
 template <typename FP>
 struct Prec;
@@ -203,21 +204,24 @@ struct Prec<double> {
 };
 template <>
 struct Prec<float> {
-  static __device__ __forceinline__ bool accept(float u, float x, bool early) {
-    if (x < -86.0f) return false;
-    const float k = __builtin_rintf(x * 0x1.715476p+0f);
+  // FP32 form: x is t = -(beta log2 e) dE; accept iff t >= -124 and u <= 2^t
+  // (every dE <= 0 passes).
+  static __device__ __forceinline__ bool accept(float u, float t, bool early) {
+    if (t < -124.0f) return false;
+    const float k = __builtin_rintf(t);
     if (early) {
       const int ki = static_cast<int>(k);
-      if (u < __builtin_ldexpf(1.0f, ki - 1)) return true;
+      if (u <= __builtin_ldexpf(1.0f, ki - 1)) return true;
       if (!(u < __builtin_ldexpf(1.0f, ki + 1))) return false;
     }
-    return u < exp_poly32(x, k);
+    return u <= exp2_poly32(t - k, k);
   }
-  // Same decision as accept(uniform32(w), x, false) for x <= 0, branch-free,
-  // comparing float(w) with exp(x) * 2^32; a mask over the wave's lanes.
-  static __device__ __forceinline__ uint64_t accept_lanes_w(uint32_t w, float x) {
-    const float p = exp_poly32_x2p32(x, __builtin_rintf(x * 0x1.715476p+0f));
-    return __builtin_amdgcn_ballot_w64(x >= -86.0f) & __builtin_amdgcn_ballot_w64(static_cast<float>(w) < p);
+  // Same decision as accept(uniform32(w), t, false), branch-free, comparing
+  // float(w) with 2^t * 2^32; a mask over the wave's lanes.
+  static __device__ __forceinline__ uint64_t accept_lanes_w(uint32_t w, float t) {
+    const float k = __builtin_rintf(t);
+    const float p = exp2_poly32_x2p32(t - k, k);
+    return __builtin_amdgcn_ballot_w64(t >= -124.0f) & __builtin_amdgcn_ballot_w64(static_cast<float>(w) <= p);
   }
   static __device__ __forceinline__ bool negative(float J) { return __float_as_int(J) < 0; }
   static __device__ __forceinline__ float magnitude(float J) { return __uint_as_float(__float_as_uint(J) & 0x7FFFFFFFu); }
@@ -516,14 +520,14 @@ __device__ __forceinline__ void attempt_group(const Geo& g, const FP* __restrict
     } else {
       // branch-free: the polynomial is evaluated for every lane (dE <= 0
       // lanes take the test's first clause; their exp value is unused)
-      uint64_t by_exp;
       if constexpr (sizeof(FP) == 8) {
-        by_exp = Prec<double>::accept_lanes(Prec<double>::u(blk, j & 1), -(beta[j] * dE));
+        acc_lanes = __builtin_amdgcn_ballot_w64(dE <= 0.0) |
+                    Prec<double>::accept_lanes(Prec<double>::u(blk, j & 1), -(beta[j] * dE));
       } else {
+        // beta[j] holds beta log2 e; u <= 2^t already accepts every dE <= 0
         const uint32_t wj = j == 0 ? blk.w0 : j == 1 ? blk.w1 : j == 2 ? blk.w2 : blk.w3;
-        by_exp = Prec<float>::accept_lanes_w(wj, -(beta[j] * dE));
+        acc_lanes = Prec<float>::accept_lanes_w(wj, -(beta[j] * dE));
       }
-      acc_lanes = __builtin_amdgcn_ballot_w64(dE <= FP(0)) | by_exp;
     }
     flips = shift_in(flips, acc_lanes);
   }

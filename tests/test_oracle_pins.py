@@ -137,17 +137,30 @@ def test_pexp_binade_bracket_and_monotone():
         assert all(a <= b for a, b in zip(vals, vals[1:]))
 
 
-def test_pexp32_within_two_float_ulp():
+def test_pexp2_32_within_two_float_ulp_and_bracketed():
+    """FP32 form's 2^t: within 2 float ulp of 2^t (evaluated in double) on
+    [-124, 30]; 0 below -124; 2^k exactly at integers; and 2^(k-1) < 2^t <
+    2^(k+1) for k = rint(t), the bracket the GPU's early-out relies on."""
     rng = np.random.default_rng(13)
-    xs = np.concatenate([-rng.uniform(0, 86, 20000), -rng.uniform(0, 1, 10000)]).astype(np.float32)
+    ts = np.concatenate([rng.uniform(-124, 0, 20000), rng.uniform(-1, 1, 10000), rng.uniform(0, 30, 2000),
+                         np.arange(-124, 31, dtype=np.float64) + 0.5]).astype(np.float32)
     worst = 0.0
-    for x in xs:
-        got = float(oracle.pexp32(x))
-        exact = math.exp(float(x))
+    for t in ts:
+        got = float(oracle.pexp2_32(t))
+        exact = 2.0 ** float(t)
         ulp = float(np.spacing(np.float32(exact)))
         worst = max(worst, abs(got - exact) / ulp)
+        k = float(np.rint(t))
+        assert 2.0 ** (k - 1) < got < 2.0 ** (k + 1), t
     assert worst <= 2.0, worst
-    assert float(oracle.pexp32(0.0)) == 1.0 and float(oracle.pexp32(-87.0)) == 0.0
+    for k in range(-124, 31):
+        assert float(oracle.pexp2_32(float(k))) == 2.0 ** k
+    assert float(oracle.pexp2_32(-124.5)) == 0.0
+    assert float(oracle.pexp2_32(-0.0)) == 1.0
+    # monotone on a fine grid across a binade boundary
+    grid = np.float32(-3.5) + np.arange(4096, dtype=np.float32) * np.float32(2.0 ** -10)
+    vals = [float(oracle.pexp2_32(t)) for t in grid]
+    assert all(a <= b for a, b in zip(vals, vals[1:]))
 
 
 # --------------------------------------------------------------------------- energies
@@ -420,16 +433,20 @@ def _predict_site0(o, precision, seed, c, n, m, beta, before, J32):
     h = np.float32(np.float32(np.float32(terms[0] + terms[1]) + np.float32(terms[2] + terms[3]))
                    + np.float32(terms[4] + terms[5]))
     dE32 = np.float32(np.float32(2.0) * np.float32(sp[0])) * h
-    return dE32 <= 0 or u < oracle.pexp32(-(np.float32(beta) * dE32))
+    # FP32 form: t = -(beta log2(e)) dE, accept iff t >= -124 and u <= 2^t
+    bl = np.float32(beta * 1.4426950408889634)
+    t = np.float32(-(bl * dE32))
+    return bool(t >= -124.0) and u <= oracle.pexp2_32(t)
 
 
 def test_metropolis_decisions_follow_the_documented_random_stream():
     """Replays single Metropolis decisions from the Philox stream (pinned above)
     and the exp routine (pinned above): clone c at site i in sweep m of EMCS t
     uses block (site | m<<16 | 2<<24, t, c//2, sample), words (0,1) for even c
-    and (2,3) for odd c, u = ((hi<<32 | lo) >> 11) * 2^-53; FP32 uses word c%4
-    of block c//4, u = float(w) * 2^-32; accept iff dE <= 0 or u < exp(-beta dE),
-    with the local field summed axis by axis ((+x,-x) + (+y,-y)) + (+z,-z).
+    and (2,3) for odd c, u = ((hi<<32 | lo) >> 11) * 2^-53, accept iff dE <= 0
+    or u < exp(-beta dE); FP32 uses word c%4 of block c//4, u = float(w) *
+    2^-32, accept iff t >= -124 and u <= 2^t with t = -(beta log2 e) dE; the
+    local field is summed axis by axis ((+x,-x) + (+y,-y)) + (+z,-z).
     A flip then changes the recorded spin.  Pins the stream plumbing and the
     resolution of the uniforms to their definition."""
     for precision in (oracle.FP64, oracle.FP32):
