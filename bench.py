@@ -31,13 +31,18 @@ VALU_PEAK_OPS = 256 * 64 * 2.4e9
 # EMCS needed to equilibrate one L=16 sample (paper, App. A.2 table).
 T_EQ_EMCS = {12: 2 ** 17, 14: 6.4e6, 16: 3.84e7, 18: 3.48e7}
 
-# Algorithmic VALU operations every Metropolis attempt must perform (see
-# the design doc): its share of a Philox4x32-10 block (80 32-bit operations, shared
-# by 4 FP32 or 2 FP64 attempts), 6 sign applications (2 each) and 5 additions
-# for the local field, dE, -beta*dE, the dE <= 0 test, the uniform (2), the
-# comparison and the flip bit.  The exponential, needed only when dE > 0 and
-# u falls within a factor 2 of exp(-beta dE), is not counted.
-OPS_PER_ATTEMPT = {"fp32": 80 // 4 + 17 + 3 + 3 + 1, "fp64": 80 // 2 + 17 + 3 + 3 + 1}
+# Algorithmic VALU operations of one Metropolis attempt, counted from the
+# method's steps with gfx950's three-operand instructions (one lane-operation
+# each), the exponential included for every attempt as the branch-free form
+# evaluates it:
+#   FP32: 1/4 of a Philox4x32-10 block (10 rounds x (2 widening multiplies +
+#   2 three-way XORs)) 10, uniform 1, local field (6 sign insertions + 5 adds)
+#   11, t = -(beta log2 e) dE 1, 2^t (rint, f, 7 Horner steps, scale 2) 11,
+#   test (2 compares) and flip bit 3: 37.
+#   FP64: 1/2 block 20, 53-bit uniform 3, local field 11, -beta dE 1, exp
+#   (2 for k, 2 Cody-Waite steps, 14 Horner steps, scale 1) 19, dE <= 0 and
+#   u < exp compares and flip bit 3: 57.
+OPS_PER_ATTEMPT = {"fp32": 10 + 1 + 11 + 1 + 11 + 3, "fp64": 20 + 3 + 11 + 1 + 19 + 3}
 
 
 # HBM bytes per sweep launch of the L=16 FP32 workload, from rocprofv3 counter
@@ -267,7 +272,7 @@ def main() -> int:
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: samples are independent, a multi-GPU run "
-              "shards them with no exchange (see DESIGN.md); use --gpus 1", file=sys.stderr)
+              "shards them with no exchange between GPUs; use --gpus 1", file=sys.stderr)
         return 2
 
     if args.workload == "mixed":

@@ -471,14 +471,12 @@ struct WordSigns {
 // binade of exp(x).  Each decision is shifted in at bit 0 of `flips`.
 template <typename FP, bool kMaybeEarly>
 __device__ __forceinline__ void attempt_group(const Geo& g, const FP* __restrict__ bc, const WordSigns& ws,
-                                              const SiteJ<FP>& sj, uint32_t c0w, uint32_t t, int sample, int grp,
-                                              int n0, int clone0, int nbits, int early_beta_bits,
-                                              uint32_t& flips) {
+                                              const SiteJ<FP>& sj, const Block& blk, int grp, int n0, int clone0,
+                                              int nbits, int early_beta_bits, uint32_t& flips) {
   constexpr int G = sizeof(FP) == 8 ? 2 : 4;  // clones per Philox block
   FP beta[G];
 #pragma unroll
   for (int j = 0; j < G; ++j) beta[j] = bc[clone0 + min(grp * G + j - n0, nbits - 1)];
-  const Block blk = philox10(c0w, t, static_cast<uint32_t>(grp), static_cast<uint32_t>(sample), g.key0, g.key1);
 #pragma unroll
   for (int j = G - 1; j >= 0; --j) {
     const int b = grp * G + j - n0;
@@ -556,8 +554,17 @@ __device__ __forceinline__ void update_word(const Geo& g, const FP* __restrict__
     }
   }
   uint32_t flips = 0;
-  for (int grp = (n0 + nbits - 1) / G; grp >= n0 / G; --grp)
-    attempt_group<FP, kMaybeEarly>(g, bc, ws, sj, c0w, t, sample, grp, n0, clone0, nbits, early_beta_bits, flips);
+  // software-pipelined: the Philox block of the next group is computed beside
+  // the attempts of the current one (independent work for the SIMD)
+  const int g_lo = n0 / G;
+  int grp = (n0 + nbits - 1) / G;
+  Block blk = philox10(c0w, t, static_cast<uint32_t>(grp), static_cast<uint32_t>(sample), g.key0, g.key1);
+  for (; grp > g_lo; --grp) {
+    const Block next = philox10(c0w, t, static_cast<uint32_t>(grp - 1), static_cast<uint32_t>(sample), g.key0, g.key1);
+    attempt_group<FP, kMaybeEarly>(g, bc, ws, sj, blk, grp, n0, clone0, nbits, early_beta_bits, flips);
+    blk = next;
+  }
+  attempt_group<FP, kMaybeEarly>(g, bc, ws, sj, blk, g_lo, n0, clone0, nbits, early_beta_bits, flips);
   if (nbits < 32) flips &= (1u << nbits) - 1u;
   plane[self_idx] = self ^ flips;
 }
