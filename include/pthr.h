@@ -172,7 +172,8 @@ int pthr_set_state(pthr_ctx *ctx, const void *blob, size_t bytes, void *stream);
  * 0 = all samples in one launch, 1 = one sample per launch (the unbatched
  * form); exp_early_out: clones with 1000/T above this value (i.e. colder than
  * T = exp_early_out/1000) decide a Metropolis test from the binade of exp(x)
- * before evaluating the polynomial; 0 = never.  Every schedule produces
+ * before evaluating the polynomial; 0 = never (the default: the branch-free
+ * polynomial is the faster form on gfx950).  Every schedule produces
  * identical bits. */
 typedef struct pthr_schedule {
   int32_t threads_per_sample;

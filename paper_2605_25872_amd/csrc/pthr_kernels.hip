@@ -574,7 +574,7 @@ __device__ __forceinline__ void update_word(const Geo& g, const FP* __restrict__
 template <typename FP, int CH>
 __device__ __forceinline__ void sweep_phase(const Geo& g, const Lds& s, const FP* Js, const FP* __restrict__ bc,
                                             int sample, uint32_t t, int m_pt0, int n_pt, int m_er0, int n_er,
-                                            float early_beta) {
+                                            float early_beta, float beta_cold) {
   const Own<CH> own(g.V);
   // Couplings of own sites in the form the field uses (SiteJ).  FP32 (and
   // FP64 with 2 sites per work-item) keeps both colours in registers for all
@@ -611,6 +611,9 @@ __device__ __forceinline__ void sweep_phase(const Geo& g, const Lds& s, const FP
   }
   const int early_bits = __float_as_int(early_beta);
   const bool er_early = g.NER > 0 && __float_as_int(static_cast<float>(bc[g.NPT])) >= early_bits;
+  // PT clones take the early-out form only if the coldest temperature is
+  // below the threshold (beta_cold: beta of T_0 in the units bc holds)
+  const bool pt_early = __float_as_int(beta_cold) >= early_bits;
   const int n_m = n_pt > n_er ? n_pt : n_er;
   // random-number index of the first reservoir clone: the first multiple of 4
   // at or above N_PT (PT clones use their own ids)
@@ -637,10 +640,16 @@ __device__ __forceinline__ void sweep_phase(const Geo& g, const Lds& s, const FP
           for (int d = 0; d < 6; ++d) nb[d] = plane_idx(neighbour(st, d, g.L), colour ^ 1, g.Vh);
           const int self_idx = colour * g.Vh + (i0 >> 1);
           if (pt_on)
-            for (int w = 0; w < g.NWPT; ++w)
-              update_word<FP, true>(g, bc, s.sp + size_t(w) * g.V, self_idx, nb, sj[slot][q],
-                                    c0pt | static_cast<uint32_t>(st.i), t, sample, 32 * w, 32 * w,
-                                    min(32, g.NPT - 32 * w), early_bits);
+            for (int w = 0; w < g.NWPT; ++w) {
+              if (pt_early)
+                update_word<FP, true>(g, bc, s.sp + size_t(w) * g.V, self_idx, nb, sj[slot][q],
+                                      c0pt | static_cast<uint32_t>(st.i), t, sample, 32 * w, 32 * w,
+                                      min(32, g.NPT - 32 * w), early_bits);
+              else
+                update_word<FP, false>(g, bc, s.sp + size_t(w) * g.V, self_idx, nb, sj[slot][q],
+                                       c0pt | static_cast<uint32_t>(st.i), t, sample, 32 * w, 32 * w,
+                                       min(32, g.NPT - 32 * w), early_bits);
+            }
           if (er_on)
             for (int w = g.NWPT; w < g.NW; ++w) {
               const int e0 = 32 * (w - g.NWPT);
@@ -1190,7 +1199,9 @@ __global__ __launch_bounds__(kMaxThreads) void sweep_kernel(Geo g, State st, Run
   const FP* Js = static_cast<const FP*>(st.J) + size_t(sample) * 3 * g.V;
   const FP* bc = static_cast<const FP*>(st.beta_clone) + size_t(sample) * g.C;
   const uint32_t t = *st.t_dev;
-  sweep_phase<FP, CH>(g, s, Js, bc, sample, t, run.m_pt0, run.n_pt, run.m_er0, run.n_er, run.early_beta);
+  // beta of the coldest temperature in the units the clone table holds
+  const float beta_cold = sizeof(FP) == 8 ? static_cast<float>(st.beta64[0]) : st.beta32[0];
+  sweep_phase<FP, CH>(g, s, Js, bc, sample, t, run.m_pt0, run.n_pt, run.m_er0, run.n_er, run.early_beta, beta_cold);
   store_spins(g, s, st, sample);
 }
 
