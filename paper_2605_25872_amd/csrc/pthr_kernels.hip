@@ -730,12 +730,27 @@ __device__ __forceinline__ int start_at(uint32_t rs, int x) {
 
 // Spin bits of clone c at the sites (x, y, z), x = 0..L-1, of row y + L z
 // (bit x set: spin down).
+// The row's sites of each colour are L/2 consecutive plane words (x even:
+// colour (y+z)&1, x odd: the other), read four at a time when L % 8 == 0.
 __device__ __forceinline__ uint32_t clone_row(const Geo& g, const uint32_t* sp, int c, int row) {
   const uint32_t* pl = sp + size_t(word_of(g, c)) * g.V;
   const int b = bit_of(g, c);
   const int yz = row % g.L + row / g.L, i0 = row * g.L;
   uint32_t m = 0;
-  for (int x = 0; x < g.L; ++x) m |= ((pl[plane_idx(i0 + x, (x + yz) & 1, g.Vh)] >> b) & 1u) << x;
+  if (g.L % 8 == 0) {
+    const int c0 = yz & 1;
+    const uint4* ev = reinterpret_cast<const uint4*>(pl + c0 * g.Vh + i0 / 2);        // x = 0, 2, 4, ...
+    const uint4* od = reinterpret_cast<const uint4*>(pl + (c0 ^ 1) * g.Vh + i0 / 2);  // x = 1, 3, 5, ...
+    for (int v = 0; v < g.L / 8; ++v) {
+      const uint4 e = ev[v], o = od[v];
+      const uint32_t part = ((e.x >> b) & 1u) | (((o.x >> b) & 1u) << 1) | (((e.y >> b) & 1u) << 2) |
+                            (((o.y >> b) & 1u) << 3) | (((e.z >> b) & 1u) << 4) | (((o.z >> b) & 1u) << 5) |
+                            (((e.w >> b) & 1u) << 6) | (((o.w >> b) & 1u) << 7);
+      m |= part << (8 * v);
+    }
+  } else {
+    for (int x = 0; x < g.L; ++x) m |= ((pl[plane_idx(i0 + x, (x + yz) & 1, g.Vh)] >> b) & 1u) << x;
+  }
   return m;
 }
 // Overlap bits of a row: bit x set where q = s^a s^b = -1.
