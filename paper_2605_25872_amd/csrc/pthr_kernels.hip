@@ -685,7 +685,7 @@ __device__ __forceinline__ void sweep_phase(const Geo& g, const Lds& s, const FP
 // is always a run start: the canonical root.
 
 struct HouLds {
-  uint32_t* sp;    // [NW][V] spin words
+  uint32_t* sp;    // [NWPT][V] spin words of the PT clones
   int32_t* cat;    // [NR][NT]
   uint32_t* lab;   // [M][V] union-find parents (entries of run starts only)
   uint32_t* qrow;  // [M][L^2] overlap bits of every row
@@ -696,7 +696,7 @@ constexpr int kHouMisc = 32 + 3 * kMaxHouMoves;
 
 __host__ __device__ inline size_t hou_lds_bytes(const Geo& g, int M) {
   size_t o = 0;
-  o = align_up(o + sizeof(uint32_t) * size_t(g.NW) * g.V, 16);
+  o = align_up(o + sizeof(uint32_t) * size_t(g.NWPT) * g.V, 16);
   o = align_up(o + sizeof(int32_t) * size_t(g.NR) * g.NT, 16);
   o = align_up(o + sizeof(uint32_t) * size_t(M) * g.V, 16);
   o = align_up(o + sizeof(uint32_t) * size_t(M) * g.L * g.L, 16);
@@ -708,7 +708,7 @@ __device__ __forceinline__ HouLds hou_view(const Geo& g, int M) {
   HouLds s;
   size_t o = 0;
   s.sp = reinterpret_cast<uint32_t*>(lds_raw + o);
-  o = align_up(o + sizeof(uint32_t) * size_t(g.NW) * g.V, 16);
+  o = align_up(o + sizeof(uint32_t) * size_t(g.NWPT) * g.V, 16);
   s.cat = reinterpret_cast<int32_t*>(lds_raw + o);
   o = align_up(o + sizeof(int32_t) * size_t(g.NR) * g.NT, 16);
   s.lab = reinterpret_cast<uint32_t*>(lds_raw + o);
@@ -1174,14 +1174,17 @@ __device__ __forceinline__ void measure_phase(const Geo& g, const State& st, con
 // changed.  One workgroup per sample; run.sample_begin offsets the grid.
 
 // Load every spin word and the permutation into LDS.
-__device__ __forceinline__ void load_spins(const Geo& g, uint32_t* sp, int32_t* cat, const State& st, int sample) {
-  const size_t words = size_t(g.NW) * g.V;
+// n_words: the first n_words spin planes of the sample (all NW by default).
+__device__ __forceinline__ void load_spins(const Geo& g, uint32_t* sp, int32_t* cat, const State& st, int sample,
+                                           int n_words = -1) {
+  const size_t stride = size_t(g.NW) * g.V;
+  const size_t words = size_t(n_words < 0 ? g.NW : n_words) * g.V;
   if (words % 4 == 0) {
-    const uint4* src = reinterpret_cast<const uint4*>(st.spins + size_t(sample) * words);
+    const uint4* src = reinterpret_cast<const uint4*>(st.spins + size_t(sample) * stride);
     uint4* dst = reinterpret_cast<uint4*>(sp);
     for (size_t x = threadIdx.x; x < words / 4; x += blockDim.x) dst[x] = src[x];
   } else {
-    const uint32_t* gsp = st.spins + size_t(sample) * words;
+    const uint32_t* gsp = st.spins + size_t(sample) * stride;
     for (size_t x = threadIdx.x; x < words; x += blockDim.x) sp[x] = gsp[x];
   }
   for (int x = threadIdx.x; x < g.NR * g.NT; x += blockDim.x) cat[x] = st.clone_at[size_t(sample) * g.NR * g.NT + x];
@@ -1189,14 +1192,16 @@ __device__ __forceinline__ void load_spins(const Geo& g, uint32_t* sp, int32_t* 
 __device__ __forceinline__ void load_spins(const Geo& g, const Lds& s, const State& st, int sample) {
   load_spins(g, s.sp, s.cat, st, sample);
 }
-__device__ __forceinline__ void store_spins(const Geo& g, const uint32_t* sp, const State& st, int sample) {
-  const size_t words = size_t(g.NW) * g.V;
+__device__ __forceinline__ void store_spins(const Geo& g, const uint32_t* sp, const State& st, int sample,
+                                            int n_words = -1) {
+  const size_t stride = size_t(g.NW) * g.V;
+  const size_t words = size_t(n_words < 0 ? g.NW : n_words) * g.V;
   if (words % 4 == 0) {
-    uint4* dst = reinterpret_cast<uint4*>(st.spins + size_t(sample) * words);
+    uint4* dst = reinterpret_cast<uint4*>(st.spins + size_t(sample) * stride);
     const uint4* src = reinterpret_cast<const uint4*>(sp);
     for (size_t x = threadIdx.x; x < words / 4; x += blockDim.x) dst[x] = src[x];
   } else {
-    uint32_t* osp = st.spins + size_t(sample) * words;
+    uint32_t* osp = st.spins + size_t(sample) * stride;
     for (size_t x = threadIdx.x; x < words; x += blockDim.x) osp[x] = sp[x];
   }
 }
@@ -1226,11 +1231,11 @@ __global__ __launch_bounds__(kMaxThreads) void houdayer_kernel(Geo g, State st, 
   const int sample = run.sample_begin + blockIdx.x;
   if (sample >= g.S) return;
   const HouLds s = hou_view(g, run.hou_moves);
-  load_spins(g, s.sp, s.cat, st, sample);
+  load_spins(g, s.sp, s.cat, st, sample, g.NWPT);  // Houdayer pairs are PT clones
   __syncthreads();
   const bool labels = (run.phases & kPhaseLabels) != 0;
   const bool bad = houdayer_moves(g, s, run.hou_moves, sample, *st.t_dev, labels ? run.labels : nullptr);
-  if (!labels) store_spins(g, s.sp, st, sample);
+  if (!labels) store_spins(g, s.sp, st, sample, g.NWPT);
   if (bad) atomicOr(&st.status[sample], kStatusUnionBound);
 }
 
