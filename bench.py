@@ -51,8 +51,8 @@ OPS_PER_ATTEMPT = {"fp32": 10 + 1 + 11 + 1 + 11 + 3, "fp64": 20 + 3 + 11 + 1 + 1
 # SHA-256 is recorded here; any other source reports null.
 SWEEP_TRAFFIC = {
     "workload": "l16_fp32",
-    "sources_sha256": "bd583e39ca4e4f79810c1485eaa30e8c269e13b77a417987720e306b5eee2519",
-    "fetch_kib": 74929.3,
+    "sources_sha256": "bf9dfb4066afadde633437ff796c87f806d0808bbebb33927d228075991c5132",
+    "fetch_kib": 75155.0,
     "write_kib": 98304.0,
 }
 KERNEL_SOURCES = ("paper_2605_25872_amd/csrc/pthr_kernels.hip", "paper_2605_25872_amd/csrc/pthr_internal.h")
@@ -251,7 +251,7 @@ def main() -> int:
                     help="only copy a MIB-MiB device buffer 3 times (HBM counter calibration)")
     ap.add_argument("--fp32-vs-fp64", action="store_true",
                     help="only compare the FP32 form with the FP64 form statistically")
-    ap.add_argument("--samples", type=int, default=256)
+    ap.add_argument("--samples", type=int, default=1024)
     ap.add_argument("--emcs", type=int, default=4096)
     args = ap.parse_args()
 
