@@ -22,7 +22,7 @@
  *   single negative-overlap cluster (Houdayer's original) ......... Sec. 3 (two key differences)
  *   PT swaps between neighbouring temperatures .................... Sec. 3 (PT step)
  *   ER: oldest reservoir clone exchanged with the PT clone at T_max Sec. 3 (ER step)
- *   round trip T_max -> T_min -> T_max after injection ............ Sec. 5, Eq. (10)
+ *   round trip T_max -> T_min -> T_max after injection ............ Sec. 5, Eq. (9)
  *
  * Readings where the paper is silent (fixed identically on the GPU side by a
  * separate implementation): checkerboard order inside a sweep; Philox counter

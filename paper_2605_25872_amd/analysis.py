@@ -1,0 +1,217 @@
+"""Analysis of PTHR observable logs: log2 time bins, disorder averages, the
+Schwinger-Dyson-Young (SDY) equilibration test, P(q) and its moments, and the
+round-trip time of the temperature random walk.
+
+Definitions followed:
+  * overlaps q and q_l of a replica pair: paper Sec. 2, Eqs. (2)-(4);
+  * SDY observable S = H/(3V) + (1 - q_l)/T and the test: the disorder
+    average of <S> is zero in equilibrium, positive before (Sec. 2, Eqs. 5-6);
+  * log2 binning: bin b = [t_max/2^(b+1) + 1, t_max/2^b] of the EMCS series,
+    bin 0 the second half of the run (Sec. 4, Eq. 8);
+  * tau_TRW = N_r N_T (EMCS) / (round trips), per sample (Sec. 5, Eq. 9).
+
+The library accumulates, per sample and temperature, sums over every measured
+EMCS (sum_r e_r, sum_r e_r^2, and over replica pairs sum q^2, q^4, q_l, S) and
+a pooled histogram of the pair overlaps Q = V q; it counts round trips per
+sample.  Snapshots of those cumulative sums at the bin edges give every bin's
+averages as differences.  Everything here is host-side arithmetic on the
+snapshots; the simulation itself runs in the HIP library (`run_logged`).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import sys
+from dataclasses import dataclass, field
+
+import numpy as np
+
+OBS = ("e", "e2", "q2", "q4", "ql", "sdy")
+
+
+def log2_bins(t_max: int, n_bins: int | None = None) -> list[tuple[int, int]]:
+    """Bins b = 0, 1, ... as inclusive EMCS ranges [t_max//2^(b+1) + 1,
+    t_max//2^b] (EMCS numbered from 1), stopping before an empty bin or after
+    n_bins bins."""
+    if t_max < 1:
+        raise ValueError("t_max must be >= 1")
+    out = []
+    b = 0
+    while n_bins is None or b < n_bins:
+        lo, hi = t_max // 2 ** (b + 1) + 1, t_max // 2 ** b
+        if hi < lo:
+            break
+        out.append((lo, hi))
+        b += 1
+    return out
+
+
+def snapshot_times(t_max: int, n_bins: int | None = None) -> list[int]:
+    """EMCS counts at which the cumulative sums are needed: 0 and every bin edge."""
+    edges = {0}
+    for lo, hi in log2_bins(t_max, n_bins):
+        edges.add(lo - 1)
+        edges.add(hi)
+    return sorted(edges)
+
+
+@dataclass
+class Snapshot:
+    """Cumulative sums after `t` EMCS (measured every EMCS)."""
+    t: int
+    n_meas: int
+    acc: np.ndarray       # [S][N_T][6] float64
+    hist: np.ndarray      # [N_T][V+1] uint64
+    rt_count: np.ndarray  # [S] uint64, round trips since initialisation
+
+
+@dataclass
+class BinResult:
+    b: int
+    lo: int
+    hi: int
+    T: np.ndarray
+    per_sample: dict = field(repr=False)  # name -> [S][N_T] thermal averages
+    e: np.ndarray            # disorder average of the energy per spin, [N_T]
+    e_err: np.ndarray
+    sdy: np.ndarray          # disorder average of <S>, [N_T]
+    sdy_err: np.ndarray
+    q2: np.ndarray           # disorder averages of <q^2>, <q^4>, <q_l>
+    q4: np.ndarray
+    ql: np.ndarray
+    binder: np.ndarray       # (3 - avg<q^4> / avg<q^2>^2) / 2
+    pq: np.ndarray           # [N_T][V+1] P(q) at q = (2j - V)/V, pooled over samples and pairs
+    round_trips: np.ndarray  # [S] round trips completed inside the bin
+    tau_trw: np.ndarray      # [S] N_r N_T (EMCS in the bin) / round trips (inf if none)
+
+    @property
+    def n_emcs(self) -> int:
+        return self.hi - self.lo + 1
+
+    def tau_trw_median(self) -> float:
+        return float(np.median(self.tau_trw))
+
+    def round_trips_per_clone_median(self, n_clones: int) -> float:
+        return float(np.median(self.round_trips / n_clones))
+
+    def sdy_z(self) -> np.ndarray:
+        """<S> disorder average in units of its error (sample-to-sample)."""
+        with np.errstate(divide="ignore", invalid="ignore"):
+            return np.where(self.sdy_err > 0, self.sdy / self.sdy_err, np.sign(self.sdy) * np.inf)
+
+    def sdy_equilibrated(self, n_sigma: float = 2.0) -> np.ndarray:
+        """Per temperature: <S> is not positive by more than n_sigma errors
+        (a positive average signals a lack of equilibrium)."""
+        return self.sdy_z() <= n_sigma
+
+
+def _mean_err(x: np.ndarray) -> tuple[np.ndarray, np.ndarray]:
+    """Mean over samples (axis 0) and its standard error."""
+    n = x.shape[0]
+    m = x.mean(axis=0)
+    e = x.std(axis=0, ddof=1) / np.sqrt(n) if n > 1 else np.zeros_like(m)
+    return m, e
+
+
+def bin_result(first: Snapshot, last: Snapshot, b: int, T: np.ndarray, n_replicas: int) -> BinResult:
+    """Averages over the EMCS first.t + 1 .. last.t."""
+    n = last.n_meas - first.n_meas
+    if n <= 0 or last.t - first.t != n:
+        raise ValueError("snapshots must bracket at least one EMCS, measured every EMCS")
+    npairs = n_replicas * (n_replicas - 1) // 2
+    d = (last.acc - first.acc) / n
+    per = {"e": d[..., 0] / n_replicas, "e2": d[..., 1] / n_replicas}
+    for j, name in enumerate(OBS[2:], start=2):
+        per[name] = d[..., j] / npairs if npairs else np.full(d.shape[:2], np.nan)
+    e, e_err = _mean_err(per["e"])
+    sdy, sdy_err = _mean_err(per["sdy"])
+    q2 = per["q2"].mean(axis=0)
+    q4 = per["q4"].mean(axis=0)
+    ql = per["ql"].mean(axis=0)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        binder = 0.5 * (3.0 - q4 / q2 ** 2)
+    h = (last.hist.astype(np.int64) - first.hist.astype(np.int64)).astype(np.float64)
+    tot = h.sum(axis=1, keepdims=True)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        pq = np.where(tot > 0, h / tot, 0.0)
+    rt = (last.rt_count.astype(np.int64) - first.rt_count.astype(np.int64)).astype(np.float64)
+    n_clones = n_replicas * len(T)
+    with np.errstate(divide="ignore"):
+        tau = np.where(rt > 0, n_clones * n / rt, np.inf)
+    return BinResult(b, first.t + 1, last.t, np.asarray(T, dtype=np.float64), per, e, e_err, sdy, sdy_err,
+                     q2, q4, ql, binder, pq, rt, tau)
+
+
+def analyse(snaps: list[Snapshot], t_max: int, T: np.ndarray, n_replicas: int,
+            n_bins: int | None = None) -> list[BinResult]:
+    """Every log2 bin of a run of t_max EMCS from snapshots at snapshot_times."""
+    at = {s.t: s for s in snaps}
+    out = []
+    for b, (lo, hi) in enumerate(log2_bins(t_max, n_bins)):
+        if lo - 1 not in at or hi not in at:
+            raise ValueError(f"no snapshot at EMCS {lo - 1} or {hi}")
+        out.append(bin_result(at[lo - 1], at[hi], b, T, n_replicas))
+    return out
+
+
+def run_logged(g, t_max: int, n_bins: int | None = None, graph_window: int | None = None) -> list[Snapshot]:
+    """Runs t_max EMCS of a library context (`pthr.Pthr`, freshly initialised
+    or continuing), measuring every EMCS, and snapshots the cumulative sums and
+    round-trip counts at every log2 bin edge (times relative to the start)."""
+    if graph_window is not None:
+        g.set_schedule(graph_window=graph_window)
+    obs = g.new_obs()
+    snaps = []
+    done = 0
+    rt0 = g.read_pt()["rt_count"].copy()
+    for t in snapshot_times(t_max, n_bins):
+        if t > done:
+            g.run(t - done, obs)
+            done = t
+        arr = g.obs_arrays(obs)
+        snaps.append(Snapshot(t, arr["n_meas"], arr["acc"].copy(), arr["hist"].copy(),
+                              g.read_pt()["rt_count"] - rt0))
+    return snaps
+
+
+def summary(res: list[BinResult], n_clones: int) -> list[dict]:
+    """One row per bin: EMCS range, the SDY average and error at T_min and its
+    largest z over T, energy per spin at T_min, median round trips per clone and
+    median tau_TRW."""
+    rows = []
+    for r in res:
+        z = r.sdy_z()
+        rows.append({"bin": r.b, "emcs": [r.lo, r.hi], "sdy_tmin": float(r.sdy[0]),
+                     "sdy_tmin_err": float(r.sdy_err[0]), "sdy_max_z": float(np.max(z)),
+                     "equilibrated_all_T": bool(np.all(r.sdy_equilibrated())),
+                     "e_tmin": float(r.e[0]), "binder_tmin": float(r.binder[0]),
+                     "round_trips_per_clone_median": r.round_trips_per_clone_median(n_clones),
+                     "tau_trw_median": r.tau_trw_median()})
+    return rows
+
+
+def main(argv=None) -> int:
+    """Runs a workload with log2-binned logging on the GPU and prints one JSON
+    row per bin."""
+    from paper_2605_25872_amd import inputs, pthr
+
+    ap = argparse.ArgumentParser(description=main.__doc__)
+    ap.add_argument("--workload", default="l8_fp64", choices=sorted(inputs.WORKLOADS))
+    ap.add_argument("--samples", type=int, default=0, help="0 = the workload's own count")
+    ap.add_argument("--tmax", type=int, default=4096)
+    ap.add_argument("--bins", type=int, default=None)
+    args = ap.parse_args(argv)
+    w = inputs.WORKLOADS[args.workload]
+    S = args.samples or w.n_samples
+    T = w.temperatures()
+    g = pthr.Pthr(w.L, S, w.n_replicas, w.n_temps, w.n_reservoir, w.sweeps_per_emcs, w.er_sweeps_per_emcs,
+                  w.precision, "acu", w.t_acu, w.seed)
+    g.init_samples(w.couplings(S), T)
+    res = analyse(run_logged(g, args.tmax, args.bins), args.tmax, T, w.n_replicas, args.bins)
+    for row in summary(res, w.n_replicas * w.n_temps):
+        print(json.dumps(row), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -220,6 +220,30 @@ def test_group_of_lattice_sizes_matches_oracle():
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_logged_run_matches_oracle(precision):
+    """The analysis layer's log2-binned run on the GPU: every snapshot of the
+    cumulative observables and round-trip counts is bit-identical to the same
+    logged run of the oracle, so every bin's averages are too."""
+    from paper_2605_25872_amd import analysis
+    from test_analysis import OracleRunner
+
+    step(f"logged run {precision}")
+    o, g = make_pair(4, 3, 2, 6, 2, precision=precision, er_sweeps=12)
+    t_max = 40
+    gs = analysis.run_logged(g, t_max, graph_window=4)
+    os_ = analysis.run_logged(OracleRunner(o), t_max)
+    assert [s.t for s in gs] == [s.t for s in os_] == analysis.snapshot_times(t_max)
+    for a, b in zip(gs, os_):
+        assert a.n_meas == b.n_meas
+        assert np.array_equal(a.acc.view(np.uint64), b.acc.view(np.uint64))
+        assert np.array_equal(a.hist, b.hist)
+        assert np.array_equal(a.rt_count, b.rt_count)
+    T = g.T
+    for ra, rb in zip(analysis.analyse(gs, t_max, T, 2), analysis.analyse(os_, t_max, T, 2)):
+        assert np.array_equal(ra.sdy, rb.sdy) and np.array_equal(ra.tau_trw, rb.tau_trw)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_every_schedule_gives_the_same_bits(precision):
     step(f"schedules {precision}")
     pthr = _pthr()
