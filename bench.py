@@ -12,6 +12,7 @@ reservoir clones per group, FP32 form.  Prints one JSON line.
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import json
 import os
 import sys
@@ -97,7 +98,7 @@ def cpu_baseline(w, n_samples: int, mode: str) -> dict:
     T = w.temperatures()
     prec = oracle.FP64 if w.precision == "fp64" else oracle.FP32
     o = oracle.Oracle(w.L, n_samples, w.n_replicas, w.n_temps, w.n_reservoir, w.sweeps_per_emcs,
-                      w.er_sweeps_per_emcs, prec, oracle.ACU if mode == "acu" else oracle.SINGLE_NEG,
+                      w.er_sweeps_per_emcs, prec, oracle.SINGLE_NEG if mode == "single" else oracle.ACU,
                       w.t_acu, w.seed)
     o.init(w.couplings(n_samples), T)
     t0 = time.perf_counter()
@@ -241,7 +242,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="l16_fp32", choices=sorted(inputs.WORKLOADS) + ["mixed"],
                     help="'mixed': L = 8..16 side by side, one graph launch per EMCS")
-    ap.add_argument("--mode", default="acu", choices=["acu", "single"])
+    ap.add_argument("--mode", default="acu", choices=["acu", "single", "plain"],
+                    help="Houdayer all-cluster (paper), single cluster, or plain PT (no Houdayer, no reservoir)")
     ap.add_argument("--cpu-samples", type=int, default=192)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--compare-fp64-samples", type=int, default=16,
@@ -283,13 +285,17 @@ def main() -> int:
     from paper_2605_25872_amd import pthr
 
     w = inputs.WORKLOADS[args.workload]
+    if args.mode == "plain":
+        # plain PT: the EMCS without the Houdayer step and the reservoir (paper Sec. 4)
+        w = dataclasses.replace(w, n_reservoir=0, t_acu=0.0)
+    lib_mode = "single" if args.mode == "single" else "acu"
     T = w.temperatures()
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     log(f"workload {w.name}: L={w.L} S={w.n_samples} NR={w.n_replicas} NT={w.n_temps} "
         f"NER={w.n_reservoir} {w.precision} {args.mode}")
     g = pthr.Pthr(w.L, w.n_samples, w.n_replicas, w.n_temps, w.n_reservoir, w.sweeps_per_emcs,
-                  w.er_sweeps_per_emcs, w.precision, args.mode, w.t_acu, w.seed)
+                  w.er_sweeps_per_emcs, w.precision, lib_mode, w.t_acu, w.seed)
     g.init_samples(w.couplings(), T)
     obs = g.new_obs()
     if args.autotune:
@@ -366,7 +372,7 @@ def main() -> int:
         n = min(args.compare_fp64_samples, w.n_samples)
         sub = inputs.Workload(**{**w.__dict__, "n_samples": n, "precision": "fp64"})
         h = pthr.Pthr(w.L, n, w.n_replicas, w.n_temps, w.n_reservoir, w.sweeps_per_emcs,
-                      w.er_sweeps_per_emcs, "fp64", args.mode, w.t_acu, w.seed)
+                      w.er_sweeps_per_emcs, "fp64", lib_mode, w.t_acu, w.seed)
         h.init_samples(sub.couplings(), T)
         h.set_schedule(samples_per_launch=1)
         hobs = h.new_obs()

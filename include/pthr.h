@@ -148,6 +148,16 @@ int pthr_run(pthr_ctx *ctx, int64_t n_emcs, void *d_obs, void *stream);
  * the smallest site index of its cluster. */
 int pthr_cluster_labels(pthr_ctx *ctx, void *d_labels, void *stream);
 
+/* Cluster statistics of the Houdayer graphs at the current state (paper
+ * Sec. 1, Fig. 1: the largest clusters of the majority and the minority):
+ * d_sizes int32 [S][N_r/2][K][2][6]; for every pair and T_k < t_acu, entry
+ * [..][0][r] is the size of the (r+1)-th largest cluster of the majority (the
+ * clusters whose overlap sign is that of the whole pair, q >= 0 counting as
+ * positive) and [..][1][r] the same for the minority; 0 where there are fewer
+ * clusters.  No spin changes.  PTHR_EUNSUPPORTED if the labels and sizes of
+ * one move do not fit in LDS. */
+int pthr_cluster_stats(pthr_ctx *ctx, void *d_sizes, void *stream);
+
 /* Read-back into host arrays (NULL pointers are skipped); synchronizes. */
 int pthr_read_spins(pthr_ctx *ctx, int8_t *spins /* [S][C][V] */, void *stream);
 int pthr_read_pt(pthr_ctx *ctx, int32_t *clone_at /* [S][N_r][N_T] */,

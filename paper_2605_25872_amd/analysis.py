@@ -20,6 +20,7 @@ snapshots; the simulation itself runs in the HIP library (`run_logged`).
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import json
 import sys
 from dataclasses import dataclass, field
@@ -200,17 +201,36 @@ def main(argv=None) -> int:
     ap.add_argument("--samples", type=int, default=0, help="0 = the workload's own count")
     ap.add_argument("--tmax", type=int, default=4096)
     ap.add_argument("--bins", type=int, default=None)
+    ap.add_argument("--mode", default="acu", choices=["acu", "single", "plain"],
+                    help="Houdayer all-cluster (paper), single cluster, or plain PT (no Houdayer, no reservoir)")
+    ap.add_argument("--clusters", action="store_true",
+                    help="also print the mean sizes of the largest clusters per temperature at the end")
     args = ap.parse_args(argv)
     w = inputs.WORKLOADS[args.workload]
+    if args.mode == "plain":
+        w = dataclasses.replace(w, n_reservoir=0, t_acu=0.0)
     S = args.samples or w.n_samples
     T = w.temperatures()
     g = pthr.Pthr(w.L, S, w.n_replicas, w.n_temps, w.n_reservoir, w.sweeps_per_emcs, w.er_sweeps_per_emcs,
-                  w.precision, "acu", w.t_acu, w.seed)
+                  w.precision, "single" if args.mode == "single" else "acu", w.t_acu, w.seed)
     g.init_samples(w.couplings(S), T)
     res = analyse(run_logged(g, args.tmax, args.bins), args.tmax, T, w.n_replicas, args.bins)
     for row in summary(res, w.n_replicas * w.n_temps):
         print(json.dumps(row), flush=True)
+    if args.clusters and g.K_acu:
+        zoo = cluster_zoology(g.cluster_stats())
+        print(json.dumps({"T": [float(x) for x in T[:g.K_acu]],
+                          **{k: v.tolist() for k, v in zoo.items()}}), flush=True)
     return 0
+
+
+def cluster_zoology(sizes: np.ndarray) -> dict:
+    """Mean size, over samples and pairs, of the r-th largest cluster of the
+    majority and of the minority at every temperature (the quantities of the
+    paper's Fig. 1), from `pthr.Pthr.cluster_stats()` ([S][N_r/2][K][2][6])."""
+    s = sizes.astype(np.float64)
+    mean = s.mean(axis=(0, 1))  # [K][2][6]
+    return {"majority_mean": mean[:, 0, :], "minority_mean": mean[:, 1, :]}
 
 
 if __name__ == "__main__":

@@ -531,6 +531,20 @@ int pthr_run(pthr_ctx* ctx, int64_t n_emcs, void* d_obs, void* stream) {
   return PTHR_OK;
 }
 
+int pthr_cluster_stats(pthr_ctx* ctx, void* d_sizes, void* stream) {
+  if (!ctx) return PTHR_EINVAL;
+  ctx->err.clear();
+  if (int rc = ctx->need_ready()) return rc;
+  if (!d_sizes) return ctx->fail(PTHR_EINVAL, "d_sizes must not be NULL");
+  if (ctx->K_acu == 0) return PTHR_OK;
+  if (pthr::houdayer_moves_per_pass(ctx->g, ctx->sch.threads_per_sample, true) < 1)
+    return ctx->fail(PTHR_EUNSUPPORTED, "cluster statistics need more LDS than one workgroup has at this size");
+  pthr::Run run{};
+  run.phases = pthr::kPhaseClusterStats;
+  run.labels = static_cast<int32_t*>(d_sizes);
+  return ctx->launch(run, nullptr, static_cast<hipStream_t>(stream));
+}
+
 int pthr_cluster_labels(pthr_ctx* ctx, void* d_labels, void* stream) {
   if (!ctx) return PTHR_EINVAL;
   ctx->err.clear();

@@ -18,6 +18,7 @@ enum Phase : uint32_t {
   kPhasePT = 4u,        // energies, PT chain, round trips, ER exchange
   kPhaseMeasure = 8u,   // observables into the obs buffer
   kPhaseLabels = 16u,   // canonical cluster labels into a caller buffer
+  kPhaseClusterStats = 32u,  // sizes of the six largest clusters per overlap sign
 };
 
 // Problem geometry, identical for every sample of a context.
@@ -66,7 +67,8 @@ struct Run {
   int do_reservoir;
   int sample_begin;   // first sample of this launch
   float early_beta;   // Metropolis tests of clones with beta >= early_beta use the exp early-out
-  int32_t* labels;    // kPhaseLabels output [S][NR/2][K_acu][V]
+  int32_t* labels;    // kPhaseLabels output [S][NR/2][K_acu][V]; kPhaseClusterStats output
+                      // [S][NR/2][K_acu][2][kStatTop]
   int hou_moves;      // Houdayer moves labelled at once (set by the launcher)
   int meas_k;         // temperatures per pass of the row-parallel overlaps (0: per-site form)
 };
@@ -81,9 +83,10 @@ struct Shape {
 
 constexpr size_t kLdsMax = 160 * 1024;  // gfx950 LDS per workgroup
 constexpr int kMaxHouMoves = 16;        // Houdayer moves labelled at once, at most
+constexpr int kStatTop = 6;             // largest clusters reported per overlap sign
 
 size_t lds_bytes(const Geo& g, int fp_bytes);
-int houdayer_moves_per_pass(const Geo& g, int threads);
+int houdayer_moves_per_pass(const Geo& g, int threads, bool stats);
 int measure_rows_per_pass(const Geo& g, int threads, int fp_bytes);
 hipError_t launch_emcs(int precision, const Geo& g, const State& st, const Obs& ob, const Run& run,
                        const Shape& sh, int n_blocks, hipStream_t stream);

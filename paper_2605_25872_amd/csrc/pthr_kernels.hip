@@ -691,10 +691,19 @@ struct HouLds {
   uint32_t* qrow;  // [M][L^2] overlap bits of every row
   uint32_t* eta;   // [M][ceil(V/32)] ACU: the root drew eta = -1
   int32_t* misc;   // [kHouMisc] scan scratch, per-move single-cluster data
+  uint32_t* size;  // cluster statistics only: [M][V] cluster size at its root
 };
-constexpr int kHouMisc = 32 + 3 * kMaxHouMoves;
+constexpr int kHouMisc = 32 + 3 * kMaxHouMoves + 7 * kMaxHouMoves;
+// misc layout: [0, 32) block scan; 32 + m: single-cluster first count of move m;
+// 32 + kMaxHouMoves: total; 33 + kMaxHouMoves + m: chosen root of move m;
+// kStatQ + m: overlap sum Q of move m; kStatKey + 6m + 2(round % 3) + sign:
+// the round's largest (size, root) key of move m and overlap sign (three
+// buffers: a round's buffer is cleared two rounds ahead, after a barrier that
+// every reader of its previous use has passed).
 
-__host__ __device__ inline size_t hou_lds_bytes(const Geo& g, int M) {
+constexpr int kStatQ = 32 + 3 * kMaxHouMoves, kStatKey = kStatQ + kMaxHouMoves;
+
+__host__ __device__ inline size_t hou_lds_bytes(const Geo& g, int M, bool stats = false) {
   size_t o = 0;
   o = align_up(o + sizeof(uint32_t) * size_t(g.NWPT) * g.V, 16);
   o = align_up(o + sizeof(int32_t) * size_t(g.NR) * g.NT, 16);
@@ -702,6 +711,7 @@ __host__ __device__ inline size_t hou_lds_bytes(const Geo& g, int M) {
   o = align_up(o + sizeof(uint32_t) * size_t(M) * g.L * g.L, 16);
   o = align_up(o + sizeof(uint32_t) * size_t(M) * ((g.V + 31) / 32), 16);
   o = align_up(o + sizeof(int32_t) * kHouMisc, 16);
+  if (stats) o = align_up(o + sizeof(uint32_t) * size_t(M) * g.V, 16);
   return o;
 }
 __device__ __forceinline__ HouLds hou_view(const Geo& g, int M) {
@@ -718,6 +728,8 @@ __device__ __forceinline__ HouLds hou_view(const Geo& g, int M) {
   s.eta = reinterpret_cast<uint32_t*>(lds_raw + o);
   o = align_up(o + sizeof(uint32_t) * size_t(M) * ((g.V + 31) / 32), 16);
   s.misc = reinterpret_cast<int32_t*>(lds_raw + o);
+  o = align_up(o + sizeof(int32_t) * kHouMisc, 16);
+  s.size = reinterpret_cast<uint32_t*>(lds_raw + o);  // valid only when laid out with stats
   return s;
 }
 
@@ -786,10 +798,71 @@ __device__ __forceinline__ void flip_pair_atomic(const Geo& g, uint32_t* sp, int
   }
 }
 
+// Sizes of the kStatTop largest clusters of the majority (clusters whose
+// overlap sign is that of the whole lattice, q >= 0 counting as +1) and of the
+// minority, after the roots are final (lab of every run start = its root).
+// Sizes accumulate at the roots; then kStatTop rounds each take the largest
+// remaining (size, smaller root) key per move and sign with LDS atomicMax.
+// out: [2][kStatTop] sizes, descending, 0 where there are fewer clusters.
+// Called by every work-item of the workgroup (it synchronizes).
+__device__ void cluster_stats(const Geo& g, const HouLds& s, bool active, int m, int M, uint32_t q, uint32_t rs,
+                              int i0, int32_t* out) {
+  const int L = g.L, V = g.V;
+  uint32_t* size = s.size + size_t(active ? m : 0) * V;
+  const uint32_t* lab = s.lab + size_t(active ? m : 0) * V;
+  if (active) {
+    for (uint32_t r = rs; r; r &= r - 1u) {
+      const int xs = __builtin_ctz(r);
+      const uint32_t rest = r & (r - 1u);
+      const int xe = rest ? __builtin_ctz(rest) : L;
+      atomicAdd(&size[lab[i0 + xs]], static_cast<uint32_t>(xe - xs));
+    }
+    atomicAdd(&s.misc[kStatQ + m], L - 2 * __builtin_popcount(q));
+  }
+  __syncthreads();
+  // q bit (1: q_i = -1) of the majority clusters of this move
+  const uint32_t maj = active && s.misc[kStatQ + m] < 0 ? 1u : 0u;
+  uint32_t taken = 0;  // bit xs: the root at run start xs has been reported
+  for (int round = 0; round < kStatTop; ++round) {
+    int32_t* key = s.misc + kStatKey + 6 * m + 2 * (round % 3);
+    if (active) {
+      uint32_t best[2] = {0u, 0u};
+      for (uint32_t r = rs; r; r &= r - 1u) {
+        const int xs = __builtin_ctz(r);
+        const int i = i0 + xs;
+        if (static_cast<int>(lab[i]) != i || ((taken >> xs) & 1u)) continue;
+        const uint32_t k = (size[i] << 16) | (0xFFFFu - static_cast<uint32_t>(i));
+        const int sign = ((q >> xs) & 1u) == maj ? 0 : 1;
+        best[sign] = k > best[sign] ? k : best[sign];
+      }
+      if (best[0]) atomicMax(reinterpret_cast<uint32_t*>(&key[0]), best[0]);
+      if (best[1]) atomicMax(reinterpret_cast<uint32_t*>(&key[1]), best[1]);
+    }
+    __syncthreads();
+    if (active) {
+      const uint32_t k0 = static_cast<uint32_t>(key[0]), k1 = static_cast<uint32_t>(key[1]);
+      if (i0 == 0) {
+        out[round] = static_cast<int32_t>(k0 >> 16);
+        out[kStatTop + round] = static_cast<int32_t>(k1 >> 16);
+      }
+      for (uint32_t r = rs; r; r &= r - 1u) {
+        const int xs = __builtin_ctz(r);
+        const uint32_t tag = 0xFFFFu - static_cast<uint32_t>(i0 + xs);
+        if ((k0 && (k0 & 0xFFFFu) == tag) || (k1 && (k1 & 0xFFFFu) == tag)) taken |= 1u << xs;
+      }
+      // clear the buffer of round + 2 (last read in round - 1, before this barrier)
+      int32_t* ahead = s.misc + kStatKey + 6 * m + 2 * ((round + 2) % 3);
+      if (i0 == 0) ahead[0] = ahead[1] = 0;
+    }
+  }
+}
+
 // One Houdayer move for every pair p and every k < K_acu (or, with `labels`,
 // the canonical labels of every such pair into labels [S][NR/2][K_acu][V]),
 // hou_moves moves per pass.
-__device__ bool houdayer_moves(const Geo& g, const HouLds& s, int M, int sample, uint32_t t, int32_t* labels) {
+__device__ bool houdayer_moves(const Geo& g, const HouLds& s, int M, int sample, uint32_t t, int32_t* labels,
+                               int32_t* stats) {
+  const bool flips = !labels && !stats;
   const int L = g.L, L2 = L * L, V = g.V;
   const uint32_t full = L == 32 ? 0xFFFFFFFFu : (1u << L) - 1u;
   const int n_moves = (g.NR / 2) * g.K_acu;
@@ -807,6 +880,11 @@ __device__ bool houdayer_moves(const Geo& g, const HouLds& s, int M, int sample,
     uint32_t* eta = s.eta + size_t(active ? m : 0) * eta_words;
     // overlap bits of the row; run starts become singleton roots
     for (int x = threadIdx.x; x < M * eta_words; x += blockDim.x) s.eta[x] = 0u;
+    if (stats) {
+      for (int x = threadIdx.x; x < M * V; x += blockDim.x) s.size[x] = 0u;
+      for (int x = threadIdx.x; x < M; x += blockDim.x) s.misc[kStatQ + x] = 0;
+      for (int x = threadIdx.x; x < 6 * M; x += blockDim.x) s.misc[kStatKey + x] = 0;
+    }
     uint32_t q = 0, rs = 0;
     if (active) {
       q = row_overlap(g, s.sp, a, b, row);
@@ -833,13 +911,17 @@ __device__ bool houdayer_moves(const Geo& g, const HouLds& s, int M, int sample,
         const int i = i0 + __builtin_ctz(r);
         const int root = find_root(lab, i, V, &bad);
         lab[i] = static_cast<uint32_t>(root);
-        if (!labels && g.mode == 0 && root == i) {
+        if (flips && g.mode == 0 && root == i) {
           const Block blk = philox10(ctr_word(i, 0, kAcu), t, slot, sample, g.key0, g.key1);
           if (blk.w0 >> 31) atomicOr(&eta[i >> 5], 1u << (i & 31));
         }
       }
     }
-    if (!labels && g.mode != 0) {
+    if (stats) {
+      __syncthreads();
+      cluster_stats(g, s, active, m, M, q, rs, i0,
+                    active ? stats + ((size_t(sample) * (g.NR / 2) + p) * g.K_acu + k) * 2 * kStatTop : nullptr);
+    } else if (flips && g.mode != 0) {
       // single cluster: the q = -1 cluster of the target-th q = -1 site in
       // site order, target uniform; per-move counts from one block scan
       int total = 0;
@@ -1234,8 +1316,10 @@ __global__ __launch_bounds__(kMaxThreads) void houdayer_kernel(Geo g, State st, 
   load_spins(g, s.sp, s.cat, st, sample, g.NWPT);  // Houdayer pairs are PT clones
   __syncthreads();
   const bool labels = (run.phases & kPhaseLabels) != 0;
-  const bool bad = houdayer_moves(g, s, run.hou_moves, sample, *st.t_dev, labels ? run.labels : nullptr);
-  if (!labels) store_spins(g, s.sp, st, sample, g.NWPT);
+  const bool stats = (run.phases & kPhaseClusterStats) != 0;
+  const bool bad = houdayer_moves(g, s, run.hou_moves, sample, *st.t_dev, labels ? run.labels : nullptr,
+                                  stats ? run.labels : nullptr);
+  if (!labels && !stats) store_spins(g, s.sp, st, sample, g.NWPT);
   if (bad) atomicOr(&st.status[sample], kStatusUnionBound);
 }
 
@@ -1331,11 +1415,13 @@ hipError_t launch_t(const Geo& g, const State& st, const Obs& ob, const Run& run
     hipLaunchKernelGGL(k, dim3(n_blocks), dim3(threads), lds, stream, g, st, run);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
-  if (run.phases & (kPhaseHoudayer | kPhaseLabels)) {
+  if (run.phases & (kPhaseHoudayer | kPhaseLabels | kPhaseClusterStats)) {
     Run r = run;
-    r.hou_moves = houdayer_moves_per_pass(g, threads);
+    const bool stats = (run.phases & kPhaseClusterStats) != 0;
+    r.hou_moves = houdayer_moves_per_pass(g, threads, stats);
     if (r.hou_moves < 1) return hipErrorInvalidConfiguration;
-    hipLaunchKernelGGL(houdayer_kernel, dim3(n_blocks), dim3(threads), hou_lds_bytes(g, r.hou_moves), stream, g, st, r);
+    hipLaunchKernelGGL(houdayer_kernel, dim3(n_blocks), dim3(threads), hou_lds_bytes(g, r.hou_moves, stats), stream,
+                       g, st, r);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   if (run.phases & kPhasePT) {
@@ -1357,7 +1443,7 @@ hipError_t launch_t(const Geo& g, const State& st, const Obs& ob, const Run& run
 }  // namespace
 
 size_t lds_bytes(const Geo& g, int fp_bytes) {
-  const size_t phases = plan_lds(g, fp_bytes).total, hou = hou_lds_bytes(g, 1);
+  const size_t phases = plan_lds(g, fp_bytes).total, hou = hou_lds_bytes(g, 1, false);
   return phases > hou ? phases : hou;
 }
 
@@ -1375,12 +1461,12 @@ int measure_rows_per_pass(const Geo& g, int threads, int fp_bytes) {
   return KC;
 }
 
-int houdayer_moves_per_pass(const Geo& g, int threads) {
+int houdayer_moves_per_pass(const Geo& g, int threads, bool stats) {
   const int n_moves = (g.NR / 2) * g.K_acu;
   int M = threads / (g.L * g.L);
   if (M > n_moves) M = n_moves;
   if (M > kMaxHouMoves) M = kMaxHouMoves;
-  while (M > 1 && hou_lds_bytes(g, M) > kLdsMax) --M;
+  while (M > 0 && hou_lds_bytes(g, M, stats) > kLdsMax) --M;
   return M;
 }
 

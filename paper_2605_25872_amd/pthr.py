@@ -28,7 +28,7 @@ EXPORTED = (
     "pthr_cluster_labels", "pthr_read_spins", "pthr_read_pt", "pthr_counters", "pthr_check",
     "pthr_blob_bytes", "pthr_get_state", "pthr_set_state", "pthr_get_schedule",
     "pthr_set_schedule", "pthr_autotune", "pthr_lds_bytes", "pthr_group_create",
-    "pthr_group_destroy", "pthr_group_last_error", "pthr_group_run",
+    "pthr_group_destroy", "pthr_group_last_error", "pthr_group_run", "pthr_cluster_stats",
 )
 
 
@@ -86,6 +86,7 @@ def library() -> ctypes.CDLL:
         "pthr_obs_clear": (i32, [vp, vp, vp]),
         "pthr_run": (i32, [vp, i64, vp, vp]),
         "pthr_cluster_labels": (i32, [vp, vp, vp]),
+        "pthr_cluster_stats": (i32, [vp, vp, vp]),
         "pthr_read_spins": (i32, [vp, vp, vp]),
         "pthr_read_pt": (i32, [vp, vp, vp, vp, vp, vp, vp, vp, vp]),
         "pthr_counters": (i32, [vp, vp, vp, vp]),
@@ -245,6 +246,15 @@ class Pthr:
                                device=self.device)
         self._check(self.lib.pthr_cluster_labels(self.ctx, ctypes.c_void_p(out.data_ptr()),
                                                  self._stream()))
+        return out.cpu().numpy()[:, :, :K]
+
+    def cluster_stats(self) -> np.ndarray:
+        """[S][N_r/2][K][2][6] sizes of the six largest majority (index 0) and
+        minority (index 1) clusters of every Houdayer pair and T_k < t_acu."""
+        K = self.K_acu
+        out = self.torch.zeros((self.S, self.NR // 2, max(K, 1), 2, 6), dtype=self.torch.int32,
+                               device=self.device)
+        self._check(self.lib.pthr_cluster_stats(self.ctx, ctypes.c_void_p(out.data_ptr()), self._stream()))
         return out.cpu().numpy()[:, :, :K]
 
     def counters(self) -> tuple[int, int, int]:

@@ -89,3 +89,20 @@ def chi2_pvalue(counts: np.ndarray, probs: np.ndarray, min_expected: float = 5.0
     stat = ((obs_c[keep] - exp_c[keep]) ** 2 / exp_c[keep]).sum()
     dof = max(int(keep.sum()) - 1, 1)
     return float(stats.chi2.sf(stat, dof))
+
+
+def cluster_stats(labels: np.ndarray, sa: np.ndarray, sb: np.ndarray, top: int = 6) -> np.ndarray:
+    """Sizes of the `top` largest clusters of the majority and of the minority
+    (paper Sec. 1, Fig. 1): clusters are the connected components of equal site
+    overlap q_i = s_i^a s_i^b given by `labels` (one id per site); the majority
+    are the clusters whose q_i has the sign of q = sum_i q_i (q >= 0 counted
+    as positive).  Returns int [2][top], descending, 0-padded."""
+    q = sa.astype(np.int64) * sb.astype(np.int64)
+    maj = 1 if q.sum() >= 0 else -1
+    out = np.zeros((2, top), dtype=np.int64)
+    ids, first, counts = np.unique(labels, return_index=True, return_counts=True)
+    sign = q[first]
+    for row, want in ((0, maj), (1, -maj)):
+        sizes = np.sort(counts[sign == want])[::-1][:top]
+        out[row, :len(sizes)] = sizes
+    return out

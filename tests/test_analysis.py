@@ -126,3 +126,15 @@ def test_logged_oracle_run_matches_per_emcs_measurements():
         np.testing.assert_allclose(r.per_sample["ql"], block[..., 4], rtol=1e-12, atol=1e-14)
         np.testing.assert_array_equal(r.round_trips, (rts[r.hi] - rts[r.lo - 1]).astype(float))
         assert np.allclose(r.pq.sum(axis=1), 1.0)
+
+
+def test_cluster_zoology_means():
+    """Mean r-th largest cluster size per temperature over samples and pairs."""
+    sizes = np.zeros((2, 2, 3, 2, 6), dtype=np.int32)
+    sizes[0, 0, 1, 0, 0] = 10
+    sizes[1, 1, 1, 0, 0] = 30
+    sizes[:, :, 2, 1, 1] = 4
+    z = analysis.cluster_zoology(sizes)
+    assert z["majority_mean"].shape == (3, 6)
+    assert z["majority_mean"][1, 0] == 10.0 and z["majority_mean"][0, 0] == 0.0
+    assert z["minority_mean"][2, 1] == 4.0

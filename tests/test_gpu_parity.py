@@ -163,6 +163,32 @@ def test_cluster_labels_match_oracle():
                 assert np.array_equal(lab[s, p, k], o.labels(s, p, k))
 
 
+def test_cluster_stats_match_the_definition():
+    """Six largest majority and minority clusters of every Houdayer pair and
+    T < 1, from the GPU's labelling, against the definition applied to the
+    oracle's labels and spins (integers, exact), on lattices with several
+    moves per pass and with one."""
+    import defs
+
+    for L, S, NR, NT in ((6, 3, 4, 5), (4, 2, 2, 7), (8, 2, 4, 6)):
+        step(f"cluster stats L={L}")
+        o, g = make_pair(L, S, NR, NT, 2, er_sweeps=8, t_range=(0.3, 1.4))
+        for e in range(3):
+            o.emcs()
+            g.emcs()
+        got = g.cluster_stats()
+        K = g.K_acu
+        assert got.shape == (S, NR // 2, K, 2, 6)
+        for s in range(S):
+            for p in range(NR // 2):
+                for k in range(K):
+                    a = o.clone_at[s, 2 * p, k]
+                    b = o.clone_at[s, 2 * p + 1, k]
+                    want = defs.cluster_stats(o.labels(s, p, k), o.spins[s, a], o.spins[s, b])
+                    assert np.array_equal(got[s, p, k], want), (L, s, p, k, got[s, p, k], want)
+        assert_same_state(o, g, "cluster statistics change nothing")
+
+
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_fused_run_equals_stepwise_and_oracle(precision):
     step(f"run vs stepwise {precision}")

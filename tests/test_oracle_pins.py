@@ -343,6 +343,22 @@ def test_cluster_labels_match_graph_components(L):
                 assert np.bincount(got, minlength=V).sum() == V
 
 
+def test_cluster_stats_definition_on_a_hand_made_case():
+    """Majority/minority cluster sizes from labels and spins: on a 1D-like
+    labelling with known components (q pattern + + - + - - + +, the first and
+    last runs joined), the majority is q = +1 (five sites) with clusters of 4
+    and 1 sites, the minority has clusters of 2 and 1; flipping every q swaps
+    the roles of the signs but not the sizes."""
+    sa = np.array([1, 1, -1, 1, -1, -1, 1, 1])
+    sb = np.ones(8, dtype=int)
+    labels = np.array([0, 0, 2, 3, 4, 4, 0, 0])  # runs joined across the boundary
+    out = defs.cluster_stats(labels, sa, sb, top=3)
+    np.testing.assert_array_equal(out, [[4, 1, 0], [2, 1, 0]])
+    # negative total overlap: the majority is q = -1
+    out = defs.cluster_stats(labels, -sa, sb, top=3)
+    np.testing.assert_array_equal(out, [[4, 1, 0], [2, 1, 0]])
+
+
 def test_acu_flips_each_cluster_with_probability_half():
     o, _ = _random_state_oracle(6, seed=31)
     flips = total = 0
