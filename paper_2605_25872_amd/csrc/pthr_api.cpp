@@ -29,7 +29,7 @@ size_t align256(size_t v) { return (v + 255) / 256 * 256; }
 
 // Byte offsets of every region of the caller's state buffer.
 struct Layout {
-  size_t beta64, beta32, spins, J, beta_clone, clone_at, er_head, pt_last, pt_count, pt_energy, rt_state,
+  size_t beta64, beta32, spins, J, beta_clone, clone_at, er_head, pt_last, pt_count, pt_energy, e_now, rt_state,
       rt_count, status, total;
 };
 
@@ -64,6 +64,7 @@ Layout layout_of(const pthr_params& p) {
   l.pt_last = o;   o = align256(o + S * NR * (NT - 1));
   l.pt_count = o;  o = align256(o + 4 * S * NR * (NT - 1));
   l.pt_energy = o; o = align256(o + 8 * S * d.NPT);
+  l.e_now = o;     o = align256(o + 8 * S * d.NPT);
   l.rt_state = o;  o = align256(o + S * d.NPT);
   l.rt_count = o;  o = align256(o + 8 * S);
   l.status = o;    o = align256(o + 4 * S);
@@ -136,6 +137,9 @@ struct pthr_ctx {
   bool ready = false;
   int64_t t = 0;
   int m_pt = 0, m_er = 0;
+  // e_now in the state buffer holds the energies of the current configurations
+  // (set by the PT step, cleared by anything that changes spins)
+  bool e_current = false;
   int K_acu = 0;
   std::vector<double> T;
   pthr_schedule sch{};
@@ -178,6 +182,7 @@ struct pthr_ctx {
     st.pt_last = b + lay.pt_last;
     st.pt_count = reinterpret_cast<uint32_t*>(b + lay.pt_count);
     st.pt_energy = reinterpret_cast<double*>(b + lay.pt_energy);
+    st.e_now = reinterpret_cast<double*>(b + lay.e_now);
     st.rt_state = b + lay.rt_state;
     st.rt_count = reinterpret_cast<uint64_t*>(b + lay.rt_count);
     st.status = reinterpret_cast<uint32_t*>(b + lay.status);
@@ -248,6 +253,7 @@ struct pthr_ctx {
     if (d_obs) {
       pthr::Run m{};
       m.phases = pthr::kPhaseMeasure;
+      m.e_current = 1;  // the PT step just left the current energies in e_now
       if (int rc = launch(m, d_obs, stream)) return rc;
     }
     return PTHR_OK;
@@ -437,6 +443,7 @@ int pthr_init_samples(pthr_ctx* ctx, const double* J_host, const double* T_host,
   if (e != hipSuccess) return ctx->hip_fail(e, "state initialisation");
   ctx->t = 0;
   ctx->m_pt = ctx->m_er = 0;
+  ctx->e_current = false;
   ctx->ready = true;
   return PTHR_OK;
 }
@@ -459,6 +466,7 @@ int pthr_sweep(pthr_ctx* ctx, int n_pt, int n_er, void* stream) {
   if (int rc = ctx->launch(run, nullptr, static_cast<hipStream_t>(stream))) return rc;
   ctx->m_pt += n_pt;
   ctx->m_er += n_er;
+  ctx->e_current = false;
   return PTHR_OK;
 }
 
@@ -469,6 +477,7 @@ int pthr_houdayer(pthr_ctx* ctx, void* stream) {
   if (ctx->K_acu == 0) return PTHR_OK;
   pthr::Run run{};
   run.phases = pthr::kPhaseHoudayer;
+  ctx->e_current = false;
   return ctx->launch(run, nullptr, static_cast<hipStream_t>(stream));
 }
 
@@ -485,6 +494,7 @@ int pthr_pt_swap(pthr_ctx* ctx, int do_reservoir, void* stream) {
   if (e != hipSuccess) return ctx->hip_fail(e, "advance t");
   ctx->t += 1;
   ctx->m_pt = ctx->m_er = 0;
+  ctx->e_current = true;
   return PTHR_OK;
 }
 
@@ -495,6 +505,7 @@ int pthr_measure(pthr_ctx* ctx, void* d_obs, void* stream) {
   if (!d_obs) return ctx->fail(PTHR_EINVAL, "d_obs must not be NULL");
   pthr::Run run{};
   run.phases = pthr::kPhaseMeasure;
+  run.e_current = ctx->e_current ? 1 : 0;
   return ctx->launch(run, d_obs, static_cast<hipStream_t>(stream));
 }
 
@@ -528,6 +539,7 @@ int pthr_run(pthr_ctx* ctx, int64_t n_emcs, void* d_obs, void* stream) {
     if (int rc = ctx->emcs(d_obs, s)) return rc;
     ctx->t += 1;
   }
+  if (n_emcs > 0) ctx->e_current = true;
   return PTHR_OK;
 }
 
@@ -681,6 +693,7 @@ int pthr_set_state(pthr_ctx* ctx, const void* blob, size_t bytes, void* stream) 
   ctx->t = h.t;
   ctx->m_pt = h.m_pt;
   ctx->m_er = h.m_er;
+  ctx->e_current = false;
   return PTHR_OK;
 }
 
@@ -715,6 +728,7 @@ int pthr_autotune(pthr_ctx* ctx, void* d_scratch, int n_emcs, double* best_ms, v
   hipStream_t s = static_cast<hipStream_t>(stream);
   unsigned char* real = ctx->d_state;
   const int64_t t_saved = ctx->t;
+  const bool e_saved = ctx->e_current;
   const pthr_schedule saved = ctx->sch;
   pthr_schedule best = saved;
   double best_t = 1e300;
@@ -755,6 +769,7 @@ int pthr_autotune(pthr_ctx* ctx, void* d_scratch, int n_emcs, double* best_ms, v
   (void)hipEventDestroy(e1);
   ctx->d_state = real;
   ctx->t = t_saved;
+  ctx->e_current = e_saved;
   ctx->sch = rc == PTHR_OK ? best : saved;
   if (best_ms) *best_ms = best_t;
   return rc;
@@ -930,13 +945,19 @@ int pthr_group_run(pthr_group* grp, int64_t n_emcs, void* const* d_obs, int grap
     for (; done + graph_window <= n_emcs; done += graph_window) {
       hipError_t e = hipGraphLaunch(grp->gexec, s);
       if (e != hipSuccess) return grp->fail(PTHR_EHIP, "graph launch: %s", hipGetErrorString(e));
-      for (pthr_ctx* c : grp->ctx) c->t += graph_window;
+      for (pthr_ctx* c : grp->ctx) {
+        c->t += graph_window;
+        c->e_current = true;
+      }
     }
   }
   if (done < n_emcs) {
     const int rest = static_cast<int>(n_emcs - done);
     if (int rc = grp->chains(rest, d_obs, s)) return rc;
-    for (pthr_ctx* c : grp->ctx) c->t += rest;
+    for (pthr_ctx* c : grp->ctx) {
+      c->t += rest;
+      c->e_current = true;
+    }
   }
   return PTHR_OK;
 }

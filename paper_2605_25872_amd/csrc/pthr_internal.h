@@ -44,7 +44,8 @@ struct State {
   int32_t* er_head;    // [S][NR]
   uint8_t* pt_last;    // [S][NR][NT-1]
   uint32_t* pt_count;  // [S][NR][NT-1]
-  double* pt_energy;   // [S][NPT]
+  double* pt_energy;   // [S][NPT] energies at the PT step (before the reservoir exchange)
+  double* e_now;       // [S][NPT] energies of the configurations after the PT step and exchange
   uint8_t* rt_state;   // [S][NPT]
   uint64_t* rt_count;  // [S]
   uint32_t* status;    // [S]
@@ -71,6 +72,7 @@ struct Run {
                       // [S][NR/2][K_acu][2][kStatTop]
   int hou_moves;      // Houdayer moves labelled at once (set by the launcher)
   int meas_k;         // temperatures per pass of the row-parallel overlaps (0: per-site form)
+  int e_current;      // measure: e_now holds the energies of the current configurations
 };
 
 // Device status bits (per sample).

@@ -273,7 +273,7 @@ struct Lds {
   uint32_t* lab;  // [2*16*NPT] energy partials
   int32_t* cat;   // [NR][NT]
   int32_t* head;  // [NR]
-  double* E;      // [NPT]
+  double* E;      // [NPT + NR] energies: PT clones, then the reservoir FIFO heads
   void* bcl;      // [C] beta per clone (FP)
   uint8_t* rt;    // [NPT]
   int32_t* qacc;  // [NT][npairs] packed Q' | Q_l' << 16
@@ -290,11 +290,11 @@ __host__ __device__ inline LdsPlan plan_lds(const Geo& g, int fp_bytes) {
   size_t o = 0;
   const int npairs = g.NR * (g.NR - 1) / 2;
   p.sp = o;   o = align_up(o + sizeof(uint32_t) * size_t(g.NW) * g.V, 16);
-  const size_t red_words = size_t(2) * kMaxWaves * g.NPT;
+  const size_t red_words = size_t(2) * kMaxWaves * (g.NPT + g.NR);  // energies of PT clones + reservoir heads
   p.lab = o;  o = align_up(o + sizeof(uint32_t) * red_words, 16);
   p.cat = o;  o = align_up(o + sizeof(int32_t) * size_t(g.NR) * g.NT, 16);
   p.head = o; o = align_up(o + sizeof(int32_t) * size_t(g.NR), 16);
-  p.E = o;    o = align_up(o + sizeof(double) * size_t(g.NPT), 16);
+  p.E = o;    o = align_up(o + sizeof(double) * size_t(g.NPT + g.NR), 16);
   p.bcl = o;  o = align_up(o + size_t(fp_bytes) * g.C, 16);
   p.rt = o;   o = align_up(o + size_t(g.NPT), 16);
   p.qacc = o; o = align_up(o + sizeof(int32_t) * 2 * size_t(g.NT) * (npairs > 0 ? npairs : 1), 16);
@@ -989,9 +989,10 @@ __device__ bool houdayer_moves(const Geo& g, const HouLds& s, int M, int sample,
 // E(c) = -sum_i a_i, a_i = (J_x[i] s_i s_{i+x} + J_y[i] s_i s_{i+y}) + J_z[i] s_i s_{i+z}
 // in double, summed by a pairwise tree in natural site order (own chunk, then
 // a butterfly across the wave, then across the waves), padded with +0.0 to a
-// power of two.  Writes s.E[0..NPT).
+// power of two.  Writes s.E[0..NPT) and, with `heads`, s.E[NPT + r] for the
+// oldest reservoir clone of every group r (s.head must be loaded).
 template <typename FP, int CH>
-__device__ __forceinline__ void energy_phase(const Geo& g, const FP* Js) {
+__device__ __forceinline__ void energy_phase(const Geo& g, const FP* Js, bool heads = false) {
   const Lds s = lds_view(g, sizeof(FP));
   const Own<CH> own(g.V);
   double jf[CH][3];
@@ -1012,9 +1013,12 @@ __device__ __forceinline__ void energy_phase(const Geo& g, const FP* Js) {
   const int nwave = (blockDim.x + kWave - 1) / kWave;
   int nwp = 1;
   while (nwp < nwave) nwp <<= 1;
-  for (int c = 0; c < g.NPT; ++c) {
-    const uint32_t* plane = s.sp + size_t(c >> 5) * g.V;
-    const int b = c & 31;
+  // entries: the PT clones, then (heads) the oldest reservoir clone of each group
+  const int n_e = g.NPT + (heads ? g.NR : 0);
+  for (int c = 0; c < n_e; ++c) {
+    const int clone = c < g.NPT ? c : g.NPT + (c - g.NPT) * g.NERG + s.head[c - g.NPT];
+    const uint32_t* plane = s.sp + size_t(word_of(g, clone)) * g.V;
+    const int b = bit_of(g, clone);
     double a[CH];
 #pragma unroll
     for (int j = 0; j < CH; ++j) {
@@ -1035,14 +1039,14 @@ __device__ __forceinline__ void energy_phase(const Geo& g, const FP* Js) {
     double v = a[0];
 #pragma unroll
     for (int off = 1; off < kWave; off <<= 1) v = v + __shfl_xor(v, off, kWave);
-    if (lane_id() == 0) red[wave_id() * g.NPT + c] = v;
+    if (lane_id() == 0) red[wave_id() * n_e + c] = v;
   }
   __syncthreads();
-  for (int c = threadIdx.x; c < g.NPT; c += blockDim.x) {
-    for (int q = nwave; q < nwp; ++q) red[q * g.NPT + c] = 0.0;
+  for (int c = threadIdx.x; c < n_e; c += blockDim.x) {
+    for (int q = nwave; q < nwp; ++q) red[q * n_e + c] = 0.0;
     for (int width = nwp; width > 1; width >>= 1)
       for (int q = 0; q < width / 2; ++q)
-        red[q * g.NPT + c] = red[(2 * q) * g.NPT + c] + red[(2 * q + 1) * g.NPT + c];
+        red[q * n_e + c] = red[(2 * q) * n_e + c] + red[(2 * q + 1) * n_e + c];
     s.E[c] = -red[c];
   }
   __syncthreads();
@@ -1053,7 +1057,8 @@ template <typename FP, int CH>
 __device__ __forceinline__ void pt_phase(const Geo& g, const State& st, int sample, uint32_t t, int do_reservoir,
                                       const FP* beta_fp) {
   const Lds s = lds_view(g, sizeof(FP));
-  energy_phase<FP, CH>(g, static_cast<const FP*>(st.J) + size_t(sample) * 3 * g.V);
+  const bool exchange = do_reservoir && g.NERG > 0;
+  energy_phase<FP, CH>(g, static_cast<const FP*>(st.J) + size_t(sample) * 3 * g.V, exchange);
   const Own<CH> own(g.V);
   const int NT = g.NT;
   if (static_cast<int>(threadIdx.x) < g.NR) {
@@ -1080,7 +1085,16 @@ __device__ __forceinline__ void pt_phase(const Geo& g, const State& st, int samp
   }
   for (int c = threadIdx.x; c < g.NPT; c += blockDim.x) st.pt_energy[size_t(sample) * g.NPT + c] = s.E[c];
   __syncthreads();
-  if (do_reservoir && g.NERG > 0) {
+  // energy of every PT clone's configuration after the step: the clone at T_max
+  // of group r receives the configuration (and energy) of the reservoir head
+  for (int c = threadIdx.x; c < g.NPT; c += blockDim.x) {
+    double e = s.E[c];
+    if (exchange)
+      for (int r = 0; r < g.NR; ++r)
+        if (s.cat[r * NT + NT - 1] == c) e = s.E[g.NPT + r];
+    st.e_now[size_t(sample) * g.NPT + c] = e;
+  }
+  if (exchange) {
     // the configuration at T_max and the oldest reservoir configuration trade places
     for (int r = 0; r < g.NR; ++r) {
       const int a = s.cat[r * NT + NT - 1];
@@ -1155,9 +1169,16 @@ __device__ void overlaps_rows(const Geo& g, const Lds& s, uint32_t* cm, int KC) 
 }
 
 template <typename FP, int CH>
-__device__ __forceinline__ void measure_phase(const Geo& g, const State& st, const Obs& ob, int sample, int KC) {
+__device__ __forceinline__ void measure_phase(const Geo& g, const State& st, const Obs& ob, int sample, int KC,
+                                              bool e_current) {
   const Lds s = lds_view(g, sizeof(FP));
-  energy_phase<FP, CH>(g, static_cast<const FP*>(st.J) + size_t(sample) * 3 * g.V);
+  if (e_current) {
+    // the PT step left the energies of the current configurations in e_now
+    for (int c = threadIdx.x; c < g.NPT; c += blockDim.x) s.E[c] = st.e_now[size_t(sample) * g.NPT + c];
+    __syncthreads();
+  } else {
+    energy_phase<FP, CH>(g, static_cast<const FP*>(st.J) + size_t(sample) * 3 * g.V);
+  }
   const Own<CH> own(g.V);
   const int NT = g.NT, NR = g.NR, npairs = NR * (NR - 1) / 2;
   for (int x = threadIdx.x; x < NT * npairs; x += blockDim.x) s.qacc[x] = 0;
@@ -1351,7 +1372,7 @@ __global__ __launch_bounds__(kMaxThreads) void measure_kernel(Geo g, State st, O
   if (sample >= g.S) return;
   load_spins(g, lds_view(g, sizeof(FP)), st, sample);
   __syncthreads();
-  measure_phase<FP, CH>(g, st, ob, sample, run.meas_k);
+  measure_phase<FP, CH>(g, st, ob, sample, run.meas_k, run.e_current != 0);
 }
 
 // Initial spins: bit = sign bit of word 0 of the INIT block of (site, clone).
