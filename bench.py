@@ -176,7 +176,7 @@ def bench_mixed(args) -> dict:
         g = pthr.Pthr(w.L, w.n_samples, w.n_replicas, w.n_temps, w.n_reservoir, w.sweeps_per_emcs,
                       w.er_sweeps_per_emcs, w.precision, args.mode, w.t_acu, w.seed)
         g.init_samples(w.couplings(), w.temperatures())
-        if args.autotune:
+        if not args.no_autotune:  # the mixed batch is defined with per-size autotuned schedules
             best = g.autotune(1)
             log(f"autotune L={w.L}: {best:.2f} ms/EMCS, {g.schedule().threads_per_sample} work-items, "
                 f"early-out below T = {g.schedule().exp_early_out / 1000:g}")
@@ -249,6 +249,7 @@ def main() -> int:
     ap.add_argument("--compare-fp64-samples", type=int, default=16,
                     help="samples for the unbatched FP64 one-sample-per-launch comparison (0 = skip)")
     ap.add_argument("--autotune", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true", help="mixed batch: keep the default schedules")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy a MIB-MiB device buffer 3 times (HBM counter calibration)")
     ap.add_argument("--fp32-vs-fp64", action="store_true",

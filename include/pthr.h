@@ -190,10 +190,14 @@ typedef struct pthr_schedule {
   int32_t samples_per_launch;
   int32_t exp_early_out;
   int32_t graph_window; /* pthr_run replays a captured HIP graph of this many EMCS (0 = plain launches) */
+  int32_t clone_split;  /* sweeps: 1, 2 or 4 work-items share each chunk of sites, each taking every
+                           clone_split-th group of clones of a word (more waves for small lattices);
+                           threads_per_sample * clone_split <= 1024 */
 } pthr_schedule;
 int pthr_get_schedule(const pthr_ctx *ctx, pthr_schedule *out);
 int pthr_set_schedule(pthr_ctx *ctx, const pthr_schedule *sch);
-/* Times candidate schedules with pthr_run on a scratch copy of the state
+/* Times candidate schedules (work-items per sample, clone_split, early-out
+ * off or below T = 0.7) with pthr_run on a scratch copy of the state
  * (d_scratch: pthr_state_bytes bytes, device) for n_emcs EMCS each, keeps the
  * fastest, restores nothing else.  best_ms (may be NULL) gets its time. */
 int pthr_autotune(pthr_ctx *ctx, void *d_scratch, int n_emcs, double *best_ms, void *stream);

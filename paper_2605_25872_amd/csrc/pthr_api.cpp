@@ -204,6 +204,7 @@ struct pthr_ctx {
   pthr::Shape shape() const {
     pthr::Shape sh{};
     sh.threads = sch.threads_per_sample;
+    sh.split = sch.clone_split;
     sh.chunk = 2;  // smallest chunk giving this many work-items (checked by set_schedule)
     while (threads_for(d.V, sh.chunk) != sch.threads_per_sample && sh.chunk < 8) sh.chunk *= 2;
     return sh;
@@ -359,6 +360,20 @@ int pthr_create(const pthr_params* p, pthr_ctx** out) {
   c->sch.samples_per_launch = 0;
   c->sch.exp_early_out = 0;  // the branch-free exponential for every clone (fastest on gfx950)
   c->sch.graph_window = 16;
+  // Batches too small to fill the GPU with waves (4 per SIMD at the sweep's
+  // register use): share each chunk's clone words among 2 or 4 waves, up to
+  // 1024 work-items per workgroup and one GPU's worth of waves.
+  int n_cu = 256, dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n_cu < 1) {
+    n_cu = 256;                // no device visible here: size for an MI355X
+    (void)hipGetLastError();   // and leave no error behind for later calls
+  }
+  const int64_t waves = int64_t(p->n_samples) * (c->sch.threads_per_sample / 64);
+  c->sch.clone_split = 1;
+  while (c->sch.clone_split < 4 && c->sch.threads_per_sample * c->sch.clone_split * 2 <= 1024 &&
+         waves * c->sch.clone_split * 2 <= int64_t(n_cu) * 16)
+    c->sch.clone_split *= 2;
   *out = c;
   g_create_error.clear();
   return PTHR_OK;
@@ -715,6 +730,10 @@ int pthr_set_schedule(pthr_ctx* ctx, const pthr_schedule* sch) {
   if (sch->samples_per_launch < 0) return ctx->fail(PTHR_EINVAL, "bad samples_per_launch");
   if (sch->graph_window < 0 || sch->graph_window > 4096) return ctx->fail(PTHR_EINVAL, "graph_window must be in [0, 4096]");
   if (sch->exp_early_out < 0) return ctx->fail(PTHR_EINVAL, "exp_early_out must be >= 0");
+  if (sch->clone_split != 1 && sch->clone_split != 2 && sch->clone_split != 4)
+    return ctx->fail(PTHR_EINVAL, "clone_split must be 1, 2 or 4");
+  if (sch->threads_per_sample * sch->clone_split > 1024)
+    return ctx->fail(PTHR_EINVAL, "threads_per_sample * clone_split must be <= 1024");
   ctx->sch = *sch;
   return PTHR_OK;
 }
@@ -739,11 +758,14 @@ int pthr_autotune(pthr_ctx* ctx, void* d_scratch, int n_emcs, double* best_ms, v
   for (int ch = 2; ch <= 8 && rc == PTHR_OK; ch *= 2) {
     if (!chunk_ok(ctx->p.precision, ctx->d.V, ch)) continue;
     if (ch > 2 && threads_for(ctx->d.V, ch) == threads_for(ctx->d.V, ch / 2)) continue;
-    for (int early : {0, 500, 700, 1000, 100000}) {
+    for (int cand_i = 0; cand_i < 6; ++cand_i) {
       if (rc != PTHR_OK) break;
+      const int early = cand_i % 2 ? 700 : 0, split = 1 << (cand_i / 2);
+      if (threads_for(ctx->d.V, ch) * split > 1024) continue;
       pthr_schedule cand = saved;
       cand.threads_per_sample = threads_for(ctx->d.V, ch);
       cand.exp_early_out = early;
+      cand.clone_split = split;
       ctx->sch = cand;
       hipError_t e = hipMemcpyAsync(d_scratch, real, ctx->lay.total, hipMemcpyDeviceToDevice, s);
       if (e != hipSuccess) {

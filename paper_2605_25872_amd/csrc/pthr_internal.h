@@ -73,6 +73,7 @@ struct Run {
   int hou_moves;      // Houdayer moves labelled at once (set by the launcher)
   int meas_k;         // temperatures per pass of the row-parallel overlaps (0: per-site form)
   int e_current;      // measure: e_now holds the energies of the current configurations
+  int clone_split;    // sweep: work-items per chunk of sites (set by the launcher)
 };
 
 // Device status bits (per sample).
@@ -81,6 +82,7 @@ enum : uint32_t { kStatusUnionBound = 1u, kStatusFindBound = 2u };
 struct Shape {
   int chunk;       // sites per work-item: 2, 4 or 8
   int threads;     // work-items per sample workgroup (multiple of 64, <= 1024)
+  int split;       // sweep only: work-items sharing each chunk's clone words (1, 2 or 4)
 };
 
 constexpr size_t kLdsMax = 160 * 1024;  // gfx950 LDS per workgroup

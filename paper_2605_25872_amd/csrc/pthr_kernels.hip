@@ -405,6 +405,8 @@ struct Own {
   int first;
   bool owns;
   __device__ __forceinline__ Own(int V) : first(static_cast<int>(threadIdx.x) * CH), owns(first < V) {}
+  // with several work-items per chunk of sites: chunk index `chunk`
+  __device__ __forceinline__ Own(int V, int chunk) : first(chunk * CH), owns(first < V) {}
 };
 
 template <typename FP>
@@ -537,10 +539,11 @@ __device__ __forceinline__ void attempt_group(const Geo& g, const FP* __restrict
 // to the first, so clone clone0+b ends at bit b of the flip mask; the bits of
 // a partial last block's surplus indices land above bit nbits-1 and are
 // masked off.
-template <typename FP, bool kMaybeEarly>
+template <typename FP, bool kMaybeEarly, bool kSplit>
 __device__ __forceinline__ void update_word(const Geo& g, const FP* __restrict__ bc, uint32_t* plane, int self_idx,
                                             const int (&nb)[6], const SiteJ<FP>& sj, uint32_t c0w, uint32_t t,
-                                            int sample, int clone0, int n0, int nbits, int early_beta_bits) {
+                                            int sample, int clone0, int n0, int nbits, int early_beta_bits,
+                                            int f, int F) {
   constexpr int G = sizeof(FP) == 8 ? 2 : 4;
   const uint32_t self = plane[self_idx];
   WordSigns ws;
@@ -554,28 +557,56 @@ __device__ __forceinline__ void update_word(const Geo& g, const FP* __restrict__
     }
   }
   uint32_t flips = 0;
-  // software-pipelined: the Philox block of the next group is computed beside
-  // the attempts of the current one (independent work for the SIMD)
-  const int g_lo = n0 / G;
-  int grp = (n0 + nbits - 1) / G;
-  Block blk = philox10(c0w, t, static_cast<uint32_t>(grp), static_cast<uint32_t>(sample), g.key0, g.key1);
-  for (; grp > g_lo; --grp) {
-    const Block next = philox10(c0w, t, static_cast<uint32_t>(grp - 1), static_cast<uint32_t>(sample), g.key0, g.key1);
-    attempt_group<FP, kMaybeEarly>(g, bc, ws, sj, blk, grp, n0, clone0, nbits, early_beta_bits, flips);
-    blk = next;
+  const int g_lo = n0 / G, g_hi = (n0 + nbits - 1) / G;
+  if constexpr (!kSplit) {
+    // software-pipelined: the Philox block of the next group is computed
+    // beside the attempts of the current one (independent work for the SIMD)
+    int grp = g_hi;
+    Block blk = philox10(c0w, t, static_cast<uint32_t>(grp), static_cast<uint32_t>(sample), g.key0, g.key1);
+    for (; grp > g_lo; --grp) {
+      const Block next =
+          philox10(c0w, t, static_cast<uint32_t>(grp - 1), static_cast<uint32_t>(sample), g.key0, g.key1);
+      attempt_group<FP, kMaybeEarly>(g, bc, ws, sj, blk, grp, n0, clone0, nbits, early_beta_bits, flips);
+      blk = next;
+    }
+    attempt_group<FP, kMaybeEarly>(g, bc, ws, sj, blk, g_lo, n0, clone0, nbits, early_beta_bits, flips);
+    if (nbits < 32) flips &= (1u << nbits) - 1u;
+    plane[self_idx] = self ^ flips;
+  } else {
+    // F waves share the word: this one takes groups g_lo + f, g_lo + f + F, ...;
+    // each group's decisions land at their own bits, and the flips of the F
+    // work-items (disjoint bits) are combined with an atomic XOR
+    const int first = g_lo + f;
+    if (first > g_hi) return;
+    int grp = first + (g_hi - first) / F * F;
+    Block blk = philox10(c0w, t, static_cast<uint32_t>(grp), static_cast<uint32_t>(sample), g.key0, g.key1);
+    for (; grp > first; grp -= F) {
+      const Block next =
+          philox10(c0w, t, static_cast<uint32_t>(grp - F), static_cast<uint32_t>(sample), g.key0, g.key1);
+      uint32_t part = 0;
+      attempt_group<FP, kMaybeEarly>(g, bc, ws, sj, blk, grp, n0, clone0, nbits, early_beta_bits, part);
+      flips |= part << (G * (grp - g_lo));
+      blk = next;
+    }
+    uint32_t part = 0;
+    attempt_group<FP, kMaybeEarly>(g, bc, ws, sj, blk, first, n0, clone0, nbits, early_beta_bits, part);
+    flips |= part << (G * (first - g_lo));
+    if (nbits < 32) flips &= (1u << nbits) - 1u;
+    if (flips) atomicXor(&plane[self_idx], flips);
   }
-  attempt_group<FP, kMaybeEarly>(g, bc, ws, sj, blk, g_lo, n0, clone0, nbits, early_beta_bits, flips);
-  if (nbits < 32) flips &= (1u << nbits) - 1u;
-  plane[self_idx] = self ^ flips;
 }
 
 // n_pt sweeps of the PT clones and n_er sweeps of the ER clones, interleaved
 // sweep by sweep (the classes are independent).
-template <typename FP, int CH>
+template <typename FP, int CH, bool kSplit>
 __device__ __forceinline__ void sweep_phase(const Geo& g, const Lds& s, const FP* Js, const FP* __restrict__ bc,
                                             int sample, uint32_t t, int m_pt0, int n_pt, int m_er0, int n_er,
-                                            float early_beta, float beta_cold) {
-  const Own<CH> own(g.V);
+                                            float early_beta, float beta_cold, int F) {
+  // kSplit: F waves share each wave-sized block of site chunks, wave f of the
+  // F taking every F-th clone group (wave-uniform, so no divergence)
+  const int wv = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) / kWave);
+  const int f = kSplit ? wv % F : 0;
+  const Own<CH> own(g.V, kSplit ? (wv / F) * kWave + lane_id() : static_cast<int>(threadIdx.x));
   // Couplings of own sites in the form the field uses (SiteJ).  FP32 (and
   // FP64 with 2 sites per work-item) keeps both colours in registers for all
   // sweeps of the phase; FP64 with 4 sites reloads the current colour's
@@ -642,26 +673,26 @@ __device__ __forceinline__ void sweep_phase(const Geo& g, const Lds& s, const FP
           if (pt_on)
             for (int w = 0; w < g.NWPT; ++w) {
               if (pt_early)
-                update_word<FP, true>(g, bc, s.sp + size_t(w) * g.V, self_idx, nb, sj[slot][q],
-                                      c0pt | static_cast<uint32_t>(st.i), t, sample, 32 * w, 32 * w,
-                                      min(32, g.NPT - 32 * w), early_bits);
+                update_word<FP, true, kSplit>(g, bc, s.sp + size_t(w) * g.V, self_idx, nb, sj[slot][q],
+                                              c0pt | static_cast<uint32_t>(st.i), t, sample, 32 * w, 32 * w,
+                                              min(32, g.NPT - 32 * w), early_bits, f, F);
               else
-                update_word<FP, false>(g, bc, s.sp + size_t(w) * g.V, self_idx, nb, sj[slot][q],
-                                       c0pt | static_cast<uint32_t>(st.i), t, sample, 32 * w, 32 * w,
-                                       min(32, g.NPT - 32 * w), early_bits);
+                update_word<FP, false, kSplit>(g, bc, s.sp + size_t(w) * g.V, self_idx, nb, sj[slot][q],
+                                               c0pt | static_cast<uint32_t>(st.i), t, sample, 32 * w, 32 * w,
+                                               min(32, g.NPT - 32 * w), early_bits, f, F);
             }
           if (er_on)
             for (int w = g.NWPT; w < g.NW; ++w) {
               const int e0 = 32 * (w - g.NWPT);
               // every reservoir clone sits at T_max: one uniform choice of path per word
               if (er_early)
-                update_word<FP, true>(g, bc, s.sp + size_t(w) * g.V, self_idx, nb, sj[slot][q],
-                                      c0er | static_cast<uint32_t>(st.i), t, sample, g.NPT + e0, n_er0 + e0,
-                                      min(32, g.NER - e0), early_bits);
+                update_word<FP, true, kSplit>(g, bc, s.sp + size_t(w) * g.V, self_idx, nb, sj[slot][q],
+                                              c0er | static_cast<uint32_t>(st.i), t, sample, g.NPT + e0, n_er0 + e0,
+                                              min(32, g.NER - e0), early_bits, f, F);
               else
-                update_word<FP, false>(g, bc, s.sp + size_t(w) * g.V, self_idx, nb, sj[slot][q],
-                                       c0er | static_cast<uint32_t>(st.i), t, sample, g.NPT + e0, n_er0 + e0,
-                                       min(32, g.NER - e0), early_bits);
+                update_word<FP, false, kSplit>(g, bc, s.sp + size_t(w) * g.V, self_idx, nb, sj[slot][q],
+                                               c0er | static_cast<uint32_t>(st.i), t, sample, g.NPT + e0, n_er0 + e0,
+                                               min(32, g.NER - e0), early_bits, f, F);
             }
         }
       }
@@ -1312,7 +1343,7 @@ __device__ __forceinline__ void store_spins(const Geo& g, const Lds& s, const St
   store_spins(g, s.sp, st, sample);
 }
 
-template <typename FP, int CH>
+template <typename FP, int CH, bool kSplit>
 __global__ __launch_bounds__(kMaxThreads) void sweep_kernel(Geo g, State st, Run run) {
   const int sample = run.sample_begin + blockIdx.x;
   if (sample >= g.S) return;  // the whole workgroup leaves together
@@ -1324,7 +1355,8 @@ __global__ __launch_bounds__(kMaxThreads) void sweep_kernel(Geo g, State st, Run
   const uint32_t t = *st.t_dev;
   // beta of the coldest temperature in the units the clone table holds
   const float beta_cold = sizeof(FP) == 8 ? static_cast<float>(st.beta64[0]) : st.beta32[0];
-  sweep_phase<FP, CH>(g, s, Js, bc, sample, t, run.m_pt0, run.n_pt, run.m_er0, run.n_er, run.early_beta, beta_cold);
+  sweep_phase<FP, CH, kSplit>(g, s, Js, bc, sample, t, run.m_pt0, run.n_pt, run.m_er0, run.n_er, run.early_beta,
+                              beta_cold, run.clone_split);
   store_spins(g, s, st, sample);
 }
 
@@ -1420,20 +1452,23 @@ hipError_t set_lds(K kern, size_t lds) {
 template <typename FP, int CH>
 hipError_t prepare_t(size_t lds) {
   hipError_t e;
-  if ((e = set_lds(sweep_kernel<FP, CH>, lds)) != hipSuccess) return e;
+  if ((e = set_lds(sweep_kernel<FP, CH, false>, lds)) != hipSuccess) return e;
+  if ((e = set_lds(sweep_kernel<FP, CH, true>, lds)) != hipSuccess) return e;
   if ((e = set_lds(houdayer_kernel, lds)) != hipSuccess) return e;
   if ((e = set_lds(pt_kernel<FP, CH>, lds)) != hipSuccess) return e;
   return set_lds(measure_kernel<FP, CH>, lds);
 }
 
 template <typename FP, int CH>
-hipError_t launch_t(const Geo& g, const State& st, const Obs& ob, const Run& run, int threads, int n_blocks,
-                    hipStream_t stream) {
+hipError_t launch_t(const Geo& g, const State& st, const Obs& ob, const Run& run, int threads, int split,
+                    int n_blocks, hipStream_t stream) {
   const size_t lds = plan_lds(g, sizeof(FP)).total;
   hipError_t e = hipSuccess;
   if (run.phases & kPhaseSweep) {
-    auto k = sweep_kernel<FP, CH>;
-    hipLaunchKernelGGL(k, dim3(n_blocks), dim3(threads), lds, stream, g, st, run);
+    Run r = run;
+    r.clone_split = split;
+    auto k = split > 1 ? sweep_kernel<FP, CH, true> : sweep_kernel<FP, CH, false>;
+    hipLaunchKernelGGL(k, dim3(n_blocks), dim3(threads * split), lds, stream, g, st, r);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   if (run.phases & (kPhaseHoudayer | kPhaseLabels | kPhaseClusterStats)) {
@@ -1493,7 +1528,7 @@ int houdayer_moves_per_pass(const Geo& g, int threads, bool stats) {
 
 hipError_t launch_emcs(int precision, const Geo& g, const State& st, const Obs& ob, const Run& run,
                        const Shape& sh, int n_blocks, hipStream_t stream) {
-#define PTHR_LAUNCH(FP, CH) return launch_t<FP, CH>(g, st, ob, run, sh.threads, n_blocks, stream)
+#define PTHR_LAUNCH(FP, CH) return launch_t<FP, CH>(g, st, ob, run, sh.threads, sh.split, n_blocks, stream)
   if (precision == 0) {
     switch (sh.chunk) {
       case 2: PTHR_LAUNCH(double, 2);

@@ -127,7 +127,10 @@ def test_l6_ragged_words_and_single_cluster(precision):
     16; 6 ER clones) and Houdayer's single-cluster mode."""
     step(f"l6 ragged single {precision}")
     o, g = make_pair(6, 3, 2, 7, 3, precision=precision, mode="single", er_sweeps=12, t_range=(0.2, 1.4))
-    stepwise(o, g, 4)
+    assert g.schedule().clone_split == 4  # 128 work-items: the default shares clone words among 4 waves
+    stepwise(o, g, 2)
+    g.set_schedule(clone_split=2)
+    stepwise(o, g, 2)
 
 
 def test_l2_smallest_lattice_and_two_temperatures():
@@ -274,9 +277,10 @@ def test_every_schedule_gives_the_same_bits(precision):
     step(f"schedules {precision}")
     pthr = _pthr()
     ref = None
-    for threads, early, per in ((256, 700, 0), (128, 100000, 0), (256, 0, 1), (128, 1000, 2)):
+    for threads, early, per, split in ((256, 700, 0, 1), (128, 100000, 0, 1), (256, 0, 1, 1), (128, 1000, 2, 1),
+                                       (256, 0, 0, 4), (128, 700, 0, 2), (128, 0, 2, 8 // 2)):
         _, g = make_pair(8, 3, 4, 10, 4, precision=precision, er_sweeps=20)
-        g.set_schedule(threads_per_sample=threads, exp_early_out=early, samples_per_launch=per)
+        g.set_schedule(threads_per_sample=threads, exp_early_out=early, samples_per_launch=per, clone_split=split)
         go = g.new_obs()
         g.run(2, go)
         got = (g.read_spins(), g.read_pt(), g.obs_arrays(go))
