@@ -14,6 +14,7 @@ from __future__ import annotations
 import argparse
 import dataclasses
 import json
+import math
 import os
 import sys
 import time
@@ -172,13 +173,18 @@ def bench_mixed(args) -> dict:
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     members = []
-    for w in inputs.MIXED_BATCH:
+    batch = [dataclasses.replace(w, n_reservoir=0, t_acu=0.0) if args.mode == "plain" else w
+             for w in inputs.MIXED_BATCH]
+    for w in batch:
         g = pthr.Pthr(w.L, w.n_samples, w.n_replicas, w.n_temps, w.n_reservoir, w.sweeps_per_emcs,
-                      w.er_sweeps_per_emcs, w.precision, args.mode, w.t_acu, w.seed)
+                      w.er_sweeps_per_emcs, w.precision, "single" if args.mode == "single" else "acu", w.t_acu,
+                      w.seed)
         g.init_samples(w.couplings(), w.temperatures())
         if not args.no_autotune:  # the mixed batch is defined with per-size autotuned schedules
-            best = g.autotune(1)
+            # each candidate timed over >= ~1.5e10 attempts, so that small lattices are not timed on one EMCS
+            best = g.autotune(max(1, math.ceil(1.5e10 / attempts_per_emcs(w))))
             log(f"autotune L={w.L}: {best:.2f} ms/EMCS, {g.schedule().threads_per_sample} work-items, "
+                f"clone split {g.schedule().clone_split}, "
                 f"early-out below T = {g.schedule().exp_early_out / 1000:g}")
         members.append(g)
     group = pthr.Group(members)
@@ -199,8 +205,8 @@ def bench_mixed(args) -> dict:
     sequential = time.perf_counter() - t1
     for g in members:
         g.check()
-    att = sum(attempts_per_emcs(w) for w in inputs.MIXED_BATCH)
-    moves = sum(moves_per_emcs(w, w.temperatures()) for w in inputs.MIXED_BATCH)
+    att = sum(attempts_per_emcs(w) for w in batch)
+    moves = sum(moves_per_emcs(w, w.temperatures()) for w in batch)
     value = att * args.steps / (elapsed * 1e9)
     log(f"mixed batch: {value:.1f} attempts/ns together, "
         f"{att * args.steps / (sequential * 1e9):.1f} one size after the other")
@@ -220,8 +226,9 @@ def bench_mixed(args) -> dict:
         "config": {"workload": "mixed_l8_to_l16",
                    "members": [{"L": w.L, "samples": w.n_samples, "temperatures": w.n_temps,
                                 "threads_per_sample": g.schedule().threads_per_sample,
-                                "exp_early_out_below_T": g.schedule().exp_early_out / 1000}
-                               for w, g in zip(inputs.MIXED_BATCH, members)],
+                                "exp_early_out_below_T": g.schedule().exp_early_out / 1000,
+                                "clone_split": g.schedule().clone_split}
+                               for w, g in zip(batch, members)],
                    "replicas": 4, "reservoir_clones": 4, "houdayer": args.mode},
         "attempts_per_emcs": att,
         "houdayer_moves_per_s": moves * args.steps / elapsed,
@@ -300,10 +307,11 @@ def main() -> int:
     g.init_samples(w.couplings(), T)
     obs = g.new_obs()
     if args.autotune:
-        best = g.autotune(1)
+        # time each candidate over >= ~1.5e10 attempts so that small lattices are not timed on one EMCS
+        best = g.autotune(max(1, math.ceil(1.5e10 / attempts_per_emcs(w))))
         sch = g.schedule()
         log(f"autotune: {best:.2f} ms/EMCS with {sch.threads_per_sample} work-items per sample, "
-            f"exp early-out below T = {sch.exp_early_out / 1000:g}")
+            f"clone split {sch.clone_split}, exp early-out below T = {sch.exp_early_out / 1000:g}")
     stream = torch.cuda.current_stream(dev)
     n_er = w.er_sweeps_per_emcs if w.n_reservoir else 0
 
@@ -357,7 +365,8 @@ def main() -> int:
                    "reservoir_clones": w.n_reservoir, "sweeps_per_emcs": w.sweeps_per_emcs,
                    "reservoir_sweeps_per_emcs": w.er_sweeps_per_emcs, "houdayer": args.mode,
                    "threads_per_sample": g.schedule().threads_per_sample,
-                   "exp_early_out_below_T": g.schedule().exp_early_out / 1000},
+                   "exp_early_out_below_T": g.schedule().exp_early_out / 1000,
+                   "clone_split": g.schedule().clone_split},
         "houdayer_moves_per_s": moves * args.steps / elapsed,
         "attempts_per_emcs": att,
         "wall_time_per_equilibrated_sample_s":

@@ -775,7 +775,9 @@ int pthr_autotune(pthr_ctx* ctx, void* d_scratch, int n_emcs, double* best_ms, v
       ctx->d_state = static_cast<unsigned char*>(d_scratch);
       ctx->t = t_saved;
       float ms = 0.f;
-      if (hipEventRecord(e0, s) != hipSuccess) rc = ctx->fail(PTHR_EHIP, "autotune event");
+      // one untimed EMCS first (caches, clocks), then the timed ones
+      rc = pthr_run(ctx, 1, nullptr, stream);
+      if (rc == PTHR_OK && hipEventRecord(e0, s) != hipSuccess) rc = ctx->fail(PTHR_EHIP, "autotune event");
       if (rc == PTHR_OK) rc = pthr_run(ctx, n_emcs, nullptr, stream);
       if (rc == PTHR_OK && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
                             hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
@@ -793,7 +795,7 @@ int pthr_autotune(pthr_ctx* ctx, void* d_scratch, int n_emcs, double* best_ms, v
   ctx->t = t_saved;
   ctx->e_current = e_saved;
   ctx->sch = rc == PTHR_OK ? best : saved;
-  if (best_ms) *best_ms = best_t;
+  if (best_ms) *best_ms = best_t / n_emcs;
   return rc;
 }
 
