@@ -26,6 +26,7 @@ CFLAGS = ["-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off"
 FP64, FP32 = 0, 1
 ACU, SINGLE_NEG = 0, 1
 SWEEP_PT, SWEEP_ER = 1, 2
+METROPOLIS, HEAT_BATH = 0, 1
 NOBS = 6
 OBS_NAMES = ("e", "e2", "q2", "q4", "ql", "sdy")
 
@@ -55,7 +56,8 @@ class OracleParams(ctypes.Structure):
                 ("n_temps", ctypes.c_int32), ("n_reservoir", ctypes.c_int32),
                 ("sweeps_per_emcs", ctypes.c_int32), ("er_sweeps_per_emcs", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("houdayer_mode", ctypes.c_int32),
-                ("t_acu", ctypes.c_double), ("seed", ctypes.c_uint64)]
+                ("t_acu", ctypes.c_double), ("seed", ctypes.c_uint64),
+                ("local_update", ctypes.c_int32)]
 
 
 def _lib() -> ctypes.CDLL:
@@ -89,6 +91,10 @@ def _lib() -> ctypes.CDLL:
     lib.oracle_uniform32.argtypes = [ctypes.c_uint32]
     lib.oracle_pexp2_32.restype = ctypes.c_float
     lib.oracle_pexp2_32.argtypes = [ctypes.c_float]
+    lib.oracle_heat_bath_flip.restype = i32
+    lib.oracle_heat_bath_flip.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double]
+    lib.oracle_heat_bath_flip32.restype = i32
+    lib.oracle_heat_bath_flip32.argtypes = [ctypes.c_float, ctypes.c_float, ctypes.c_float]
     lib.oracle_energy.restype = ctypes.c_double
     lib.oracle_energy.argtypes = [vp, i32, i32]
     lib.oracle_delta_e.restype = ctypes.c_double
@@ -128,6 +134,14 @@ def pexp2_32(t: float) -> np.float32:
     return np.float32(_lib().oracle_pexp2_32(float(np.float32(t))))
 
 
+def heat_bath_flip(u: float, a: float, dE: float, fp32: bool = False) -> bool:
+    """Heat-bath test given a = exp(-beta |dE|) (FP32 form if fp32)."""
+    if fp32:
+        return bool(_lib().oracle_heat_bath_flip32(float(np.float32(u)), float(np.float32(a)),
+                                                   float(np.float32(dE))))
+    return bool(_lib().oracle_heat_bath_flip(float(u), float(a), float(dE)))
+
+
 class Observables:
     """Accumulators filled by ``measure``: acc [S][N_T][6] (sum e, e^2, q^2, q^4,
     q_l, S), the pooled overlap histogram hist [N_T][V+1] and the count."""
@@ -144,11 +158,11 @@ class Oracle:
 
     def __init__(self, L, n_samples=1, n_replicas=2, n_temps=8, n_reservoir=0,
                  sweeps_per_emcs=10, er_sweeps_per_emcs=240, precision=FP64,
-                 houdayer_mode=ACU, t_acu=1.0, seed=1, first_sample=0):
+                 houdayer_mode=ACU, t_acu=1.0, seed=1, first_sample=0, local_update=METROPOLIS):
         self.lib = _lib()
         self.params = OracleParams(L, n_samples, first_sample, n_replicas, n_temps, n_reservoir,
                                    sweeps_per_emcs, er_sweeps_per_emcs, precision, houdayer_mode,
-                                   t_acu, seed)
+                                   t_acu, seed, local_update)
         err = ctypes.create_string_buffer(256)
         self.ctx = self.lib.oracle_create(ctypes.byref(self.params), err, 256)
         if not self.ctx:

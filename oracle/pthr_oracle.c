@@ -204,6 +204,7 @@ oracle_ctx *oracle_create(const oracle_params *p, char *err, size_t err_len) {
   else if (p->er_sweeps_per_emcs < 0 || p->er_sweeps_per_emcs > 256) msg = "er_sweeps_per_emcs must be in [0, 256]";
   else if (p->precision != ORACLE_FP64 && p->precision != ORACLE_FP32) msg = "precision must be FP64 or FP32";
   else if (p->houdayer_mode != ORACLE_ACU && p->houdayer_mode != ORACLE_SINGLE_NEG) msg = "houdayer_mode must be ACU or SINGLE_NEG";
+  else if (p->local_update != ORACLE_METROPOLIS && p->local_update != ORACLE_HEAT_BATH) msg = "local_update must be METROPOLIS or HEAT_BATH";
   if (msg) {
     if (err && err_len) snprintf(err, err_len, "%s", msg);
     return NULL;
@@ -315,26 +316,46 @@ static int metro_index(const oracle_ctx *c, int clone) {
   return clone < c->NPT ? clone : (c->NPT + 3) / 4 * 4 + (clone - c->NPT);
 }
 
-/* One Metropolis attempt on site i of a clone at inverse temperature index k:
- * accept with probability min{1, exp(-beta dE)}.  With n = metro_index(clone):
+/* Heat-bath test for a = exp(-beta |dE|): flip with probability a / (1 + a)
+ * if dE > 0, else 1 / (1 + a); u (1 + a) is formed as one fused
+ * multiply-add u a + u. */
+int oracle_heat_bath_flip(double u, double a, double dE) { return fma(u, a, u) < (dE > 0.0 ? a : 1.0); }
+int oracle_heat_bath_flip32(float u, float a, float dE) { return fmaf(u, a, u) < (dE > 0.0f ? a : 1.0f); }
+
+/* One local update of site i of a clone at inverse temperature index k.
+ * Metropolis (Sec. 3): accept the flip with probability min{1, exp(-beta dE)}.
+ * Heat bath (named in Sec. 3 as the alternative): flip with probability
+ * 1 / (1 + exp(beta dE)), the conditional Boltzmann probability of the
+ * flipped spin; with a = exp(-beta |dE|) it is a / (1 + a) for dE > 0 and
+ * 1 / (1 + a) otherwise, tested as u (1 + a) < a (resp. 1) with u (1 + a)
+ * rounded once (fma(u, a, u)).  Random numbers, with n = metro_index(clone):
  * FP64: the uniform takes words (0,1) of block n/2 for even n and (2,3) for
  * odd n.  FP32: word n%4 of block n/4. */
 static void metropolis_attempt(oracle_ctx *c, int s, int clone, int i, int k, int m) {
   int8_t *sp = clone_spins(c, s, clone);
   const int n = metro_index(c, clone);
+  const int heat_bath = c->p.local_update == ORACLE_HEAT_BATH;
   uint32_t w[4];
   int accept;
   if (c->p.precision == ORACLE_FP64) {
     draw(c, PURPOSE_METRO, (uint32_t)i, (uint32_t)m, (uint32_t)c->t, (uint32_t)(n / 2), s, w);
     double u = (n % 2 == 0) ? oracle_uniform53(w[0], w[1]) : oracle_uniform53(w[2], w[3]);
     double dE = oracle_delta_e(c, s, clone, i);
-    accept = (dE <= 0.0) || (u < oracle_pexp(-(c->beta[k] * dE)));
+    if (heat_bath) {
+      accept = oracle_heat_bath_flip(u, oracle_pexp(-(c->beta[k] * fabs(dE))), dE);
+    } else {
+      accept = (dE <= 0.0) || (u < oracle_pexp(-(c->beta[k] * dE)));
+    }
   } else {
     draw(c, PURPOSE_METRO, (uint32_t)i, (uint32_t)m, (uint32_t)c->t, (uint32_t)(n / 4), s, w);
     float u = oracle_uniform32(w[n % 4]);
     float dE = delta_e32(c, s, clone, i);
-    float t = -(c->bl32[k] * dE);
-    accept = (t >= -124.0f) && (u <= oracle_pexp2_32(t));
+    if (heat_bath) {
+      accept = oracle_heat_bath_flip32(u, oracle_pexp2_32(-(c->bl32[k] * fabsf(dE))), dE);
+    } else {
+      float t = -(c->bl32[k] * dE);
+      accept = (t >= -124.0f) && (u <= oracle_pexp2_32(t));
+    }
   }
   if (accept) sp[i] = (int8_t)-sp[i];
 }

@@ -35,6 +35,14 @@
  * (beta log2 e rounded to float once per temperature), accept iff t >= -124
  * and u <= 2^t, which accepts every dE <= 0.  Energies, the PT exponent and
  * all observable sums stay double in both forms.
+ *
+ * Local update: Metropolis (the paper's choice) or heat bath (the alternative
+ * Sec. 3 names): the spin is drawn from its conditional Boltzmann weight, i.e.
+ * flipped with probability 1 / (1 + exp(beta dE)).  With a = exp(-beta |dE|)
+ * (the same exponential routine; FP32: a = 2^t, t = -(beta log2 e)|dE|) that
+ * is a / (1 + a) for dE > 0 and 1 / (1 + a) for dE <= 0; the test is written
+ * without a division, flip iff fma(u, a, u) < a, resp. < 1, with the same
+ * random numbers as the Metropolis test.
  */
 #ifndef PTHR_ORACLE_H
 #define PTHR_ORACLE_H
@@ -49,6 +57,7 @@ extern "C" {
 enum { ORACLE_FP64 = 0, ORACLE_FP32 = 1 };
 enum { ORACLE_ACU = 0, ORACLE_SINGLE_NEG = 1 };
 enum { ORACLE_SWEEP_PT = 1, ORACLE_SWEEP_ER = 2 };
+enum { ORACLE_METROPOLIS = 0, ORACLE_HEAT_BATH = 1 };
 enum { ORACLE_NOBS = 6 }; /* sum e, sum e^2, sum q^2, sum q^4, sum q_l, sum S */
 
 typedef struct oracle_params {
@@ -64,6 +73,7 @@ typedef struct oracle_params {
   int32_t houdayer_mode;      /* ORACLE_ACU or ORACLE_SINGLE_NEG               */
   double t_acu;               /* Houdayer moves at T_k < t_acu (paper: 1.0)    */
   uint64_t seed;
+  int32_t local_update;       /* ORACLE_METROPOLIS (paper) or ORACLE_HEAT_BATH */
 } oracle_params;
 
 typedef struct oracle_ctx oracle_ctx;
@@ -114,6 +124,9 @@ double oracle_pexp(double x);
 double oracle_uniform53(uint32_t lo, uint32_t hi);
 float oracle_uniform32(uint32_t w);
 float oracle_pexp2_32(float t); /* FP32 form: 2^t, 0 below t = -124 */
+/* Heat-bath flip test given a = exp(-beta |dE|): fma(u, a, u) < (dE > 0 ? a : 1). */
+int oracle_heat_bath_flip(double u, double a, double dE);
+int oracle_heat_bath_flip32(float u, float a, float dE);
 double oracle_energy(const oracle_ctx *c, int s, int clone);
 double oracle_delta_e(const oracle_ctx *c, int s, int clone, int site);
 int oracle_num_threads(void);

@@ -51,10 +51,12 @@ def boltzmann(J: np.ndarray, L: int, beta: float) -> np.ndarray:
     return w / w.sum()
 
 
-def sweep_kernel(J: np.ndarray, L: int, beta: float) -> np.ndarray:
-    """Exact transition matrix of one checkerboard Metropolis sweep: sites of
-    parity 0 in increasing order, then parity 1, each flipped with probability
-    min{1, exp(-beta (H(flipped) - H))} (paper Sec. 3 and App. A.1)."""
+def sweep_kernel(J: np.ndarray, L: int, beta: float, rule: str = "metropolis") -> np.ndarray:
+    """Exact transition matrix of one checkerboard sweep: sites of parity 0 in
+    increasing order, then parity 1, each flipped with probability
+    min{1, exp(-beta dH)} (Metropolis, paper Sec. 3 and App. A.1) or
+    1 / (1 + exp(beta dH)) (heat bath: the spin drawn from its conditional
+    Boltzmann weight), dH = H(flipped) - H."""
     V = L ** 3
     states = all_states(V)
     E = energy(states, J, L)
@@ -65,7 +67,11 @@ def sweep_kernel(J: np.ndarray, L: int, beta: float) -> np.ndarray:
     idx = np.arange(n)
     for i in order:
         flipped = idx ^ (1 << i)
-        acc = np.minimum(1.0, np.exp(-beta * (E[flipped] - E)))
+        dH = E[flipped] - E
+        if rule == "metropolis":
+            acc = np.minimum(1.0, np.exp(-beta * dH))
+        else:
+            acc = 1.0 / (1.0 + np.exp(beta * dH))
         K = np.zeros((n, n))
         K[idx, flipped] = acc
         K[idx, idx] = 1.0 - acc

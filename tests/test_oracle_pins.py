@@ -11,6 +11,7 @@ import shutil
 import subprocess
 import tempfile
 from decimal import Decimal, getcontext
+from fractions import Fraction
 
 import numpy as np
 import pytest
@@ -192,16 +193,19 @@ def _reset_identity(o):
         o.clone_at[:, r, :] = r * o.NT + np.arange(o.NT)
 
 
+@pytest.mark.parametrize("rule", ["metropolis", "heatbath"])
 @pytest.mark.parametrize("precision", [oracle.FP64, oracle.FP32])
-def test_one_sweep_matches_exact_kernel_L2(precision):
+def test_one_sweep_matches_exact_kernel_L2(precision, rule):
     """Distribution after one checkerboard sweep from a fixed state equals the
-    row of the exact sweep kernel built from min{1, exp(-beta dE)}."""
+    row of the exact sweep kernel built from min{1, exp(-beta dE)}
+    (Metropolis) or 1 / (1 + exp(beta dE)) (heat bath)."""
     L, beta = 2, 1.0 / 0.9
     J = inputs.couplings(L, 1, seed=21)
-    P = defs.sweep_kernel(J[0], L, beta)
+    P = defs.sweep_kernel(J[0], L, beta, rule)
     pi = defs.boltzmann(J[0], L, beta)
     assert np.allclose(pi @ P, pi, atol=1e-14)  # the kernel itself is stationary
-    o = oracle.Oracle(L, 1, 2, 2, 0, precision=precision, t_acu=0.0, seed=99)
+    update = oracle.METROPOLIS if rule == "metropolis" else oracle.HEAT_BATH
+    o = oracle.Oracle(L, 1, 2, 2, 0, precision=precision, t_acu=0.0, seed=99, local_update=update)
     T = np.array([0.9, 1.9])
     o.init(J, T)
     start = o.spins[0, 0].copy()
@@ -217,17 +221,18 @@ def test_one_sweep_matches_exact_kernel_L2(precision):
     assert defs.chi2_pvalue(counts, P[g0]) > 1e-4
 
 
+@pytest.mark.parametrize("update", [oracle.METROPOLIS, oracle.HEAT_BATH])
 @pytest.mark.parametrize("precision", [oracle.FP64, oracle.FP32])
-def test_chain_samples_boltzmann_L2(precision):
-    """Metropolis + ACU + PT + ER at L=2: the state of the clone at every
-    temperature is Boltzmann distributed (paper Sec. 3: every step satisfies
-    detailed balance)."""
+def test_chain_samples_boltzmann_L2(precision, update):
+    """Metropolis (or heat bath) + ACU + PT + ER at L=2: the state of the clone
+    at every temperature is Boltzmann distributed (paper Sec. 3: every step
+    satisfies detailed balance)."""
     L = 2
     J = inputs.couplings(L, 1, seed=4)
     T = np.array([0.6, 1.0, 1.6])
     o = oracle.Oracle(L, n_samples=4, n_replicas=2, n_temps=3, n_reservoir=2,
                       sweeps_per_emcs=1, er_sweeps_per_emcs=2, precision=precision,
-                      t_acu=1.2, seed=17)
+                      t_acu=1.2, seed=17, local_update=update)
     o.init(np.repeat(J, 4, axis=0), T)
     counts = np.zeros((3, 256))
     for _ in range(6000):
@@ -490,6 +495,130 @@ def test_metropolis_decisions_follow_the_documented_random_stream():
         assert checked == 300 * 4
 
 
+def _round_to_float(x: Fraction, bits: int) -> Fraction:
+    """x > 0 rounded to the nearest binary floating-point number with a
+    `bits`-bit significand, ties to even (normal range only)."""
+    e = x.numerator.bit_length() - x.denominator.bit_length()
+    if Fraction(2) ** e > x:
+        e -= 1
+    scale = Fraction(2) ** (e - bits + 1)  # one unit in the last place
+    m = x / scale
+    n = m.numerator // m.denominator
+    rem = m - n
+    if rem > Fraction(1, 2) or (rem == Fraction(1, 2) and n % 2 == 1):
+        n += 1
+    return n * scale
+
+
+def _heat_bath_site0(o, precision, seed, c, n, m, beta, before, J32):
+    """Heat-bath decision of site 0 for clone c (random-number index n, sweep
+    m): flip with probability 1/(1 + exp(beta dE)), written as
+    u (1 + a) < a (dE > 0) or < 1 (dE <= 0) with a = exp(-beta |dE|) and
+    u (1 + a) = u a + u rounded once (a fused multiply-add).  The rounding is
+    done here on exact rationals."""
+    if precision == oracle.FP64:
+        dE = o.delta_e(0, c, 0)
+        blk = oracle.philox([0 | (m << 16) | (2 << 24), o.t, n // 2, 0], [seed & 0xFFFFFFFF, seed >> 32])
+        lo, hi = (blk[0], blk[1]) if n % 2 == 0 else (blk[2], blk[3])
+        u = Fraction(((int(hi) << 32) | int(lo)) >> 11, 2 ** 53)
+        a = Fraction(oracle.pexp(-(beta * abs(dE))))
+        bits = 53
+        pos = dE > 0
+    else:
+        blk = oracle.philox([0 | (m << 16) | (2 << 24), o.t, n // 4, 0], [seed & 0xFFFFFFFF, seed >> 32])
+        u = Fraction(float(np.float32(np.float32(blk[n % 4]) * np.float32(2.0 ** -32))))
+        sp = before[c]
+        nb = [(1, 0, 0), (1, 0, 1), (2, 1, 0), (2, 1, 1), (4, 2, 0), (4, 2, 1)]
+        terms = [np.float32(J32[axis][j if back else 0]) * np.float32(sp[j]) for j, axis, back in nb]
+        h = np.float32(np.float32(np.float32(terms[0] + terms[1]) + np.float32(terms[2] + terms[3]))
+                       + np.float32(terms[4] + terms[5]))
+        dE32 = np.float32(np.float32(2.0) * np.float32(sp[0])) * h
+        bl = np.float32(beta * 1.4426950408889634)
+        a = Fraction(float(oracle.pexp2_32(np.float32(-(bl * np.float32(abs(dE32)))))))
+        bits = 24
+        pos = dE32 > 0
+    lhs = u * a + u
+    if lhs > 0:
+        lhs = _round_to_float(lhs, bits)
+    return lhs < (a if pos else 1)
+
+
+def test_heat_bath_decisions_follow_the_documented_random_stream():
+    """Replays heat-bath decisions at site 0 from the pinned Philox stream and
+    exponentials, with the fused multiply-add rounded on exact rationals; both
+    precisions, with temperatures where both outcomes are frequent."""
+    for precision in (oracle.FP64, oracle.FP32):
+        L, seed = 2, 78
+        o = oracle.Oracle(L, 1, 2, 2, 0, precision=precision, t_acu=0.0, seed=seed,
+                          local_update=oracle.HEAT_BATH)
+        J = inputs.couplings(L, 1, seed=3)
+        T = np.array([0.7, 3.0])
+        o.init(J, T)
+        J32 = J[0].astype(np.float32).astype(np.float64)
+        checked = flips = 0
+        for _ in range(300):
+            _reset_identity(o)
+            before = o.spins[0].copy()
+            predictions = {}
+            for c in range(o.NPT):
+                k = list(o.clone_at[0].ravel()).index(c) % o.NT
+                predictions[c] = _heat_bath_site0(o, precision, seed, c, c, 0, 1.0 / T[k], before, J32)
+            o.sweep(1, oracle.SWEEP_PT)
+            for c, acc in predictions.items():
+                assert (o.spins[0, c, 0] != before[c, 0]) == acc
+                checked += 1
+                flips += int(acc)
+            o.pt_swap(False)
+        assert checked == 300 * 4 and 0.2 * checked < flips < 0.8 * checked
+
+
+def test_heat_bath_test_rounds_once_and_is_strict():
+    """The heat-bath test flips iff RN(u a + u) < a (dE > 0) or < 1 (dE <= 0),
+    with ONE rounding of u a + u and a strict comparison.  Cases are built next
+    to the threshold u = a / (1 + a) (resp. 1 / (1 + a)), where a rounding of
+    u a before the add, or a non-strict comparison, changes the outcome; the
+    expected outcome is computed on exact rationals."""
+    rng = np.random.default_rng(11)
+    ties = double_rounding_witnesses = 0
+    for fp32, bits in ((False, 53), (True, 24)):
+        for _ in range(400):
+            a_f = float(np.float32(rng.uniform(0.05, 1.0))) if fp32 else float(rng.uniform(0.05, 1.0))
+            a = Fraction(a_f)
+            for dE, th in ((1.0, a), (-1.0, Fraction(1))):
+                u0 = th / (1 + a)
+                u0 = _round_to_float(u0, bits)
+                e = u0.numerator.bit_length() - u0.denominator.bit_length()
+                if Fraction(2) ** e > u0:
+                    e -= 1
+                ulp = Fraction(2) ** (e - bits + 1)
+                for j in range(-3, 4):
+                    u = u0 + j * ulp
+                    if _round_to_float(u, bits) != u:
+                        continue  # crossed into a coarser binade
+                    lhs = _round_to_float(u * a + u, bits)
+                    expect = lhs < th
+                    got = oracle.heat_bath_flip(float(u), a_f, dE, fp32)
+                    assert got == expect, (fp32, float(u), a_f, dE)
+                    ties += int(lhs == th)
+                    two = _round_to_float(_round_to_float(u * a, bits) + u, bits)
+                    double_rounding_witnesses += int((two < th) != expect)
+    # the grid really contains the cases that tell the definitions apart
+    assert ties > 0 and double_rounding_witnesses > 0, (ties, double_rounding_witnesses)
+
+
+def test_heat_bath_rounding_helper():
+    """The rational rounding used above against IEEE arithmetic on values
+    where no fused operation is involved."""
+    rng = np.random.default_rng(5)
+    for _ in range(200):
+        x, y = rng.random(2) + 0.01
+        assert _round_to_float(Fraction(float(x)) * Fraction(float(y)), 53) == Fraction(float(x) * float(y))
+        xf, yf = np.float32(x), np.float32(y)
+        assert _round_to_float(Fraction(float(xf)) * Fraction(float(yf)), 24) == Fraction(float(xf * yf))
+    assert _round_to_float(Fraction(3, 2) + Fraction(1, 2 ** 53), 53) == Fraction(3, 2)
+    assert _round_to_float(Fraction(1) + Fraction(3, 2 ** 53), 53) == 1 + Fraction(4, 2 ** 53)
+
+
 def test_reservoir_decisions_use_the_offset_random_index():
     """Reservoir clone e (id N_PT + e) draws its Metropolis numbers with index
     n = 4*ceil(N_PT/4) + e, at beta_max, on its own sweep counter.  With
@@ -600,15 +729,17 @@ def test_exact_enumerator_matches_numpy_at_L2():
         assert res["ql"][t] == pytest.approx(pi @ QL @ pi / 24, rel=1e-10)
 
 
-def test_chain_matches_exact_enumeration_L3():
-    """Full PTHR (Metropolis with the sequential checkerboard order, ACU at
-    T < 1, PT, ER) on an L=3 sample against its exact <H>/V, <q_l> and P(Q)."""
+@pytest.mark.parametrize("update", [oracle.METROPOLIS, oracle.HEAT_BATH])
+def test_chain_matches_exact_enumeration_L3(update):
+    """Full PTHR (Metropolis or heat bath with the sequential checkerboard
+    order, ACU at T < 1, PT, ER) on an L=3 sample against its exact <H>/V,
+    <q_l> and P(Q)."""
     g = json.load(open(os.path.join(HERE, "golden", "l3_exact.json")))
     L, T = g["L"], np.array(g["T"])
     S = 16
     J = inputs.couplings(L, 1, seed=g["seed"], first_sample=g["sample"])
     o = oracle.Oracle(L, n_samples=S, n_replicas=2, n_temps=len(T), n_reservoir=4,
-                      sweeps_per_emcs=2, er_sweeps_per_emcs=6, t_acu=1.0, seed=23)
+                      sweeps_per_emcs=2, er_sweeps_per_emcs=6, t_acu=1.0, seed=23, local_update=update)
     o.init(np.repeat(J, S, axis=0), T)
     o.run(200)  # burn-in
     obs = o.new_observables()
