@@ -130,7 +130,8 @@ def uniform32(w: int) -> np.float32:
 
 
 def pexp2_32(t: float) -> np.float32:
-    """FP32 form of the Metropolis exponential: 2^t (0 below t = -124)."""
+    """FP32 form of the Metropolis exponential: 2^t (IEEE overflow to +inf,
+    gradual underflow to 0)."""
     return np.float32(_lib().oracle_pexp2_32(float(np.float32(t))))
 
 

@@ -138,9 +138,10 @@ double oracle_pexp(double x) {
  * t = -(beta log2(e)) dE.  t = k + f with k = rint(t) and f = t - k (exact,
  * |f| <= 1/2); 2^f = e^(f ln 2) by its Taylor polynomial of degree 7, the
  * coefficients (ln 2)^n / n! computed in double and rounded to float, Horner
- * with fma; then 2^k.  0 below t = -124. */
+ * with fma; then 2^k by ldexpf, which overflows to +inf and underflows
+ * gradually to 0 (the Metropolis test below decides the same whether a GPU
+ * keeps or flushes those subnormals: u is 0 or at least 2^-32). */
 float oracle_pexp2_32(float t) {
-  if (t < -124.0f) return 0.0f;
   float coef[8];
   double v = 1.0;
   for (int n = 0; n <= 7; ++n) {
@@ -351,10 +352,13 @@ static void metropolis_attempt(oracle_ctx *c, int s, int clone, int i, int k, in
     float u = oracle_uniform32(w[n % 4]);
     float dE = delta_e32(c, s, clone, i);
     if (heat_bath) {
-      accept = oracle_heat_bath_flip32(u, oracle_pexp2_32(-(c->bl32[k] * fabsf(dE))), dE);
+      /* a = 0 below t = -124, where 2^t would be subnormal and the test
+       * would depend on how the hardware treats subnormals */
+      float t = -(c->bl32[k] * fabsf(dE));
+      accept = oracle_heat_bath_flip32(u, t >= -124.0f ? oracle_pexp2_32(t) : 0.0f, dE);
     } else {
       float t = -(c->bl32[k] * dE);
-      accept = (t >= -124.0f) && (u <= oracle_pexp2_32(t));
+      accept = u <= oracle_pexp2_32(t);
     }
   }
   if (accept) sp[i] = (int8_t)-sp[i];

@@ -32,14 +32,16 @@
  * double: accept iff dE <= 0 or u < exp(-beta dE).  ORACLE_FP32 computes
  * couplings, local fields and the Metropolis exponent in float, as the FP32
  * form of the GPU path, with the exponent in base 2: t = -(beta log2 e) dE
- * (beta log2 e rounded to float once per temperature), accept iff t >= -124
- * and u <= 2^t, which accepts every dE <= 0.  Energies, the PT exponent and
- * all observable sums stay double in both forms.
+ * (beta log2 e rounded to float once per temperature), accept iff u <= 2^t
+ * (2^t by a float polynomial and 2^k, overflowing to +inf and underflowing to
+ * 0), which accepts every dE <= 0.  Energies, the PT exponent and all
+ * observable sums stay double in both forms.
  *
  * Local update: Metropolis (the paper's choice) or heat bath (the alternative
  * Sec. 3 names): the spin is drawn from its conditional Boltzmann weight, i.e.
  * flipped with probability 1 / (1 + exp(beta dE)).  With a = exp(-beta |dE|)
- * (the same exponential routine; FP32: a = 2^t, t = -(beta log2 e)|dE|) that
+ * (the same exponential routine; FP32: a = 2^t, t = -(beta log2 e)|dE|, and
+ * a = 0 below t = -124 where 2^t would be subnormal) that
  * is a / (1 + a) for dE > 0 and 1 / (1 + a) for dE <= 0; the test is written
  * without a division, flip iff fma(u, a, u) < a, resp. < 1, with the same
  * random numbers as the Metropolis test.
@@ -123,7 +125,7 @@ void oracle_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t
 double oracle_pexp(double x);
 double oracle_uniform53(uint32_t lo, uint32_t hi);
 float oracle_uniform32(uint32_t w);
-float oracle_pexp2_32(float t); /* FP32 form: 2^t, 0 below t = -124 */
+float oracle_pexp2_32(float t); /* FP32 form: 2^t (IEEE overflow and gradual underflow) */
 /* Heat-bath flip test given a = exp(-beta |dE|): fma(u, a, u) < (dE > 0 ? a : 1). */
 int oracle_heat_bath_flip(double u, double a, double dE);
 int oracle_heat_bath_flip32(float u, float a, float dE);

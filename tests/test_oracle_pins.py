@@ -140,8 +140,9 @@ def test_pexp_binade_bracket_and_monotone():
 
 def test_pexp2_32_within_two_float_ulp_and_bracketed():
     """FP32 form's 2^t: within 2 float ulp of 2^t (evaluated in double) on
-    [-124, 30]; 0 below -124; 2^k exactly at integers; and 2^(k-1) < 2^t <
-    2^(k+1) for k = rint(t), the bracket the GPU's early-out relies on."""
+    [-124, 30]; IEEE underflow below (subnormal, then 0) and overflow to
+    +inf; 2^k exactly at integers; and 2^(k-1) < 2^t < 2^(k+1) for
+    k = rint(t), the bracket the GPU's early-out relies on."""
     rng = np.random.default_rng(13)
     ts = np.concatenate([rng.uniform(-124, 0, 20000), rng.uniform(-1, 1, 10000), rng.uniform(0, 30, 2000),
                          np.arange(-124, 31, dtype=np.float64) + 0.5]).astype(np.float32)
@@ -156,7 +157,10 @@ def test_pexp2_32_within_two_float_ulp_and_bracketed():
     assert worst <= 2.0, worst
     for k in range(-124, 31):
         assert float(oracle.pexp2_32(float(k))) == 2.0 ** k
-    assert float(oracle.pexp2_32(-124.5)) == 0.0
+    assert 2.0 ** -125 < float(oracle.pexp2_32(-124.5)) < 2.0 ** -124
+    assert 0.0 < float(oracle.pexp2_32(-140.0)) == 2.0 ** -140  # subnormal, exact
+    assert float(oracle.pexp2_32(-200.0)) == 0.0
+    assert float(oracle.pexp2_32(200.0)) == float("inf")
     assert float(oracle.pexp2_32(-0.0)) == 1.0
     # monotone on a fine grid across a binade boundary
     grid = np.float32(-3.5) + np.arange(4096, dtype=np.float32) * np.float32(2.0 ** -10)
@@ -454,10 +458,10 @@ def _predict_site0(o, precision, seed, c, n, m, beta, before, J32):
     h = np.float32(np.float32(np.float32(terms[0] + terms[1]) + np.float32(terms[2] + terms[3]))
                    + np.float32(terms[4] + terms[5]))
     dE32 = np.float32(np.float32(2.0) * np.float32(sp[0])) * h
-    # FP32 form: t = -(beta log2(e)) dE, accept iff t >= -124 and u <= 2^t
+    # FP32 form: t = -(beta log2(e)) dE, accept iff u <= 2^t
     bl = np.float32(beta * 1.4426950408889634)
     t = np.float32(-(bl * dE32))
-    return bool(t >= -124.0) and u <= oracle.pexp2_32(t)
+    return bool(u <= oracle.pexp2_32(t))
 
 
 def test_metropolis_decisions_follow_the_documented_random_stream():
@@ -466,7 +470,7 @@ def test_metropolis_decisions_follow_the_documented_random_stream():
     uses block (site | m<<16 | 2<<24, t, c//2, sample), words (0,1) for even c
     and (2,3) for odd c, u = ((hi<<32 | lo) >> 11) * 2^-53, accept iff dE <= 0
     or u < exp(-beta dE); FP32 uses word c%4 of block c//4, u = float(w) *
-    2^-32, accept iff t >= -124 and u <= 2^t with t = -(beta log2 e) dE; the
+    2^-32, accept iff u <= 2^t with t = -(beta log2 e) dE; the
     local field is summed axis by axis ((+x,-x) + (+y,-y)) + (+z,-z).
     A flip then changes the recorded spin.  Pins the stream plumbing and the
     resolution of the uniforms to their definition."""
@@ -534,7 +538,8 @@ def _heat_bath_site0(o, precision, seed, c, n, m, beta, before, J32):
                        + np.float32(terms[4] + terms[5]))
         dE32 = np.float32(np.float32(2.0) * np.float32(sp[0])) * h
         bl = np.float32(beta * 1.4426950408889634)
-        a = Fraction(float(oracle.pexp2_32(np.float32(-(bl * np.float32(abs(dE32)))))))
+        t = np.float32(-(bl * np.float32(abs(dE32))))
+        a = Fraction(float(oracle.pexp2_32(t))) if t >= -124.0 else Fraction(0)
         bits = 24
         pos = dE32 > 0
     lhs = u * a + u
