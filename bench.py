@@ -27,24 +27,55 @@ sys.path.insert(0, ROOT)
 from paper_2605_25872_amd import inputs  # noqa: E402
 
 METRIC = "spin-flip attempts/ns + Houdayer moves/s, batched 3D EA L=16, one MI355X"
-# MI355X: 256 compute units x 4 SIMD x 16 lanes at 2.4 GHz -> one 32-bit (or
-# FP64) VALU operation per lane per cycle.
-VALU_PEAK_OPS = 256 * 64 * 2.4e9
+# MI355X: 256 compute units x 4 SIMDs at 2.4 GHz.  gfx950 issues a wave64
+# VALU instruction in 2 cycles (32 lane-operations per SIMD per cycle, the
+# FP32 vector rate of 157.3 TFLOP/s) for 32-bit floating-point add, mul and
+# fma and integer add, sub, logic and right shifts, and in 4 cycles (16 per
+# cycle, the FP64 vector rate of 78.6 TFLOP/s) for FP64 arithmetic and the
+# other 32-bit instructions the sweep needs: widening multiplies, three-input
+# logic, conversions, compares, rounding, ldexp, bit-field ops and left
+# shifts (`bench.py --issue-rates` measures each kind).
+FAST_OPS_PER_S = 256 * 4 * 32 * 2.4e9
+HALF_OPS_PER_S = 256 * 4 * 16 * 2.4e9
 # EMCS needed to equilibrate one L=16 sample (paper, App. A.2 table).
 T_EQ_EMCS = {12: 2 ** 17, 14: 6.4e6, 16: 3.84e7, 18: 3.48e7}
 
-# Algorithmic VALU operations of one Metropolis attempt, counted from the
-# method's steps with gfx950's three-operand instructions (one lane-operation
-# each), the exponential included for every attempt as the branch-free form
-# evaluates it:
-#   FP32: 1/4 of a Philox4x32-10 block (10 rounds x (2 widening multiplies +
-#   2 three-way XORs)) 10, uniform 1, local field (6 sign insertions + 5 adds)
-#   11, t = -(beta log2 e) dE 1, 2^t (rint, f, 7 Horner steps, scale 2) 11,
-#   test (2 compares) and flip bit 3: 37.
-#   FP64: 1/2 block 20, 53-bit uniform 3, local field 11, -beta dE 1, exp
-#   (2 for k, 2 Cody-Waite steps, 14 Horner steps, scale 1) 19, dE <= 0 and
-#   u < exp compares and flip bit 3: 57.
-OPS_PER_ATTEMPT = {"fp32": 10 + 1 + 11 + 1 + 11 + 3, "fp64": 20 + 3 + 11 + 1 + 19 + 3}
+# Algorithmic VALU operations of one attempt, counted from the method's steps
+# (one lane-operation per step, the exponential included for every attempt as
+# the branch-free form evaluates it), split by issue class ("fast": 2-cycle,
+# "half": 4-cycle instructions).
+#   Metropolis FP32 (36): half = 1/4 of a Philox4x32-10 block (10 rounds x
+#   (2 widening multiplies + 2 three-way XORs)) 10, float(w) 1, rint 1,
+#   2^k (convert + ldexp) 2, flip bit 1; fast = local field (6 sign
+#   insertions + 5 adds) 11, t = -(beta log2 e) dE 1, f = t - k 1, 7 Horner
+#   steps, test (2^t 2^32 - float(w)) 1.
+#   Metropolis FP64 (57): half = 1/2 block 20, two converts of the 53-bit
+#   uniform 2, 5 adds of the local field, -beta dE 1, exp (2 for k, 2
+#   Cody-Waite steps, 14 Horner steps, scale 1) 19, dE <= 0 and u < exp
+#   compares and the flip bit 3; fast = 6 sign insertions, 1 shift of the
+#   uniform.
+#   Heat bath FP32 (42): as Metropolis, plus u = float(w) 2^-32 (fast), a
+#   zeroed below the cut and the threshold a or 1 (a compare and a select
+#   each, half), the fused multiply-add (fast), and a compare instead of the
+#   subtraction (half).
+#   Heat bath FP64 (63): as Metropolis, plus the zeroing of a and the choice
+#   of threshold (a compare and two selects each) and the fused multiply-add
+#   (half), less the dE <= 0 compare.
+OPS_BY_CLASS = {
+    ("metropolis", "fp32"): {"fast": 11 + 1 + 1 + 7 + 1, "half": 10 + 1 + 1 + 2 + 1},
+    ("metropolis", "fp64"): {"fast": 6 + 1, "half": 20 + 2 + 5 + 1 + 19 + 3},
+    ("heatbath", "fp32"): {"fast": 11 + 1 + 1 + 7 + 1 + 1, "half": 10 + 1 + 1 + 2 + 2 + 2 + 1 + 1},
+    ("heatbath", "fp64"): {"fast": 6 + 1, "half": 20 + 2 + 5 + 1 + 19 + 3 + 3 + 1 + 2},
+}
+
+
+def valu_peak(update: str, precision: str) -> tuple[float, int]:
+    """Issue-limited rate of algorithmic operations (lane-operations per s)
+    for the attempt's mix of 2- and 4-cycle instructions, and the operations
+    per attempt."""
+    c = OPS_BY_CLASS[(update, precision)]
+    n = c["fast"] + c["half"]
+    return n / (c["fast"] / FAST_OPS_PER_S + c["half"] / HALF_OPS_PER_S), n
 
 
 # HBM bytes per sweep launch of the L=16 FP32 workload, from rocprofv3 counter
@@ -92,7 +123,7 @@ def moves_per_emcs(w, T) -> int:
     return w.n_samples * (w.n_replicas // 2) * k_acu
 
 
-def cpu_baseline(w, n_samples: int, mode: str) -> dict:
+def cpu_baseline(w, n_samples: int, mode: str, update: str = "metropolis") -> dict:
     """The CPU oracle on a bounded sample of the same workload (all host cores)."""
     import oracle
 
@@ -100,7 +131,8 @@ def cpu_baseline(w, n_samples: int, mode: str) -> dict:
     prec = oracle.FP64 if w.precision == "fp64" else oracle.FP32
     o = oracle.Oracle(w.L, n_samples, w.n_replicas, w.n_temps, w.n_reservoir, w.sweeps_per_emcs,
                       w.er_sweeps_per_emcs, prec, oracle.SINGLE_NEG if mode == "single" else oracle.ACU,
-                      w.t_acu, w.seed)
+                      w.t_acu, w.seed,
+                      local_update=oracle.HEAT_BATH if update == "heatbath" else oracle.METROPOLIS)
     o.init(w.couplings(n_samples), T)
     t0 = time.perf_counter()
     o.run(1)
@@ -111,6 +143,36 @@ def cpu_baseline(w, n_samples: int, mode: str) -> dict:
             "kind": "oracle", "seconds": dt,
             "houdayer_moves_per_s": moves_per_emcs(sub, T) / dt,
             "sample": f"{n_samples} of {w.n_samples} samples, 1 EMCS, {w.precision} oracle"}
+
+
+def issue_rates() -> dict:
+    """Cycles per wave64 instruction per SIMD for the VALU instruction kinds
+    of the sweep (libvaluprobe.so: 8 independent chains per work-item of one
+    inline-assembly instruction, 64 waves per SIMD offered), at the measured
+    time and the 2.4 GHz clock, 1024 SIMDs."""
+    import ctypes
+
+    import torch  # noqa: F401  (loads the HIP runtime the probe binds to)
+
+    path = os.path.join(ROOT, "paper_2605_25872_amd", "libvaluprobe.so")
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} not found: build it with `python -m paper_2605_25872_amd.build`")
+    lib = ctypes.CDLL(path)
+    lib.valu_probe_name.restype = ctypes.c_char_p
+    lib.valu_probe_name.argtypes = [ctypes.c_int]
+    lib.valu_probe_run.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
+                                   ctypes.POINTER(ctypes.c_double)]
+    out = {}
+    blocks = 1024 * 64 // 4  # 64 waves per SIMD of 4-wave workgroups, 1024 SIMDs
+    for k in range(lib.valu_probe_kinds()):
+        ms, n = ctypes.c_double(), ctypes.c_double()
+        rc = lib.valu_probe_run(k, blocks, 5, ctypes.byref(ms), ctypes.byref(n))
+        if rc != 0:
+            raise RuntimeError(f"valu_probe_run({k}) failed ({rc})")
+        cycles = ms.value * 1e-3 * 2.4e9 * 1024 / n.value
+        out[lib.valu_probe_name(k).decode()] = round(cycles, 2)
+        log(f"{lib.valu_probe_name(k).decode():18s} {cycles:.2f} cycles per wave64 instruction per SIMD")
+    return {"issue_cycles_per_wave64_instruction": out, "clock_ghz": 2.4, "simds": 1024}
 
 
 def precision_check(args) -> dict:
@@ -251,6 +313,8 @@ def main() -> int:
                     help="'mixed': L = 8..16 side by side, one graph launch per EMCS")
     ap.add_argument("--mode", default="acu", choices=["acu", "single", "plain"],
                     help="Houdayer all-cluster (paper), single cluster, or plain PT (no Houdayer, no reservoir)")
+    ap.add_argument("--update", default="metropolis", choices=["metropolis", "heatbath"],
+                    help="local update: Metropolis (paper) or heat bath")
     ap.add_argument("--cpu-samples", type=int, default=192)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--compare-fp64-samples", type=int, default=16,
@@ -259,6 +323,8 @@ def main() -> int:
     ap.add_argument("--no-autotune", action="store_true", help="mixed batch: keep the default schedules")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy a MIB-MiB device buffer 3 times (HBM counter calibration)")
+    ap.add_argument("--issue-rates", action="store_true",
+                    help="only measure the issue cost of the VALU instruction kinds the sweep uses")
     ap.add_argument("--fp32-vs-fp64", action="store_true",
                     help="only compare the FP32 form with the FP64 form statistically")
     ap.add_argument("--samples", type=int, default=1024)
@@ -267,6 +333,9 @@ def main() -> int:
 
     if args.fp32_vs_fp64:
         print(json.dumps(precision_check(args)), flush=True)
+        return 0
+    if args.issue_rates:
+        print(json.dumps(issue_rates()), flush=True)
         return 0
 
     if args.copy_calibration:
@@ -303,7 +372,7 @@ def main() -> int:
     log(f"workload {w.name}: L={w.L} S={w.n_samples} NR={w.n_replicas} NT={w.n_temps} "
         f"NER={w.n_reservoir} {w.precision} {args.mode}")
     g = pthr.Pthr(w.L, w.n_samples, w.n_replicas, w.n_temps, w.n_reservoir, w.sweeps_per_emcs,
-                  w.er_sweeps_per_emcs, w.precision, lib_mode, w.t_acu, w.seed)
+                  w.er_sweeps_per_emcs, w.precision, lib_mode, w.t_acu, w.seed, local_update=args.update)
     g.init_samples(w.couplings(), T)
     obs = g.new_obs()
     if args.autotune:
@@ -345,7 +414,8 @@ def main() -> int:
     moves = moves_per_emcs(w, T)
     ms_per_step = elapsed / args.steps * 1e3
     value = att * args.steps / (elapsed * 1e9)
-    ops = OPS_PER_ATTEMPT[w.precision] * att
+    peak_ops, ops_per_attempt = valu_peak(args.update, w.precision)
+    ops = ops_per_attempt * att
     achieved = ops / (sweep_ms * 1e-3)
     out = {
         "metric": METRIC,
@@ -364,6 +434,7 @@ def main() -> int:
                    "temperatures": w.n_temps, "t_range": [w.t_min, w.t_max],
                    "reservoir_clones": w.n_reservoir, "sweeps_per_emcs": w.sweeps_per_emcs,
                    "reservoir_sweeps_per_emcs": w.er_sweeps_per_emcs, "houdayer": args.mode,
+                   "local_update": args.update,
                    "threads_per_sample": g.schedule().threads_per_sample,
                    "exp_early_out_below_T": g.schedule().exp_early_out / 1000,
                    "clone_split": g.schedule().clone_split},
@@ -372,9 +443,11 @@ def main() -> int:
         "wall_time_per_equilibrated_sample_s":
             (elapsed / args.steps) / w.n_samples * T_EQ_EMCS.get(w.L, float("nan")),
         "roofline": {"bound": "alu", "kernel": "sweep_kernel", "achieved": achieved / 1e12,
-                     "peak": VALU_PEAK_OPS / 1e12, "unit": "TOP/s", "frac": achieved / VALU_PEAK_OPS,
-                     "traffic": sweep_traffic_bytes(w.name), "traffic_unit": "HBM bytes per launch",
-                     "ops_per_attempt": OPS_PER_ATTEMPT[w.precision],
+                     "peak": peak_ops / 1e12, "unit": "TOP/s", "frac": achieved / peak_ops,
+                     "traffic": sweep_traffic_bytes(w.name) if args.update == "metropolis" else None,
+                     "traffic_unit": "HBM bytes per launch",
+                     "ops_per_attempt": ops_per_attempt,
+                     "ops_by_issue_class": OPS_BY_CLASS[(args.update, w.precision)],
                      "sweep_ms_per_launch": sweep_ms},
     }
 
@@ -382,7 +455,7 @@ def main() -> int:
         n = min(args.compare_fp64_samples, w.n_samples)
         sub = inputs.Workload(**{**w.__dict__, "n_samples": n, "precision": "fp64"})
         h = pthr.Pthr(w.L, n, w.n_replicas, w.n_temps, w.n_reservoir, w.sweeps_per_emcs,
-                      w.er_sweeps_per_emcs, "fp64", lib_mode, w.t_acu, w.seed)
+                      w.er_sweeps_per_emcs, "fp64", lib_mode, w.t_acu, w.seed, local_update=args.update)
         h.init_samples(sub.couplings(), T)
         h.set_schedule(samples_per_launch=1)
         hobs = h.new_obs()
@@ -401,7 +474,7 @@ def main() -> int:
 
     if not args.no_cpu_baseline:
         log(f"cpu baseline: oracle on {args.cpu_samples} samples x 1 EMCS")
-        out["cpu_baseline"] = cpu_baseline(w, args.cpu_samples, args.mode)
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_samples, args.mode, args.update)
         log(f"cpu baseline: {out['cpu_baseline']['value']:.4f} attempts/ns "
             f"on {out['cpu_baseline']['cores']} threads")
     print(json.dumps(out), flush=True)

@@ -37,6 +37,14 @@
  * Metropolis exponent in float (couplings rounded to float once, also for the
  * energies); PT exponents, energies and all observable sums stay double.
  *
+ * Local update (pthr_params.local_update): PTHR_METROPOLIS, the paper's
+ * choice, accepts a flip with probability min{1, exp(-beta dE)}; PTHR_HEAT_BATH,
+ * the alternative Sec. 3 names, draws the spin from its conditional Boltzmann
+ * weight, i.e. flips with probability 1 / (1 + exp(beta dE)), tested as
+ * fma(u, a, u) < a (dE > 0) or < 1 (dE <= 0) with a = exp(-beta |dE|) from the
+ * same exp routine and the same random numbers.  Both are bit-exact with the
+ * reference.
+ *
  * Memory and ownership
  *   The library never allocates device memory.  The caller allocates the state
  *   buffer (pthr_state_bytes) and observable buffers (pthr_obs_bytes) on the
@@ -70,6 +78,7 @@ enum {
 };
 enum { PTHR_FP64 = 0, PTHR_FP32 = 1 };
 enum { PTHR_ACU = 0, PTHR_SINGLE_NEG = 1 };
+enum { PTHR_METROPOLIS = 0, PTHR_HEAT_BATH = 1 };
 enum { PTHR_NOBS = 6 }; /* per (sample, T): sum e, sum e^2, sum q^2, sum q^4, sum q_l, sum S */
 
 typedef struct pthr_params {
@@ -82,7 +91,7 @@ typedef struct pthr_params {
   int32_t er_sweeps_per_emcs; /* ER sweeps per EMCS (paper: 960/4 = 240), 0..256 */
   int32_t precision;          /* PTHR_FP64 or PTHR_FP32                        */
   int32_t houdayer_mode;      /* PTHR_ACU (paper) or PTHR_SINGLE_NEG (Houdayer's original) */
-  int32_t reserved;           /* must be 0                                     */
+  int32_t local_update;       /* PTHR_METROPOLIS (paper) or PTHR_HEAT_BATH     */
   double t_acu;               /* Houdayer moves at T_k < t_acu (paper: 1.0)    */
   uint64_t seed;              /* Philox key                                    */
 } pthr_params;

@@ -89,6 +89,7 @@ pthr::Geo geo_of(const pthr_params& p, int K_acu) {
   g.NWPT = d.NWPT;
   g.K_acu = K_acu;
   g.mode = p.houdayer_mode;
+  g.update = p.local_update;
   g.key0 = static_cast<uint32_t>(p.seed);
   g.key1 = static_cast<uint32_t>(p.seed >> 32);
   return g;
@@ -121,7 +122,8 @@ const char* validate(const pthr_params& p) {
   if (p.er_sweeps_per_emcs < 0 || p.er_sweeps_per_emcs > 256) return "er_sweeps_per_emcs must be in [0, 256]";
   if (p.precision != PTHR_FP64 && p.precision != PTHR_FP32) return "precision must be PTHR_FP64 or PTHR_FP32";
   if (p.houdayer_mode != PTHR_ACU && p.houdayer_mode != PTHR_SINGLE_NEG) return "houdayer_mode must be PTHR_ACU or PTHR_SINGLE_NEG";
-  if (p.reserved != 0) return "reserved must be 0";
+  if (p.local_update != PTHR_METROPOLIS && p.local_update != PTHR_HEAT_BATH)
+    return "local_update must be PTHR_METROPOLIS or PTHR_HEAT_BATH";
   if (std::isnan(p.t_acu)) return "t_acu must not be NaN";
   return nullptr;
 }

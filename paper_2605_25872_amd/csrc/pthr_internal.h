@@ -31,6 +31,7 @@ struct Geo {
   int NW, NWPT;      // 32-clone spin words per site: all, PT only
   int K_acu;         // number of temperatures with T_k < t_acu (a prefix)
   int mode;          // 0 all-cluster, 1 single negative cluster
+  int update;        // local update: 0 Metropolis, 1 heat bath
   uint32_t key0, key1;
 };
 

@@ -133,9 +133,11 @@ __device__ __forceinline__ float exp2_poly32(float f, float k) {
   return __builtin_ldexpf(p, static_cast<int>(k));
 }
 // 2^t * 2^32 with the same rounding steps as exp2_poly32: every Horner
-// coefficient is scaled by 2^32, which commutes with each rounding (no
-// overflow or underflow for t >= -124), so float(w) <= exp2_poly32_x2p32(f, k)
-// decides exactly as float(w) * 2^-32 <= exp2_poly32(f, k).
+// coefficient is scaled by 2^32, which commutes with each rounding (the
+// polynomial stays far from overflow and underflow), so float(w) <=
+// exp2_poly32_x2p32(f, k) decides exactly as float(w) * 2^-32 <=
+// exp2_poly32(f, k) (where the scaled 2^k underflows, float(w) * 2^-32 is 0
+// or at least 2^-32 and both sides agree).
 __device__ __forceinline__ float exp2_poly32_x2p32(float f, float k) {
   float p = 0x1.ffcbfcp+15f;
   p = __builtin_fmaf(p, f, 0x1.430912p+19f);
@@ -192,6 +194,14 @@ struct Prec<double> {
     const double p = exp_poly64(x, __builtin_rint(x * 0x1.71547652b82fep+0));
     return __builtin_amdgcn_ballot_w64(x >= -708.0) & __builtin_amdgcn_ballot_w64(u < p);
   }
+  // Heat bath: flip with probability 1 / (1 + exp(beta dE)), tested as
+  // fma(u, a, u) < (dE > 0 ? a : 1) with a = exp(-beta |dE|) (0 below -708).
+  static __device__ __forceinline__ uint64_t heat_bath_lanes(double u, double beta, double dE) {
+    const double x = -(beta * __builtin_fabs(dE));
+    const double p = exp_poly64(x, __builtin_rint(x * 0x1.71547652b82fep+0));
+    const double a = x >= -708.0 ? p : 0.0;
+    return __builtin_amdgcn_ballot_w64(__builtin_fma(u, a, u) < (dE > 0.0 ? a : 1.0));
+  }
   static __device__ __forceinline__ bool negative(double J) { return __double2hiint(J) < 0; }
   static __device__ __forceinline__ double magnitude(double J) {
     return __hiloint2double(__double2hiint(J) & 0x7FFFFFFF, __double2loint(J));
@@ -204,10 +214,10 @@ struct Prec<double> {
 };
 template <>
 struct Prec<float> {
-  // FP32 form: x is t = -(beta log2 e) dE; accept iff t >= -124 and u <= 2^t
-  // (every dE <= 0 passes).
+  // FP32 form: x is t = -(beta log2 e) dE; accept iff u <= 2^t (every
+  // dE <= 0 passes; 2^t overflows to +inf and underflows to 0, and u is 0 or
+  // at least 2^-32, so subnormal results decide nothing).
   static __device__ __forceinline__ bool accept(float u, float t, bool early) {
-    if (t < -124.0f) return false;
     const float k = __builtin_rintf(t);
     if (early) {
       const int ki = static_cast<int>(k);
@@ -216,12 +226,24 @@ struct Prec<float> {
     }
     return u <= exp2_poly32(t - k, k);
   }
-  // Same decision as accept(uniform32(w), t, false), branch-free, comparing
-  // float(w) with 2^t * 2^32; a mask over the wave's lanes.
-  static __device__ __forceinline__ uint64_t accept_lanes_w(uint32_t w, float t) {
+  // The opposite of accept(uniform32(w), t, false), branch-free, in the sign
+  // bit: p - float(w) with p = 2^t * 2^32 is negative exactly when
+  // float(w) > p (a difference of two floats is zero only when they are
+  // equal, and rounding keeps its sign; +inf - float(w) = +inf).
+  static __device__ __forceinline__ uint32_t reject_sign(uint32_t w, float t) {
     const float k = __builtin_rintf(t);
     const float p = exp2_poly32_x2p32(t - k, k);
-    return __builtin_amdgcn_ballot_w64(t >= -124.0f) & __builtin_amdgcn_ballot_w64(static_cast<float>(w) <= p);
+    return __float_as_uint(p - static_cast<float>(w));
+  }
+  // Heat bath, FP32 form: a = 2^t, t = -(beta log2 e)|dE| (0 below t = -124),
+  // u = float(w) 2^-32; flip iff fma(u, a, u) < (dE > 0 ? a : 1).
+  static __device__ __forceinline__ uint64_t heat_bath_lanes_w(uint32_t w, float bl, float dE) {
+    const float t = -(bl * __builtin_fabsf(dE));
+    const float k = __builtin_rintf(t);
+    const float p = exp2_poly32(t - k, k);
+    const float a = t >= -124.0f ? p : 0.0f;
+    const float u = static_cast<float>(w) * 0x1p-32f;
+    return __builtin_amdgcn_ballot_w64(__builtin_fmaf(u, a, u) < (dE > 0.0f ? a : 1.0f));
   }
   static __device__ __forceinline__ bool negative(float J) { return __float_as_int(J) < 0; }
   static __device__ __forceinline__ float magnitude(float J) { return __uint_as_float(__float_as_uint(J) & 0x7FFFFFFFu); }
@@ -464,15 +486,52 @@ struct WordSigns {
   uint32_t x[6], y[3], z[3];
 };
 
+// x + x as one v_add_u32: gfx950 issues it at twice the rate of a left shift
+// (v_lshlrev_b32), which the compiler would otherwise choose.
+__device__ __forceinline__ uint32_t twice(uint32_t x) {
+  uint32_t r;
+  asm("v_add_u32 %0, %1, %1" : "=v"(r) : "v"(x));
+  return r;
+}
+
+// The sign words of a word, shifted so that the bit of the clone being
+// updated sits at bit 31; one doubling per attempt moves on to the next lower
+// clone.  FP32: y[0..2] then z[0..2]; FP64: x[0..5].
+struct RunSigns {
+  uint32_t s[6];
+};
+template <typename FP>
+__device__ __forceinline__ RunSigns run_signs(const WordSigns& ws, int b_top) {
+  RunSigns r;
+  const uint32_t sh = 31u - static_cast<uint32_t>(b_top);
+#pragma unroll
+  for (int a = 0; a < 6; ++a) {
+    if constexpr (sizeof(FP) == 4) {
+      r.s[a] = (a < 3 ? ws.y[a] : ws.z[a - 3]) << sh;
+    } else {
+      r.s[a] = ws.x[a] << sh;
+    }
+  }
+  return r;
+}
+
 // The Metropolis attempts of random-number indices n = grp*G + j (j from G-1
 // down to 0) of one word, all drawing on Philox block grp.  The word's clones
 // are clone0 + (n - n0), n0 = the index of clone0 (a multiple of G); indices
 // past the word's last clone (a partial last block) run on that clone's beta
 // and are discarded by the caller.  Accept iff dE <= 0 or u < exp(-beta dE).
 // kMaybeEarly: clones colder than the early-out threshold may decide from the
-// binade of exp(x).  Each decision is shifted in at bit 0 of `flips`.
-template <typename FP, bool kMaybeEarly>
-__device__ __forceinline__ void attempt_group(const Geo& g, const FP* __restrict__ bc, const WordSigns& ws,
+// binade of exp(x).  kHB: heat-bath test instead of Metropolis (no early-out).
+// Each decision is shifted in at bit 0 of `flips`.  `rs` holds the sign words
+// positioned for the group's first (highest) clone and is advanced past the
+// group.
+// attempt_group shifts in reject bits instead of accept bits (FP32 Metropolis
+// without early-out).
+template <typename FP, bool kMaybeEarly, bool kHB>
+constexpr bool kRejectBits = sizeof(FP) == 4 && !kMaybeEarly && !kHB;
+
+template <typename FP, bool kMaybeEarly, bool kHB>
+__device__ __forceinline__ void attempt_group(const Geo& g, const FP* __restrict__ bc, RunSigns& rs,
                                               const SiteJ<FP>& sj, const Block& blk, int grp, int n0, int clone0,
                                               int nbits, int early_beta_bits, uint32_t& flips) {
   constexpr int G = sizeof(FP) == 8 ? 2 : 4;  // clones per Philox block
@@ -481,30 +540,37 @@ __device__ __forceinline__ void attempt_group(const Geo& g, const FP* __restrict
   for (int j = 0; j < G; ++j) beta[j] = bc[clone0 + min(grp * G + j - n0, nbits - 1)];
 #pragma unroll
   for (int j = G - 1; j >= 0; --j) {
-    const int b = grp * G + j - n0;
-    const uint32_t sh = 31u - static_cast<uint32_t>(b);
     FP dE;  // the couplings carry the factor 2: the sum is dE = 2h
     if constexpr (sizeof(FP) == 4) {
       float ax[3];
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
         // all ones where the axis' two terms have unlike signs: take |M|, else P
-        const uint32_t pick = static_cast<uint32_t>(__builtin_amdgcn_sbfe(static_cast<int>(ws.y[a]), b, 1));
+        const uint32_t pick = static_cast<uint32_t>(static_cast<int32_t>(rs.s[a]) >> 31);
         ax[a] = Prec<float>::with_sign(__uint_as_float(bitfield_insert(pick, __float_as_uint(sj.v[2 * a + 1]),
                                                                        __float_as_uint(sj.v[2 * a]))),
-                                       ws.z[a] << sh);
+                                       rs.s[3 + a]);
       }
       dE = (ax[0] + ax[1]) + ax[2];
     } else {
       FP tt[6];
 #pragma unroll
-      for (int d = 0; d < 6; ++d) tt[d] = Prec<FP>::with_sign(sj.v[d], ws.x[d] << sh);
+      for (int d = 0; d < 6; ++d) tt[d] = Prec<FP>::with_sign(sj.v[d], rs.s[d]);
       dE = ((tt[0] + tt[1]) + (tt[2] + tt[3])) + (tt[4] + tt[5]);
     }
+#pragma unroll
+    for (int a = 0; a < 6; ++a) rs.s[a] = twice(rs.s[a]);
     // beta > 0: comparing the float bit patterns as integers orders them
     const bool early = kMaybeEarly && __float_as_int(static_cast<float>(beta[j])) >= early_beta_bits;
     uint64_t acc_lanes;
-    if (early) {
+    if constexpr (kHB) {
+      if constexpr (sizeof(FP) == 8) {
+        acc_lanes = Prec<double>::heat_bath_lanes(Prec<double>::u(blk, j & 1), beta[j], dE);
+      } else {
+        const uint32_t wj = j == 0 ? blk.w0 : j == 1 ? blk.w1 : j == 2 ? blk.w2 : blk.w3;
+        acc_lanes = Prec<float>::heat_bath_lanes_w(wj, beta[j], dE);
+      }
+    } else if (early) {
       // cold clone (uniform branch): most tests are decided by the binade
       bool acc = dE <= FP(0);
       if (!acc) {
@@ -524,9 +590,18 @@ __device__ __forceinline__ void attempt_group(const Geo& g, const FP* __restrict
         acc_lanes = __builtin_amdgcn_ballot_w64(dE <= 0.0) |
                     Prec<double>::accept_lanes(Prec<double>::u(blk, j & 1), -(beta[j] * dE));
       } else {
-        // beta[j] holds beta log2 e; u <= 2^t already accepts every dE <= 0
+        // beta[j] holds beta log2 e; u <= 2^t already accepts every dE <= 0.
         const uint32_t wj = j == 0 ? blk.w0 : j == 1 ? blk.w1 : j == 2 ? blk.w2 : blk.w3;
-        acc_lanes = Prec<float>::accept_lanes_w(wj, -(beta[j] * dE));
+        const uint32_t rej = Prec<float>::reject_sign(wj, -(beta[j] * dE));
+        if constexpr (kRejectBits<FP, kMaybeEarly, kHB>) {
+          // the reject bit (sign of p - float(w)) shifted in with one
+          // v_alignbit_b32; the caller inverts the word
+          flips = __builtin_amdgcn_alignbit(flips, rej, 31);
+          continue;
+        } else {
+          // next to early-out clones of the same word: accept bits
+          acc_lanes = __builtin_amdgcn_ballot_w64(static_cast<int32_t>(rej) >= 0);
+        }
       }
     }
     flips = shift_in(flips, acc_lanes);
@@ -539,7 +614,7 @@ __device__ __forceinline__ void attempt_group(const Geo& g, const FP* __restrict
 // to the first, so clone clone0+b ends at bit b of the flip mask; the bits of
 // a partial last block's surplus indices land above bit nbits-1 and are
 // masked off.
-template <typename FP, bool kMaybeEarly, bool kSplit>
+template <typename FP, bool kMaybeEarly, bool kSplit, bool kHB>
 __device__ __forceinline__ void update_word(const Geo& g, const FP* __restrict__ bc, uint32_t* plane, int self_idx,
                                             const int (&nb)[6], const SiteJ<FP>& sj, uint32_t c0w, uint32_t t,
                                             int sample, int clone0, int n0, int nbits, int early_beta_bits,
@@ -562,14 +637,17 @@ __device__ __forceinline__ void update_word(const Geo& g, const FP* __restrict__
     // software-pipelined: the Philox block of the next group is computed
     // beside the attempts of the current one (independent work for the SIMD)
     int grp = g_hi;
+    // groups run from the highest clone down, one clone per doubling
+    RunSigns rs = run_signs<FP>(ws, g_hi * G + G - 1 - n0);
     Block blk = philox10(c0w, t, static_cast<uint32_t>(grp), static_cast<uint32_t>(sample), g.key0, g.key1);
     for (; grp > g_lo; --grp) {
       const Block next =
           philox10(c0w, t, static_cast<uint32_t>(grp - 1), static_cast<uint32_t>(sample), g.key0, g.key1);
-      attempt_group<FP, kMaybeEarly>(g, bc, ws, sj, blk, grp, n0, clone0, nbits, early_beta_bits, flips);
+      attempt_group<FP, kMaybeEarly, kHB>(g, bc, rs, sj, blk, grp, n0, clone0, nbits, early_beta_bits, flips);
       blk = next;
     }
-    attempt_group<FP, kMaybeEarly>(g, bc, ws, sj, blk, g_lo, n0, clone0, nbits, early_beta_bits, flips);
+    attempt_group<FP, kMaybeEarly, kHB>(g, bc, rs, sj, blk, g_lo, n0, clone0, nbits, early_beta_bits, flips);
+    if constexpr (kRejectBits<FP, kMaybeEarly, kHB>) flips = ~flips;
     if (nbits < 32) flips &= (1u << nbits) - 1u;
     plane[self_idx] = self ^ flips;
   } else {
@@ -584,12 +662,16 @@ __device__ __forceinline__ void update_word(const Geo& g, const FP* __restrict__
       const Block next =
           philox10(c0w, t, static_cast<uint32_t>(grp - F), static_cast<uint32_t>(sample), g.key0, g.key1);
       uint32_t part = 0;
-      attempt_group<FP, kMaybeEarly>(g, bc, ws, sj, blk, grp, n0, clone0, nbits, early_beta_bits, part);
+      RunSigns rs = run_signs<FP>(ws, grp * G + G - 1 - n0);
+      attempt_group<FP, kMaybeEarly, kHB>(g, bc, rs, sj, blk, grp, n0, clone0, nbits, early_beta_bits, part);
+      if constexpr (kRejectBits<FP, kMaybeEarly, kHB>) part = ~part & ((1u << G) - 1u);
       flips |= part << (G * (grp - g_lo));
       blk = next;
     }
     uint32_t part = 0;
-    attempt_group<FP, kMaybeEarly>(g, bc, ws, sj, blk, first, n0, clone0, nbits, early_beta_bits, part);
+    RunSigns rs = run_signs<FP>(ws, first * G + G - 1 - n0);
+    attempt_group<FP, kMaybeEarly, kHB>(g, bc, rs, sj, blk, first, n0, clone0, nbits, early_beta_bits, part);
+    if constexpr (kRejectBits<FP, kMaybeEarly, kHB>) part = ~part & ((1u << G) - 1u);
     flips |= part << (G * (first - g_lo));
     if (nbits < 32) flips &= (1u << nbits) - 1u;
     if (flips) atomicXor(&plane[self_idx], flips);
@@ -598,7 +680,7 @@ __device__ __forceinline__ void update_word(const Geo& g, const FP* __restrict__
 
 // n_pt sweeps of the PT clones and n_er sweeps of the ER clones, interleaved
 // sweep by sweep (the classes are independent).
-template <typename FP, int CH, bool kSplit>
+template <typename FP, int CH, bool kSplit, bool kHB>
 __device__ __forceinline__ void sweep_phase(const Geo& g, const Lds& s, const FP* Js, const FP* __restrict__ bc,
                                             int sample, uint32_t t, int m_pt0, int n_pt, int m_er0, int n_er,
                                             float early_beta, float beta_cold, int F) {
@@ -670,29 +752,24 @@ __device__ __forceinline__ void sweep_phase(const Geo& g, const Lds& s, const FP
 #pragma unroll
           for (int d = 0; d < 6; ++d) nb[d] = plane_idx(neighbour(st, d, g.L), colour ^ 1, g.Vh);
           const int self_idx = colour * g.Vh + (i0 >> 1);
+          // one word of clones: early-out form or not (a uniform choice per word; never for heat bath)
+          auto word = [&](bool early, int w, uint32_t c0, int clone0, int n0, int nbits) {
+            if (!kHB && early)
+              update_word<FP, !kHB, kSplit, kHB>(g, bc, s.sp + size_t(w) * g.V, self_idx, nb, sj[slot][q],
+                                                 c0 | static_cast<uint32_t>(st.i), t, sample, clone0, n0, nbits,
+                                                 early_bits, f, F);
+            else
+              update_word<FP, false, kSplit, kHB>(g, bc, s.sp + size_t(w) * g.V, self_idx, nb, sj[slot][q],
+                                                  c0 | static_cast<uint32_t>(st.i), t, sample, clone0, n0, nbits,
+                                                  early_bits, f, F);
+          };
           if (pt_on)
-            for (int w = 0; w < g.NWPT; ++w) {
-              if (pt_early)
-                update_word<FP, true, kSplit>(g, bc, s.sp + size_t(w) * g.V, self_idx, nb, sj[slot][q],
-                                              c0pt | static_cast<uint32_t>(st.i), t, sample, 32 * w, 32 * w,
-                                              min(32, g.NPT - 32 * w), early_bits, f, F);
-              else
-                update_word<FP, false, kSplit>(g, bc, s.sp + size_t(w) * g.V, self_idx, nb, sj[slot][q],
-                                               c0pt | static_cast<uint32_t>(st.i), t, sample, 32 * w, 32 * w,
-                                               min(32, g.NPT - 32 * w), early_bits, f, F);
-            }
+            for (int w = 0; w < g.NWPT; ++w) word(pt_early, w, c0pt, 32 * w, 32 * w, min(32, g.NPT - 32 * w));
           if (er_on)
             for (int w = g.NWPT; w < g.NW; ++w) {
               const int e0 = 32 * (w - g.NWPT);
               // every reservoir clone sits at T_max: one uniform choice of path per word
-              if (er_early)
-                update_word<FP, true, kSplit>(g, bc, s.sp + size_t(w) * g.V, self_idx, nb, sj[slot][q],
-                                              c0er | static_cast<uint32_t>(st.i), t, sample, g.NPT + e0, n_er0 + e0,
-                                              min(32, g.NER - e0), early_bits, f, F);
-              else
-                update_word<FP, false, kSplit>(g, bc, s.sp + size_t(w) * g.V, self_idx, nb, sj[slot][q],
-                                               c0er | static_cast<uint32_t>(st.i), t, sample, g.NPT + e0, n_er0 + e0,
-                                               min(32, g.NER - e0), early_bits, f, F);
+              word(er_early, w, c0er, g.NPT + e0, n_er0 + e0, min(32, g.NER - e0));
             }
         }
       }
@@ -1343,7 +1420,7 @@ __device__ __forceinline__ void store_spins(const Geo& g, const Lds& s, const St
   store_spins(g, s.sp, st, sample);
 }
 
-template <typename FP, int CH, bool kSplit>
+template <typename FP, int CH, bool kSplit, bool kHB>
 __global__ __launch_bounds__(kMaxThreads) void sweep_kernel(Geo g, State st, Run run) {
   const int sample = run.sample_begin + blockIdx.x;
   if (sample >= g.S) return;  // the whole workgroup leaves together
@@ -1355,8 +1432,8 @@ __global__ __launch_bounds__(kMaxThreads) void sweep_kernel(Geo g, State st, Run
   const uint32_t t = *st.t_dev;
   // beta of the coldest temperature in the units the clone table holds
   const float beta_cold = sizeof(FP) == 8 ? static_cast<float>(st.beta64[0]) : st.beta32[0];
-  sweep_phase<FP, CH, kSplit>(g, s, Js, bc, sample, t, run.m_pt0, run.n_pt, run.m_er0, run.n_er, run.early_beta,
-                              beta_cold, run.clone_split);
+  sweep_phase<FP, CH, kSplit, kHB>(g, s, Js, bc, sample, t, run.m_pt0, run.n_pt, run.m_er0, run.n_er,
+                                   run.early_beta, beta_cold, run.clone_split);
   store_spins(g, s, st, sample);
 }
 
@@ -1452,8 +1529,10 @@ hipError_t set_lds(K kern, size_t lds) {
 template <typename FP, int CH>
 hipError_t prepare_t(size_t lds) {
   hipError_t e;
-  if ((e = set_lds(sweep_kernel<FP, CH, false>, lds)) != hipSuccess) return e;
-  if ((e = set_lds(sweep_kernel<FP, CH, true>, lds)) != hipSuccess) return e;
+  if ((e = set_lds(sweep_kernel<FP, CH, false, false>, lds)) != hipSuccess) return e;
+  if ((e = set_lds(sweep_kernel<FP, CH, true, false>, lds)) != hipSuccess) return e;
+  if ((e = set_lds(sweep_kernel<FP, CH, false, true>, lds)) != hipSuccess) return e;
+  if ((e = set_lds(sweep_kernel<FP, CH, true, true>, lds)) != hipSuccess) return e;
   if ((e = set_lds(houdayer_kernel, lds)) != hipSuccess) return e;
   if ((e = set_lds(pt_kernel<FP, CH>, lds)) != hipSuccess) return e;
   return set_lds(measure_kernel<FP, CH>, lds);
@@ -1467,7 +1546,8 @@ hipError_t launch_t(const Geo& g, const State& st, const Obs& ob, const Run& run
   if (run.phases & kPhaseSweep) {
     Run r = run;
     r.clone_split = split;
-    auto k = split > 1 ? sweep_kernel<FP, CH, true> : sweep_kernel<FP, CH, false>;
+    auto k = g.update ? (split > 1 ? sweep_kernel<FP, CH, true, true> : sweep_kernel<FP, CH, false, true>)
+                      : (split > 1 ? sweep_kernel<FP, CH, true, false> : sweep_kernel<FP, CH, false, false>);
     hipLaunchKernelGGL(k, dim3(n_blocks), dim3(threads * split), lds, stream, g, st, r);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(PKG, "libpthr.so")
 PTHR_OK, PTHR_EINVAL, PTHR_EUNSUPPORTED, PTHR_EHIP, PTHR_ESTATE, PTHR_EDEVICE = 0, -1, -2, -3, -4, -5
 FP64, FP32 = 0, 1
 ACU, SINGLE_NEG = 0, 1
+METROPOLIS, HEAT_BATH = 0, 1
 NOBS = 6
 OBS_NAMES = ("e", "e2", "q2", "q4", "ql", "sdy")
 
@@ -43,7 +44,7 @@ class Params(ctypes.Structure):
                 ("n_replicas", ctypes.c_int32), ("n_temps", ctypes.c_int32),
                 ("n_reservoir", ctypes.c_int32), ("sweeps_per_emcs", ctypes.c_int32),
                 ("er_sweeps_per_emcs", ctypes.c_int32), ("precision", ctypes.c_int32),
-                ("houdayer_mode", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("houdayer_mode", ctypes.c_int32), ("local_update", ctypes.c_int32),
                 ("t_acu", ctypes.c_double), ("seed", ctypes.c_uint64)]
 
 
@@ -117,13 +118,16 @@ def _np_ptr(a: np.ndarray) -> int:
 
 
 def make_params(L, n_samples, n_replicas, n_temps, n_reservoir, sweeps_per_emcs=10,
-                er_sweeps_per_emcs=240, precision=FP64, houdayer_mode=ACU, t_acu=1.0, seed=1) -> Params:
+                er_sweeps_per_emcs=240, precision=FP64, houdayer_mode=ACU, t_acu=1.0, seed=1,
+                local_update=METROPOLIS) -> Params:
     if isinstance(precision, str):
         precision = {"fp64": FP64, "fp32": FP32}[precision]
     if isinstance(houdayer_mode, str):
         houdayer_mode = {"acu": ACU, "single": SINGLE_NEG}[houdayer_mode]
+    if isinstance(local_update, str):
+        local_update = {"metropolis": METROPOLIS, "heatbath": HEAT_BATH}[local_update]
     return Params(L, n_samples, n_replicas, n_temps, n_reservoir, sweeps_per_emcs,
-                  er_sweeps_per_emcs, precision, houdayer_mode, 0, t_acu, seed)
+                  er_sweeps_per_emcs, precision, houdayer_mode, local_update, t_acu, seed)
 
 
 class Pthr:
@@ -132,13 +136,13 @@ class Pthr:
 
     def __init__(self, L, n_samples, n_replicas=4, n_temps=8, n_reservoir=4, sweeps_per_emcs=10,
                  er_sweeps_per_emcs=240, precision=FP64, houdayer_mode=ACU, t_acu=1.0, seed=1,
-                 device="cuda:0"):
+                 device="cuda:0", local_update=METROPOLIS):
         import torch
 
         self.torch = torch
         self.lib = library()
         self.params = make_params(L, n_samples, n_replicas, n_temps, n_reservoir, sweeps_per_emcs,
-                                  er_sweeps_per_emcs, precision, houdayer_mode, t_acu, seed)
+                                  er_sweeps_per_emcs, precision, houdayer_mode, t_acu, seed, local_update)
         ctx = ctypes.c_void_p()
         rc = self.lib.pthr_create(ctypes.byref(self.params), ctypes.byref(ctx))
         if rc != PTHR_OK:

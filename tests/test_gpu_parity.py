@@ -27,14 +27,15 @@ def _pthr():
 
 
 def make_pair(L, S, NR, NT, NER, precision="fp64", mode="acu", t_acu=1.0, sweeps=10, er_sweeps=240,
-              seed=1, jseed=1, T=None, t_range=(0.3, 1.6)):
+              seed=1, jseed=1, T=None, t_range=(0.3, 1.6), update="metropolis"):
     pthr = _pthr()
     J = inputs.couplings(L, S, seed=jseed)
     T = inputs.temperatures(*t_range, NT) if T is None else np.asarray(T, dtype=np.float64)
     prec_o = oracle.FP64 if precision == "fp64" else oracle.FP32
     mode_o = oracle.ACU if mode == "acu" else oracle.SINGLE_NEG
-    o = oracle.Oracle(L, S, NR, NT, NER, sweeps, er_sweeps, prec_o, mode_o, t_acu, seed)
-    g = pthr.Pthr(L, S, NR, NT, NER, sweeps, er_sweeps, precision, mode, t_acu, seed)
+    upd_o = oracle.METROPOLIS if update == "metropolis" else oracle.HEAT_BATH
+    o = oracle.Oracle(L, S, NR, NT, NER, sweeps, er_sweeps, prec_o, mode_o, t_acu, seed, local_update=upd_o)
+    g = pthr.Pthr(L, S, NR, NT, NER, sweeps, er_sweeps, precision, mode, t_acu, seed, local_update=update)
     o.init(J, T)
     g.init_samples(J, T)
     return o, g
@@ -295,6 +296,37 @@ def test_every_schedule_gives_the_same_bits(precision):
     del pthr
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_heat_bath_ragged_every_substep(precision):
+    """Heat-bath local update (flip with probability 1/(1 + exp(beta dE))):
+    partial clone words and Philox blocks, every sub-step, then shared clone
+    words (clone_split 2) and a fused graph-replayed run."""
+    step(f"heat bath l6 ragged {precision}")
+    o, g = make_pair(6, 3, 2, 7, 3, precision=precision, er_sweeps=12, t_range=(0.2, 1.4), update="heatbath")
+    stepwise(o, g, 2)
+    g.set_schedule(clone_split=2)
+    stepwise(o, g, 2)
+    g.set_schedule(clone_split=1, graph_window=2)
+    oo, go = o.new_observables(), g.new_obs()
+    o.run(3, oo)
+    g.run(3, go)
+    g.check()
+    assert_same_state(o, g, "heat bath fused run")
+    assert_same_obs(oo, g, go)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_heat_bath_schedules_and_tiles(precision):
+    """Heat bath at L=8 over several workgroup tiles, with every chunk size and
+    clone split the library offers for the shape."""
+    step(f"heat bath l8 schedules {precision}")
+    o, g = make_pair(8, 3, 4, 10, 4, precision=precision, er_sweeps=20, update="heatbath")
+    stepwise(o, g, 1)
+    for threads, split in ((128, 1), (256, 2), (128, 4)):
+        g.set_schedule(threads_per_sample=threads, clone_split=split)
+        stepwise(o, g, 1, check_each=False)
+
+
 def test_checkpoint_resume_is_bit_identical():
     step("checkpoint")
     pthr = _pthr()
@@ -335,7 +367,7 @@ def test_errors_are_reported_not_raised_on_device():
 
 
 # ----------------------------------------------------------------------------- full workloads, sampled
-def sampled_check(name, samples, n_emcs, mode="acu"):
+def sampled_check(name, samples, n_emcs, mode="acu", update="metropolis"):
     """Run the whole workload on the GPU; recompute the chosen samples with the
     oracle (same global sample ids) and compare them bit for bit."""
     pthr = _pthr()
@@ -343,7 +375,7 @@ def sampled_check(name, samples, n_emcs, mode="acu"):
     T = w.temperatures()
     step(f"full {name}: {w.n_samples} samples, {n_emcs} EMCS on the GPU")
     g = pthr.Pthr(w.L, w.n_samples, w.n_replicas, w.n_temps, w.n_reservoir, w.sweeps_per_emcs,
-                  w.er_sweeps_per_emcs, w.precision, mode, w.t_acu, w.seed)
+                  w.er_sweeps_per_emcs, w.precision, mode, w.t_acu, w.seed, local_update=update)
     g.init_samples(w.couplings(), T)
     go = g.new_obs()
     g.run(n_emcs, go)
@@ -356,7 +388,8 @@ def sampled_check(name, samples, n_emcs, mode="acu"):
         step(f"  oracle sample {s}")
         o1 = oracle.Oracle(w.L, 1, w.n_replicas, w.n_temps, w.n_reservoir, w.sweeps_per_emcs,
                            w.er_sweeps_per_emcs, prec, oracle.ACU if mode == "acu" else oracle.SINGLE_NEG,
-                           w.t_acu, w.seed, first_sample=s)
+                           w.t_acu, w.seed, first_sample=s,
+                           local_update=oracle.METROPOLIS if update == "metropolis" else oracle.HEAT_BATH)
         o1.init(w.couplings(1, first_sample=s), T)
         oo = o1.new_observables()
         o1.run(n_emcs, oo)
@@ -376,3 +409,7 @@ def test_full_l16_fp32_workload_sampled():
 
 def test_full_l16_fp32_single_cluster_sampled():
     sampled_check("l16_fp32", [511], 1, mode="single")
+
+
+def test_full_l16_fp32_heat_bath_sampled():
+    sampled_check("l16_fp32", [700], 1, update="heatbath")

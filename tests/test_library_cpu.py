@@ -59,7 +59,7 @@ def test_validation(lib):
     rc, msg, _ = _create(lib, L=16, n_temps=64, precision="fp32")
     assert rc == pthr.PTHR_EUNSUPPORTED and "LDS" in msg
     bad = pthr.make_params(8, 4, 4, 20, 4)
-    bad.reserved = 1
+    bad.local_update = 2
     ctx = ctypes.c_void_p()
     assert lib.pthr_create(ctypes.byref(bad), ctypes.byref(ctx)) == pthr.PTHR_EINVAL
     assert lib.pthr_state_bytes(ctypes.byref(bad)) == 0
