@@ -84,8 +84,8 @@ def valu_peak(update: str, precision: str) -> tuple[float, int]:
 # SHA-256 is recorded here; any other source reports null.
 SWEEP_TRAFFIC = {
     "workload": "l16_fp32",
-    "sources_sha256": "bf9dfb4066afadde633437ff796c87f806d0808bbebb33927d228075991c5132",
-    "fetch_kib": 75155.0,
+    "sources_sha256": "dd5a16eaccf483a82dd869ad132738e42cd9d6e04526788321c3a6bd71dedab3",
+    "fetch_kib": 74990.25,
     "write_kib": 98304.0,
 }
 KERNEL_SOURCES = ("paper_2605_25872_amd/csrc/pthr_kernels.hip", "paper_2605_25872_amd/csrc/pthr_internal.h")

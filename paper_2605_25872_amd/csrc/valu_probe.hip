@@ -60,6 +60,32 @@ __global__ __launch_bounds__(kThreads) void probe_kernel(uint32_t* out, uint32_t
   if constexpr (KIND == 15) PROBE_LOOP(asm volatile("v_fma_f64 %0, %0, %1, %1" : "+v"(d[c]) : "v"(da)))
   if constexpr (KIND == 16) PROBE_LOOP(asm volatile("v_add_f64 %0, %0, %1" : "+v"(d[c]) : "v"(da)))
   if constexpr (KIND == 17) PROBE_LOOP(asm volatile("v_exp_f32 %0, %0" : "+v"(v[c])))
+  if constexpr (KIND == 18) PROBE_LOOP(asm volatile("v_sub_f32 %0, %0, %1" : "+v"(v[c]) : "v"(a)))
+  if constexpr (KIND == 19) PROBE_LOOP(asm volatile("v_mul_f32_e64 %0, -%0, %1" : "+v"(v[c]) : "v"(fa)))
+  if constexpr (KIND == 20) PROBE_LOOP(asm volatile("v_fmaak_f32 %0, %0, %1, 0x3f000000" : "+v"(v[c]) : "v"(fa)))
+  if constexpr (KIND == 21) PROBE_LOOP(asm volatile("v_and_b32 %0, %0, %1" : "+v"(v[c]) : "v"(a)))
+  if constexpr (KIND == 22) PROBE_LOOP(asm volatile("v_or_b32 %0, %0, %1" : "+v"(v[c]) : "v"(a)))
+  if constexpr (KIND == 23) PROBE_LOOP(asm volatile("v_sub_u32 %0, %0, %1" : "+v"(v[c]) : "v"(a)))
+  if constexpr (KIND == 24) PROBE_LOOP(asm volatile("v_lshrrev_b32 %0, %1, %0" : "+v"(v[c]) : "v"(a)))
+  if constexpr (KIND == 25) PROBE_LOOP(asm volatile("v_mov_b32 %0, %1" : "=v"(v[c]) : "v"(v[(c + 1) % kChains])))
+  if constexpr (KIND == 26) PROBE_LOOP(asm volatile("v_bfe_i32 %0, %0, %1, 1" : "+v"(v[c]) : "v"(a)))
+  if constexpr (KIND == 27) PROBE_LOOP(asm volatile("v_max_f32 %0, %0, %1" : "+v"(v[c]) : "v"(a)))
+  if constexpr (KIND == 28) PROBE_LOOP(asm volatile("v_add3_u32 %0, %0, %1, %2" : "+v"(v[c]) : "v"(a), "v"(b)))
+  if constexpr (KIND == 29) PROBE_LOOP(asm volatile("v_lshl_add_u32 %0, %0, 3, %1" : "+v"(v[c]) : "v"(a)))
+  if constexpr (KIND == 30) PROBE_LOOP(asm volatile("v_perm_b32 %0, %0, %1, %2" : "+v"(v[c]) : "v"(a), "v"(b)))
+  if constexpr (KIND == 31) PROBE_LOOP(asm volatile("v_cvt_i32_f32 %0, %0" : "+v"(v[c])))
+  if constexpr (KIND == 32) PROBE_LOOP(asm volatile("v_mul_lo_u32 %0, %0, %1" : "+v"(v[c]) : "v"(a)))
+  if constexpr (KIND == 33) PROBE_LOOP(asm volatile("v_mul_hi_u32 %0, %0, %1" : "+v"(v[c]) : "v"(a)))
+  if constexpr (KIND == 34) PROBE_LOOP({
+    uint64_t co;
+    asm volatile("v_addc_co_u32_e64 %0, %1, %0, %0, %2" : "+v"(v[c]), "=s"(co) : "s"(m[0]));
+  })
+  if constexpr (KIND == 35) PROBE_LOOP(asm volatile("v_cndmask_b32_e64 %0, %0, %1, %2" : "+v"(v[c]) : "v"(a), "s"(m[0])))
+  if constexpr (KIND == 36) PROBE_LOOP(asm volatile("v_mul_f64 %0, %0, %1" : "+v"(d[c]) : "v"(da)))
+  if constexpr (KIND == 37) PROBE_LOOP(asm volatile("v_ldexp_f64 %0, %0, %1" : "+v"(d[c]) : "v"(a)))
+  if constexpr (KIND == 38) PROBE_LOOP(asm volatile("v_rndne_f64 %0, %0" : "+v"(d[c])))
+  if constexpr (KIND == 39) PROBE_LOOP(asm volatile("v_cvt_f64_u32 %0, %1" : "=v"(d[c]) : "v"(v[c])))
+  if constexpr (KIND == 40) PROBE_LOOP(asm volatile("v_cmp_lt_f64_e64 %0, %1, %2" : "+s"(m[c]) : "v"(d[c]), "v"(da)))
   uint32_t acc = 0;
   for (int c = 0; c < kChains; ++c)
     acc ^= v[c] ^ static_cast<uint32_t>(__double_as_longlong(d[c])) ^ static_cast<uint32_t>(m[c]);
@@ -69,7 +95,12 @@ __global__ __launch_bounds__(kThreads) void probe_kernel(uint32_t* out, uint32_t
 const char* const kNames[] = {"v_add_f32",     "v_fma_f32",     "v_xor_b32",    "v_add_u32",        "v_ashrrev_i32",
                               "v_lshlrev_b32", "v_bfi_b32",     "v_and_or_b32", "v_bitop3_b32",     "v_mad_u64_u32",
                               "v_cvt_f32_u32", "v_rndne_f32",   "v_ldexp_f32",  "v_cmp_le_f32_e64", "v_alignbit_b32",
-                              "v_fma_f64",     "v_add_f64",     "v_exp_f32"};
+                              "v_fma_f64",     "v_add_f64",     "v_exp_f32",    "v_sub_f32",        "v_mul_f32_e64_neg",
+                              "v_fmaak_f32",   "v_and_b32",     "v_or_b32",     "v_sub_u32",        "v_lshrrev_b32",
+                              "v_mov_b32",     "v_bfe_i32",     "v_max_f32",    "v_add3_u32",       "v_lshl_add_u32",
+                              "v_perm_b32",    "v_cvt_i32_f32", "v_mul_lo_u32", "v_mul_hi_u32",     "v_addc_co_u32_e64",
+                              "v_cndmask_b32_e64", "v_mul_f64", "v_ldexp_f64",  "v_rndne_f64",      "v_cvt_f64_u32",
+                              "v_cmp_lt_f64_e64"};
 constexpr int kKinds = sizeof(kNames) / sizeof(kNames[0]);
 
 template <int KIND>
