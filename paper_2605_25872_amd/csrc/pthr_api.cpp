@@ -58,7 +58,10 @@ Layout layout_of(const pthr_params& p) {
   l.beta32 = o;    o = align256(o + 4 * NT);
   l.spins = o;     o = align256(o + 4 * S * d.NW * d.V);
   l.J = o;         o = align256(o + fp * S * 3 * d.V);
-  l.beta_clone = o; o = align256(o + fp * S * d.C);
+  // + 16 bytes: the sweep reads the factors of a Philox block's clones as one
+  // contiguous load, and a partial last block reaches up to 3 (FP32) or 1
+  // (FP64) entries past the table
+  l.beta_clone = o; o = align256(o + fp * S * d.C + 16);
   l.clone_at = o;  o = align256(o + 4 * S * NR * NT);
   l.er_head = o;   o = align256(o + 4 * S * NR);
   l.pt_last = o;   o = align256(o + S * NR * (NT - 1));

@@ -518,8 +518,8 @@ __device__ __forceinline__ RunSigns run_signs(const WordSigns& ws, int b_top) {
 // The Metropolis attempts of random-number indices n = grp*G + j (j from G-1
 // down to 0) of one word, all drawing on Philox block grp.  The word's clones
 // are clone0 + (n - n0), n0 = the index of clone0 (a multiple of G); indices
-// past the word's last clone (a partial last block) run on that clone's beta
-// and are discarded by the caller.  Accept iff dE <= 0 or u < exp(-beta dE).
+// past the word's last clone (a partial last block) run on the next entries of
+// the clone-factor table and are discarded by the caller.  Accept iff dE <= 0 or u < exp(-beta dE).
 // kMaybeEarly: clones colder than the early-out threshold may decide from the
 // binade of exp(x).  kHB: heat-bath test instead of Metropolis (no early-out).
 // Each decision is shifted in at bit 0 of `flips`.  `rs` holds the sign words
@@ -535,9 +535,13 @@ __device__ __forceinline__ void attempt_group(const Geo& g, const FP* __restrict
                                               const SiteJ<FP>& sj, const Block& blk, int grp, int n0, int clone0,
                                               int nbits, int early_beta_bits, uint32_t& flips) {
   constexpr int G = sizeof(FP) == 8 ? 2 : 4;  // clones per Philox block
+  // the factors of the block's G clones, one contiguous (scalar) load; in a
+  // partial last block the surplus entries belong to the next clones or to
+  // the table's padding, and their decisions are discarded
+  const FP* __restrict__ bg = bc + (clone0 + grp * G - n0);
   FP beta[G];
 #pragma unroll
-  for (int j = 0; j < G; ++j) beta[j] = bc[clone0 + min(grp * G + j - n0, nbits - 1)];
+  for (int j = 0; j < G; ++j) beta[j] = bg[j];
 #pragma unroll
   for (int j = G - 1; j >= 0; --j) {
     FP dE;  // the couplings carry the factor 2: the sum is dE = 2h
