@@ -84,8 +84,8 @@ def valu_peak(update: str, precision: str) -> tuple[float, int]:
 # SHA-256 is recorded here; any other source reports null.
 SWEEP_TRAFFIC = {
     "workload": "l16_fp32",
-    "sources_sha256": "dd5a16eaccf483a82dd869ad132738e42cd9d6e04526788321c3a6bd71dedab3",
-    "fetch_kib": 74990.25,
+    "sources_sha256": "1c5ae5283cdf16f02150173293408233f74ea6f5022b83f19cc9facdae74d646",
+    "fetch_kib": 75007.5625,
     "write_kib": 98304.0,
 }
 KERNEL_SOURCES = ("paper_2605_25872_amd/csrc/pthr_kernels.hip", "paper_2605_25872_amd/csrc/pthr_internal.h")
