@@ -380,43 +380,43 @@ __device__ int block_exclusive_scan(int v, int32_t* misc, int* total) {
 }
 
 // ---------------------------------------------------------------- union-find
-// Lock-free union-find in LDS.  Links always point from a root to a smaller
-// site of the same cluster (atomicMin), so lab[x] <= x for every x, chains
-// strictly decrease, and the surviving root of a cluster is its smallest
-// site.  find() halves paths as it walks (lab[x] := lab[lab[x]]); a racing
-// store can only replace a parent by another ancestor-or-relinked site that
-// is smaller and in the same cluster, which keeps both properties.
-__device__ __forceinline__ int find_root(uint32_t* lab, int x, int V, bool* bad) {
-  int n = 0;
+// Lock-free union-find in LDS.  Every entry that is read is a run start
+// initialised to itself before the unions start, and every write keeps
+// lab[x] <= x with equality only at roots: links go from a root to a smaller
+// site of the same cluster (atomicMin), and find() splits paths as it walks
+// (lab[x] := lab[lab[x]] <= lab[x] < x).  Chains therefore strictly decrease,
+// a find ends within x steps, and the surviving root of a cluster is its
+// smallest site.  A racing store can only replace a parent by another
+// ancestor-or-relinked site that is smaller and in the same cluster, which
+// keeps both properties; a link that loses a race is retried from the value
+// atomicMin returned.  Each loop has a single exit condition: the exec-mask
+// bookkeeping of divergent loops is scalar work that competes for issue.
+__device__ __forceinline__ int find_root(uint32_t* lab, int x) {
   int p = static_cast<int>(lab[x]);
   while (p != x) {
     const int gp = static_cast<int>(lab[p]);
-    if (gp != p) lab[x] = static_cast<uint32_t>(gp);  // path halving
-    x = gp;
-    p = static_cast<int>(lab[x]);
-    if (++n > V) {
-      *bad = true;
-      break;
-    }
+    lab[x] = static_cast<uint32_t>(gp);  // path splitting
+    x = p;
+    p = gp;
   }
   return x;
 }
+// Joins the clusters of a and b.  Every failed link replaces the larger root
+// by the smaller value found in its entry, so the larger of the two roots
+// strictly decreases and the loop ends within V rounds; the bound only guards
+// that argument (reported as an error).
 __device__ __forceinline__ void unite(uint32_t* lab, int a, int b, int V, bool* bad) {
-  for (int n = 0; n < 4 * V + 8; ++n) {
-    a = find_root(lab, a, V, bad);
-    b = find_root(lab, b, V, bad);
-    if (a == b) return;
-    if (a < b) {
-      const int old = static_cast<int>(atomicMin(&lab[b], static_cast<uint32_t>(a)));
-      if (old == b) return;
-      b = old;
-    } else {
-      const int old = static_cast<int>(atomicMin(&lab[a], static_cast<uint32_t>(b)));
-      if (old == a) return;
-      a = old;
-    }
+  bool linked = false;
+  for (int n = 0; !linked && n < V + 2; ++n) {
+    a = find_root(lab, a);
+    b = find_root(lab, b);
+    const int lo = a < b ? a : b, hi = a < b ? b : a;
+    const int old = lo == hi ? hi : static_cast<int>(atomicMin(&lab[hi], static_cast<uint32_t>(lo)));
+    linked = old == hi;
+    a = lo;
+    b = old;
   }
-  *bad = true;
+  if (!linked) *bad = true;
 }
 
 // ---------------------------------------------------------------- the kernel
@@ -1021,7 +1021,7 @@ __device__ bool houdayer_moves(const Geo& g, const HouLds& s, int M, int sample,
     if (active) {
       for (uint32_t r = rs; r; r &= r - 1u) {
         const int i = i0 + __builtin_ctz(r);
-        const int root = find_root(lab, i, V, &bad);
+        const int root = find_root(lab, i);
         lab[i] = static_cast<uint32_t>(root);
         if (flips && g.mode == 0 && root == i) {
           const Block blk = philox10(ctr_word(i, 0, kAcu), t, slot, sample, g.key0, g.key1);
