@@ -1064,12 +1064,16 @@ __device__ bool houdayer_moves(const Geo& g, const HouLds& s, int M, int sample,
         const int last = (m + 1 < M && base + m + 1 < n_moves) ? s.misc[32 + m + 1] : s.misc[32 + kMaxHouMoves];
         if (last > first) {
           const uint32_t root = static_cast<uint32_t>(s.misc[32 + kMaxHouMoves + 1 + m]);
+          uint32_t fl = 0;
           for (uint32_t r = rs; r; r &= r - 1u) {
             const int xs = __builtin_ctz(r);
-            if (lab[i0 + xs] != root) continue;
             const uint32_t rest = r & (r - 1u);
-            const int xe = rest ? __builtin_ctz(rest) : L;
-            for (int x = xs; x < xe; ++x) flip_pair_atomic(g, s.sp, a, b, plane_idx(i0 + x, (x + y + z) & 1, g.Vh));
+            const uint32_t run = (rest ? (rest & (0u - rest)) : (full + 1u)) - (1u << xs);  // bits xs .. xe-1
+            fl |= lab[i0 + xs] == root ? run : 0u;
+          }
+          for (; fl; fl &= fl - 1u) {
+            const int x = __builtin_ctz(fl);
+            flip_pair_atomic(g, s.sp, a, b, plane_idx(i0 + x, (x + y + z) & 1, g.Vh));
           }
         }
       }
@@ -1080,14 +1084,19 @@ __device__ bool houdayer_moves(const Geo& g, const HouLds& s, int M, int sample,
           int32_t* out = labels + ((size_t(sample) * (g.NR / 2) + p) * g.K_acu + k) * V;
           for (int x = 0; x < L; ++x) out[i0 + x] = static_cast<int32_t>(lab[i0 + start_at(rs, x)]);
         } else {
-          // all-cluster update: flip both replicas on clusters whose root drew eta = -1
+          // all-cluster update: flip both replicas on clusters whose root drew
+          // eta = -1; the row's sites to flip are gathered into one mask first
+          uint32_t fl = 0;
           for (uint32_t r = rs; r; r &= r - 1u) {
             const int xs = __builtin_ctz(r);
             const uint32_t root = lab[i0 + xs];
-            if (!((eta[root >> 5] >> (root & 31)) & 1u)) continue;
             const uint32_t rest = r & (r - 1u);
-            const int xe = rest ? __builtin_ctz(rest) : L;
-            for (int x = xs; x < xe; ++x) flip_pair_atomic(g, s.sp, a, b, plane_idx(i0 + x, (x + y + z) & 1, g.Vh));
+            const uint32_t run = (rest ? (rest & (0u - rest)) : (full + 1u)) - (1u << xs);  // bits xs .. xe-1
+            fl |= (eta[root >> 5] >> (root & 31)) & 1u ? run : 0u;
+          }
+          for (; fl; fl &= fl - 1u) {
+            const int x = __builtin_ctz(fl);
+            flip_pair_atomic(g, s.sp, a, b, plane_idx(i0 + x, (x + y + z) & 1, g.Vh));
           }
         }
       }
