@@ -882,18 +882,44 @@ __device__ __forceinline__ uint32_t row_overlap(const Geo& g, const uint32_t* sp
   return clone_row(g, sp, a, row) ^ clone_row(g, sp, b, row);
 }
 
-// Joins the runs of row `row` (mask q, starts rs) with those of row `nrow`
-// (mask qn) wherever a bond between the rows has equal overlap at both ends:
-// one union per maximal interval in which both runs stay the same.
-__device__ __forceinline__ void join_rows(const Geo& g, uint32_t* lab, uint32_t q, uint32_t rs, int row, uint32_t qn,
-                                          int nrow, uint32_t full, bool* bad) {
-  const uint32_t rsn = run_starts(qn, full);
+// Positions x where a run of a row (mask q, starts rs) must be joined with a
+// run of the next row (mask qn, starts rsn): the bond between the rows has
+// equal overlap at both ends, one union per maximal interval in which both
+// runs stay the same.
+__device__ __forceinline__ uint32_t join_points(uint32_t q, uint32_t rs, uint32_t qn, uint32_t rsn, uint32_t full) {
   const uint32_t eq = ~(q ^ qn) & full;
-  uint32_t u = eq & (~(eq << 1) | rs | rsn);
-  while (u) {
-    const int x = __builtin_ctz(u);
-    u &= u - 1u;
-    unite(lab, start_at(rs, x) + g.L * row, start_at(rsn, x) + g.L * nrow, g.V, bad);
+  return eq & (~(eq << 1) | rs | rsn);
+}
+
+// All unions of one row: the periodic +x bond (if the row's first and last
+// sites have equal overlap and lie in different runs) and the join points
+// with the +y row ry and the +z row rz, in one loop (the wave runs as many
+// rounds as its busiest work-item, not the sum of three such maxima).
+__device__ __forceinline__ void join_row(const Geo& g, uint32_t* lab, uint32_t q, uint32_t rs, int row, uint32_t qy,
+                                         int ry, uint32_t qz, int rz, uint32_t full, bool* bad) {
+  const int L = g.L;
+  const uint32_t rsy = run_starts(qy, full), rsz = run_starts(qz, full);
+  uint32_t uy = join_points(q, rs, qy, rsy, full), uz = join_points(q, rs, qz, rsz, full);
+  const int xl = 31 - __builtin_clz(rs);
+  bool ux = xl > 0 && ((q >> (L - 1)) & 1u) == (q & 1u);
+  while (ux || (uy | uz)) {
+    int a, b;
+    if (ux) {
+      a = L * row;
+      b = L * row + xl;
+      ux = false;
+    } else if (uy) {
+      const int x = __builtin_ctz(uy);
+      uy &= uy - 1u;
+      a = start_at(rs, x) + L * row;
+      b = start_at(rsy, x) + L * ry;
+    } else {
+      const int x = __builtin_ctz(uz);
+      uz &= uz - 1u;
+      a = start_at(rs, x) + L * row;
+      b = start_at(rsz, x) + L * rz;
+    }
+    unite(lab, a, b, g.V, bad);
   }
 }
 
@@ -1008,26 +1034,27 @@ __device__ bool houdayer_moves(const Geo& g, const HouLds& s, int M, int sample,
       }
     }
     __syncthreads();
-    // unions: the periodic +x bond of the row, then the +y and +z rows
+    // unions: the periodic +x bond of the row, the +y and the +z rows
     if (active) {
-      const int xl = 31 - __builtin_clz(rs);
-      if (xl > 0 && ((q >> (L - 1)) & 1u) == (q & 1u)) unite(lab, i0, i0 + xl, V, &bad);
       const int ry = (y + 1 == L ? 0 : y + 1) + L * z, rz = y + L * (z + 1 == L ? 0 : z + 1);
-      join_rows(g, lab, q, rs, row, s.qrow[m * L2 + ry], ry, full, &bad);
-      join_rows(g, lab, q, rs, row, s.qrow[m * L2 + rz], rz, full, &bad);
+      join_row(g, lab, q, rs, row, s.qrow[m * L2 + ry], ry, s.qrow[m * L2 + rz], rz, full, &bad);
     }
     __syncthreads();
     // roots; under ACU every root draws its eta from the block (ACU, root, slot)
     if (active) {
+      uint32_t own_roots = 0;  // run starts that are the roots of their clusters
       for (uint32_t r = rs; r; r &= r - 1u) {
-        const int i = i0 + __builtin_ctz(r);
-        const int root = find_root(lab, i);
-        lab[i] = static_cast<uint32_t>(root);
-        if (flips && g.mode == 0 && root == i) {
+        const int x = __builtin_ctz(r);
+        const int root = find_root(lab, i0 + x);
+        lab[i0 + x] = static_cast<uint32_t>(root);
+        own_roots |= root == i0 + x ? 1u << x : 0u;
+      }
+      if (flips && g.mode == 0)
+        for (; own_roots; own_roots &= own_roots - 1u) {
+          const int i = i0 + __builtin_ctz(own_roots);
           const Block blk = philox10(ctr_word(i, 0, kAcu), t, slot, sample, g.key0, g.key1);
           if (blk.w0 >> 31) atomicOr(&eta[i >> 5], 1u << (i & 31));
         }
-      }
     }
     if (stats) {
       __syncthreads();
