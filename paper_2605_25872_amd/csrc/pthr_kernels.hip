@@ -1136,25 +1136,51 @@ __device__ bool houdayer_moves(const Geo& g, const HouLds& s, int M, int sample,
 // ------------------------------------------------------------------ energies
 // E(c) = -sum_i a_i, a_i = (J_x[i] s_i s_{i+x} + J_y[i] s_i s_{i+y}) + J_z[i] s_i s_{i+z}
 // in double, summed by a pairwise tree in natural site order (own chunk, then
-// a butterfly across the wave, then across the waves), padded with +0.0 to a
+// across the wave's lanes, then across the waves), padded with +0.0 to a
 // power of two.  Writes s.E[0..NPT) and, with `heads`, s.E[NPT + r] for the
 // oldest reservoir clone of every group r (s.head must be loaded).
+//
+// The PT clones are taken 16 at a time from their 32-clone words: a
+// work-item reads the words of its sites and their +x, +y, +z neighbours
+// once per word and walks the clones' bits with one doubling per clone.  The
+// 16 lane trees of a batch run transposed: at the level that adds lanes l and
+// l ^ o (o = 1, 2, 4, 8) each lane keeps the half of its clones selected by
+// bit o of its lane id and adds its partner's value of them, so after four
+// levels lane l holds clone (l & 15) summed over its 16 lanes; levels 16 and
+// 32 are ordinary exchanges.  Every addition pairs the same two subtrees as
+// the tree does, so the sums are bit-identical to it.
+template <int CH>
+struct EnergySites {
+  double jf[CH][3];
+  int self[CH], fn[CH][3];
+};
+
+// Pairwise tree over the work-item's CH site terms of one clone.
+template <int CH>
+__device__ __forceinline__ double own_tree(double (&a)[CH]) {
+#pragma unroll
+  for (int w = CH; w > 1; w >>= 1) {
+#pragma unroll
+    for (int j = 0; j < w / 2; ++j) a[j] = a[2 * j] + a[2 * j + 1];
+  }
+  return a[0];
+}
+
 template <typename FP, int CH>
 __device__ __forceinline__ void energy_phase(const Geo& g, const FP* Js, bool heads = false) {
   const Lds s = lds_view(g, sizeof(FP));
   const Own<CH> own(g.V);
-  double jf[CH][3];
-  int self[CH], fn[CH][3];
+  EnergySites<CH> es;
 #pragma unroll
   for (int j = 0; j < CH; ++j) {
     const int i = own.owns ? own.first + j : 0;
     const Site st = site_of(i, g.L);
     const int col = colour_of(st);
-    self[j] = plane_idx(i, col, g.Vh);
+    es.self[j] = plane_idx(i, col, g.Vh);
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-      jf[j][d] = own.owns ? static_cast<double>(Js[size_t(d) * g.V + i]) : 0.0;
-      fn[j][d] = plane_idx(neighbour(st, 2 * d, g.L), col ^ 1, g.Vh);
+      es.jf[j][d] = own.owns ? static_cast<double>(Js[size_t(d) * g.V + i]) : 0.0;
+      es.fn[j][d] = plane_idx(neighbour(st, 2 * d, g.L), col ^ 1, g.Vh);
     }
   }
   double* red = reinterpret_cast<double*>(s.lab);
@@ -1163,8 +1189,59 @@ __device__ __forceinline__ void energy_phase(const Geo& g, const FP* Js, bool he
   while (nwp < nwave) nwp <<= 1;
   // entries: the PT clones, then (heads) the oldest reservoir clone of each group
   const int n_e = g.NPT + (heads ? g.NR : 0);
-  for (int c = 0; c < n_e; ++c) {
-    const int clone = c < g.NPT ? c : g.NPT + (c - g.NPT) * g.NERG + s.head[c - g.NPT];
+  const int lane = lane_id();
+  // clones per batch: 16 (8 with 8 sites per work-item, for registers)
+  constexpr int B = CH >= 8 ? 8 : 16;
+  for (int c0 = 0; c0 < g.NPT; c0 += B) {
+    // bond-sign words of this batch's word: bit b set where the two spins of
+    // a bond differ (the term is -J), moved so that clone c0 + B - 1 sits at
+    // bit 31; element k of v is clone c0 + B - 1 - k
+    const uint32_t* plane = s.sp + size_t(c0 >> 5) * g.V;
+    uint32_t xs[CH][3];
+#pragma unroll
+    for (int j = 0; j < CH; ++j) {
+      const uint32_t si = own.owns ? plane[es.self[j]] : 0u;
+#pragma unroll
+      for (int d = 0; d < 3; ++d) xs[j][d] = (own.owns ? si ^ plane[es.fn[j][d]] : 0u) << (32 - B - (c0 & 31));
+    }
+    double v[B];
+#pragma unroll
+    for (int k = 0; k < B; ++k) {
+      double a[CH];
+#pragma unroll
+      for (int j = 0; j < CH; ++j) {
+        const double tx = neg_if64(es.jf[j][0], xs[j][0] >> 31);
+        const double ty = neg_if64(es.jf[j][1], xs[j][1] >> 31);
+        const double tz = neg_if64(es.jf[j][2], xs[j][2] >> 31);
+        a[j] = (tx + ty) + tz;
+      }
+      v[k] = own_tree<CH>(a);
+#pragma unroll
+      for (int j = 0; j < CH; ++j)
+#pragma unroll
+        for (int d = 0; d < 3; ++d) xs[j][d] += xs[j][d];
+    }
+    // transposed lane tree over lanes B m .. B m + B - 1
+#pragma unroll
+    for (int o = 1, n = B; o < B; o <<= 1, n >>= 1) {
+      const bool upper = (lane & o) != 0;
+#pragma unroll
+      for (int k = 0; k < n / 2; ++k) {
+        // keep element 2k + upper, send the other one
+        const double keep = upper ? v[2 * k + 1] : v[2 * k];
+        const double send = upper ? v[2 * k] : v[2 * k + 1];
+        v[k] = keep + __shfl_xor(send, o, kWave);
+      }
+    }
+    double t = v[0];  // element lane % B, summed over the lane's group of B
+#pragma unroll
+    for (int o = B; o < kWave; o <<= 1) t = t + __shfl_xor(t, o, kWave);
+    const int c = c0 + B - 1 - (lane % B);
+    if (lane < B && c < g.NPT) red[wave_id() * n_e + c] = t;
+  }
+  // the reservoir heads, one clone at a time
+  for (int c = g.NPT; c < n_e; ++c) {
+    const int clone = g.NPT + (c - g.NPT) * g.NERG + s.head[c - g.NPT];
     const uint32_t* plane = s.sp + size_t(word_of(g, clone)) * g.V;
     const int b = bit_of(g, clone);
     double a[CH];
@@ -1172,22 +1249,17 @@ __device__ __forceinline__ void energy_phase(const Geo& g, const FP* Js, bool he
     for (int j = 0; j < CH; ++j) {
       a[j] = 0.0;
       if (own.owns) {
-        const uint32_t si = plane[self[j]] >> b;
-        const double tx = neg_if64(jf[j][0], (si ^ (plane[fn[j][0]] >> b)) & 1u);
-        const double ty = neg_if64(jf[j][1], (si ^ (plane[fn[j][1]] >> b)) & 1u);
-        const double tz = neg_if64(jf[j][2], (si ^ (plane[fn[j][2]] >> b)) & 1u);
+        const uint32_t si = plane[es.self[j]] >> b;
+        const double tx = neg_if64(es.jf[j][0], (si ^ (plane[es.fn[j][0]] >> b)) & 1u);
+        const double ty = neg_if64(es.jf[j][1], (si ^ (plane[es.fn[j][1]] >> b)) & 1u);
+        const double tz = neg_if64(es.jf[j][2], (si ^ (plane[es.fn[j][2]] >> b)) & 1u);
         a[j] = (tx + ty) + tz;
       }
     }
-#pragma unroll
-    for (int w = CH; w > 1; w >>= 1) {
-#pragma unroll
-      for (int j = 0; j < w / 2; ++j) a[j] = a[2 * j] + a[2 * j + 1];
-    }
-    double v = a[0];
+    double v = own_tree<CH>(a);
 #pragma unroll
     for (int off = 1; off < kWave; off <<= 1) v = v + __shfl_xor(v, off, kWave);
-    if (lane_id() == 0) red[wave_id() * n_e + c] = v;
+    if (lane == 0) red[wave_id() * n_e + c] = v;
   }
   __syncthreads();
   for (int c = threadIdx.x; c < n_e; c += blockDim.x) {
