@@ -140,6 +140,17 @@ def test_l2_smallest_lattice_and_two_temperatures():
     stepwise(o, g, 6)
 
 
+@pytest.mark.parametrize("L,precision", [(20, "fp32"), (16, "fp64")])
+def test_largest_lattices(L, precision):
+    """The largest lattice each form supports with one workgroup per sample
+    (L=20 FP32: 8 sites per work-item, 1000 work-items; L=16 FP64: 4 sites per
+    work-item), with ragged clone words, the reservoir and every sub-step."""
+    step(f"largest lattice L={L} {precision}")
+    o, g = make_pair(L, 2, 2, 5, 2, precision=precision, sweeps=2, er_sweeps=4, t_range=(0.3, 1.5))
+    assert g.schedule().threads_per_sample == 1024
+    stepwise(o, g, 2)
+
+
 def test_no_houdayer_no_reservoir():
     step("plain PT")
     o, g = make_pair(4, 2, 2, 5, 0, t_acu=0.0)
