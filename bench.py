@@ -84,8 +84,8 @@ def valu_peak(update: str, precision: str) -> tuple[float, int]:
 # SHA-256 is recorded here; any other source reports null.
 SWEEP_TRAFFIC = {
     "workload": "l16_fp32",
-    "sources_sha256": "1c5ae5283cdf16f02150173293408233f74ea6f5022b83f19cc9facdae74d646",
-    "fetch_kib": 75007.5625,
+    "sources_sha256": "4ffeef297e25a32b5d993546e24b10ca769417c379f6c803210c9facad803886",
+    "fetch_kib": 75012.0625,
     "write_kib": 98304.0,
 }
 KERNEL_SOURCES = ("paper_2605_25872_amd/csrc/pthr_kernels.hip", "paper_2605_25872_amd/csrc/pthr_internal.h")
