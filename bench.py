@@ -47,8 +47,8 @@ T_EQ_EMCS = {12: 2 ** 17, 14: 6.4e6, 16: 3.84e7, 18: 3.48e7}
 #   Metropolis FP32 (36): half = 1/4 of a Philox4x32-10 block (10 rounds x
 #   (2 widening multiplies + 2 three-way XORs)) 10, float(w) 1, rint 1,
 #   2^k (convert + ldexp) 2, flip bit 1; fast = local field (6 sign
-#   insertions + 5 adds) 11, t = -(beta log2 e) dE 1, f = t - k 1, 7 Horner
-#   steps, test (2^t 2^32 - float(w)) 1.
+#   insertions + 5 adds) 11, t = -(beta log2 e) dE 1, f = t - k 1, 6 Horner
+#   steps (degree-6 polynomial of 2^f), test (2^t 2^32 - float(w)) 1.
 #   Metropolis FP64 (57): half = 1/2 block 20, two converts of the 53-bit
 #   uniform 2, 5 adds of the local field, -beta dE 1, exp (2 for k, 2
 #   Cody-Waite steps, 14 Horner steps, scale 1) 19, dE <= 0 and u < exp
@@ -62,9 +62,9 @@ T_EQ_EMCS = {12: 2 ** 17, 14: 6.4e6, 16: 3.84e7, 18: 3.48e7}
 #   of threshold (a compare and two selects each) and the fused multiply-add
 #   (half), less the dE <= 0 compare.
 OPS_BY_CLASS = {
-    ("metropolis", "fp32"): {"fast": 11 + 1 + 1 + 7 + 1, "half": 10 + 1 + 1 + 2 + 1},
+    ("metropolis", "fp32"): {"fast": 11 + 1 + 1 + 6 + 1, "half": 10 + 1 + 1 + 2 + 1},
     ("metropolis", "fp64"): {"fast": 6 + 1, "half": 20 + 2 + 5 + 1 + 19 + 3},
-    ("heatbath", "fp32"): {"fast": 11 + 1 + 1 + 7 + 1 + 1, "half": 10 + 1 + 1 + 2 + 2 + 2 + 1 + 1},
+    ("heatbath", "fp32"): {"fast": 11 + 1 + 1 + 6 + 1 + 1, "half": 10 + 1 + 1 + 2 + 2 + 2 + 1 + 1},
     ("heatbath", "fp64"): {"fast": 6 + 1, "half": 20 + 2 + 5 + 1 + 19 + 3 + 3 + 1 + 2},
 }
 
@@ -84,8 +84,8 @@ def valu_peak(update: str, precision: str) -> tuple[float, int]:
 # SHA-256 is recorded here; any other source reports null.
 SWEEP_TRAFFIC = {
     "workload": "l16_fp32",
-    "sources_sha256": "4ffeef297e25a32b5d993546e24b10ca769417c379f6c803210c9facad803886",
-    "fetch_kib": 75012.0625,
+    "sources_sha256": "c6e5914084a146f1eb36086915294c8186d8697c2cf099b94a3fa979395848b0",
+    "fetch_kib": 75011.375,
     "write_kib": 98304.0,
 }
 KERNEL_SOURCES = ("paper_2605_25872_amd/csrc/pthr_kernels.hip", "paper_2605_25872_amd/csrc/pthr_internal.h")
@@ -384,13 +384,15 @@ def main() -> int:
     stream = torch.cuda.current_stream(dev)
     n_er = w.er_sweeps_per_emcs if w.n_reservoir else 0
 
-    def step(ev_a=None, ev_b=None):
-        if ev_a is not None:
-            ev_a.record(stream)
+    def step(ev=None):
+        if ev is not None:
+            ev[0].record(stream)
         g.sweep(w.sweeps_per_emcs, n_er)
-        if ev_b is not None:
-            ev_b.record(stream)
+        if ev is not None:
+            ev[1].record(stream)
         g.houdayer()
+        if ev is not None:
+            ev[2].record(stream)
         g.pt_swap(True)
         g.measure(obs)
 
@@ -398,16 +400,16 @@ def main() -> int:
         step()
         torch.cuda.synchronize()
         log(f"warmup step {i + 1}/{args.warmup} done")
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-           for _ in range(args.steps)]
+    evs = [tuple(torch.cuda.Event(enable_timing=True) for _ in range(3)) for _ in range(args.steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for a, b in evs:
-        step(a, b)
+    for ev in evs:
+        step(ev)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     g.check()
-    sweep_ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+    sweep_ms = float(np.mean([a.elapsed_time(b) for a, b, _ in evs]))
+    houdayer_ms = float(np.mean([b.elapsed_time(c) for _, b, c in evs]))
     log(f"timed {args.steps} steps in {elapsed:.3f} s; sweep kernel {sweep_ms:.2f} ms per launch")
 
     att = attempts_per_emcs(w)
@@ -439,6 +441,8 @@ def main() -> int:
                    "exp_early_out_below_T": g.schedule().exp_early_out / 1000,
                    "clone_split": g.schedule().clone_split},
         "houdayer_moves_per_s": moves * args.steps / elapsed,
+        "houdayer_kernel": {"ms_per_launch": houdayer_ms,
+                            "moves_per_s": moves / (houdayer_ms * 1e-3) if moves else None},
         "attempts_per_emcs": att,
         "wall_time_per_equilibrated_sample_s":
             (elapsed / args.steps) / w.n_samples * T_EQ_EMCS.get(w.L, float("nan")),

@@ -91,6 +91,8 @@ def _lib() -> ctypes.CDLL:
     lib.oracle_uniform32.argtypes = [ctypes.c_uint32]
     lib.oracle_pexp2_32.restype = ctypes.c_float
     lib.oracle_pexp2_32.argtypes = [ctypes.c_float]
+    lib.oracle_pexp2_32_coef.restype = ctypes.c_float
+    lib.oracle_pexp2_32_coef.argtypes = [ctypes.c_int]
     lib.oracle_heat_bath_flip.restype = i32
     lib.oracle_heat_bath_flip.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double]
     lib.oracle_heat_bath_flip32.restype = i32
@@ -133,6 +135,11 @@ def pexp2_32(t: float) -> np.float32:
     """FP32 form of the Metropolis exponential: 2^t (IEEE overflow to +inf,
     gradual underflow to 0)."""
     return np.float32(_lib().oracle_pexp2_32(float(np.float32(t))))
+
+
+def pexp2_32_coefficients() -> list[float]:
+    """Coefficients c0..c6 of the polynomial pexp2_32 evaluates for 2^f."""
+    return [float(_lib().oracle_pexp2_32_coef(n)) for n in range(7)]
 
 
 def heat_bath_flip(u: float, a: float, dE: float, fp32: bool = False) -> bool:

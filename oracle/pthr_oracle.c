@@ -111,13 +111,11 @@ float oracle_uniform32(uint32_t w) { return (float)w * 0x1p-32f; }
 /* ------------------------------------------------------------------------- */
 /* exp(x) for x <= 0, written out so both implementations compute the same
  * bits: Cody-Waite reduction x = k ln2 + r with a two-word ln2, then the
- * Taylor polynomial of degree 13 (FP64) or 7 (FP32) with coefficients 1/n!
- * rounded to the working precision, evaluated by Horner with fused
- * multiply-adds, then scaled by 2^k. */
+ * Taylor polynomial of degree 13 with coefficients 1/n! rounded to double,
+ * evaluated by Horner with fused multiply-adds, then scaled by 2^k. */
 static const double LOG2E = 0x1.71547652b82fep+0;   /* RN(1/ln 2)                      */
 static const double LN2_HI = 0x1.62e42feep-1;       /* ln 2 truncated to 32 bits       */
 static const double LN2_LO = 0x1.a39ef35793c76p-33; /* RN(ln 2 - LN2_HI)               */
-static const double LN2_D = 0x1.62e42fefa39efp-1;   /* RN(ln 2)                        */
 
 double oracle_pexp(double x) {
   if (x < -708.0) return 0.0;
@@ -136,22 +134,21 @@ double oracle_pexp(double x) {
 
 /* FP32 form of the Metropolis exponential, in base 2: 2^t for
  * t = -(beta log2(e)) dE.  t = k + f with k = rint(t) and f = t - k (exact,
- * |f| <= 1/2); 2^f = e^(f ln 2) by its Taylor polynomial of degree 7, the
- * coefficients (ln 2)^n / n! computed in double and rounded to float, Horner
- * with fma; then 2^k by ldexpf, which overflows to +inf and underflows
- * gradually to 0 (the Metropolis test below decides the same whether a GPU
- * keeps or flushes those subnormals: u is 0 or at least 2^-32). */
+ * |f| <= 1/2); 2^f by the degree-6 polynomial 1 + c1 f + ... + c6 f^6 whose
+ * coefficients minimise the largest relative error on |f| <= 1/2 (fitted by
+ * oracle/exp2_fit.py, rounded to float; within 0.952 float ulp of 2^f for
+ * every float f there), Horner with fmaf; then 2^k by ldexpf, which
+ * overflows to +inf and underflows gradually to 0 (the Metropolis test below
+ * decides the same whether a GPU keeps or flushes those subnormals: u is 0 or
+ * at least 2^-32). */
+static const float EXP2_COEF[7] = {0x1p+0f,        0x1.62e43p-1f,   0x1.ebfbdcp-3f, 0x1.c6aee8p-5f,
+                                   0x1.3b2d4cp-7f, 0x1.5f3e54p-10f, 0x1.41fbbcp-13f};
+float oracle_pexp2_32_coef(int n) { return n >= 0 && n <= 6 ? EXP2_COEF[n] : 0.0f; }
 float oracle_pexp2_32(float t) {
-  float coef[8];
-  double v = 1.0;
-  for (int n = 0; n <= 7; ++n) {
-    if (n > 0) v *= LN2_D / n;
-    coef[n] = (float)v;
-  }
   float k = nearbyintf(t);
   float f = t - k;
-  float p = coef[7];
-  for (int n = 6; n >= 0; --n) p = fmaf(p, f, coef[n]);
+  float p = EXP2_COEF[6];
+  for (int n = 5; n >= 0; --n) p = fmaf(p, f, EXP2_COEF[n]);
   return ldexpf(p, (int)k);
 }
 

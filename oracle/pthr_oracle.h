@@ -126,6 +126,7 @@ double oracle_pexp(double x);
 double oracle_uniform53(uint32_t lo, uint32_t hi);
 float oracle_uniform32(uint32_t w);
 float oracle_pexp2_32(float t); /* FP32 form: 2^t (IEEE overflow and gradual underflow) */
+float oracle_pexp2_32_coef(int n); /* its polynomial's coefficient c_n, n = 0..6 */
 /* Heat-bath flip test given a = exp(-beta |dE|): fma(u, a, u) < (dE > 0 ? a : 1). */
 int oracle_heat_bath_flip(double u, double a, double dE);
 int oracle_heat_bath_flip32(float u, float a, float dE);
