@@ -45,24 +45,26 @@ T_EQ_EMCS = {12: 2 ** 17, 14: 6.4e6, 16: 3.84e7, 18: 3.48e7}
 # the branch-free form evaluates it), split by issue class ("fast": 2-cycle,
 # "half": 4-cycle instructions).
 #   Metropolis FP32 (36): half = 1/4 of a Philox4x32-10 block (10 rounds x
-#   (2 widening multiplies + 2 three-way XORs)) 10, float(w) 1, rint 1,
-#   2^k (convert + ldexp) 2, flip bit 1; fast = local field (6 sign
-#   insertions + 5 adds) 11, t = -(beta log2 e) dE 1, f = t - k 1, 6 Horner
+#   (2 widening multiplies + 2 three-way XORs)) 10, float(w) 1, ldexp 1,
+#   flip bit 1; fast = local field (6 sign insertions + 5 adds) 11,
+#   t = -(beta log2 e) dE 1, k = rint(t) by the float adder (add and
+#   subtract 1.5 2^23, integer k from the sum's bits) 3, f = t - k 1, 6 Horner
 #   steps (degree-6 polynomial of 2^f), test (2^t 2^32 - float(w)) 1.
 #   Metropolis FP64 (57): half = 1/2 block 20, two converts of the 53-bit
 #   uniform 2, 5 adds of the local field, -beta dE 1, exp (2 for k, 2
 #   Cody-Waite steps, 14 Horner steps, scale 1) 19, dE <= 0 and u < exp
 #   compares and the flip bit 3; fast = 6 sign insertions, 1 shift of the
 #   uniform.
-#   Heat bath FP32 (42): as Metropolis, plus u = float(w) 2^-32 (fast), a
-#   zeroed below the cut and the threshold a or 1 (a compare and a select
-#   each, half), the fused multiply-add (fast), and a compare instead of the
-#   subtraction (half).
+#   Heat bath FP32 (41): fast = field 11, t 1, f 1, 6 Horner steps,
+#   u = float(w) 2^-32 1, the fused multiply-add 1; half = Philox 10,
+#   float(w) 1, rint 1, 2^k (convert + ldexp) 2, a zeroed below the cut and
+#   the threshold a or 1 (a compare and a select each) 4, the final compare
+#   1, flip bit 1.
 #   Heat bath FP64 (63): as Metropolis, plus the zeroing of a and the choice
 #   of threshold (a compare and two selects each) and the fused multiply-add
 #   (half), less the dE <= 0 compare.
 OPS_BY_CLASS = {
-    ("metropolis", "fp32"): {"fast": 11 + 1 + 1 + 6 + 1, "half": 10 + 1 + 1 + 2 + 1},
+    ("metropolis", "fp32"): {"fast": 11 + 1 + 3 + 1 + 6 + 1, "half": 10 + 1 + 1 + 1},
     ("metropolis", "fp64"): {"fast": 6 + 1, "half": 20 + 2 + 5 + 1 + 19 + 3},
     ("heatbath", "fp32"): {"fast": 11 + 1 + 1 + 6 + 1 + 1, "half": 10 + 1 + 1 + 2 + 2 + 2 + 1 + 1},
     ("heatbath", "fp64"): {"fast": 6 + 1, "half": 20 + 2 + 5 + 1 + 19 + 3 + 3 + 1 + 2},
@@ -84,8 +86,8 @@ def valu_peak(update: str, precision: str) -> tuple[float, int]:
 # SHA-256 is recorded here; any other source reports null.
 SWEEP_TRAFFIC = {
     "workload": "l16_fp32",
-    "sources_sha256": "c6e5914084a146f1eb36086915294c8186d8697c2cf099b94a3fa979395848b0",
-    "fetch_kib": 75011.375,
+    "sources_sha256": "3a6b73b38d1b064db87fdc913d437a8b6c5087a415bf2e577e03f349a1853e97",
+    "fetch_kib": 75013.1875,
     "write_kib": 98304.0,
 }
 KERNEL_SOURCES = ("paper_2605_25872_amd/csrc/pthr_kernels.hip", "paper_2605_25872_amd/csrc/pthr_internal.h")

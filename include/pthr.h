@@ -123,7 +123,10 @@ size_t pthr_obs_hist_offset(const pthr_params *p);
  * strictly increasing, > 0; beta_k = 1/T_k), draws the initial spins, sets
  * every clone at its starting temperature and every reservoir FIFO to slot 0,
  * and resets the EMCS counter t and the sweep counters.  PTHR_EINVAL on
- * non-finite J or a bad grid. */
+ * non-finite J or a bad grid, and for PTHR_FP32 when the Metropolis exponent
+ * could leave the range its float rounding is exact in:
+ * (1/T_0) log2(e) 12 max|J| must stay below 2^22 (T_0 above about 1e-4 for
+ * Gaussian couplings). */
 int pthr_init_samples(pthr_ctx *ctx, const double *J_host, const double *T_host, void *d_state,
                       void *stream);
 

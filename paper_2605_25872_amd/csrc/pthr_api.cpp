@@ -408,6 +408,17 @@ int pthr_init_samples(pthr_ctx* ctx, const double* J_host, const double* T_host,
   const size_t nJ = size_t(p.n_samples) * 3 * ctx->d.V;
   for (size_t n = 0; n < nJ; ++n)
     if (!std::isfinite(J_host[n])) return ctx->fail(PTHR_EINVAL, "J[%zu] is not finite", n);
+  if (p.precision == PTHR_FP32) {
+    // The FP32 sweep rounds its exponent t = -(beta log2 e) dE to an integer
+    // with the float adder, exact while |t| < 2^22; |dE| <= 12 max|J|.
+    double jmax = 0.0;
+    for (size_t n = 0; n < nJ; ++n) jmax = std::max(jmax, std::fabs(static_cast<double>(static_cast<float>(J_host[n]))));
+    const double tmax = static_cast<double>(static_cast<float>(1.0 / T_host[0] * kLog2e)) * 12.0 * jmax * 1.001;
+    if (!(tmax < 4194304.0))
+      return ctx->fail(PTHR_EINVAL,
+                       "FP32 form: beta_max log2(e) 12 max|J| = %g must stay below 2^22 (raise T_min or use FP64)",
+                       tmax);
+  }
   hipStream_t s = static_cast<hipStream_t>(stream);
   // host image of the small regions and the couplings
   std::vector<double> b64(NT);

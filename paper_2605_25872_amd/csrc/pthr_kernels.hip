@@ -138,7 +138,7 @@ __device__ __forceinline__ float exp2_poly32(float f, float k) {
 // exp2_poly32_x2p32(f, k) decides exactly as float(w) * 2^-32 <=
 // exp2_poly32(f, k) (where the scaled 2^k underflows, float(w) * 2^-32 is 0
 // or at least 2^-32 and both sides agree).
-__device__ __forceinline__ float exp2_poly32_x2p32(float f, float k) {
+__device__ __forceinline__ float exp2_poly32_x2p32(float f, int k) {
   float p = 0x1.41fbbcp+19f;
   p = __builtin_fmaf(p, f, 0x1.5f3e54p+22f);
   p = __builtin_fmaf(p, f, 0x1.3b2d4cp+25f);
@@ -146,7 +146,7 @@ __device__ __forceinline__ float exp2_poly32_x2p32(float f, float k) {
   p = __builtin_fmaf(p, f, 0x1.ebfbdcp+29f);
   p = __builtin_fmaf(p, f, 0x1.62e430p+31f);
   p = __builtin_fmaf(p, f, 0x1p+32f);
-  return __builtin_ldexpf(p, static_cast<int>(k));
+  return __builtin_ldexpf(p, k);
 }
 
 // (a & mask) | (b & ~mask) as one v_bfi_b32.
@@ -229,9 +229,16 @@ struct Prec<float> {
   // bit: p - float(w) with p = 2^t * 2^32 is negative exactly when
   // float(w) > p (a difference of two floats is zero only when they are
   // equal, and rounding keeps its sign; +inf - float(w) = +inf).
+  // k = rint(t) comes from the float adder: t + 1.5 2^23 lies in
+  // [2^23, 2^24), where floats are the integers, so the sum rounds t to the
+  // nearest integer with ties to even, and k is the sum's representation less
+  // that of 1.5 2^23.  Valid for |t| < 2^22, which the library checks at
+  // initialisation (beta_max log2(e) max_i 2 sum_d |J| < 2^22).
   static __device__ __forceinline__ uint32_t reject_sign(uint32_t w, float t) {
-    const float k = __builtin_rintf(t);
-    const float p = exp2_poly32_x2p32(t - k, k);
+    const float kf = t + 0x1.8p23f;
+    const float k = kf - 0x1.8p23f;
+    const int ki = __float_as_int(kf) - 0x4B400000;
+    const float p = exp2_poly32_x2p32(t - k, ki);
     return __float_as_uint(p - static_cast<float>(w));
   }
   // Heat bath, FP32 form: a = 2^t, t = -(beta log2 e)|dE| (0 below t = -124),

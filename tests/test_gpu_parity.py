@@ -377,6 +377,19 @@ def test_errors_are_reported_not_raised_on_device():
         g.init_samples(inputs.couplings(4, 1), np.array([1.0, 0.5, 2.0, 3.0]))
 
 
+def test_fp32_form_rejects_temperatures_beyond_its_exponent_range():
+    """The FP32 sweep rounds t = -(beta log2 e) dE with the float adder,
+    exact for |t| < 2^22: initialisation refuses a grid whose coldest
+    temperature could take |t| past that, and accepts the paper's range."""
+    pthr = _pthr()
+    g = pthr.Pthr(4, 1, 2, 4, 0, 2, 0, "fp32", "acu", 1.0, 5)
+    J = inputs.couplings(4, 1)
+    with pytest.raises(pthr.PthrError, match="2\\^22"):
+        g.init_samples(J, np.array([1e-6, 0.5, 1.0, 1.5]))
+    g.init_samples(J, np.array([0.2, 0.5, 1.0, 1.5]))
+    g.sweep(2)
+
+
 # ----------------------------------------------------------------------------- full workloads, sampled
 def sampled_check(name, samples, n_emcs, mode="acu", update="metropolis"):
     """Run the whole workload on the GPU; recompute the chosen samples with the
