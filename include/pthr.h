@@ -205,6 +205,10 @@ typedef struct pthr_schedule {
   int32_t clone_split;  /* sweeps: 1, 2 or 4 work-items share each chunk of sites, each taking every
                            clone_split-th group of clones of a word (more waves for small lattices);
                            threads_per_sample * clone_split <= 1024 */
+  int32_t exp_filter;   /* FP64 Metropolis: 1 (default) decides each test against a float bound on
+                           exp first and evaluates the FP64 polynomial only when u lies within
+                           2^-20 of it; 0 evaluates the polynomial for every test.  Both give the
+                           same decisions. */
 } pthr_schedule;
 int pthr_get_schedule(const pthr_ctx *ctx, pthr_schedule *out);
 int pthr_set_schedule(pthr_ctx *ctx, const pthr_schedule *sch);

@@ -93,6 +93,8 @@ pthr::Geo geo_of(const pthr_params& p, int K_acu) {
   g.K_acu = K_acu;
   g.mode = p.houdayer_mode;
   g.update = p.local_update;
+  g.exp_lo = 0x1.ffffep-1f;  // 1 - 2^-20
+  g.exp_hi = 0x1.00001p+0f;  // 1 + 2^-20
   g.key0 = static_cast<uint32_t>(p.seed);
   g.key1 = static_cast<uint32_t>(p.seed >> 32);
   return g;
@@ -226,7 +228,12 @@ struct pthr_ctx {
     for (int s0 = 0; s0 < p.n_samples; s0 += per) {
       run.sample_begin = s0;
       const int nb = std::min(per, p.n_samples - s0);
-      hipError_t e = pthr::launch_emcs(p.precision, g, st, ob, run, shape(), nb, stream);
+      pthr::Geo gl = g;
+      if (!sch.exp_filter) {
+        gl.exp_lo = 0.0f;
+        gl.exp_hi = INFINITY;
+      }
+      hipError_t e = pthr::launch_emcs(p.precision, gl, st, ob, run, shape(), nb, stream);
       if (e != hipSuccess) return hip_fail(e, "EMCS kernel launch");
     }
     return PTHR_OK;
@@ -364,6 +371,7 @@ int pthr_create(const pthr_params* p, pthr_ctx** out) {
   c->sch.threads_per_sample = threads_for(d.V, ch);
   c->sch.samples_per_launch = 0;
   c->sch.exp_early_out = 0;  // the branch-free exponential for every clone (fastest on gfx950)
+  c->sch.exp_filter = 1;
   c->sch.graph_window = 16;
   // Batches too small to fill the GPU with waves (4 per SIMD at the sweep's
   // register use): share each chunk's clone words among 2 or 4 waves, up to
@@ -746,6 +754,7 @@ int pthr_set_schedule(pthr_ctx* ctx, const pthr_schedule* sch) {
   if (sch->samples_per_launch < 0) return ctx->fail(PTHR_EINVAL, "bad samples_per_launch");
   if (sch->graph_window < 0 || sch->graph_window > 4096) return ctx->fail(PTHR_EINVAL, "graph_window must be in [0, 4096]");
   if (sch->exp_early_out < 0) return ctx->fail(PTHR_EINVAL, "exp_early_out must be >= 0");
+  if (sch->exp_filter != 0 && sch->exp_filter != 1) return ctx->fail(PTHR_EINVAL, "exp_filter must be 0 or 1");
   if (sch->clone_split != 1 && sch->clone_split != 2 && sch->clone_split != 4)
     return ctx->fail(PTHR_EINVAL, "clone_split must be 1, 2 or 4");
   if (sch->threads_per_sample * sch->clone_split > 1024)

@@ -32,6 +32,8 @@ struct Geo {
   int K_acu;         // number of temperatures with T_k < t_acu (a prefix)
   int mode;          // 0 all-cluster, 1 single negative cluster
   int update;        // local update: 0 Metropolis, 1 heat bath
+  float exp_lo, exp_hi;  // FP64 Metropolis: factors of the float bounds on exp (set per launch:
+                        // 1 -+ 2^-20, or 0 and +inf to take the FP64 polynomial for every test)
   uint32_t key0, key1;
 };
 

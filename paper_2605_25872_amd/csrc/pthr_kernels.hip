@@ -122,15 +122,17 @@ __device__ __forceinline__ double exp_neg64(double x) {
 // minimise the largest relative error on |f| <= 1/2 (within 0.952 float ulp
 // of 2^f for every float f there), Horner with fused multiply-adds, then 2^k.
 // The result lies strictly inside (2^(k-1), 2^(k+1)).
-__device__ __forceinline__ float exp2_poly32(float f, float k) {
+__device__ __forceinline__ float exp2_frac32(float f) {
   float p = 0x1.41fbbcp-13f;
   p = __builtin_fmaf(p, f, 0x1.5f3e54p-10f);
   p = __builtin_fmaf(p, f, 0x1.3b2d4cp-7f);
   p = __builtin_fmaf(p, f, 0x1.c6aee8p-5f);
   p = __builtin_fmaf(p, f, 0x1.ebfbdcp-3f);
   p = __builtin_fmaf(p, f, 0x1.62e430p-1f);
-  p = __builtin_fmaf(p, f, 1.0f);
-  return __builtin_ldexpf(p, static_cast<int>(k));
+  return __builtin_fmaf(p, f, 1.0f);
+}
+__device__ __forceinline__ float exp2_poly32(float f, float k) {
+  return __builtin_ldexpf(exp2_frac32(f), static_cast<int>(k));
 }
 // 2^t * 2^32 with the same rounding steps as exp2_poly32: every Horner
 // coefficient is scaled by 2^32, which commutes with each rounding (the
@@ -187,11 +189,33 @@ struct Prec<double> {
     }
     return u < exp_poly64(x, k);
   }
-  // Same decision as accept(u, x, false) for x <= 0, without branches, as a
-  // mask over the wave's lanes (each clause is its own compare).
-  static __device__ __forceinline__ uint64_t accept_lanes(double u, double x) {
-    const double p = exp_poly64(x, __builtin_rint(x * 0x1.71547652b82fep+0));
-    return __builtin_amdgcn_ballot_w64(x >= -708.0) & __builtin_amdgcn_ballot_w64(u < p);
+  // Same decision as accept(u, x, false) for x <= 0, as a mask over the
+  // wave's lanes.  With x = k ln2 + r (the reduction of exp_poly64), the test
+  // u < p 2^k is d < p for d = u 2^-k (exact scaling for these u and k), p
+  // the FP64 polynomial's value of e^r.  It is first decided against
+  // q = exp2_frac32(float(r) log2 e), within 1.3e-7 of e^r relative (at most
+  // 1.05e-7 for every float r with |r| <= 0.35, checked exhaustively, plus
+  // the rounding of r to float): float(d) below q (1 - 2^-20) proves
+  // acceptance and float(d) at or above q (1 + 2^-20) proves rejection, the
+  // roundings of d and of the two bounds (2^-24 each) included.
+  // Only when some lane falls between the bounds (about once in 10^6 tests)
+  // does the wave evaluate the FP64 polynomial.
+  // u is uniform53(lo, hi); bound factors f_lo = 1 - 2^-20 and
+  // f_hi = 1 + 2^-20 (with 0 and +inf every test takes the FP64 polynomial).
+  static __device__ __forceinline__ uint64_t accept_lanes(uint32_t lo, uint32_t hi, double x, float f_lo,
+                                                          float f_hi) {
+    const double k = __builtin_rint(x * 0x1.71547652b82fep+0);
+    double r = __builtin_fma(-k, 0x1.62e42feep-1, x);
+    r = __builtin_fma(-k, 0x1.a39ef35793c76p-33, r);
+    const float q = exp2_frac32(static_cast<float>(r) * 0x1.715476p+0f);
+    const double bits = static_cast<double>(((static_cast<uint64_t>(hi) << 32) | lo) >> 11);
+    const float d = static_cast<float>(__builtin_ldexp(bits, -53 - static_cast<int>(k)));  // u 2^-k
+    const uint64_t in_range = __builtin_amdgcn_ballot_w64(x >= -708.0);
+    const uint64_t below = __builtin_amdgcn_ballot_w64(d < q * f_lo);
+    const uint64_t above = __builtin_amdgcn_ballot_w64(!(d < q * f_hi));
+    if ((in_range & ~below & ~above) == 0) return in_range & below;
+    const double u = __builtin_ldexp(bits, -53);
+    return in_range & __builtin_amdgcn_ballot_w64(u < exp_poly64(x, k));
   }
   // Heat bath: flip with probability 1 / (1 + exp(beta dE)), tested as
   // fma(u, a, u) < (dE > 0 ? a : 1) with a = exp(-beta |dE|) (0 below -708).
@@ -598,7 +622,8 @@ __device__ __forceinline__ void attempt_group(const Geo& g, const FP* __restrict
       // lanes take the test's first clause; their exp value is unused)
       if constexpr (sizeof(FP) == 8) {
         acc_lanes = __builtin_amdgcn_ballot_w64(dE <= 0.0) |
-                    Prec<double>::accept_lanes(Prec<double>::u(blk, j & 1), -(beta[j] * dE));
+                    Prec<double>::accept_lanes(j & 1 ? blk.w2 : blk.w0, j & 1 ? blk.w3 : blk.w1, -(beta[j] * dE),
+                                               g.exp_lo, g.exp_hi);
       } else {
         // beta[j] holds beta log2 e; u <= 2^t already accepts every dE <= 0.
         const uint32_t wj = j == 0 ? blk.w0 : j == 1 ? blk.w1 : j == 2 ? blk.w2 : blk.w3;

@@ -51,7 +51,7 @@ class Params(ctypes.Structure):
 class Schedule(ctypes.Structure):
     _fields_ = [("threads_per_sample", ctypes.c_int32), ("samples_per_launch", ctypes.c_int32),
                 ("exp_early_out", ctypes.c_int32), ("graph_window", ctypes.c_int32),
-                ("clone_split", ctypes.c_int32)]
+                ("clone_split", ctypes.c_int32), ("exp_filter", ctypes.c_int32)]
 
 
 _lib = None
@@ -285,8 +285,10 @@ class Pthr:
         return sch
 
     def set_schedule(self, threads_per_sample=None, samples_per_launch=None, exp_early_out=None,
-                     graph_window=None, clone_split=None) -> None:
+                     graph_window=None, clone_split=None, exp_filter=None) -> None:
         sch = self.schedule()
+        if exp_filter is not None:
+            sch.exp_filter = int(exp_filter)
         if clone_split is not None:
             sch.clone_split = clone_split
         if graph_window is not None:

@@ -289,10 +289,12 @@ def test_every_schedule_gives_the_same_bits(precision):
     step(f"schedules {precision}")
     pthr = _pthr()
     ref = None
-    for threads, early, per, split in ((256, 700, 0, 1), (128, 100000, 0, 1), (256, 0, 1, 1), (128, 1000, 2, 1),
-                                       (256, 0, 0, 4), (128, 700, 0, 2), (128, 0, 2, 8 // 2)):
+    for threads, early, per, split, filt in ((256, 700, 0, 1, 1), (128, 100000, 0, 1, 1), (256, 0, 1, 1, 1),
+                                             (128, 1000, 2, 1, 1), (256, 0, 0, 4, 1), (128, 700, 0, 2, 1),
+                                             (128, 0, 2, 8 // 2, 1), (256, 0, 0, 1, 0), (128, 0, 0, 2, 0)):
         _, g = make_pair(8, 3, 4, 10, 4, precision=precision, er_sweeps=20)
-        g.set_schedule(threads_per_sample=threads, exp_early_out=early, samples_per_launch=per, clone_split=split)
+        g.set_schedule(threads_per_sample=threads, exp_early_out=early, samples_per_launch=per, clone_split=split,
+                       exp_filter=filt)
         go = g.new_obs()
         g.run(2, go)
         got = (g.read_spins(), g.read_pt(), g.obs_arrays(go))
@@ -305,6 +307,15 @@ def test_every_schedule_gives_the_same_bits(precision):
         assert np.array_equal(got[2]["acc"], ref[2]["acc"])
         assert np.array_equal(got[2]["hist"], ref[2]["hist"])
     del pthr
+
+
+def test_fp64_exact_exponential_every_test():
+    """exp_filter = 0: the FP64 polynomial decides every Metropolis test (the
+    path the float bound falls back to), every sub-step against the oracle."""
+    step("fp64 exp_filter 0")
+    o, g = make_pair(6, 3, 2, 7, 3, er_sweeps=12, t_range=(0.2, 1.4))
+    g.set_schedule(exp_filter=0)
+    stepwise(o, g, 3)
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])

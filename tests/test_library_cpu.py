@@ -106,3 +106,26 @@ def test_group_argument_checks(lib):
         assert lib.pthr_group_run(None, 1, None, 0, None) == pthr.PTHR_EINVAL
     finally:
         lib.pthr_destroy(ctx)
+
+
+def test_schedule_defaults_and_checks(lib):
+    """The default schedule decides FP64 tests against the float bound first
+    (exp_filter = 1); set_schedule accepts 0 and refuses other values, and a
+    refused schedule leaves the previous one in place."""
+    p = pthr.make_params(8, 4, 4, 20, 4)
+    ctx = ctypes.c_void_p()
+    assert lib.pthr_create(ctypes.byref(p), ctypes.byref(ctx)) == 0
+    try:
+        sch = pthr.Schedule()
+        assert lib.pthr_get_schedule(ctx, ctypes.byref(sch)) == 0
+        assert sch.exp_filter == 1 and sch.exp_early_out == 0 and sch.clone_split in (1, 2, 4)
+        sch.exp_filter = 0
+        assert lib.pthr_set_schedule(ctx, ctypes.byref(sch)) == 0
+        sch.exp_filter = 2
+        assert lib.pthr_set_schedule(ctx, ctypes.byref(sch)) == pthr.PTHR_EINVAL
+        assert b"exp_filter" in lib.pthr_last_error(ctx)
+        back = pthr.Schedule()
+        assert lib.pthr_get_schedule(ctx, ctypes.byref(back)) == 0
+        assert back.exp_filter == 0
+    finally:
+        lib.pthr_destroy(ctx)
