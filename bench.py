@@ -90,8 +90,8 @@ def valu_peak(update: str, precision: str) -> tuple[float, int]:
 # SHA-256 is recorded here; any other source reports null.
 SWEEP_TRAFFIC = {
     "workload": "l16_fp32",
-    "sources_sha256": "3a6b73b38d1b064db87fdc913d437a8b6c5087a415bf2e577e03f349a1853e97",
-    "fetch_kib": 75013.1875,
+    "sources_sha256": "c7a430167e0876dd07261ffad22ef59983c40f60c46c17ed12bbe95bc028adfe",
+    "fetch_kib": 75022.3125,
     "write_kib": 98304.0,
 }
 KERNEL_SOURCES = ("paper_2605_25872_amd/csrc/pthr_kernels.hip", "paper_2605_25872_amd/csrc/pthr_internal.h")
