@@ -50,11 +50,11 @@ T_EQ_EMCS = {12: 2 ** 17, 14: 6.4e6, 16: 3.84e7, 18: 3.48e7}
 #   t = -(beta log2 e) dE 1, k = rint(t) by the float adder (add and
 #   subtract 1.5 2^23, integer k from the sum's bits) 3, f = t - k 1, 6 Horner
 #   steps (degree-6 polynomial of 2^f), test (2^t 2^32 - float(w)) 1.
-#   Metropolis FP64 (57): half = 1/2 block 20, two converts of the 53-bit
-#   uniform 2, 5 adds of the local field, -beta dE 1, k (multiply, rint) 2,
-#   2 Cody-Waite steps, r to float 1, k to int 1, d = u 2^-k (ldexp, to
-#   float) 2, compares (dE <= 0, x >= -708, d against the two float bounds)
-#   4, flip bit 1; fast = 6 sign insertions, 1 shift of the uniform,
+#   Metropolis FP64 (57): half = 1/2 block 20, 5 adds of the local field,
+#   -beta dE 1, k (multiply, rint) 2, 2 Cody-Waite steps, r to float 1, k to
+#   int 1, d = u 2^-k in float (two converts of the 53 random bits, ldexp) 3,
+#   compares (dE <= 0, x >= -708, d against the two float bounds) 4, flip bit
+#   1; fast = 6 sign insertions, the random bits' shift and multiply-add 2,
 #   f = r log2 e 1, 6 Horner steps of the float 2^f, the two bounds 2.  The
 #   FP64 polynomial that decides tests within 2^-20 of the bound (about one
 #   in 10^6) is not counted.
@@ -63,15 +63,17 @@ T_EQ_EMCS = {12: 2 ** 17, 14: 6.4e6, 16: 3.84e7, 18: 3.48e7}
 #   float(w) 1, rint 1, 2^k (convert + ldexp) 2, a zeroed below the cut and
 #   the threshold a or 1 (a compare and a select each) 4, the final compare
 #   1, flip bit 1.
-#   Heat bath FP64 (63): as the Metropolis count with the FP64 exponential
-#   (exp: 2 for k, 2 Cody-Waite steps, 14 Horner steps, scale 1), plus the
-#   zeroing of a and the choice of threshold (a compare and two selects each)
-#   and the fused multiply-add (half), less the dE <= 0 compare.
+#   Heat bath FP64 (63): half = 1/2 block 20, two converts of the 53-bit
+#   uniform 2, the field's 5 adds, -beta |dE| 1, the FP64 exponential (2 for
+#   k, 2 Cody-Waite steps, 14 Horner steps, scale 1) 19, a zeroed below the
+#   cut and the threshold a or 1 (a compare and two selects each) 6, the
+#   fused multiply-add 1, the final compare 1, flip bit 1; fast = 6 sign
+#   insertions, 1 shift of the uniform.
 OPS_BY_CLASS = {
     ("metropolis", "fp32"): {"fast": 11 + 1 + 3 + 1 + 6 + 1, "half": 10 + 1 + 1 + 1},
-    ("metropolis", "fp64"): {"fast": 6 + 1 + 1 + 6 + 2, "half": 20 + 2 + 5 + 1 + 2 + 2 + 1 + 1 + 2 + 4 + 1},
+    ("metropolis", "fp64"): {"fast": 6 + 2 + 1 + 6 + 2, "half": 20 + 5 + 1 + 2 + 2 + 1 + 1 + 3 + 4 + 1},
     ("heatbath", "fp32"): {"fast": 11 + 1 + 1 + 6 + 1 + 1, "half": 10 + 1 + 1 + 2 + 2 + 2 + 1 + 1},
-    ("heatbath", "fp64"): {"fast": 6 + 1, "half": 20 + 2 + 5 + 1 + 19 + 2 + 3 + 1 + 3},
+    ("heatbath", "fp64"): {"fast": 6 + 1, "half": 20 + 2 + 5 + 1 + 19 + 6 + 1 + 1 + 1},
 }
 
 

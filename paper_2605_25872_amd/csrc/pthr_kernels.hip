@@ -195,9 +195,9 @@ struct Prec<double> {
   // the FP64 polynomial's value of e^r.  It is first decided against
   // q = exp2_frac32(float(r) log2 e), within 1.3e-7 of e^r relative (at most
   // 1.05e-7 for every float r with |r| <= 0.35, checked exhaustively, plus
-  // the rounding of r to float): float(d) below q (1 - 2^-20) proves
-  // acceptance and float(d) at or above q (1 + 2^-20) proves rejection, the
-  // roundings of d and of the two bounds (2^-24 each) included.
+  // the rounding of r to float): d in float below q (1 - 2^-20) proves
+  // acceptance and at or above q (1 + 2^-20) proves rejection, the roundings
+  // of d (2^-23) and of the two bounds (2^-24 each) included.
   // Only when some lane falls between the bounds (about once in 10^6 tests)
   // does the wave evaluate the FP64 polynomial.
   // u is uniform53(lo, hi); bound factors f_lo = 1 - 2^-20 and
@@ -208,14 +208,17 @@ struct Prec<double> {
     double r = __builtin_fma(-k, 0x1.62e42feep-1, x);
     r = __builtin_fma(-k, 0x1.a39ef35793c76p-33, r);
     const float q = exp2_frac32(static_cast<float>(r) * 0x1.715476p+0f);
-    const double bits = static_cast<double>(((static_cast<uint64_t>(hi) << 32) | lo) >> 11);
-    const float d = static_cast<float>(__builtin_ldexp(bits, -53 - static_cast<int>(k)));  // u 2^-k
+    // u 2^-k in float, from the 53 random bits hi 2^21 + (lo >> 11): float(hi)
+    // and the fused multiply-add round once each (the low part is exact), so
+    // d is within 2^-23 of u 2^-k relative (or is 0 or subnormal where
+    // u 2^-k is far below q, or +inf where it is far above)
+    const float hb = __builtin_fmaf(static_cast<float>(hi), 0x1p21f, static_cast<float>(lo >> 11));
+    const float d = __builtin_ldexpf(hb, -53 - static_cast<int>(k));
     const uint64_t in_range = __builtin_amdgcn_ballot_w64(x >= -708.0);
     const uint64_t below = __builtin_amdgcn_ballot_w64(d < q * f_lo);
     const uint64_t above = __builtin_amdgcn_ballot_w64(!(d < q * f_hi));
     if ((in_range & ~below & ~above) == 0) return in_range & below;
-    const double u = __builtin_ldexp(bits, -53);
-    return in_range & __builtin_amdgcn_ballot_w64(u < exp_poly64(x, k));
+    return in_range & __builtin_amdgcn_ballot_w64(uniform53(lo, hi) < exp_poly64(x, k));
   }
   // Heat bath: flip with probability 1 / (1 + exp(beta dE)), tested as
   // fma(u, a, u) < (dE > 0 ? a : 1) with a = exp(-beta |dE|) (0 below -708).
