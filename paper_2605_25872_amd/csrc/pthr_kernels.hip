@@ -272,8 +272,9 @@ struct Prec<float> {
   // u = float(w) 2^-32; flip iff fma(u, a, u) < (dE > 0 ? a : 1).
   static __device__ __forceinline__ uint64_t heat_bath_lanes_w(uint32_t w, float bl, float dE) {
     const float t = -(bl * __builtin_fabsf(dE));
-    const float k = __builtin_rintf(t);
-    const float p = exp2_poly32(t - k, k);
+    const float kf = t + 0x1.8p23f;  // k = rint(t) from the adder, as in reject_sign
+    const float k = kf - 0x1.8p23f;
+    const float p = __builtin_ldexpf(exp2_frac32(t - k), __float_as_int(kf) - 0x4B400000);
     const float a = t >= -124.0f ? p : 0.0f;
     const float u = static_cast<float>(w) * 0x1p-32f;
     return __builtin_amdgcn_ballot_w64(__builtin_fmaf(u, a, u) < (dE > 0.0f ? a : 1.0f));
