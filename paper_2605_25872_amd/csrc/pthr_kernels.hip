@@ -140,14 +140,13 @@ __device__ __forceinline__ float exp2_poly32(float f, float k) {
 // exp2_poly32_x2p32(f, k) decides exactly as float(w) * 2^-32 <=
 // exp2_poly32(f, k) (where the scaled 2^k underflows, float(w) * 2^-32 is 0
 // or at least 2^-32 and both sides agree).
+// exp2_frac32's coefficients c0 .. c6 scaled by 2^32.
+constexpr float kExp2x2p32[7] = {0x1p+32f,       0x1.62e430p+31f, 0x1.ebfbdcp+29f, 0x1.c6aee8p+27f,
+                                 0x1.3b2d4cp+25f, 0x1.5f3e54p+22f, 0x1.41fbbcp+19f};
 __device__ __forceinline__ float exp2_poly32_x2p32(float f, int k) {
-  float p = 0x1.41fbbcp+19f;
-  p = __builtin_fmaf(p, f, 0x1.5f3e54p+22f);
-  p = __builtin_fmaf(p, f, 0x1.3b2d4cp+25f);
-  p = __builtin_fmaf(p, f, 0x1.c6aee8p+27f);
-  p = __builtin_fmaf(p, f, 0x1.ebfbdcp+29f);
-  p = __builtin_fmaf(p, f, 0x1.62e430p+31f);
-  p = __builtin_fmaf(p, f, 0x1p+32f);
+  float p = kExp2x2p32[6];
+#pragma unroll
+  for (int n = 5; n >= 0; --n) p = __builtin_fmaf(p, f, kExp2x2p32[n]);
   return __builtin_ldexpf(p, k);
 }
 
@@ -576,6 +575,46 @@ __device__ __forceinline__ void attempt_group(const Geo& g, const FP* __restrict
   FP beta[G];
 #pragma unroll
   for (int j = 0; j < G; ++j) beta[j] = bg[j];
+  if constexpr (kRejectBits<FP, kMaybeEarly, kHB>) {
+    // FP32 Metropolis, branch-free: the same steps as reject_sign, taken for
+    // the group's clones side by side so that every step offers the SIMD G
+    // independent instructions
+    const uint32_t w[4] = {blk.w0, blk.w1, blk.w2, blk.w3};
+    float t[G], f[G], p[G];
+    int k[G];
+#pragma unroll
+    for (int j = G - 1; j >= 0; --j) {
+      float ax[3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const uint32_t pick = static_cast<uint32_t>(static_cast<int32_t>(rs.s[a]) >> 31);
+        ax[a] = Prec<float>::with_sign(__uint_as_float(bitfield_insert(pick, __float_as_uint(sj.v[2 * a + 1]),
+                                                                       __float_as_uint(sj.v[2 * a]))),
+                                       rs.s[3 + a]);
+      }
+#pragma unroll
+      for (int a = 0; a < 6; ++a) rs.s[a] = twice(rs.s[a]);
+      t[j] = -(static_cast<float>(beta[j]) * ((ax[0] + ax[1]) + ax[2]));
+    }
+#pragma unroll
+    for (int j = G - 1; j >= 0; --j) {
+      const float kf = t[j] + 0x1.8p23f;
+      f[j] = t[j] - (kf - 0x1.8p23f);
+      k[j] = __float_as_int(kf) - 0x4B400000;
+    }
+#pragma unroll
+    for (int j = G - 1; j >= 0; --j) p[j] = kExp2x2p32[6];
+#pragma unroll
+    for (int n = 5; n >= 0; --n)
+#pragma unroll
+      for (int j = G - 1; j >= 0; --j) p[j] = __builtin_fmaf(p[j], f[j], kExp2x2p32[n]);
+#pragma unroll
+    for (int j = G - 1; j >= 0; --j) {
+      const float q = __builtin_ldexpf(p[j], k[j]);
+      flips = __builtin_amdgcn_alignbit(flips, __float_as_uint(q - static_cast<float>(w[j])), 31);
+    }
+    return;
+  }
 #pragma unroll
   for (int j = G - 1; j >= 0; --j) {
     FP dE;  // the couplings carry the factor 2: the sum is dE = 2h
