@@ -227,11 +227,15 @@ size_t pthr_lds_bytes(const pthr_params *p);
  * Every context keeps its own state buffer, schedule and counters; a group
  * only owns HIP streams and events (pthr_group_create) and a cached graph.
  * pthr_group_run performs n_emcs complete EMCS of every context, each exactly
- * as pthr_run would (bit-identical), with each context's chain on a stream of
- * its own, forked from and joined back into `stream`, so that the lattices
- * share the GPU.  With graph_window > 0, windows of that many EMCS of all
- * contexts are captured into one graph (one branch per context) and replayed;
- * the remainder runs as plain launches.  d_obs: NULL (no observables) or an
+ * as pthr_run would (bit-identical), the contexts' chains spread over as many
+ * streams as the GPU has hardware queues (GPU_MAX_HW_QUEUES, 4 by default; a
+ * further stream would share a queue with another and serialise against
+ * it), larger batches first, each stream taking the next context while its
+ * load (samples x sites x attempts per site) is the smallest; the streams are
+ * forked from and joined back into `stream`, so that the lattices share the
+ * GPU.  With graph_window > 0, windows of that many EMCS of all contexts are
+ * captured into one graph (one branch per stream) and replayed; the
+ * remainder runs as plain launches.  d_obs: NULL (no observables) or an
  * array of n_ctx observable buffers, entries may be NULL.  The contexts must
  * stay alive while the group exists and must not be used from another thread
  * during a run.  PTHR_ESTATE if a context is not initialised or inside an

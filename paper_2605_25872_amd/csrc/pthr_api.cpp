@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdlib>
 #include <chrono>
 #include <cmath>
 #include <cstdarg>
@@ -831,9 +832,17 @@ int pthr_autotune(pthr_ctx* ctx, void* d_scratch, int n_emcs, double* best_ms, v
 // of its own, forked from and joined back into the caller's stream, so the
 // chains of different lattices share the GPU.  Windows of EMCS are captured
 // once into a single graph with one parallel branch per context.
+// Hardware queues HIP gives a process (GPU_MAX_HW_QUEUES, 4 by default).
+static int hw_queues() {
+  const char* v = std::getenv("GPU_MAX_HW_QUEUES");
+  const int n = v ? std::atoi(v) : 0;
+  return n >= 1 && n <= 32 ? n : 4;
+}
+
 struct pthr_group {
   std::vector<pthr_ctx*> ctx;
-  std::vector<hipStream_t> side;
+  std::vector<int> lane;          // stream of each context
+  std::vector<hipStream_t> side;  // one per lane
   std::vector<hipEvent_t> join;
   hipEvent_t fork = nullptr;
   hipStream_t cap_stream = nullptr;
@@ -867,18 +876,22 @@ struct pthr_group {
     err = buf;
     return code;
   }
-  // n EMCS of every context, forked from `from` and joined back into it.
+  // n EMCS of every context, the contexts of a lane one after the other on
+  // its stream, forked from `from` and joined back into it.
   int chains(int n, void* const* d_obs, hipStream_t from) {
     hipError_t e = hipEventRecord(fork, from);
     if (e != hipSuccess) return fail(PTHR_EHIP, "fork: %s", hipGetErrorString(e));
-    for (size_t i = 0; i < ctx.size(); ++i) {
-      if ((e = hipStreamWaitEvent(side[i], fork, 0)) != hipSuccess)
+    for (size_t s = 0; s < side.size(); ++s) {
+      if ((e = hipStreamWaitEvent(side[s], fork, 0)) != hipSuccess)
         return fail(PTHR_EHIP, "fork wait: %s", hipGetErrorString(e));
-      for (int w = 0; w < n; ++w)
-        if (int rc = ctx[i]->emcs(d_obs ? d_obs[i] : nullptr, side[i]))
-          return fail(rc, "context %zu: %s", i, ctx[i]->err.c_str());
-      if ((e = hipEventRecord(join[i], side[i])) != hipSuccess ||
-          (e = hipStreamWaitEvent(from, join[i], 0)) != hipSuccess)
+      for (size_t i = 0; i < ctx.size(); ++i) {
+        if (lane[i] != static_cast<int>(s)) continue;
+        for (int w = 0; w < n; ++w)
+          if (int rc = ctx[i]->emcs(d_obs ? d_obs[i] : nullptr, side[s]))
+            return fail(rc, "context %zu: %s", i, ctx[i]->err.c_str());
+      }
+      if ((e = hipEventRecord(join[s], side[s])) != hipSuccess ||
+          (e = hipStreamWaitEvent(from, join[s], 0)) != hipSuccess)
         return fail(PTHR_EHIP, "join: %s", hipGetErrorString(e));
     }
     return PTHR_OK;
@@ -951,12 +964,32 @@ int pthr_group_create(pthr_ctx* const* ctxs, int n_ctx, pthr_group** out) {
   }
   pthr_group* grp = new pthr_group();
   grp->ctx.assign(ctxs, ctxs + n_ctx);
-  grp->side.assign(n_ctx, nullptr);
-  grp->join.assign(n_ctx, nullptr);
+  // lanes: at most one stream per hardware queue; contexts by decreasing
+  // load, each to the lane with the smallest load so far
+  const int n_lanes = std::min(n_ctx, hw_queues());
+  std::vector<double> load(n_lanes, 0.0), work(n_ctx);
+  std::vector<int> order(n_ctx);
+  for (int i = 0; i < n_ctx; ++i) {
+    const pthr_params& p = ctxs[i]->p;
+    const double V = static_cast<double>(p.L) * p.L * p.L;
+    work[i] = p.n_samples * V *
+              (double(p.n_replicas) * p.n_temps * p.sweeps_per_emcs +
+               double(p.n_replicas) * p.n_reservoir * p.er_sweeps_per_emcs);
+    order[i] = i;
+  }
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return work[a] > work[b]; });
+  grp->lane.assign(n_ctx, 0);
+  for (int i : order) {
+    const int s = static_cast<int>(std::min_element(load.begin(), load.end()) - load.begin());
+    grp->lane[i] = s;
+    load[s] += work[i];
+  }
+  grp->side.assign(n_lanes, nullptr);
+  grp->join.assign(n_lanes, nullptr);
   hipError_t e = hipEventCreateWithFlags(&grp->fork, hipEventDisableTiming);
-  for (int i = 0; i < n_ctx && e == hipSuccess; ++i) {
-    e = hipStreamCreateWithFlags(&grp->side[i], hipStreamNonBlocking);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&grp->join[i], hipEventDisableTiming);
+  for (int s = 0; s < n_lanes && e == hipSuccess; ++s) {
+    e = hipStreamCreateWithFlags(&grp->side[s], hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&grp->join[s], hipEventDisableTiming);
   }
   if (e != hipSuccess) {
     g_create_error = std::string("stream or event creation: ") + hipGetErrorString(e);

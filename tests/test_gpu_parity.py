@@ -234,6 +234,29 @@ def test_graph_replays_match_oracle(precision):
     assert_same_obs(oo, g, go)
 
 
+def test_group_of_six_contexts_shares_streams():
+    """Six contexts, more than the GPU's hardware queues: several contexts
+    share a stream (one after the other in its branch of the graph and in the
+    plain launches), and every member stays bit-identical to its own oracle."""
+    step("group of six contexts")
+    pthr = _pthr()
+    cases = [(4, 2, 2, 5, 1, "fp64"), (4, 3, 2, 4, 2, "fp32"), (6, 2, 2, 6, 2, "fp32"),
+             (6, 1, 4, 5, 1, "fp64"), (8, 2, 2, 4, 1, "fp32"), (4, 1, 2, 3, 0, "fp32")]
+    pairs = [make_pair(L, S, NR, NT, NER, precision=prec, er_sweeps=8, jseed=20 + i, seed=7 + i)
+             for i, (L, S, NR, NT, NER, prec) in enumerate(cases)]
+    group = pthr.Group([g for _, g in pairs])
+    gobs = [g.new_obs() for _, g in pairs]
+    oobs = [o.new_observables() for o, _ in pairs]
+    for stretch in (6, 3):  # 2 replays of a 3-EMCS graph; then the plain launches
+        for (o, _), oo in zip(pairs, oobs):
+            o.run(stretch, oo)
+        group.run(stretch, gobs, graph_window=3 if stretch == 6 else 0)
+        for i, (o, g) in enumerate(pairs):
+            assert_same_state(o, g, f"member {i} after a stretch of {stretch}")
+    for (o, g), oo, go in zip(pairs, oobs, gobs):
+        assert_same_obs(oo, g, go)
+
+
 def test_group_of_lattice_sizes_matches_oracle():
     """A group of three lattices (L = 4, 6, 8; FP64 and FP32 members) advanced
     together: one captured graph with a branch per context, replayed, then the
