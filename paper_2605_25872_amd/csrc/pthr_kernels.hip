@@ -198,11 +198,14 @@ struct Prec<double> {
   // acceptance and at or above q (1 + 2^-20) proves rejection, the roundings
   // of d (2^-23) and of the two bounds (2^-24 each) included.
   // Only when some lane falls between the bounds (about once in 10^6 tests)
-  // does the wave evaluate the FP64 polynomial.
+  // does the wave evaluate the FP64 polynomial (the caller redoes the word).
   // u is uniform53(lo, hi); bound factors f_lo = 1 - 2^-20 and
-  // f_hi = 1 + 2^-20 (with 0 and +inf every test takes the FP64 polynomial).
-  static __device__ __forceinline__ uint64_t accept_lanes(uint32_t lo, uint32_t hi, double x, float f_lo,
-                                                          float f_hi) {
+  // f_hi = 1 + 2^-20 (with 0 and +inf every lane is left open).
+  struct Bound {
+    uint64_t sure;  // lanes whose test the bound proves accepted
+    uint64_t open;  // lanes in range the bound leaves undecided
+  };
+  static __device__ __forceinline__ Bound bound_lanes(uint32_t lo, uint32_t hi, double x, float f_lo, float f_hi) {
     const double k = __builtin_rint(x * 0x1.71547652b82fep+0);
     double r = __builtin_fma(-k, 0x1.62e42feep-1, x);
     r = __builtin_fma(-k, 0x1.a39ef35793c76p-33, r);
@@ -216,8 +219,11 @@ struct Prec<double> {
     const uint64_t in_range = __builtin_amdgcn_ballot_w64(x >= -708.0);
     const uint64_t below = __builtin_amdgcn_ballot_w64(d < q * f_lo);
     const uint64_t above = __builtin_amdgcn_ballot_w64(!(d < q * f_hi));
-    if ((in_range & ~below & ~above) == 0) return in_range & below;
-    return in_range & __builtin_amdgcn_ballot_w64(uniform53(lo, hi) < exp_poly64(x, k));
+    return Bound{in_range & below, in_range & ~below & ~above};
+  }
+  // The test with the FP64 polynomial for every lane (k = rint(x log2 e)).
+  static __device__ __forceinline__ uint64_t exact_lanes(uint32_t lo, uint32_t hi, double x, double k) {
+    return __builtin_amdgcn_ballot_w64(x >= -708.0) & __builtin_amdgcn_ballot_w64(uniform53(lo, hi) < exp_poly64(x, k));
   }
   // Heat bath: flip with probability 1 / (1 + exp(beta dE)), tested as
   // fma(u, a, u) < (dE > 0 ? a : 1) with a = exp(-beta |dE|) (0 below -708).
@@ -563,10 +569,15 @@ __device__ __forceinline__ RunSigns run_signs(const WordSigns& ws, int b_top) {
 template <typename FP, bool kMaybeEarly, bool kHB>
 constexpr bool kRejectBits = sizeof(FP) == 4 && !kMaybeEarly && !kHB;
 
-template <typename FP, bool kMaybeEarly, bool kHB>
+// FP64 Metropolis (branch-free form): decisions come from the float bound
+// on exp.  With kDefer the lanes it leaves open are added to `open` and the
+// caller redoes the word with kExact (the FP64 polynomial for every test) if
+// any lane was; without, a group with an open lane takes the polynomial at
+// once.
+template <typename FP, bool kMaybeEarly, bool kHB, bool kExact = false, bool kDefer = false>
 __device__ __forceinline__ void attempt_group(const Geo& g, const FP* __restrict__ bc, RunSigns& rs,
                                               const SiteJ<FP>& sj, const Block& blk, int grp, int n0, int clone0,
-                                              int nbits, int early_beta_bits, uint32_t& flips) {
+                                              int nbits, int early_beta_bits, uint32_t& flips, uint64_t& open) {
   constexpr int G = sizeof(FP) == 8 ? 2 : 4;  // clones per Philox block
   // the factors of the block's G clones, one contiguous (scalar) load; in a
   // partial last block the surplus entries belong to the next clones or to
@@ -664,9 +675,21 @@ __device__ __forceinline__ void attempt_group(const Geo& g, const FP* __restrict
       // branch-free: the polynomial is evaluated for every lane (dE <= 0
       // lanes take the test's first clause; their exp value is unused)
       if constexpr (sizeof(FP) == 8) {
-        acc_lanes = __builtin_amdgcn_ballot_w64(dE <= 0.0) |
-                    Prec<double>::accept_lanes(j & 1 ? blk.w2 : blk.w0, j & 1 ? blk.w3 : blk.w1, -(beta[j] * dE),
-                                               g.exp_lo, g.exp_hi);
+        const uint32_t lo = j & 1 ? blk.w2 : blk.w0, hi = j & 1 ? blk.w3 : blk.w1;
+        const double x = -(beta[j] * dE);
+        const uint64_t nonpos = __builtin_amdgcn_ballot_w64(dE <= 0.0);
+        if constexpr (kExact) {
+          acc_lanes = nonpos | Prec<double>::exact_lanes(lo, hi, x, __builtin_rint(x * 0x1.71547652b82fep+0));
+        } else if constexpr (kDefer) {
+          const typename Prec<double>::Bound b = Prec<double>::bound_lanes(lo, hi, x, g.exp_lo, g.exp_hi);
+          acc_lanes = nonpos | b.sure;
+          open |= b.open & ~nonpos;
+        } else {
+          const typename Prec<double>::Bound b = Prec<double>::bound_lanes(lo, hi, x, g.exp_lo, g.exp_hi);
+          acc_lanes = nonpos | (b.open == 0 ? b.sure
+                                            : Prec<double>::exact_lanes(lo, hi, x,
+                                                                        __builtin_rint(x * 0x1.71547652b82fep+0)));
+        }
       } else {
         // beta[j] holds beta log2 e; u <= 2^t already accepts every dE <= 0.
         const uint32_t wj = j == 0 ? blk.w0 : j == 1 ? blk.w1 : j == 2 ? blk.w2 : blk.w3;
@@ -709,22 +732,37 @@ __device__ __forceinline__ void update_word(const Geo& g, const FP* __restrict__
       ws.z[a] = ws.x[2 * a] ^ (ws.y[a] & (0u - ((sj.sign >> (8 + a)) & 1u)));
     }
   }
-  uint32_t flips = 0;
   const int g_lo = n0 / G, g_hi = (n0 + nbits - 1) / G;
+  // FP64 Metropolis words whose float bounds left a lane open are redone with
+  // the FP64 polynomial (the word's spins are written only at the end); the
+  // shared-word form, with few groups per wave, takes the polynomial per group
+  constexpr bool kRedo = sizeof(FP) == 8 && !kMaybeEarly && !kHB && !kSplit;
+  uint64_t open = 0;
   if constexpr (!kSplit) {
     // software-pipelined: the Philox block of the next group is computed
     // beside the attempts of the current one (independent work for the SIMD)
-    int grp = g_hi;
-    // groups run from the highest clone down, one clone per doubling
-    RunSigns rs = run_signs<FP>(ws, g_hi * G + G - 1 - n0);
-    Block blk = philox10(c0w, t, static_cast<uint32_t>(grp), static_cast<uint32_t>(sample), g.key0, g.key1);
-    for (; grp > g_lo; --grp) {
-      const Block next =
-          philox10(c0w, t, static_cast<uint32_t>(grp - 1), static_cast<uint32_t>(sample), g.key0, g.key1);
-      attempt_group<FP, kMaybeEarly, kHB>(g, bc, rs, sj, blk, grp, n0, clone0, nbits, early_beta_bits, flips);
-      blk = next;
+    auto groups = [&](auto exact_tag) {
+      constexpr bool kExact = decltype(exact_tag)::value;
+      uint32_t fl = 0;
+      int grp = g_hi;
+      // groups run from the highest clone down, one clone per doubling
+      RunSigns rs = run_signs<FP>(ws, g_hi * G + G - 1 - n0);
+      Block blk = philox10(c0w, t, static_cast<uint32_t>(grp), static_cast<uint32_t>(sample), g.key0, g.key1);
+      for (; grp > g_lo; --grp) {
+        const Block next =
+            philox10(c0w, t, static_cast<uint32_t>(grp - 1), static_cast<uint32_t>(sample), g.key0, g.key1);
+        attempt_group<FP, kMaybeEarly, kHB, kExact, kRedo>(g, bc, rs, sj, blk, grp, n0, clone0, nbits,
+                                                           early_beta_bits, fl, open);
+        blk = next;
+      }
+      attempt_group<FP, kMaybeEarly, kHB, kExact, kRedo>(g, bc, rs, sj, blk, g_lo, n0, clone0, nbits,
+                                                         early_beta_bits, fl, open);
+      return fl;
+    };
+    uint32_t flips = groups(std::false_type{});
+    if constexpr (kRedo) {
+      if (open != 0) flips = groups(std::true_type{});
     }
-    attempt_group<FP, kMaybeEarly, kHB>(g, bc, rs, sj, blk, g_lo, n0, clone0, nbits, early_beta_bits, flips);
     if constexpr (kRejectBits<FP, kMaybeEarly, kHB>) flips = ~flips;
     if (nbits < 32) flips &= (1u << nbits) - 1u;
     plane[self_idx] = self ^ flips;
@@ -734,6 +772,7 @@ __device__ __forceinline__ void update_word(const Geo& g, const FP* __restrict__
     // work-items (disjoint bits) are combined with an atomic XOR
     const int first = g_lo + f;
     if (first > g_hi) return;
+    uint32_t flips = 0;
     int grp = first + (g_hi - first) / F * F;
     Block blk = philox10(c0w, t, static_cast<uint32_t>(grp), static_cast<uint32_t>(sample), g.key0, g.key1);
     for (; grp > first; grp -= F) {
@@ -741,14 +780,14 @@ __device__ __forceinline__ void update_word(const Geo& g, const FP* __restrict__
           philox10(c0w, t, static_cast<uint32_t>(grp - F), static_cast<uint32_t>(sample), g.key0, g.key1);
       uint32_t part = 0;
       RunSigns rs = run_signs<FP>(ws, grp * G + G - 1 - n0);
-      attempt_group<FP, kMaybeEarly, kHB>(g, bc, rs, sj, blk, grp, n0, clone0, nbits, early_beta_bits, part);
+      attempt_group<FP, kMaybeEarly, kHB>(g, bc, rs, sj, blk, grp, n0, clone0, nbits, early_beta_bits, part, open);
       if constexpr (kRejectBits<FP, kMaybeEarly, kHB>) part = ~part & ((1u << G) - 1u);
       flips |= part << (G * (grp - g_lo));
       blk = next;
     }
     uint32_t part = 0;
     RunSigns rs = run_signs<FP>(ws, first * G + G - 1 - n0);
-    attempt_group<FP, kMaybeEarly, kHB>(g, bc, rs, sj, blk, first, n0, clone0, nbits, early_beta_bits, part);
+    attempt_group<FP, kMaybeEarly, kHB>(g, bc, rs, sj, blk, first, n0, clone0, nbits, early_beta_bits, part, open);
     if constexpr (kRejectBits<FP, kMaybeEarly, kHB>) part = ~part & ((1u << G) - 1u);
     flips |= part << (G * (first - g_lo));
     if (nbits < 32) flips &= (1u << nbits) - 1u;
