@@ -334,11 +334,15 @@ def test_every_schedule_gives_the_same_bits(precision):
 
 def test_fp64_exact_exponential_every_test():
     """exp_filter = 0: the FP64 polynomial decides every Metropolis test (the
-    path the float bound falls back to), every sub-step against the oracle."""
+    paths the float bound falls back to: the redo of a whole word when one
+    work-item owns it, the group at once when waves share it), every sub-step
+    against the oracle."""
     step("fp64 exp_filter 0")
     o, g = make_pair(6, 3, 2, 7, 3, er_sweeps=12, t_range=(0.2, 1.4))
-    g.set_schedule(exp_filter=0)
-    stepwise(o, g, 3)
+    g.set_schedule(exp_filter=0, clone_split=1)
+    stepwise(o, g, 2)
+    g.set_schedule(clone_split=4)
+    stepwise(o, g, 2)
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
