@@ -92,8 +92,8 @@ def valu_peak(update: str, precision: str) -> tuple[float, int]:
 # SHA-256 is recorded here; any other source reports null.
 SWEEP_TRAFFIC = {
     "workload": "l16_fp32",
-    "sources_sha256": "c1866fe18f4a5c6ef8cd576cb27efe9b88b3412503e25eacd13533491c4c95b2",
-    "fetch_kib": 75021.0625,
+    "sources_sha256": "12d4c90bf5a801c63efd781547d0e4dccbc3e8f3d1451923f81e0f0f84f26d2d",
+    "fetch_kib": 75023.0625,
     "write_kib": 98304.0,
 }
 KERNEL_SOURCES = ("paper_2605_25872_amd/csrc/pthr_kernels.hip", "paper_2605_25872_amd/csrc/pthr_internal.h")
