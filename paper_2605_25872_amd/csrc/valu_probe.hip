@@ -86,6 +86,10 @@ __global__ __launch_bounds__(kThreads) void probe_kernel(uint32_t* out, uint32_t
   if constexpr (KIND == 38) PROBE_LOOP(asm volatile("v_rndne_f64 %0, %0" : "+v"(d[c])))
   if constexpr (KIND == 39) PROBE_LOOP(asm volatile("v_cvt_f64_u32 %0, %1" : "=v"(d[c]) : "v"(v[c])))
   if constexpr (KIND == 40) PROBE_LOOP(asm volatile("v_cmp_lt_f64_e64 %0, %1, %2" : "+s"(m[c]) : "v"(d[c]), "v"(da)))
+  if constexpr (KIND == 41) PROBE_LOOP(asm volatile("v_lshlrev_b64 %0, 1, %0" : "+v"(m[c])))
+  if constexpr (KIND == 42) PROBE_LOOP(asm volatile("v_lshl_add_u64 %0, %0, 1, %1" : "+v"(m[c]) : "v"(m[(c + 1) % kChains])))
+  if constexpr (KIND == 43) PROBE_LOOP(asm volatile("v_pk_add_u16 %0, %0, %1" : "+v"(v[c]) : "v"(a)))
+  if constexpr (KIND == 44) PROBE_LOOP(asm volatile("v_lshl_or_b32 %0, %0, 1, %1" : "+v"(v[c]) : "v"(a)))
   uint32_t acc = 0;
   for (int c = 0; c < kChains; ++c)
     acc ^= v[c] ^ static_cast<uint32_t>(__double_as_longlong(d[c])) ^ static_cast<uint32_t>(m[c]);
@@ -100,7 +104,7 @@ const char* const kNames[] = {"v_add_f32",     "v_fma_f32",     "v_xor_b32",    
                               "v_mov_b32",     "v_bfe_i32",     "v_max_f32",    "v_add3_u32",       "v_lshl_add_u32",
                               "v_perm_b32",    "v_cvt_i32_f32", "v_mul_lo_u32", "v_mul_hi_u32",     "v_addc_co_u32_e64",
                               "v_cndmask_b32_e64", "v_mul_f64", "v_ldexp_f64",  "v_rndne_f64",      "v_cvt_f64_u32",
-                              "v_cmp_lt_f64_e64"};
+                              "v_cmp_lt_f64_e64", "v_lshlrev_b64", "v_lshl_add_u64", "v_pk_add_u16", "v_lshl_or_b32"};
 constexpr int kKinds = sizeof(kNames) / sizeof(kNames[0]);
 
 template <int KIND>

@@ -165,6 +165,36 @@ def test_many_replicas_cross_word_pairs():
     stepwise(o, g, 3)
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_degenerate_emcs_zero_sweeps_and_zero_runs(precision):
+    """EMCS with no local sweeps (only the Houdayer step, the swaps and the
+    reservoir exchange) and with reservoir sweeps only, through the step-wise
+    calls, the fused call and graph replays; a run of zero EMCS changes
+    nothing and measures nothing."""
+    step(f"zero sweeps {precision}")
+    o, g = make_pair(6, 3, 4, 5, 4, precision=precision, sweeps=0, er_sweeps=0, seed=11)
+    oo, go = o.new_observables(), g.new_obs()
+    before = g.read_spins()
+    g.run(0, go)
+    assert np.array_equal(g.read_spins(), before)
+    assert g.counters() == (0, 0, 0)
+    assert g.obs_arrays(go)["n_meas"] == 0
+    stepwise(o, g, 2)
+    g.set_schedule(graph_window=2)
+    o.run(5, oo)
+    g.run(5, go)
+    assert_same_state(o, g, "5 EMCS without local sweeps")
+    assert_same_obs(oo, g, go)
+    step(f"reservoir sweeps only {precision}")
+    o, g = make_pair(6, 2, 2, 7, 4, precision=precision, sweeps=0, er_sweeps=7, seed=12)
+    stepwise(o, g, 2)
+    oo, go = o.new_observables(), g.new_obs()
+    o.run(3, oo)
+    g.run(3, go)
+    assert_same_state(o, g, "3 EMCS of reservoir sweeps only")
+    assert_same_obs(oo, g, go)
+
+
 # ----------------------------------------------------------------------------- labels, run, schedules
 def test_cluster_labels_match_oracle():
     step("labels")
