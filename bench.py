@@ -96,6 +96,17 @@ SWEEP_TRAFFIC = {
     "fetch_kib": 75023.0625,
     "write_kib": 98304.0,
 }
+# Utilisation of the Houdayer kernel in the same counter runs (L=16 FP32, all-
+# cluster moves): VALU issue = SQ_INSTS_VALU x 4 cycles / (1024 SIMDs x kernel
+# cycles); LDS pipe busy = (2 cycles per LDS wave instruction + bank-conflict
+# cycles) / (256 CUs x kernel cycles), a lower bound.  Neither is saturated:
+# the kernel waits on the latency of dependent union-find steps.
+HOUDAYER_COUNTERS = {
+    "workload": "l16_fp32",
+    "sources_sha256": SWEEP_TRAFFIC["sources_sha256"],
+    "valu_issue": 0.527,
+    "lds_pipe_busy": 0.486,
+}
 KERNEL_SOURCES = ("paper_2605_25872_amd/csrc/pthr_kernels.hip", "paper_2605_25872_amd/csrc/pthr_internal.h")
 
 
@@ -114,6 +125,16 @@ def sweep_traffic_bytes(workload: str):
     if workload != SWEEP_TRAFFIC["workload"] or kernel_sources_sha256() != SWEEP_TRAFFIC["sources_sha256"]:
         return None
     return 1024.0 * (2.0 * SWEEP_TRAFFIC["fetch_kib"] + 1.0 * SWEEP_TRAFFIC["write_kib"])
+
+
+def houdayer_utilisation(workload: str, mode: str):
+    """Counter-measured VALU and LDS utilisation of the Houdayer kernel, or
+    None if the kernel sources changed since the counters were taken (or
+    another workload or Houdayer mode)."""
+    c = HOUDAYER_COUNTERS
+    if workload != c["workload"] or mode != "acu" or kernel_sources_sha256() != c["sources_sha256"]:
+        return None
+    return {"bound": "lds latency", "valu_issue": c["valu_issue"], "lds_pipe_busy": c["lds_pipe_busy"]}
 
 
 def log(msg: str) -> None:
@@ -456,7 +477,8 @@ def main() -> int:
                    "clone_split": g.schedule().clone_split},
         "houdayer_moves_per_s": moves * args.steps / elapsed,
         "houdayer_kernel": {"ms_per_launch": houdayer_ms,
-                            "moves_per_s": moves / (houdayer_ms * 1e-3) if moves else None},
+                            "moves_per_s": moves / (houdayer_ms * 1e-3) if moves else None,
+                            "utilisation": houdayer_utilisation(w.name, args.mode)},
         "attempts_per_emcs": att,
         "wall_time_per_equilibrated_sample_s":
             (elapsed / args.steps) / w.n_samples * T_EQ_EMCS.get(w.L, float("nan")),
