@@ -36,6 +36,15 @@ constexpr int kMaxWaves = kMaxThreads / kWave;
 struct Block {
   uint32_t w0, w1, w2, w3;
 };
+// float(w) of a block's four words (the FP32 Metropolis test compares with
+// them); converted as soon as the block is taken up, so that its integer
+// words are dead before the next block is produced
+struct Floats4 {
+  float u[4];
+};
+__device__ __forceinline__ Floats4 to_floats(const Block& b) {
+  return {{static_cast<float>(b.w0), static_cast<float>(b.w1), static_cast<float>(b.w2), static_cast<float>(b.w3)}};
+}
 
 // a ^ b ^ k in one VALU operation (three-input bitwise function, truth table
 // 0x96); k is wave-uniform and read from a scalar register.
@@ -576,8 +585,9 @@ constexpr bool kRejectBits = sizeof(FP) == 4 && !kMaybeEarly && !kHB;
 // once.
 template <typename FP, bool kMaybeEarly, bool kHB, bool kExact = false, bool kDefer = false>
 __device__ __forceinline__ void attempt_group(const Geo& g, const FP* __restrict__ bc, RunSigns& rs,
-                                              const SiteJ<FP>& sj, const Block& blk, int grp, int n0, int clone0,
-                                              int nbits, int early_beta_bits, uint32_t& flips, uint64_t& open) {
+                                              const SiteJ<FP>& sj, const Block& blk, const Floats4& fw, int grp,
+                                              int n0, int clone0, int nbits, int early_beta_bits, uint32_t& flips,
+                                              uint64_t& open) {
   constexpr int G = sizeof(FP) == 8 ? 2 : 4;  // clones per Philox block
   // the factors of the block's G clones, one contiguous (scalar) load; in a
   // partial last block the surplus entries belong to the next clones or to
@@ -589,8 +599,7 @@ __device__ __forceinline__ void attempt_group(const Geo& g, const FP* __restrict
   if constexpr (kRejectBits<FP, kMaybeEarly, kHB>) {
     // FP32 Metropolis, branch-free: the same steps as reject_sign, taken for
     // the group's clones side by side so that every step offers the SIMD G
-    // independent instructions
-    const uint32_t w[4] = {blk.w0, blk.w1, blk.w2, blk.w3};
+    // independent instructions; fw holds float(w) of the block's words
     float t[G], f[G], p[G];
     int k[G];
 #pragma unroll
@@ -622,7 +631,7 @@ __device__ __forceinline__ void attempt_group(const Geo& g, const FP* __restrict
 #pragma unroll
     for (int j = G - 1; j >= 0; --j) {
       const float q = __builtin_ldexpf(p[j], k[j]);
-      flips = __builtin_amdgcn_alignbit(flips, __float_as_uint(q - static_cast<float>(w[j])), 31);
+      flips = __builtin_amdgcn_alignbit(flips, __float_as_uint(q - fw.u[j]), 31);
     }
     return;
   }
@@ -737,6 +746,7 @@ __device__ __forceinline__ void update_word(const Geo& g, const FP* __restrict__
   // the FP64 polynomial (the word's spins are written only at the end); the
   // shared-word form, with few groups per wave, takes the polynomial per group
   constexpr bool kRedo = sizeof(FP) == 8 && !kMaybeEarly && !kHB && !kSplit;
+  constexpr bool kUsesFloats = kRejectBits<FP, kMaybeEarly, kHB>;
   uint64_t open = 0;
   if constexpr (!kSplit) {
     // software-pipelined: the Philox block of the next group is computed
@@ -749,13 +759,15 @@ __device__ __forceinline__ void update_word(const Geo& g, const FP* __restrict__
       RunSigns rs = run_signs<FP>(ws, g_hi * G + G - 1 - n0);
       Block blk = philox10(c0w, t, static_cast<uint32_t>(grp), static_cast<uint32_t>(sample), g.key0, g.key1);
       for (; grp > g_lo; --grp) {
+        const Floats4 fw = kUsesFloats ? to_floats(blk) : Floats4{};
         const Block next =
             philox10(c0w, t, static_cast<uint32_t>(grp - 1), static_cast<uint32_t>(sample), g.key0, g.key1);
-        attempt_group<FP, kMaybeEarly, kHB, kExact, kRedo>(g, bc, rs, sj, blk, grp, n0, clone0, nbits,
+        attempt_group<FP, kMaybeEarly, kHB, kExact, kRedo>(g, bc, rs, sj, blk, fw, grp, n0, clone0, nbits,
                                                            early_beta_bits, fl, open);
         blk = next;
       }
-      attempt_group<FP, kMaybeEarly, kHB, kExact, kRedo>(g, bc, rs, sj, blk, g_lo, n0, clone0, nbits,
+      const Floats4 fw = kUsesFloats ? to_floats(blk) : Floats4{};
+      attempt_group<FP, kMaybeEarly, kHB, kExact, kRedo>(g, bc, rs, sj, blk, fw, g_lo, n0, clone0, nbits,
                                                          early_beta_bits, fl, open);
       return fl;
     };
@@ -776,18 +788,22 @@ __device__ __forceinline__ void update_word(const Geo& g, const FP* __restrict__
     int grp = first + (g_hi - first) / F * F;
     Block blk = philox10(c0w, t, static_cast<uint32_t>(grp), static_cast<uint32_t>(sample), g.key0, g.key1);
     for (; grp > first; grp -= F) {
+      const Floats4 fw = kUsesFloats ? to_floats(blk) : Floats4{};
       const Block next =
           philox10(c0w, t, static_cast<uint32_t>(grp - F), static_cast<uint32_t>(sample), g.key0, g.key1);
       uint32_t part = 0;
       RunSigns rs = run_signs<FP>(ws, grp * G + G - 1 - n0);
-      attempt_group<FP, kMaybeEarly, kHB>(g, bc, rs, sj, blk, grp, n0, clone0, nbits, early_beta_bits, part, open);
+      attempt_group<FP, kMaybeEarly, kHB>(g, bc, rs, sj, blk, fw, grp, n0, clone0, nbits, early_beta_bits, part,
+                                          open);
       if constexpr (kRejectBits<FP, kMaybeEarly, kHB>) part = ~part & ((1u << G) - 1u);
       flips |= part << (G * (grp - g_lo));
       blk = next;
     }
     uint32_t part = 0;
     RunSigns rs = run_signs<FP>(ws, first * G + G - 1 - n0);
-    attempt_group<FP, kMaybeEarly, kHB>(g, bc, rs, sj, blk, first, n0, clone0, nbits, early_beta_bits, part, open);
+    const Floats4 fw = kUsesFloats ? to_floats(blk) : Floats4{};
+    attempt_group<FP, kMaybeEarly, kHB>(g, bc, rs, sj, blk, fw, first, n0, clone0, nbits, early_beta_bits, part,
+                                        open);
     if constexpr (kRejectBits<FP, kMaybeEarly, kHB>) part = ~part & ((1u << G) - 1u);
     flips |= part << (G * (first - g_lo));
     if (nbits < 32) flips &= (1u << nbits) - 1u;
