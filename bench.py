@@ -92,8 +92,8 @@ def valu_peak(update: str, precision: str) -> tuple[float, int]:
 # SHA-256 is recorded here; any other source reports null.
 SWEEP_TRAFFIC = {
     "workload": "l16_fp32",
-    "sources_sha256": "12d4c90bf5a801c63efd781547d0e4dccbc3e8f3d1451923f81e0f0f84f26d2d",
-    "fetch_kib": 75023.0625,
+    "sources_sha256": "93f6d8cb1298c63a98cd703fcb7e25428442da061db4fef9c2c2e9bc6395ee5d",
+    "fetch_kib": 75007.6875,
     "write_kib": 98304.0,
 }
 # Utilisation of the Houdayer kernel in the same counter runs (L=16 FP32, all-
@@ -104,8 +104,8 @@ SWEEP_TRAFFIC = {
 HOUDAYER_COUNTERS = {
     "workload": "l16_fp32",
     "sources_sha256": SWEEP_TRAFFIC["sources_sha256"],
-    "valu_issue": 0.527,
-    "lds_pipe_busy": 0.486,
+    "valu_issue": 0.528,
+    "lds_pipe_busy": 0.487,
 }
 KERNEL_SOURCES = ("paper_2605_25872_amd/csrc/pthr_kernels.hip", "paper_2605_25872_amd/csrc/pthr_internal.h")
 
