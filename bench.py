@@ -92,8 +92,8 @@ def valu_peak(update: str, precision: str) -> tuple[float, int]:
 # SHA-256 is recorded here; any other source reports null.
 SWEEP_TRAFFIC = {
     "workload": "l16_fp32",
-    "sources_sha256": "93f6d8cb1298c63a98cd703fcb7e25428442da061db4fef9c2c2e9bc6395ee5d",
-    "fetch_kib": 75007.6875,
+    "sources_sha256": "79a8dcc595cc6da8b8f35e7b571fc53829f198cb500b48edb900fb823dcf5375",
+    "fetch_kib": 75000.0625,
     "write_kib": 98304.0,
 }
 # Utilisation of the Houdayer kernel in the same counter runs (L=16 FP32, all-

@@ -36,8 +36,8 @@ constexpr int kMaxWaves = kMaxThreads / kWave;
 struct Block {
   uint32_t w0, w1, w2, w3;
 };
-// float(w) of a block's four words (the FP32 Metropolis test compares with
-// them); converted as soon as the block is taken up, so that its integer
+// float(w) of a block's four words (the FP32 Metropolis and heat-bath tests
+// use them); converted as soon as the block is taken up, so that its integer
 // words are dead before the next block is produced
 struct Floats4 {
   float u[4];
@@ -284,13 +284,14 @@ struct Prec<float> {
   }
   // Heat bath, FP32 form: a = 2^t, t = -(beta log2 e)|dE| (0 below t = -124),
   // u = float(w) 2^-32; flip iff fma(u, a, u) < (dE > 0 ? a : 1).
-  static __device__ __forceinline__ uint64_t heat_bath_lanes_w(uint32_t w, float bl, float dE) {
+  // fw = float(w) of the random word; u = fw 2^-32 exactly
+  static __device__ __forceinline__ uint64_t heat_bath_lanes_w(float fw, float bl, float dE) {
     const float t = -(bl * __builtin_fabsf(dE));
     const float kf = t + 0x1.8p23f;  // k = rint(t) from the adder, as in reject_sign
     const float k = kf - 0x1.8p23f;
     const float p = __builtin_ldexpf(exp2_frac32(t - k), __float_as_int(kf) - 0x4B400000);
     const float a = t >= -124.0f ? p : 0.0f;
-    const float u = static_cast<float>(w) * 0x1p-32f;
+    const float u = fw * 0x1p-32f;
     return __builtin_amdgcn_ballot_w64(__builtin_fmaf(u, a, u) < (dE > 0.0f ? a : 1.0f));
   }
   static __device__ __forceinline__ bool negative(float J) { return __float_as_int(J) < 0; }
@@ -664,8 +665,7 @@ __device__ __forceinline__ void attempt_group(const Geo& g, const FP* __restrict
       if constexpr (sizeof(FP) == 8) {
         acc_lanes = Prec<double>::heat_bath_lanes(Prec<double>::u(blk, j & 1), beta[j], dE);
       } else {
-        const uint32_t wj = j == 0 ? blk.w0 : j == 1 ? blk.w1 : j == 2 ? blk.w2 : blk.w3;
-        acc_lanes = Prec<float>::heat_bath_lanes_w(wj, beta[j], dE);
+        acc_lanes = Prec<float>::heat_bath_lanes_w(fw.u[j], beta[j], dE);
       }
     } else if (early) {
       // cold clone (uniform branch): most tests are decided by the binade
@@ -746,7 +746,7 @@ __device__ __forceinline__ void update_word(const Geo& g, const FP* __restrict__
   // the FP64 polynomial (the word's spins are written only at the end); the
   // shared-word form, with few groups per wave, takes the polynomial per group
   constexpr bool kRedo = sizeof(FP) == 8 && !kMaybeEarly && !kHB && !kSplit;
-  constexpr bool kUsesFloats = kRejectBits<FP, kMaybeEarly, kHB>;
+  constexpr bool kUsesFloats = kRejectBits<FP, kMaybeEarly, kHB> || (sizeof(FP) == 4 && kHB);
   uint64_t open = 0;
   if constexpr (!kSplit) {
     // software-pipelined: the Philox block of the next group is computed
