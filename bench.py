@@ -92,7 +92,7 @@ def valu_peak(update: str, precision: str) -> tuple[float, int]:
 # SHA-256 is recorded here; any other source reports null.
 SWEEP_TRAFFIC = {
     "workload": "l16_fp32",
-    "sources_sha256": "79a8dcc595cc6da8b8f35e7b571fc53829f198cb500b48edb900fb823dcf5375",
+    "sources_sha256": "dd7338e22f58498d9f4ba1852d7bbec178076a07002b52e0642661f36256abc8",
     "fetch_kib": 75000.0625,
     "write_kib": 98304.0,
 }

@@ -583,7 +583,8 @@ constexpr bool kRejectBits = sizeof(FP) == 4 && !kMaybeEarly && !kHB;
 // on exp.  With kDefer the lanes it leaves open are added to `open` and the
 // caller redoes the word with kExact (the FP64 polynomial for every test) if
 // any lane was; without, a group with an open lane takes the polynomial at
-// once.
+// once.  fw: float(w) of the block's words, read by the FP32 Metropolis test
+// without early-out and by the FP32 heat-bath test (the other forms read blk).
 template <typename FP, bool kMaybeEarly, bool kHB, bool kExact = false, bool kDefer = false>
 __device__ __forceinline__ void attempt_group(const Geo& g, const FP* __restrict__ bc, RunSigns& rs,
                                               const SiteJ<FP>& sj, const Block& blk, const Floats4& fw, int grp,
