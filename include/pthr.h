@@ -214,9 +214,9 @@ int pthr_get_schedule(const pthr_ctx *ctx, pthr_schedule *out);
 int pthr_set_schedule(pthr_ctx *ctx, const pthr_schedule *sch);
 /* Times candidate schedules (work-items per sample, clone_split, early-out
  * off or below T = 0.7) with pthr_run on a scratch copy of the state
- * (d_scratch: pthr_state_bytes bytes, device) for n_emcs EMCS each after one
- * untimed EMCS, keeps the
- * fastest, restores nothing else.  best_ms (may be NULL) gets its time per EMCS. */
+ * (d_scratch: pthr_state_bytes bytes, device): after one untimed EMCS, two
+ * timed stretches of n_emcs EMCS each, the faster counting; keeps the
+ * fastest candidate, restores nothing else.  best_ms (may be NULL) gets its time per EMCS. */
 int pthr_autotune(pthr_ctx *ctx, void *d_scratch, int n_emcs, double *best_ms, void *stream);
 
 /* Dynamic LDS bytes one sample workgroup needs (0 if invalid). */

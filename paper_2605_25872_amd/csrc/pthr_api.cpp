@@ -801,13 +801,19 @@ int pthr_autotune(pthr_ctx* ctx, void* d_scratch, int n_emcs, double* best_ms, v
       ctx->d_state = static_cast<unsigned char*>(d_scratch);
       ctx->t = t_saved;
       float ms = 0.f;
-      // one untimed EMCS first (caches, clocks), then the timed ones
+      // one untimed EMCS first (caches, clocks), then two timed stretches of
+      // n_emcs EMCS; the faster one counts (a single stretch varies with the
+      // clocks and with work on other streams)
       rc = pthr_run(ctx, 1, nullptr, stream);
-      if (rc == PTHR_OK && hipEventRecord(e0, s) != hipSuccess) rc = ctx->fail(PTHR_EHIP, "autotune event");
-      if (rc == PTHR_OK) rc = pthr_run(ctx, n_emcs, nullptr, stream);
-      if (rc == PTHR_OK && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-                            hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
-        rc = ctx->fail(PTHR_EHIP, "autotune timing");
+      for (int rep = 0; rep < 2 && rc == PTHR_OK; ++rep) {
+        float rep_ms = 0.f;
+        if (hipEventRecord(e0, s) != hipSuccess) rc = ctx->fail(PTHR_EHIP, "autotune event");
+        if (rc == PTHR_OK) rc = pthr_run(ctx, n_emcs, nullptr, stream);
+        if (rc == PTHR_OK && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                              hipEventElapsedTime(&rep_ms, e0, e1) != hipSuccess))
+          rc = ctx->fail(PTHR_EHIP, "autotune timing");
+        if (rc == PTHR_OK && (rep == 0 || rep_ms < ms)) ms = rep_ms;
+      }
       if (rc == PTHR_OK && ms < best_t) {
         best_t = ms;
         best = cand;
