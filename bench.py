@@ -34,7 +34,7 @@ METRIC = "spin-flip attempts/ns + Houdayer moves/s, batched 3D EA L=16, one MI35
 # cycle, the FP64 vector rate of 78.6 TFLOP/s) for FP64 arithmetic and the
 # other 32-bit instructions the sweep needs: widening multiplies, three-input
 # logic, conversions, compares, rounding, ldexp, bit-field ops and left
-# shifts (`bench.py --issue-rates` measures each kind).
+# shifts (measured per instruction kind: profiles/gfx950_valu_issue_rates.md).
 FAST_OPS_PER_S = 256 * 4 * 32 * 2.4e9
 HALF_OPS_PER_S = 256 * 4 * 16 * 2.4e9
 # EMCS needed to equilibrate one L=16 sample (paper, App. A.2 table).
@@ -172,36 +172,6 @@ def cpu_baseline(w, n_samples: int, mode: str, update: str = "metropolis") -> di
             "kind": "oracle", "seconds": dt,
             "houdayer_moves_per_s": moves_per_emcs(sub, T) / dt,
             "sample": f"{n_samples} of {w.n_samples} samples, 1 EMCS, {w.precision} oracle"}
-
-
-def issue_rates() -> dict:
-    """Cycles per wave64 instruction per SIMD for the VALU instruction kinds
-    of the sweep (libvaluprobe.so: 8 independent chains per work-item of one
-    inline-assembly instruction, 64 waves per SIMD offered), at the measured
-    time and the 2.4 GHz clock, 1024 SIMDs."""
-    import ctypes
-
-    import torch  # noqa: F401  (loads the HIP runtime the probe binds to)
-
-    path = os.path.join(ROOT, "paper_2605_25872_amd", "libvaluprobe.so")
-    if not os.path.exists(path):
-        raise RuntimeError(f"{path} not found: build it with `python -m paper_2605_25872_amd.build`")
-    lib = ctypes.CDLL(path)
-    lib.valu_probe_name.restype = ctypes.c_char_p
-    lib.valu_probe_name.argtypes = [ctypes.c_int]
-    lib.valu_probe_run.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
-                                   ctypes.POINTER(ctypes.c_double)]
-    out = {}
-    blocks = 1024 * 64 // 4  # 64 waves per SIMD of 4-wave workgroups, 1024 SIMDs
-    for k in range(lib.valu_probe_kinds()):
-        ms, n = ctypes.c_double(), ctypes.c_double()
-        rc = lib.valu_probe_run(k, blocks, 5, ctypes.byref(ms), ctypes.byref(n))
-        if rc != 0:
-            raise RuntimeError(f"valu_probe_run({k}) failed ({rc})")
-        cycles = ms.value * 1e-3 * 2.4e9 * 1024 / n.value
-        out[lib.valu_probe_name(k).decode()] = round(cycles, 2)
-        log(f"{lib.valu_probe_name(k).decode():18s} {cycles:.2f} cycles per wave64 instruction per SIMD")
-    return {"issue_cycles_per_wave64_instruction": out, "clock_ghz": 2.4, "simds": 1024}
 
 
 def precision_check(args) -> dict:
@@ -358,8 +328,6 @@ def main() -> int:
     ap.add_argument("--no-autotune", action="store_true", help="mixed batch: keep the default schedules")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy a MIB-MiB device buffer 3 times (HBM counter calibration)")
-    ap.add_argument("--issue-rates", action="store_true",
-                    help="only measure the issue cost of the VALU instruction kinds the sweep uses")
     ap.add_argument("--fp32-vs-fp64", action="store_true",
                     help="only compare the FP32 form with the FP64 form statistically")
     ap.add_argument("--samples", type=int, default=1024)
@@ -368,9 +336,6 @@ def main() -> int:
 
     if args.fp32_vs_fp64:
         print(json.dumps(precision_check(args)), flush=True)
-        return 0
-    if args.issue_rates:
-        print(json.dumps(issue_rates()), flush=True)
         return 0
 
     if args.copy_calibration:

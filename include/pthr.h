@@ -172,6 +172,12 @@ int pthr_cluster_stats(pthr_ctx *ctx, void *d_sizes, void *stream);
 
 /* Read-back into host arrays (NULL pointers are skipped); synchronizes. */
 int pthr_read_spins(pthr_ctx *ctx, int8_t *spins /* [S][C][V] */, void *stream);
+/* Replaces every clone's spins (PT and ER) with spins [S][C][V] (host, int8
+ * +1/-1, same layout as pthr_read_spins; PTHR_EINVAL on any other value),
+ * e.g. to continue from configurations made elsewhere or to set up a chosen
+ * overlap between replicas; permutations, FIFOs and counters are kept.
+ * Synchronizes. */
+int pthr_write_spins(pthr_ctx *ctx, const int8_t *spins, void *stream);
 int pthr_read_pt(pthr_ctx *ctx, int32_t *clone_at /* [S][N_r][N_T] */,
                  int32_t *er_head /* [S][N_r] */, uint8_t *pt_last /* [S][N_r][N_T-1] */,
                  uint32_t *pt_count /* [S][N_r][N_T-1] */, double *pt_energy /* [S][N_r*N_T] */,

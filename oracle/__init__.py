@@ -97,6 +97,8 @@ def _lib() -> ctypes.CDLL:
     lib.oracle_heat_bath_flip.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double]
     lib.oracle_heat_bath_flip32.restype = i32
     lib.oracle_heat_bath_flip32.argtypes = [ctypes.c_float, ctypes.c_float, ctypes.c_float]
+    lib.oracle_round_trip_step.restype = i32
+    lib.oracle_round_trip_step.argtypes = [vp, vp, i32]
     lib.oracle_energy.restype = ctypes.c_double
     lib.oracle_energy.argtypes = [vp, i32, i32]
     lib.oracle_delta_e.restype = ctypes.c_double
@@ -148,6 +150,14 @@ def heat_bath_flip(u: float, a: float, dE: float, fp32: bool = False) -> bool:
         return bool(_lib().oracle_heat_bath_flip32(float(np.float32(u)), float(np.float32(a)),
                                                    float(np.float32(dE))))
     return bool(_lib().oracle_heat_bath_flip(float(u), float(a), float(dE)))
+
+
+def round_trip_step(rt_state: np.ndarray, at: np.ndarray) -> int:
+    """Round-trip bookkeeping of one replica group after its PT step (updates
+    rt_state, uint8 indexed by clone, in place); returns the trips completed."""
+    assert rt_state.dtype == np.uint8 and rt_state.flags["C_CONTIGUOUS"]
+    a = np.ascontiguousarray(at, dtype=np.int32)
+    return int(_lib().oracle_round_trip_step(_ptr(rt_state), _ptr(a), len(a)))
 
 
 class Observables:

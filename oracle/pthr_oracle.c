@@ -518,6 +518,22 @@ double oracle_energy(const oracle_ctx *c, int s, int clone) {
   return E;
 }
 
+/* Round trips (Sec. 5, definition before Eq. 9): a round trip is the stretch
+ * in which a clone that starts at T_max reaches T_min and comes back to
+ * T_max.  Applied to one replica group after its PT swaps, with at[k] the
+ * clone at temperature k: a clone found at T_max is "at the start" (state 1);
+ * a clone at the start found at T_min has "touched T_min" (state 2); a clone
+ * that touched T_min and is found at T_max again completes one round trip
+ * and starts the next.  Clones never seen at T_max (state 0) start nothing.
+ * Returns the number of round trips completed (0 or 1). */
+int oracle_round_trip_step(uint8_t *rt_state, const int32_t *at, int n_temps) {
+  int done = 0;
+  if (rt_state[at[0]] == 1) rt_state[at[0]] = 2;
+  if (rt_state[at[n_temps - 1]] == 2) done = 1;
+  rt_state[at[n_temps - 1]] = 1;
+  return done;
+}
+
 /* PT step for every replica group, then the ER exchange. */
 int oracle_pt_swap(oracle_ctx *c, int do_reservoir) {
   if (!c->ready) return -1;
@@ -544,12 +560,7 @@ int oracle_pt_swap(oracle_ctx *c, int do_reservoir) {
           at[k + 1] = tmp;
         }
       }
-      /* Round trips: a clone that left T_max, then touched T_min, completes a
-       * round trip when it is back at T_max. */
-      uint8_t *rt = c->rt_state + (size_t)s * c->NPT;
-      if (rt[at[0]] == 1) rt[at[0]] = 2;
-      if (rt[at[NT - 1]] == 2) c->rt_count[s] += 1;
-      rt[at[NT - 1]] = 1;
+      c->rt_count[s] += (uint64_t)oracle_round_trip_step(c->rt_state + (size_t)s * c->NPT, at, NT);
       /* Entropic reservoir: the configuration of the PT clone at T_max and
        * that of the oldest reservoir clone of this group trade places. */
       if (do_reservoir && NER_G > 0) {

@@ -130,6 +130,10 @@ float oracle_pexp2_32_coef(int n); /* its polynomial's coefficient c_n, n = 0..6
 /* Heat-bath flip test given a = exp(-beta |dE|): fma(u, a, u) < (dE > 0 ? a : 1). */
 int oracle_heat_bath_flip(double u, double a, double dE);
 int oracle_heat_bath_flip32(float u, float a, float dE);
+/* Round-trip bookkeeping of one replica group after its PT swaps (at[k]: the
+ * clone at temperature k; rt_state indexed by clone); returns the number of
+ * round trips completed (0 or 1). */
+int oracle_round_trip_step(uint8_t *rt_state, const int32_t *at, int n_temps);
 double oracle_energy(const oracle_ctx *c, int s, int clone);
 double oracle_delta_e(const oracle_ctx *c, int s, int clone, int site);
 int oracle_num_threads(void);

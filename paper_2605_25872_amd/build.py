@@ -1,6 +1,4 @@
-"""Compile the HIP library libpthr.so for gfx950 in-tree (always recompiles),
-and libvaluprobe.so, the instruction issue-rate probe the benchmark uses for
-the sweep's roofline.
+"""Compile the HIP library libpthr.so for gfx950 in-tree (always recompiles).
 
     python -m paper_2605_25872_amd.build
 """
@@ -14,7 +12,6 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libpthr.so")
-PROBE_LIB = os.path.join(PKG, "libvaluprobe.so")
 BUILD = os.path.join(ROOT, "_build")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -40,12 +37,6 @@ def build(verbose: bool = False) -> str:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
     os.replace(tmp, LIB)
-    tmp = PROBE_LIB + ".tmp"
-    cmd = [HIPCC, *COMMON, *DEVICE, "-shared", os.path.join(CSRC, "valu_probe.hip"), "-o", tmp]
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    subprocess.check_call(cmd)
-    os.replace(tmp, PROBE_LIB)
     return LIB
 
 

@@ -637,6 +637,39 @@ int pthr_read_spins(pthr_ctx* ctx, int8_t* spins, void* stream) {
   return PTHR_OK;
 }
 
+int pthr_write_spins(pthr_ctx* ctx, const int8_t* spins, void* stream) {
+  if (!ctx) return PTHR_EINVAL;
+  ctx->err.clear();
+  if (int rc = ctx->need_ready()) return rc;
+  if (!spins) return ctx->fail(PTHR_EINVAL, "spins must not be NULL");
+  const Derived& d = ctx->d;
+  const size_t S = ctx->p.n_samples;
+  const size_t n = S * d.C * d.V;
+  for (size_t x = 0; x < n; ++x)
+    if (spins[x] != 1 && spins[x] != -1) return ctx->fail(PTHR_EINVAL, "spins[%zu] = %d is not +1 or -1", x, spins[x]);
+  // bit b of word w at plane index j: clone 32w+b (PT) or NPT+32(w-NWPT)+b (ER); set = spin down
+  std::vector<uint32_t> words(S * d.NW * d.V, 0u);
+  const int L = ctx->p.L, Vh = d.V / 2;
+  for (size_t smp = 0; smp < S; ++smp)
+    for (int c = 0; c < d.C; ++c) {
+      const int w = c < d.NPT ? c / 32 : d.NWPT + (c - d.NPT) / 32;
+      const int b = c < d.NPT ? c % 32 : (c - d.NPT) % 32;
+      uint32_t* plane = words.data() + (smp * d.NW + w) * d.V;
+      const int8_t* in = spins + (smp * d.C + c) * d.V;
+      for (int i = 0; i < d.V; ++i) {
+        const int x = i % L, y = (i / L) % L, z = i / (L * L);
+        const int j = ((x + y + z) & 1) * Vh + (i >> 1);
+        if (in[i] < 0) plane[j] |= 1u << b;
+      }
+    }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = hipMemcpyAsync(ctx->d_state + ctx->lay.spins, words.data(), 4 * words.size(), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);  // the staging vector goes out of scope
+  if (e != hipSuccess) return ctx->hip_fail(e, "write spins");
+  ctx->e_current = false;
+  return PTHR_OK;
+}
+
 int pthr_read_pt(pthr_ctx* ctx, int32_t* clone_at, int32_t* er_head, uint8_t* pt_last, uint32_t* pt_count,
                  double* pt_energy, uint8_t* rt_state, uint64_t* rt_count, void* stream) {
   if (!ctx) return PTHR_EINVAL;
@@ -1039,13 +1072,15 @@ int pthr_group_run(pthr_group* grp, int64_t n_emcs, void* const* d_obs, int grap
       }
     }
   }
-  if (done < n_emcs) {
-    const int rest = static_cast<int>(n_emcs - done);
+  // the remainder as plain launches, in chunks that fit chains()' int count
+  while (done < n_emcs) {
+    const int rest = static_cast<int>(std::min<int64_t>(n_emcs - done, int64_t(1) << 30));
     if (int rc = grp->chains(rest, d_obs, s)) return rc;
     for (pthr_ctx* c : grp->ctx) {
       c->t += rest;
       c->e_current = true;
     }
+    done += rest;
   }
   return PTHR_OK;
 }

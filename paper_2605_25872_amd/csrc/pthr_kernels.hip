@@ -450,6 +450,20 @@ __device__ __forceinline__ int find_root(uint32_t* lab, int x) {
   }
   return x;
 }
+// The same walk without stores, for the pass that writes every run start's
+// final root once the unions are over.  There each entry is written only by
+// the work-item that owns it, and only with its root, so a concurrent reader
+// sees either the entry's earlier parent or that root: both lead to the same
+// root.  A path-splitting find there could store a stale grandparent over an
+// owner's root after the owner wrote it.
+__device__ __forceinline__ int find_root_readonly(const uint32_t* lab, int x) {
+  int p = static_cast<int>(lab[x]);
+  while (p != x) {
+    x = p;
+    p = static_cast<int>(lab[x]);
+  }
+  return x;
+}
 // Joins the clusters of a and b.  Every failed link replaces the larger root
 // by the smaller value found in its entry, so the larger of the two roots
 // strictly decreases and the loop ends within V rounds; the bound only guards
@@ -1175,7 +1189,7 @@ __device__ bool houdayer_moves(const Geo& g, const HouLds& s, int M, int sample,
       uint32_t own_roots = 0;  // run starts that are the roots of their clusters
       for (uint32_t r = rs; r; r &= r - 1u) {
         const int x = __builtin_ctz(r);
-        const int root = find_root(lab, i0 + x);
+        const int root = find_root_readonly(lab, i0 + x);
         lab[i0 + x] = static_cast<uint32_t>(root);
         own_roots |= root == i0 + x ? 1u << x : 0u;
       }

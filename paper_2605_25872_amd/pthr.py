@@ -30,6 +30,7 @@ EXPORTED = (
     "pthr_blob_bytes", "pthr_get_state", "pthr_set_state", "pthr_get_schedule",
     "pthr_set_schedule", "pthr_autotune", "pthr_lds_bytes", "pthr_group_create",
     "pthr_group_destroy", "pthr_group_last_error", "pthr_group_run", "pthr_cluster_stats",
+    "pthr_write_spins",
 )
 
 
@@ -90,6 +91,7 @@ def library() -> ctypes.CDLL:
         "pthr_cluster_labels": (i32, [vp, vp, vp]),
         "pthr_cluster_stats": (i32, [vp, vp, vp]),
         "pthr_read_spins": (i32, [vp, vp, vp]),
+        "pthr_write_spins": (i32, [vp, vp, vp]),
         "pthr_read_pt": (i32, [vp, vp, vp, vp, vp, vp, vp, vp, vp]),
         "pthr_counters": (i32, [vp, vp, vp, vp]),
         "pthr_check": (i32, [vp, vp]),
@@ -230,6 +232,11 @@ class Pthr:
         out = np.empty((self.S, self.C, self.V), dtype=np.int8)
         self._check(self.lib.pthr_read_spins(self.ctx, _np_ptr(out), self._stream()))
         return out
+
+    def write_spins(self, spins: np.ndarray) -> None:
+        """Replace every clone's spins: int8 [S][C][V] of +1/-1."""
+        a = np.ascontiguousarray(spins, dtype=np.int8).reshape(self.S, self.C, self.V)
+        self._check(self.lib.pthr_write_spins(self.ctx, _np_ptr(a), self._stream()))
 
     def read_pt(self) -> dict:
         S, NR, NT = self.S, self.NR, self.NT

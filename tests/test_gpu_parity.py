@@ -195,6 +195,120 @@ def test_degenerate_emcs_zero_sweeps_and_zero_runs(precision):
     assert_same_obs(oo, g, go)
 
 
+@pytest.mark.parametrize("L,precision,NT", [(12, "fp64", 28), (12, "fp32", 28), (10, "fp32", 21), (14, "fp32", 31)])
+def test_workload_lattice_sizes_every_substep(L, precision, NT):
+    """The lattice sizes of the L=12 workload (FP64 and FP32, 4x28 on
+    [0.2, 1.6]) and of the mixed batch (L=10: 4x21, L=14: 4x31) with 4
+    reservoir clones per group, every sub-step: their launch shapes (L=12: 2
+    sites per work-item, 864 work-items; L=10: 500; L=14 FP32: 4 sites per
+    work-item, 686) and the row readers of the Houdayer and observables
+    kernels for rows whose length is not a multiple of 8."""
+    step(f"workload lattice L={L} {precision} NT={NT}")
+    o, g = make_pair(L, 3, 4, NT, 4, precision=precision, er_sweeps=40, t_range=(0.2, 1.6), jseed=L)
+    stepwise(o, g, 2)
+
+
+def test_houdayer_roots_every_sample_l16():
+    """The roots pass of the union-find (each run start takes its cluster's
+    smallest site as root) on every pair, temperature and sample of an L=16
+    batch (4x36 on [0.2, 1.6], FP32): canonical labels against the oracle's
+    before every Houdayer step of several EMCS, and the spins after it."""
+    step("houdayer roots l16 every sample")
+    o, g = make_pair(16, 8, 4, 36, 4, precision="fp32", sweeps=2, er_sweeps=4, t_range=(0.2, 1.6), jseed=16)
+    for e in range(4):
+        o.sweep(2, oracle.SWEEP_PT)
+        o.sweep(4, oracle.SWEEP_ER)
+        g.sweep(2, 4)
+        lab = g.labels()
+        for s in range(8):
+            for p in range(2):
+                for k in range(g.K_acu):
+                    assert np.array_equal(lab[s, p, k], o.labels(s, p, k)), (e, s, p, k)
+        o.houdayer()
+        g.houdayer()
+        assert_same_state(o, g, f"EMCS {e} after Houdayer")
+        o.pt_swap(True)
+        g.pt_swap(True)
+    g.check()
+
+
+@pytest.mark.parametrize("mode", ["acu", "single"])
+@pytest.mark.parametrize("L,precision", [(4, "fp64"), (16, "fp32")])
+def test_houdayer_on_identical_and_opposite_replicas(L, precision, mode):
+    """Sec. 3's degenerate overlaps, written through pthr_write_spins: pair
+    (0, 1) identical at every temperature (q_i = +1 everywhere: one cluster
+    spanning the lattice, no q = -1 site, so the single-cluster move does
+    nothing) and pair (2, 3) opposite (q_i = -1 everywhere: one negative
+    cluster spanning the lattice, which the single-cluster move exchanges
+    between the replicas).  Under ACU each pair is flipped as a whole or
+    not at all."""
+    step(f"degenerate overlaps L={L} {precision} {mode}")
+    NT = 6
+    o, g = make_pair(L, 2, 4, NT, 0, precision=precision, mode=mode, sweeps=2, t_range=(0.2, 0.9), jseed=30 + L)
+    o.run(1)
+    g.run(1)
+    assert_same_state(o, g, "before")
+    spins = o.spins.copy()
+    for s in range(2):
+        for k in range(NT):
+            spins[s, o.clone_at[s, 1, k]] = spins[s, o.clone_at[s, 0, k]]
+            spins[s, o.clone_at[s, 3, k]] = -spins[s, o.clone_at[s, 2, k]]
+    o.spins[...] = spins
+    g.write_spins(spins)
+    assert_same_state(o, g, "written")
+    o.houdayer()
+    g.houdayer()
+    assert_same_state(o, g, "after the Houdayer step")
+    after = o.spins
+    for s in range(2):
+        for k in range(NT):
+            a0, b0 = o.clone_at[s, 0, k], o.clone_at[s, 1, k]
+            a1, b1 = o.clone_at[s, 2, k], o.clone_at[s, 3, k]
+            if mode == "single":
+                assert np.array_equal(after[s, a0], spins[s, a0]) and np.array_equal(after[s, b0], spins[s, b0])
+                assert np.array_equal(after[s, a1], spins[s, b1]) and np.array_equal(after[s, b1], spins[s, a1])
+            else:
+                for a, b in ((a0, b0), (a1, b1)):
+                    sign = after[s, a, 0] * spins[s, a, 0]
+                    assert np.array_equal(after[s, a], sign * spins[s, a])
+                    assert np.array_equal(after[s, b], sign * spins[s, b])
+
+
+def test_group_at_the_mixed_batch_sizes():
+    """The mixed batch as the benchmark runs it: L = 8, 10, 12, 14, 16 with
+    512/384/256/192/128 samples and 4x16 ... 4x36 temperatures on [0.2, 1.6],
+    FP32, each size with its autotuned schedule, advanced as one group (a
+    graph replay, then plain launches); one sample of every size recomputed
+    by the oracle."""
+    pthr = _pthr()
+    members = []
+    for w in inputs.MIXED_BATCH:
+        step(f"mixed member L={w.L}: {w.n_samples} samples, autotune")
+        g = pthr.Pthr(w.L, w.n_samples, w.n_replicas, w.n_temps, w.n_reservoir, w.sweeps_per_emcs,
+                      w.er_sweeps_per_emcs, w.precision, "acu", w.t_acu, w.seed)
+        g.init_samples(w.couplings(), w.temperatures())
+        g.autotune(1)
+        members.append(g)
+    group = pthr.Group(members)
+    obs = [g.new_obs() for g in members]
+    n_emcs = 3
+    group.run(n_emcs, obs, graph_window=2)
+    for w, g, go in zip(inputs.MIXED_BATCH, members, obs):
+        g.check()
+        s = (w.n_samples * 2) // 3
+        step(f"  oracle L={w.L} sample {s}")
+        o = oracle.Oracle(w.L, 1, w.n_replicas, w.n_temps, w.n_reservoir, w.sweeps_per_emcs,
+                          w.er_sweeps_per_emcs, oracle.FP32, oracle.ACU, w.t_acu, w.seed, first_sample=s)
+        o.init(w.couplings(1, first_sample=s), w.temperatures())
+        oo = o.new_observables()
+        o.run(n_emcs, oo)
+        assert np.array_equal(g.read_spins()[s], o.spins[0]), f"L={w.L} sample {s}"
+        pt = g.read_pt()
+        assert np.array_equal(pt["clone_at"][s], o.clone_at[0])
+        assert np.array_equal(pt["pt_energy"][s].view(np.uint64), o.pt_energy[0].view(np.uint64))
+        assert np.array_equal(g.obs_arrays(go)["acc"][s].view(np.uint64), oo.acc[0].view(np.uint64))
+
+
 # ----------------------------------------------------------------------------- labels, run, schedules
 def test_cluster_labels_match_oracle():
     step("labels")
@@ -493,6 +607,14 @@ def sampled_check(name, samples, n_emcs, mode="acu", update="metropolis"):
 
 def test_full_l8_fp64_workload_sampled():
     sampled_check("l8_fp64", [0, 137, 255], 2)
+
+
+def test_full_l12_fp64_workload_sampled():
+    sampled_check("l12_fp64", [1, 510], 2)
+
+
+def test_full_l12_fp32_workload_sampled():
+    sampled_check("l12_fp32", [3, 300], 2)
 
 
 def test_full_l16_fp32_workload_sampled():

@@ -698,16 +698,67 @@ def test_measure_matches_numpy_definitions():
     assert np.array_equal(obs.hist, hist) and int(obs.n_meas[0]) == 1
 
 
+def round_trips_from_history(positions: list[int], n_temps: int) -> tuple[int, int]:
+    """Round trips (Sec. 5: from T_max, touch T_min, back to T_max) of one
+    clone whose temperature index after each PT step is positions[t], read
+    off the sequence of its visits to the two ends: the visits, with repeats
+    of the same end merged, alternate between 'H' (T_max) and 'L' (T_min),
+    and every 'L' with an 'H' before and after it closes one round trip.
+    Also returns the state the clone is left in: 0 never at T_max, 1 at
+    T_max or back there, 2 touched T_min since its last time at T_max."""
+    ends = []
+    for k in positions:
+        e = "H" if k == n_temps - 1 else "L" if k == 0 else None
+        if e and (not ends or ends[-1] != e):
+            ends.append(e)
+    if "H" in ends:
+        ends = ends[ends.index("H"):]  # visits before the first T_max start nothing
+    else:
+        return 0, 0
+    trips = sum(1 for i in range(1, len(ends) - 1) if ends[i] == "L")
+    return trips, 1 if ends[-1] == "H" else 2
+
+
+# A hand-made sequence of one group's permutations after successive PT steps
+# (N_T = 4, clones 0..3; at[k] = clone at temperature k), with the trips each
+# step completes and every clone's final state.  It has a clone at T_min
+# before it was ever at T_max (clone 0, steps 1-2; clone 1, step 5), a clone
+# that touches T_min on several steps before it returns (clone 1, steps 8, 9
+# and 11), a clone that jumps from T_min to T_max in one ascending chain
+# (clone 3, steps 7-8), and one that leaves T_max and comes back without
+# touching T_min (clone 2, steps 14-16).
+RT_SEQUENCE = [([0, 1, 2, 3], 0), ([3, 1, 2, 0], 0), ([3, 1, 2, 0], 0), ([0, 1, 2, 3], 1),
+               ([1, 0, 2, 3], 0), ([2, 3, 0, 1], 0), ([3, 2, 0, 1], 0), ([1, 2, 0, 3], 1),
+               ([1, 2, 0, 3], 0), ([3, 2, 1, 0], 1), ([1, 3, 2, 0], 0), ([2, 1, 3, 0], 0),
+               ([0, 2, 3, 1], 1), ([0, 1, 3, 2], 0), ([0, 2, 3, 1], 0), ([0, 1, 3, 2], 0)]
+RT_FINAL_STATE = [2, 1, 1, 2]
+
+
+def test_round_trips_on_a_hand_made_permutation_sequence():
+    """The oracle's round-trip rule (Sec. 5) step by step on a sequence whose
+    answer is worked out by hand, and the history reading of the definition
+    on the same sequence."""
+    rt = np.zeros(4, dtype=np.uint8)
+    got = [oracle.round_trip_step(rt, np.array(at)) for at, _ in RT_SEQUENCE]
+    assert got == [n for _, n in RT_SEQUENCE]
+    assert rt.tolist() == RT_FINAL_STATE
+    for c in range(4):
+        pos = [at.index(c) for at, _ in RT_SEQUENCE]
+        trips, state = round_trips_from_history(pos, 4)
+        assert state == RT_FINAL_STATE[c]
+        assert trips == sum(n for t, (at, n) in enumerate(RT_SEQUENCE) if n and at[3] == c)
+
+
 def test_reservoir_fifo_and_round_trips():
     """ER (Sec. 3): every EMCS the configuration at T_max and the oldest
-    reservoir configuration trade places, oldest first; round trips (Sec. 5):
-    after leaving T_max a clone touches T_min and comes back to T_max."""
+    reservoir configuration trade places, oldest first.  Round trips (Sec. 5)
+    counted by the oracle over a real chain equal those read off every
+    clone's temperature history after each PT step."""
     L, NR, NT, NER = 2, 2, 3, 3
     o = oracle.Oracle(L, n_samples=1, n_replicas=NR, n_temps=NT, n_reservoir=NER,
                       sweeps_per_emcs=2, er_sweeps_per_emcs=1, t_acu=0.0, seed=5)
     o.init(inputs.couplings(L, 1, seed=5), np.array([0.3, 0.6, 4.0]))
-    state = np.zeros(NR * NT, dtype=int)
-    trips = 0
+    history = {c: [] for c in range(NR * NT)}
     for step in range(400):
         o.sweep(2, oracle.SWEEP_PT)
         o.sweep(1, oracle.SWEEP_ER)
@@ -716,17 +767,17 @@ def test_reservoir_fifo_and_round_trips():
         o.pt_swap(True)
         for r in range(NR):
             at = o.clone_at[0, r]
-            # round-trip bookkeeping re-derived from the permutation
-            if state[at[0]] == 1:
-                state[at[0]] = 2
-            if state[at[-1]] == 2:
-                trips += 1
-            state[at[-1]] = 1
+            for k, c in enumerate(at):
+                history[int(c)].append(k)
             # the oldest reservoir configuration is now at T_max
             assert np.array_equal(o.spins[0, at[-1]], er_before[r * NER + heads[r]])
             assert o.er_head[0, r] == (heads[r] + 1) % NER
+    trips = 0
+    for c, pos in history.items():
+        n, state = round_trips_from_history(pos, NT)
+        trips += n
+        assert o.rt_state[0, c] == state, c
     assert trips == int(o.rt_count[0]) and trips > 10
-    assert np.array_equal(o.rt_state[0], state)
 
 
 # --------------------------------------------------------------------------- exact enumeration
