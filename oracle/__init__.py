@@ -26,7 +26,7 @@ CFLAGS = ["-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off"
 FP64, FP32 = 0, 1
 ACU, SINGLE_NEG = 0, 1
 SWEEP_PT, SWEEP_ER = 1, 2
-METROPOLIS, HEAT_BATH = 0, 1
+METROPOLIS, HEAT_BATH, MICSA = 0, 1, 2
 NOBS = 6
 OBS_NAMES = ("e", "e2", "q2", "q4", "ql", "sdy")
 
@@ -57,7 +57,7 @@ class OracleParams(ctypes.Structure):
                 ("sweeps_per_emcs", ctypes.c_int32), ("er_sweeps_per_emcs", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("houdayer_mode", ctypes.c_int32),
                 ("t_acu", ctypes.c_double), ("seed", ctypes.c_uint64),
-                ("local_update", ctypes.c_int32)]
+                ("local_update", ctypes.c_int32), ("micsa_refresh", ctypes.c_int32)]
 
 
 def _lib() -> ctypes.CDLL:
@@ -76,7 +76,8 @@ def _lib() -> ctypes.CDLL:
     lib.oracle_run.argtypes = [vp, i64, vp, vp, vp]
     lib.oracle_cluster_labels.argtypes = [vp, i32, i32, i32, vp]
     for name in ("oracle_spins", "oracle_clone_at", "oracle_er_head", "oracle_pt_last",
-                 "oracle_pt_count", "oracle_pt_energy", "oracle_rt_state", "oracle_rt_count"):
+                 "oracle_pt_count", "oracle_pt_energy", "oracle_rt_state", "oracle_rt_count",
+                 "oracle_walker"):
         getattr(lib, name).restype = vp
         getattr(lib, name).argtypes = [vp]
     lib.oracle_t.restype = i64
@@ -85,6 +86,8 @@ def _lib() -> ctypes.CDLL:
     lib.oracle_philox4x32_10.argtypes = [vp, vp, vp]
     lib.oracle_pexp.restype = ctypes.c_double
     lib.oracle_pexp.argtypes = [ctypes.c_double]
+    lib.oracle_plog.restype = ctypes.c_double
+    lib.oracle_plog.argtypes = [ctypes.c_double]
     lib.oracle_uniform53.restype = ctypes.c_double
     lib.oracle_uniform53.argtypes = [ctypes.c_uint32, ctypes.c_uint32]
     lib.oracle_uniform32.restype = ctypes.c_float
@@ -123,6 +126,11 @@ def philox(ctr, key) -> np.ndarray:
 
 def pexp(x: float) -> float:
     return float(_lib().oracle_pexp(float(x)))
+
+
+def plog(u: float) -> float:
+    """ln(u) for 0 < u <= 1, the routine the MicSA walker refresh uses."""
+    return float(_lib().oracle_plog(float(u)))
 
 
 def uniform53(lo: int, hi: int) -> float:
@@ -176,11 +184,12 @@ class Oracle:
 
     def __init__(self, L, n_samples=1, n_replicas=2, n_temps=8, n_reservoir=0,
                  sweeps_per_emcs=10, er_sweeps_per_emcs=240, precision=FP64,
-                 houdayer_mode=ACU, t_acu=1.0, seed=1, first_sample=0, local_update=METROPOLIS):
+                 houdayer_mode=ACU, t_acu=1.0, seed=1, first_sample=0, local_update=METROPOLIS,
+                 micsa_refresh=0):
         self.lib = _lib()
         self.params = OracleParams(L, n_samples, first_sample, n_replicas, n_temps, n_reservoir,
                                    sweeps_per_emcs, er_sweeps_per_emcs, precision, houdayer_mode,
-                                   t_acu, seed, local_update)
+                                   t_acu, seed, local_update, micsa_refresh)
         err = ctypes.create_string_buffer(256)
         self.ctx = self.lib.oracle_create(ctypes.byref(self.params), err, 256)
         if not self.ctx:
@@ -270,6 +279,11 @@ class Oracle:
     @property
     def pt_energy(self) -> np.ndarray:
         return self._view("oracle_pt_energy", np.float64, (self.S, self.NPT))
+
+    @property
+    def walker(self) -> np.ndarray:
+        """MicSA walker energy of every PT clone, [S][N_r*N_T] (writable view)."""
+        return self._view("oracle_walker", np.float64, (self.S, self.NPT))
 
     @property
     def rt_state(self) -> np.ndarray:

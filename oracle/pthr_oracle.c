@@ -42,7 +42,7 @@
 #include <omp.h>
 #endif
 
-enum { PURPOSE_INIT = 1, PURPOSE_METRO = 2, PURPOSE_ACU = 3, PURPOSE_HSEED = 4, PURPOSE_PT = 5 };
+enum { PURPOSE_INIT = 1, PURPOSE_METRO = 2, PURPOSE_ACU = 3, PURPOSE_HSEED = 4, PURPOSE_PT = 5, PURPOSE_WALKER = 6 };
 
 struct oracle_ctx {
   oracle_params p;
@@ -61,6 +61,7 @@ struct oracle_ctx {
   double *pt_energy;  /* [S][NPT]                                                        */
   uint8_t *rt_state;  /* [S][NPT]: 0 unseen, 1 left T_max, 2 touched T_min since         */
   uint64_t *rt_count; /* [S]                                                             */
+  double *walker;     /* [S][NPT]: MicSA walker energy of every PT clone                  */
   int64_t t;
   int m_pt, m_er;
   int ready;
@@ -130,6 +131,30 @@ double oracle_pexp(double x) {
     p = fma(p, r, 1.0 / fact);
   }
   return ldexp(p, (int)k);
+}
+
+/* ln(u) for 0 < u <= 1 (normal u), written out so both implementations
+ * compute the same bits: u = 2^e m with m in [sqrt(1/2), sqrt(2)) (exact),
+ * f = m - 1 (exact), s = f / (2 + f), and ln m = 2 atanh(s) =
+ * 2 (s + s^3/3 + s^5/5 + ...) summed to s^23 (|s| < 0.172, so the next term
+ * is below 2^-60 of the sum) by Horner in z = s^2 with coefficients
+ * 2/(2n+1) rounded to double; then ln u = e LN2_HI + (e LN2_LO + ln m)
+ * (e LN2_HI is exact: LN2_HI has at most 33 significant bits, |e| <= 1074). */
+static const double SQRT_HALF = 0x1.6a09e667f3bcdp-1; /* RN(sqrt(1/2)) */
+double oracle_plog(double u) {
+  int e;
+  double m = frexp(u, &e); /* u = m 2^e, m in [1/2, 1) */
+  if (m < SQRT_HALF) {
+    m *= 2.0;
+    e -= 1;
+  }
+  double f = m - 1.0;
+  double sv = f / (2.0 + f);
+  double z = sv * sv;
+  double p = 2.0 / 23.0;
+  for (int n = 10; n >= 0; --n) p = fma(p, z, 2.0 / (2 * n + 1));
+  double lm = sv * p;
+  return fma((double)e, LN2_HI, fma((double)e, LN2_LO, lm));
 }
 
 /* FP32 form of the Metropolis exponential, in base 2: 2^t for
@@ -202,7 +227,9 @@ oracle_ctx *oracle_create(const oracle_params *p, char *err, size_t err_len) {
   else if (p->er_sweeps_per_emcs < 0 || p->er_sweeps_per_emcs > 256) msg = "er_sweeps_per_emcs must be in [0, 256]";
   else if (p->precision != ORACLE_FP64 && p->precision != ORACLE_FP32) msg = "precision must be FP64 or FP32";
   else if (p->houdayer_mode != ORACLE_ACU && p->houdayer_mode != ORACLE_SINGLE_NEG) msg = "houdayer_mode must be ACU or SINGLE_NEG";
-  else if (p->local_update != ORACLE_METROPOLIS && p->local_update != ORACLE_HEAT_BATH) msg = "local_update must be METROPOLIS or HEAT_BATH";
+  else if (p->local_update != ORACLE_METROPOLIS && p->local_update != ORACLE_HEAT_BATH && p->local_update != ORACLE_MICSA)
+    msg = "local_update must be METROPOLIS, HEAT_BATH or MICSA";
+  else if (p->micsa_refresh < 0 || p->micsa_refresh > 256) msg = "micsa_refresh must be in [0, 256]";
   if (msg) {
     if (err && err_len) snprintf(err, err_len, "%s", msg);
     return NULL;
@@ -229,6 +256,7 @@ oracle_ctx *oracle_create(const oracle_params *p, char *err, size_t err_len) {
   c->pt_energy = (double *)calloc((size_t)S * c->NPT, sizeof(double));
   c->rt_state = (uint8_t *)calloc((size_t)S * c->NPT, 1);
   c->rt_count = (uint64_t *)calloc((size_t)S, sizeof(uint64_t));
+  c->walker = (double *)calloc((size_t)S * c->NPT, sizeof(double));
   build_lattice(c);
   return c;
 }
@@ -237,7 +265,7 @@ void oracle_destroy(oracle_ctx *c) {
   if (!c) return;
   free(c->nbr); free(c->parity); free(c->J); free(c->J32); free(c->T); free(c->beta);
   free(c->bl32); free(c->spins); free(c->clone_at); free(c->er_head); free(c->pt_last);
-  free(c->pt_count); free(c->pt_energy); free(c->rt_state); free(c->rt_count);
+  free(c->pt_count); free(c->pt_energy); free(c->rt_state); free(c->rt_count); free(c->walker);
   free(c);
 }
 
@@ -281,6 +309,7 @@ int oracle_init_samples(oracle_ctx *c, const double *J, const double *T) {
   memset(c->pt_energy, 0, sizeof(double) * (size_t)S * c->NPT);
   memset(c->rt_state, 0, (size_t)S * c->NPT);
   memset(c->rt_count, 0, sizeof(uint64_t) * (size_t)S);
+  memset(c->walker, 0, sizeof(double) * (size_t)S * c->NPT);
   c->t = 0;
   c->m_pt = c->m_er = 0;
   c->ready = 1;
@@ -368,6 +397,51 @@ static void sweep_clone(oracle_ctx *c, int s, int clone, int k, int m) {
       if (c->parity[i] == par) metropolis_attempt(c, s, clone, i, k, m);
 }
 
+/* MicSA walker of a PT clone at temperature index k redrawn from its
+ * Boltzmann law: W = T_k (-ln u), u = (b + 1) 2^-53 in (0, 1] from the 53
+ * bits b of words (0, 1) of the block (WALKER, site 0, sweep m).  The FP32
+ * form keeps the value rounded to float. */
+static void refresh_walker(oracle_ctx *c, int s, int clone, int k, int m) {
+  uint32_t w[4];
+  draw(c, PURPOSE_WALKER, 0, (uint32_t)m, (uint32_t)c->t, (uint32_t)clone, s, w);
+  uint64_t b = (((uint64_t)w[1] << 32) | w[0]) >> 11;
+  double u = (double)(b + 1) * 0x1p-53;
+  double W = c->T[k] * -oracle_plog(u);
+  if (c->p.precision == ORACLE_FP32) W = (double)(float)W;
+  c->walker[(size_t)s * c->NPT + clone] = W;
+}
+
+/* One MicSA sweep of a PT clone, in the order of sweep_clone: the spin at i
+ * flips iff the walker holds at least dE, which it then gives up. */
+static void micsa_sweep_clone(oracle_ctx *c, int s, int clone) {
+  int8_t *sp = clone_spins(c, s, clone);
+  double *W = c->walker + (size_t)s * c->NPT + clone;
+  for (int par = 0; par < 2; ++par)
+    for (int i = 0; i < c->V; ++i) {
+      if (c->parity[i] != par) continue;
+      if (c->p.precision == ORACLE_FP64) {
+        double dE = oracle_delta_e(c, s, clone, i);
+        if (*W >= dE) {
+          sp[i] = (int8_t)-sp[i];
+          *W = *W - dE;
+        }
+      } else {
+        float dE = delta_e32(c, s, clone, i);
+        float w32 = (float)*W;
+        if (w32 >= dE) {
+          sp[i] = (int8_t)-sp[i];
+          *W = (double)(w32 - dE);
+        }
+      }
+    }
+}
+
+/* MicSA's refresh cadence in PT sweeps. */
+static int micsa_period(const oracle_ctx *c) {
+  if (c->p.micsa_refresh > 0) return c->p.micsa_refresh;
+  return c->p.sweeps_per_emcs > 0 ? c->p.sweeps_per_emcs : 1;
+}
+
 int oracle_sweep(oracle_ctx *c, int n, int which) {
   if (!c->ready || n < 0 || (which & ~3)) return -1;
   int do_pt = (which & ORACLE_SWEEP_PT) != 0, do_er = (which & ORACLE_SWEEP_ER) != 0 && c->NER > 0;
@@ -379,7 +453,14 @@ int oracle_sweep(oracle_ctx *c, int n, int which) {
       for (int r = 0; r < NR; ++r)
         for (int k = 0; k < NT; ++k) {
           int clone = c->clone_at[((size_t)s * NR + r) * NT + k];
-          for (int mm = 0; mm < n; ++mm) sweep_clone(c, s, clone, k, c->m_pt + mm);
+          for (int mm = 0; mm < n; ++mm) {
+            if (c->p.local_update == ORACLE_MICSA) {
+              if ((c->m_pt + mm) % micsa_period(c) == 0) refresh_walker(c, s, clone, k, c->m_pt + mm);
+              micsa_sweep_clone(c, s, clone);
+            } else {
+              sweep_clone(c, s, clone, k, c->m_pt + mm);
+            }
+          }
         }
     if (do_er)
       for (int e = 0; e < c->NER; ++e)
@@ -662,6 +743,7 @@ int32_t *oracle_er_head(oracle_ctx *c) { return c->er_head; }
 uint8_t *oracle_pt_last(oracle_ctx *c) { return c->pt_last; }
 uint32_t *oracle_pt_count(oracle_ctx *c) { return c->pt_count; }
 double *oracle_pt_energy(oracle_ctx *c) { return c->pt_energy; }
+double *oracle_walker(oracle_ctx *c) { return c->walker; }
 uint8_t *oracle_rt_state(oracle_ctx *c) { return c->rt_state; }
 uint64_t *oracle_rt_count(oracle_ctx *c) { return c->rt_count; }
 int64_t oracle_t(const oracle_ctx *c) { return c->t; }

@@ -45,6 +45,20 @@
  * is a / (1 + a) for dE > 0 and 1 / (1 + a) for dE <= 0; the test is written
  * without a division, flip iff fma(u, a, u) < a, resp. < 1, with the same
  * random numbers as the Metropolis test.
+ *
+ * MicSA (App. A.1, energy-LUT paragraph; App. A.2): microcanonical local
+ * update of the PT clones.  Every PT clone carries a walker holding an
+ * energy W >= 0; a spin flips iff W >= dE, and then W -= dE.  The walker is
+ * redrawn from its Boltzmann law at the clone's temperature T_k,
+ * W = T_k (-ln u) (density exp(-W/T_k)/T_k), at the start of every PT sweep
+ * whose index m in the EMCS is a multiple of micsa_refresh, so at least once
+ * per EMCS; u = (b + 1) 2^-53 from 53 bits b of the block (WALKER, site 0,
+ * m, t, clone id, sample), ln by the routine oracle_plog below.  FP64 form:
+ * W and dE in double; FP32 form: W = (float)(T_k (-ln u)) and the test and
+ * subtraction in float with the FP32 form's dE.  Reservoir clones keep
+ * Metropolis (the paper's reservoir always used its probability table).
+ * The cadence of the refresh is not in the paper (it cites a reference this
+ * reading stands in for).
  */
 #ifndef PTHR_ORACLE_H
 #define PTHR_ORACLE_H
@@ -59,7 +73,7 @@ extern "C" {
 enum { ORACLE_FP64 = 0, ORACLE_FP32 = 1 };
 enum { ORACLE_ACU = 0, ORACLE_SINGLE_NEG = 1 };
 enum { ORACLE_SWEEP_PT = 1, ORACLE_SWEEP_ER = 2 };
-enum { ORACLE_METROPOLIS = 0, ORACLE_HEAT_BATH = 1 };
+enum { ORACLE_METROPOLIS = 0, ORACLE_HEAT_BATH = 1, ORACLE_MICSA = 2 };
 enum { ORACLE_NOBS = 6 }; /* sum e, sum e^2, sum q^2, sum q^4, sum q_l, sum S */
 
 typedef struct oracle_params {
@@ -75,7 +89,8 @@ typedef struct oracle_params {
   int32_t houdayer_mode;      /* ORACLE_ACU or ORACLE_SINGLE_NEG               */
   double t_acu;               /* Houdayer moves at T_k < t_acu (paper: 1.0)    */
   uint64_t seed;
-  int32_t local_update;       /* ORACLE_METROPOLIS (paper) or ORACLE_HEAT_BATH */
+  int32_t local_update;       /* ORACLE_METROPOLIS (paper), ORACLE_HEAT_BATH or ORACLE_MICSA */
+  int32_t micsa_refresh;      /* MicSA: PT sweeps between walker refreshes (0 = sweeps_per_emcs) */
 } oracle_params;
 
 typedef struct oracle_ctx oracle_ctx;
@@ -116,6 +131,7 @@ uint32_t *oracle_pt_count(oracle_ctx *c); /* [S][N_r][N_T-1] cumulative      */
 double *oracle_pt_energy(oracle_ctx *c);  /* [S][N_r*N_T] E per PT clone at the last PT step */
 uint8_t *oracle_rt_state(oracle_ctx *c);  /* [S][N_r*N_T] round-trip state    */
 uint64_t *oracle_rt_count(oracle_ctx *c); /* [S] completed round trips       */
+double *oracle_walker(oracle_ctx *c);     /* [S][N_r*N_T] MicSA walker energy per PT clone */
 int64_t oracle_t(const oracle_ctx *c);
 int oracle_m(const oracle_ctx *c, int cls);
 int oracle_n_clones(const oracle_ctx *c);
@@ -124,6 +140,8 @@ int oracle_n_clones(const oracle_ctx *c);
 void oracle_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
 double oracle_pexp(double x);
 double oracle_uniform53(uint32_t lo, uint32_t hi);
+/* ln(u) for 0 < u <= 1 (u normal), the MicSA walker's logarithm. */
+double oracle_plog(double u);
 float oracle_uniform32(uint32_t w);
 float oracle_pexp2_32(float t); /* FP32 form: 2^t (IEEE overflow and gradual underflow) */
 float oracle_pexp2_32_coef(int n); /* its polynomial's coefficient c_n, n = 0..6 */

@@ -79,6 +79,42 @@ def sweep_kernel(J: np.ndarray, L: int, beta: float, rule: str = "metropolis") -
     return P
 
 
+def micsa_kernel(J: np.ndarray, L: int, beta: float, n_sweeps: int) -> np.ndarray:
+    """Exact transition matrix of one MicSA period (App. A.1): a walker drawn
+    from its Boltzmann law (density beta exp(-beta W), W >= 0), then n_sweeps
+    sweeps in the checkerboard order in which each spin flips iff the walker
+    holds at least dH, which the walker then gives up.  Given the state the
+    period is a deterministic function of the drawn W0, piecewise constant:
+    every test W0 - (energy given up so far) >= dH splits the current interval
+    of W0 at one threshold, and a final state collects the probability
+    exp(-beta a) - exp(-beta b) of each interval [a, b) leading to it."""
+    V = L ** 3
+    states = all_states(V)
+    E = energy(states, J, L)
+    n = 2 ** V
+    x, y, z = np.arange(V) % L, (np.arange(V) // L) % L, np.arange(V) // (L * L)
+    order = [i for p in (0, 1) for i in range(V) if (x[i] + y[i] + z[i]) % 2 == p] * n_sweeps
+    P = np.zeros((n, n))
+    for g0 in range(n):
+        pieces = [(0.0, np.inf, g0, 0.0)]  # W0 in [a, b), state, energy given up
+        for i in order:
+            nxt = []
+            for a, b, g, c in pieces:
+                f = g ^ (1 << i)
+                th = E[f] - E[g] + c  # accept iff W0 >= th
+                if th <= a:
+                    nxt.append((a, b, f, c + E[f] - E[g]))
+                elif th >= b:
+                    nxt.append((a, b, g, c))
+                else:
+                    nxt.append((a, th, g, c))
+                    nxt.append((th, b, f, c + E[f] - E[g]))
+            pieces = nxt
+        for a, b, g, _ in pieces:
+            P[g0, g] += np.exp(-beta * a) - (0.0 if np.isinf(b) else np.exp(-beta * b))
+    return P
+
+
 def chi2_pvalue(counts: np.ndarray, probs: np.ndarray, min_expected: float = 5.0) -> float:
     """Pearson chi-square goodness of fit, pooling cells with small expectation."""
     counts = np.asarray(counts, dtype=np.float64)
