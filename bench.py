@@ -176,52 +176,58 @@ def cpu_baseline(w, n_samples: int, mode: str, update: str = "metropolis") -> di
 
 def precision_check(args) -> dict:
     """FP32 form against the FP64 form (bit-identical to the FP64 oracle) on
-    the same samples: per-temperature mean energy per spin, paired over
-    samples, and the total-variation distance between the pooled overlap
-    histograms, set against the distance between two FP64 runs with different
-    seeds.  Measurements are taken over the second half of the run."""
+    the L=12 workload's shape (4 x 28 temperatures on [0.2, 1.6], 4 reservoir
+    clones): per-temperature energy per spin paired on couplings and seed,
+    and the P(q) distance against the spread between independent FP64 runs
+    (analysis.precision_statement states the criteria)."""
+    from paper_2605_25872_amd import analysis
+
+    w = inputs.WORKLOADS[args.precision_workload]
+    res = analysis.compare_precisions(w, args.samples, args.emcs,
+                                      list(range(1, args.seeds + 1)), progress=log)
+    return {"mode": "fp32_vs_fp64", "workload_name": w.name, **res}
+
+
+def reservoir_decorrelation(args) -> dict:
+    """C(tau) = (1/V) sum_i sigma_i(t) sigma_i(t + tau) of reservoir clones
+    swept at T_max from an equilibrated start (paper Sec. 3, ER paragraph:
+    the 960-sweep residence is calibrated by C(960) < 1e-3 at the paper's
+    T_max), at the workload's T_max and at the paper's T_max = 2, on the GPU:
+    per tau the mean over samples of each sample's average over its 8
+    reservoir clones and its sites, with its standard error."""
     import torch
     from paper_2605_25872_amd import pthr
 
-    w = inputs.WORKLOADS["l8_fp64"]
-    S, n = args.samples, args.emcs
-    T = w.temperatures()
-    J = w.couplings(S)
-    res = {}
-    for label, prec, seed in (("fp64", "fp64", 1), ("fp32", "fp32", 1), ("fp64_seed2", "fp64", 2)):
-        g = pthr.Pthr(w.L, S, w.n_replicas, w.n_temps, w.n_reservoir, w.sweeps_per_emcs,
-                      w.er_sweeps_per_emcs, prec, "acu", w.t_acu, seed)
-        g.init_samples(J, T)
-        obs = g.new_obs()
-        t0 = time.perf_counter()
-        half = n // 2
-        for done in range(0, half, 256):
-            g.run(min(256, half - done))
-            torch.cuda.synchronize()
-        for done in range(0, n - half, 256):
-            g.run(min(256, n - half - done), obs)
-            torch.cuda.synchronize()
-            log(f"precision check {label}: {half + done + min(256, n - half - done)}/{n} EMCS")
+    w = inputs.WORKLOADS[args.workload if args.workload != "mixed" else "l16_fp32"]
+    S = min(args.samples, w.n_samples)
+    taus = [60, 120, 240, 480, 720, 960, 1440, 1920]
+    out = {"mode": "reservoir_decorrelation", "L": w.L, "samples": S, "precision": w.precision,
+           "reservoir_clones_per_sample": 8, "warmup_sweeps": 960, "taus": taus, "C": {}}
+    for t_max in sorted({w.t_max, 2.0}):
+        g = pthr.Pthr(w.L, S, 2, 2, 4, 0, 240, w.precision, "acu", 0.0, 5)
+        g.init_samples(w.couplings(S), np.array([t_max - 0.1, t_max]))
+        for _ in range(4):
+            g.sweep(0, 240)
+            g.pt_swap(False)  # closes the EMCS without a reservoir exchange
+        er = slice(4, 12)
+        s0 = g.read_spins()[:, er].astype(np.int8)
+        done, m, rows = 0, 0, []
+        for tau in taus:
+            while done < tau:
+                n = min(tau - done, 240 - m)
+                g.sweep(0, n)
+                done += n
+                m += n
+                if m == 240:
+                    g.pt_swap(False)
+                    m = 0
+            cs = (s0.astype(np.int32) * g.read_spins()[:, er]).mean(axis=(1, 2))
+            rows.append([float(cs.mean()), float(cs.std(ddof=1) / np.sqrt(S))])
+            log(f"T_max={t_max}: C({tau}) = {rows[-1][0]:.5f} +- {rows[-1][1]:.5f}")
+        torch.cuda.synchronize()
         g.check()
-        arr = g.obs_arrays(obs)
-        m = arr["n_meas"]
-        res[label] = {"e": arr["acc"][:, :, 0] / (m * w.n_replicas), "hist": arr["hist"].astype(float),
-                      "seconds": time.perf_counter() - t0}
-    d = res["fp32"]["e"] - res["fp64"]["e"]            # [S][N_T], paired on samples
-    diff = d.mean(axis=0)
-    sigma = d.std(axis=0, ddof=1) / np.sqrt(S)
-    tv = lambda a, b: 0.5 * np.abs(a / a.sum(1, keepdims=True) - b / b.sum(1, keepdims=True)).sum(1)
-    tv32 = tv(res["fp32"]["hist"], res["fp64"]["hist"])
-    tv64 = tv(res["fp64_seed2"]["hist"], res["fp64"]["hist"])
-    return {"mode": "fp32_vs_fp64", "workload": f"L=8, {S} samples, 4x20 temperatures on [0.3, 1.6], "
-            f"4 reservoir clones, {n} EMCS, second half measured",
-            "T": T.tolist(), "e_fp64": res["fp64"]["e"].mean(0).tolist(),
-            "e_diff_fp32_minus_fp64": diff.tolist(), "e_diff_sigma": sigma.tolist(),
-            "max_abs_diff": float(np.abs(diff).max()), "max_abs_z": float(np.abs(diff / sigma).max()),
-            "within_1e-4": bool(np.all(np.abs(diff) <= 1e-4)),
-            "within_3_sigma": bool(np.all(np.abs(diff) <= 3 * sigma)),
-            "pq_tv_fp32_vs_fp64": tv32.tolist(), "pq_tv_fp64_vs_fp64_other_seed": tv64.tolist(),
-            "seconds": {k: v["seconds"] for k, v in res.items()}}
+        out["C"][str(t_max)] = rows
+    return out
 
 
 def bench_mixed(args) -> dict:
@@ -324,16 +330,26 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--compare-fp64-samples", type=int, default=16,
                     help="samples for the unbatched FP64 one-sample-per-launch comparison (0 = skip)")
+    ap.add_argument("--shard-samples", type=int, default=128,
+                    help="also time one GPU's share of the batch sharded over 8 GPUs (0 = skip)")
     ap.add_argument("--autotune", action="store_true")
     ap.add_argument("--no-autotune", action="store_true", help="mixed batch: keep the default schedules")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy a MIB-MiB device buffer 3 times (HBM counter calibration)")
+    ap.add_argument("--reservoir-decorrelation", action="store_true",
+                    help="only measure C(tau) of reservoir clones at T_max (the workload's and 2.0)")
     ap.add_argument("--fp32-vs-fp64", action="store_true",
                     help="only compare the FP32 form with the FP64 form statistically")
-    ap.add_argument("--samples", type=int, default=1024)
-    ap.add_argument("--emcs", type=int, default=4096)
+    ap.add_argument("--precision-workload", default="l12_fp64", choices=sorted(inputs.WORKLOADS),
+                    help="--fp32-vs-fp64: the workload whose shape both forms run")
+    ap.add_argument("--samples", type=int, default=512)
+    ap.add_argument("--emcs", type=int, default=2048)
+    ap.add_argument("--seeds", type=int, default=4, help="--fp32-vs-fp64: independent runs per form")
     args = ap.parse_args()
 
+    if args.reservoir_decorrelation:
+        print(json.dumps(reservoir_decorrelation(args)), flush=True)
+        return 0
     if args.fp32_vs_fp64:
         print(json.dumps(precision_check(args)), flush=True)
         return 0
@@ -383,39 +399,54 @@ def main() -> int:
             f"clone split {sch.clone_split}, exp early-out below T = {sch.exp_early_out / 1000:g}")
     stream = torch.cuda.current_stream(dev)
     n_er = w.er_sweeps_per_emcs if w.n_reservoir else 0
+    att = attempts_per_emcs(w)
+    moves = moves_per_emcs(w, T)
 
-    def step(ev=None):
-        if ev is not None:
-            ev[0].record(stream)
-        g.sweep(w.sweeps_per_emcs, n_er)
-        if ev is not None:
-            ev[1].record(stream)
-        g.houdayer()
-        if ev is not None:
-            ev[2].record(stream)
-        g.pt_swap(True)
-        g.measure(obs)
-
-    for i in range(args.warmup):
-        step()
-        torch.cuda.synchronize()
-        log(f"warmup step {i + 1}/{args.warmup} done")
-    evs = [tuple(torch.cuda.Event(enable_timing=True) for _ in range(3)) for _ in range(args.steps)]
+    # Timed region: the persistent form the L=16 workload names, K EMCS as
+    # replays of a captured graph of the phase kernels (pthr_run), with the
+    # observables accumulated every EMCS.  The warm-up captures the graph.
+    window = max(1, min(args.steps, 32))
+    g.set_schedule(graph_window=window)
+    g.run(max(args.warmup, window), obs)
     torch.cuda.synchronize()
+    log(f"warm-up done ({max(args.warmup, window)} EMCS, graph of {window} EMCS captured)")
     t0 = time.perf_counter()
-    for ev in evs:
-        step(ev)
+    g.run(args.steps, obs)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     g.check()
-    sweep_ms = float(np.mean([a.elapsed_time(b) for a, b, _ in evs]))
-    houdayer_ms = float(np.mean([b.elapsed_time(c) for _, b, c in evs]))
-    log(f"timed {args.steps} steps in {elapsed:.3f} s; sweep kernel {sweep_ms:.2f} ms per launch")
-
-    att = attempts_per_emcs(w)
-    moves = moves_per_emcs(w, T)
     ms_per_step = elapsed / args.steps * 1e3
     value = att * args.steps / (elapsed * 1e9)
+    log(f"timed {args.steps} EMCS (graph replays) in {elapsed:.3f} s: {value:.1f} attempts/ns")
+
+    # Kernel breakdown: the same EMCS as eager per-phase launches on the same
+    # stream, HIP events around the sweep and Houdayer kernels (the sweep's
+    # roofline is taken from these launches: the same kernel, launch shape and
+    # data as in the graph).
+    def step(ev):
+        ev[0].record(stream)
+        g.sweep(w.sweeps_per_emcs, n_er)
+        ev[1].record(stream)
+        g.houdayer()
+        ev[2].record(stream)
+        g.pt_swap(True)
+        g.measure(obs)
+        ev[3].record(stream)
+
+    evs = [tuple(torch.cuda.Event(enable_timing=True) for _ in range(4)) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for ev in evs:
+        step(ev)
+    torch.cuda.synchronize()
+    eager_elapsed = time.perf_counter() - t1
+    g.check()
+    sweep_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in evs]))
+    houdayer_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in evs]))
+    pt_measure_ms = float(np.mean([e[2].elapsed_time(e[3]) for e in evs]))
+    log(f"eager per-phase EMCS: {att * args.steps / (eager_elapsed * 1e9):.1f} attempts/ns; "
+        f"sweep kernel {sweep_ms:.2f} ms, Houdayer {houdayer_ms:.3f} ms, PT + observables {pt_measure_ms:.3f} ms")
+
     peak_ops, ops_per_attempt = valu_peak(args.update, w.precision)
     ops = ops_per_attempt * att
     achieved = ops / (sweep_ms * 1e-3)
@@ -439,8 +470,13 @@ def main() -> int:
                    "local_update": args.update,
                    "threads_per_sample": g.schedule().threads_per_sample,
                    "exp_early_out_below_T": g.schedule().exp_early_out / 1000,
-                   "clone_split": g.schedule().clone_split},
+                   "clone_split": g.schedule().clone_split,
+                   "timed_form": f"pthr_run replaying a captured graph of {window} EMCS, observables every EMCS"},
         "houdayer_moves_per_s": moves * args.steps / elapsed,
+        "eager_per_phase": {"value": att * args.steps / (eager_elapsed * 1e9),
+                            "ms_per_step": eager_elapsed / args.steps * 1e3,
+                            "sweep_ms": sweep_ms, "houdayer_ms": houdayer_ms,
+                            "pt_and_observables_ms": pt_measure_ms},
         "houdayer_kernel": {"ms_per_launch": houdayer_ms,
                             "moves_per_s": moves / (houdayer_ms * 1e-3) if moves else None,
                             "utilisation": houdayer_utilisation(w.name, args.mode)},
@@ -455,6 +491,33 @@ def main() -> int:
                      "ops_by_issue_class": OPS_BY_CLASS[(args.update, w.precision)],
                      "sweep_ms_per_launch": sweep_ms},
     }
+
+    if args.shard_samples > 0 and args.shard_samples < w.n_samples:
+        # One GPU's share of the batch sharded over 8 GPUs (samples are
+        # independent): the first S/8 samples, same form and timing as above.
+        n = args.shard_samples
+        sub = inputs.Workload(**{**w.__dict__, "n_samples": n})
+        h = pthr.Pthr(w.L, n, w.n_replicas, w.n_temps, w.n_reservoir, w.sweeps_per_emcs,
+                      w.er_sweeps_per_emcs, w.precision, lib_mode, w.t_acu, w.seed, local_update=args.update)
+        h.init_samples(sub.couplings(), T)
+        if args.autotune:
+            h.autotune(max(1, math.ceil(1.5e10 / attempts_per_emcs(sub))))
+        h.set_schedule(graph_window=window)
+        hobs = h.new_obs()
+        h.run(max(args.warmup, window), hobs)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        h.run(args.steps, hobs)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t1
+        h.check()
+        sch = h.schedule()
+        out["per_gpu_shard"] = {
+            "samples": n, "value": attempts_per_emcs(sub) * args.steps / (dt * 1e9),
+            "unit": "spin-flip attempts/ns", "ms_per_step": dt / args.steps * 1e3,
+            "threads_per_sample": sch.threads_per_sample, "clone_split": sch.clone_split}
+        log(f"per-GPU shard of {n} samples: {out['per_gpu_shard']['value']:.1f} attempts/ns")
+        del h
 
     if args.compare_fp64_samples > 0:
         n = min(args.compare_fp64_samples, w.n_samples)

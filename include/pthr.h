@@ -42,8 +42,15 @@
  * the alternative Sec. 3 names, draws the spin from its conditional Boltzmann
  * weight, i.e. flips with probability 1 / (1 + exp(beta dE)), tested as
  * fma(u, a, u) < a (dE > 0) or < 1 (dE <= 0) with a = exp(-beta |dE|) from the
- * same exp routine and the same random numbers.  Both are bit-exact with the
- * reference.
+ * same exp routine and the same random numbers.  PTHR_MICSA (PTHR*, the
+ * paper's update for its longest runs; App. A.1 energy-LUT paragraph and
+ * App. A.2): every PT clone carries a walker holding an energy W >= 0; a spin
+ * flips iff W >= dE, and the walker then gives up dE.  The walker is redrawn
+ * from its Boltzmann law at the clone's temperature, W = T_k (-ln u), at the
+ * start of every PT sweep whose index m in the EMCS is a multiple of
+ * micsa_refresh (u from 53 random bits, ln by a specified double routine;
+ * the FP32 form rounds W to float and tests and subtracts in float); the
+ * reservoir clones keep Metropolis.  All are bit-exact with the reference.
  *
  * Memory and ownership
  *   The library never allocates device memory.  The caller allocates the state
@@ -78,7 +85,7 @@ enum {
 };
 enum { PTHR_FP64 = 0, PTHR_FP32 = 1 };
 enum { PTHR_ACU = 0, PTHR_SINGLE_NEG = 1 };
-enum { PTHR_METROPOLIS = 0, PTHR_HEAT_BATH = 1 };
+enum { PTHR_METROPOLIS = 0, PTHR_HEAT_BATH = 1, PTHR_MICSA = 2 };
 enum { PTHR_NOBS = 6 }; /* per (sample, T): sum e, sum e^2, sum q^2, sum q^4, sum q_l, sum S */
 
 typedef struct pthr_params {
@@ -91,9 +98,11 @@ typedef struct pthr_params {
   int32_t er_sweeps_per_emcs; /* ER sweeps per EMCS (paper: 960/4 = 240), 0..256 */
   int32_t precision;          /* PTHR_FP64 or PTHR_FP32                        */
   int32_t houdayer_mode;      /* PTHR_ACU (paper) or PTHR_SINGLE_NEG (Houdayer's original) */
-  int32_t local_update;       /* PTHR_METROPOLIS (paper) or PTHR_HEAT_BATH     */
+  int32_t local_update;       /* PTHR_METROPOLIS (paper), PTHR_HEAT_BATH or PTHR_MICSA (PTHR*) */
   double t_acu;               /* Houdayer moves at T_k < t_acu (paper: 1.0)    */
   uint64_t seed;              /* Philox key                                    */
+  int32_t micsa_refresh;      /* PTHR_MICSA: PT sweeps between walker refreshes, 0..256
+                                 (0 = sweeps_per_emcs: once per EMCS)          */
 } pthr_params;
 
 typedef struct pthr_ctx pthr_ctx;
@@ -182,6 +191,9 @@ int pthr_read_pt(pthr_ctx *ctx, int32_t *clone_at /* [S][N_r][N_T] */,
                  int32_t *er_head /* [S][N_r] */, uint8_t *pt_last /* [S][N_r][N_T-1] */,
                  uint32_t *pt_count /* [S][N_r][N_T-1] */, double *pt_energy /* [S][N_r*N_T] */,
                  uint8_t *rt_state /* [S][N_r*N_T] */, uint64_t *rt_count /* [S] */, void *stream);
+/* MicSA walker energies [S][N_r*N_T] (host, double; FP32 form: float
+ * values) of every PT clone, by clone id; synchronizes. */
+int pthr_read_walkers(pthr_ctx *ctx, double *walker, void *stream);
 /* EMCS counter and the sweep counters of the current EMCS. */
 int pthr_counters(const pthr_ctx *ctx, int64_t *t, int32_t *m_pt, int32_t *m_er);
 /* Checks the device-side status words (synchronizes): PTHR_EDEVICE if any

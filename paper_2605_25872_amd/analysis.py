@@ -24,6 +24,7 @@ import dataclasses
 import json
 import sys
 from dataclasses import dataclass, field
+from statistics import NormalDist
 
 import numpy as np
 
@@ -189,6 +190,121 @@ def summary(res: list[BinResult], n_clones: int) -> list[dict]:
                      "round_trips_per_clone_median": r.round_trips_per_clone_median(n_clones),
                      "tau_trw_median": r.tau_trw_median()})
     return rows
+
+
+def total_variation(a: np.ndarray, b: np.ndarray) -> np.ndarray:
+    """Total-variation distance of two histograms per row (temperature):
+    half the summed absolute difference of the normalised rows."""
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return 0.5 * np.abs(a / a.sum(axis=1, keepdims=True) - b / b.sum(axis=1, keepdims=True)).sum(axis=1)
+
+
+@dataclass
+class FormRun:
+    """The second-half averages of one run: energy per spin per sample and
+    temperature, [S][N_T], and the pooled overlap histogram [N_T][V+1]."""
+    e: np.ndarray
+    hist: np.ndarray
+
+
+def precision_statement(fp64: list[FormRun], fp32: list[FormRun], e_tol: float = 1e-4,
+                        n_sigma: float = 3.0) -> dict:
+    """The FP32 form's error against the FP64 form, per observable, from runs
+    paired on the couplings and the seed (fp64[i] and fp32[i] share both;
+    different i are independent chains of the same samples).
+
+    Energy per spin (Sec. 2, Eq. 1): the paired differences e32 - e64 of every
+    seed and sample; their mean must lie within e_tol at every temperature,
+    and within n_sigma standard errors read as a bound on the whole
+    temperature grid: the largest |difference| / error over the N_T
+    temperatures must stay below the normal quantile that the n_sigma
+    two-sided level (0.27 % for 3 sigma) gives a family of N_T comparisons
+    (Sidak: 3.0 for one temperature, 3.8 for 20, 3.9 for 28).  The
+    temperature-averaged difference (per run and sample, then averaged) is
+    reported with its error as one more test of a common bias.
+
+    Overlap distribution P(q) (Sec. 2, Eqs. 2-3): every run's total-variation
+    distance, per temperature, to the pooled histogram of the FP64 runs of
+    the other seeds (leave one seed out, so an FP32 run and an FP64 run are
+    measured against the same kind of pool and, if the FP32 form has the FP64
+    form's P(q), their distances have the same distribution).  Averaged over
+    temperatures, the mean distance of the FP32 runs must not exceed that of
+    the FP64 runs by more than n_sigma standard errors of the difference."""
+    n = len(fp64)
+    if n != len(fp32) or n < 3:
+        raise ValueError("need the same number (>= 3) of FP64 and FP32 runs")
+    d = np.concatenate([b.e - a.e for a, b in zip(fp64, fp32)], axis=0)  # [n S][N_T]
+    diff = d.mean(axis=0)
+    sigma = d.std(axis=0, ddof=1) / np.sqrt(d.shape[0])
+    z = diff / sigma
+    n_t = d.shape[1]
+    level = 2.0 * NormalDist().cdf(-n_sigma)  # two-sided tail of n_sigma
+    z_family = NormalDist().inv_cdf(1.0 - 0.5 * (1.0 - (1.0 - level) ** (1.0 / n_t)))
+    dbar = d.mean(axis=1)  # per run and sample, averaged over temperatures
+    pool = lambda i: np.sum([fp64[j].hist for j in range(n) if j != i], axis=0)
+    tv64 = np.array([total_variation(fp64[i].hist, pool(i)) for i in range(n)])  # [n][N_T]
+    tv32 = np.array([total_variation(fp32[i].hist, pool(i)) for i in range(n)])
+    D64, D32 = tv64.mean(axis=1), tv32.mean(axis=1)
+    gap = D32.mean() - D64.mean()
+    gap_se = np.sqrt(D32.var(ddof=1) / n + D64.var(ddof=1) / n)
+    return {
+        "e_diff_fp32_minus_fp64": diff.tolist(), "e_diff_sigma": sigma.tolist(),
+        "max_abs_e_diff": float(np.abs(diff).max()), "max_abs_z": float(np.abs(z).max()),
+        "e_within_tolerance": bool(np.all(np.abs(diff) <= e_tol)),
+        "e_z_bound_over_the_grid": float(z_family),
+        "e_within_n_sigma": bool(np.all(np.abs(z) <= z_family)),
+        "e_temperatures_beyond_n_sigma": int(np.sum(np.abs(z) > n_sigma)),
+        "e_diff_averaged_over_T": float(dbar.mean()),
+        "e_diff_averaged_over_T_sigma": float(dbar.std(ddof=1) / np.sqrt(len(dbar))),
+        "pq_tv_fp32_to_fp64_pool": tv32.mean(axis=0).tolist(),
+        "pq_tv_fp64_to_fp64_pool": tv64.mean(axis=0).tolist(),
+        "pq_tv_mean_over_T": {"fp32": D32.tolist(), "fp64": D64.tolist()},
+        "pq_tv_gap": float(gap), "pq_tv_gap_se": float(gap_se),
+        "pq_within_fp64_spread": bool(gap <= n_sigma * gap_se),
+        "criteria": {"e_abs_tol": e_tol, "n_sigma": n_sigma, "runs_per_form": n,
+                     "pq": "mean over T of the TV distance to the other seeds' pooled FP64 histogram, "
+                           "FP32 runs against FP64 runs"},
+    }
+
+
+def compare_precisions(w, n_samples: int, n_emcs: int, seeds, progress=None) -> dict:
+    """Runs the FP64 and the FP32 form of workload `w` (an `inputs.Workload`)
+    on its first n_samples samples for n_emcs EMCS with every seed in `seeds`
+    (each seed: one run per form, same couplings), measures over the second
+    half, and returns the precision statement with the per-temperature data."""
+    import torch
+
+    from paper_2605_25872_amd import pthr
+
+    T = w.temperatures()
+    J = w.couplings(n_samples)
+    runs = {"fp64": [], "fp32": []}
+    half = n_emcs // 2
+    for seed in seeds:
+        for prec in ("fp64", "fp32"):
+            g = pthr.Pthr(w.L, n_samples, w.n_replicas, w.n_temps, w.n_reservoir, w.sweeps_per_emcs,
+                          w.er_sweeps_per_emcs, prec, "acu", w.t_acu, seed)
+            g.init_samples(J, T)
+            obs = g.new_obs()
+            for done in range(0, half, 256):
+                g.run(min(256, half - done))
+            for done in range(0, n_emcs - half, 256):
+                g.run(min(256, n_emcs - half - done), obs)
+                torch.cuda.synchronize()
+                if progress:
+                    progress(f"{prec} seed {seed}: {half + min(done + 256, n_emcs - half)}/{n_emcs} EMCS")
+            g.check()
+            arr = g.obs_arrays(obs)
+            runs[prec].append(FormRun(arr["acc"][:, :, 0] / (arr["n_meas"] * w.n_replicas),
+                                      arr["hist"].astype(np.float64)))
+            del g, obs
+    out = precision_statement(runs["fp64"], runs["fp32"])
+    out.update({"T": [float(x) for x in T], "e_fp64": np.mean([r.e.mean(0) for r in runs["fp64"]], axis=0).tolist(),
+                "workload": {"L": w.L, "samples": n_samples, "replicas": w.n_replicas, "temperatures": w.n_temps,
+                             "t_range": [w.t_min, w.t_max], "reservoir_clones": w.n_reservoir,
+                             "emcs": n_emcs, "measured": "second half", "seeds": list(seeds)}})
+    return out
 
 
 def main(argv=None) -> int:

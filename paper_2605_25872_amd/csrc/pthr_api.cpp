@@ -30,8 +30,8 @@ size_t align256(size_t v) { return (v + 255) / 256 * 256; }
 
 // Byte offsets of every region of the caller's state buffer.
 struct Layout {
-  size_t beta64, beta32, spins, J, beta_clone, clone_at, er_head, pt_last, pt_count, pt_energy, e_now, rt_state,
-      rt_count, status, total;
+  size_t beta64, beta32, T64, spins, J, beta_clone, clone_at, er_head, pt_last, pt_count, pt_energy, e_now, rt_state,
+      rt_count, status, walker, total;
 };
 
 struct Derived {
@@ -57,6 +57,7 @@ Layout layout_of(const pthr_params& p) {
   size_t o = 256;  // header: the EMCS counter t (uint32) at offset 0
   l.beta64 = o;    o = align256(o + 8 * NT);
   l.beta32 = o;    o = align256(o + 4 * NT);
+  l.T64 = o;       o = align256(o + 8 * NT);
   l.spins = o;     o = align256(o + 4 * S * d.NW * d.V);
   l.J = o;         o = align256(o + fp * S * 3 * d.V);
   // + 16 bytes: the sweep reads the factors of a Philox block's clones as one
@@ -72,6 +73,7 @@ Layout layout_of(const pthr_params& p) {
   l.rt_state = o;  o = align256(o + S * d.NPT);
   l.rt_count = o;  o = align256(o + 8 * S);
   l.status = o;    o = align256(o + 4 * S);
+  l.walker = o;    o = align256(o + 8 * S * d.NPT);
   l.total = o;
   return l;
 }
@@ -94,6 +96,7 @@ pthr::Geo geo_of(const pthr_params& p, int K_acu) {
   g.K_acu = K_acu;
   g.mode = p.houdayer_mode;
   g.update = p.local_update;
+  g.micsa_refresh = p.micsa_refresh > 0 ? p.micsa_refresh : (p.sweeps_per_emcs > 0 ? p.sweeps_per_emcs : 1);
   g.exp_lo = 0x1.ffffep-1f;  // 1 - 2^-20
   g.exp_hi = 0x1.00001p+0f;  // 1 + 2^-20
   g.key0 = static_cast<uint32_t>(p.seed);
@@ -128,8 +131,9 @@ const char* validate(const pthr_params& p) {
   if (p.er_sweeps_per_emcs < 0 || p.er_sweeps_per_emcs > 256) return "er_sweeps_per_emcs must be in [0, 256]";
   if (p.precision != PTHR_FP64 && p.precision != PTHR_FP32) return "precision must be PTHR_FP64 or PTHR_FP32";
   if (p.houdayer_mode != PTHR_ACU && p.houdayer_mode != PTHR_SINGLE_NEG) return "houdayer_mode must be PTHR_ACU or PTHR_SINGLE_NEG";
-  if (p.local_update != PTHR_METROPOLIS && p.local_update != PTHR_HEAT_BATH)
-    return "local_update must be PTHR_METROPOLIS or PTHR_HEAT_BATH";
+  if (p.local_update != PTHR_METROPOLIS && p.local_update != PTHR_HEAT_BATH && p.local_update != PTHR_MICSA)
+    return "local_update must be PTHR_METROPOLIS, PTHR_HEAT_BATH or PTHR_MICSA";
+  if (p.micsa_refresh < 0 || p.micsa_refresh > 256) return "micsa_refresh must be in [0, 256]";
   if (std::isnan(p.t_acu)) return "t_acu must not be NaN";
   return nullptr;
 }
@@ -197,6 +201,8 @@ struct pthr_ctx {
     st.beta64 = reinterpret_cast<const double*>(b + lay.beta64);
     st.beta32 = reinterpret_cast<const float*>(b + lay.beta32);
     st.beta_clone = b + lay.beta_clone;
+    st.T64 = reinterpret_cast<const double*>(b + lay.T64);
+    st.walker = reinterpret_cast<double*>(b + lay.walker);
     return st;
   }
   pthr::Obs obs(void* d_obs) const {
@@ -446,6 +452,7 @@ int pthr_init_samples(pthr_ctx* ctx, const double* J_host, const double* T_host,
   hipError_t e;
   e = hipMemcpyAsync(ctx->d_state + l.beta64, b64.data(), 8 * NT, hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipMemcpyAsync(ctx->d_state + l.beta32, b32.data(), 4 * NT, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(ctx->d_state + l.T64, T_host, 8 * NT, hipMemcpyHostToDevice, s);
   std::vector<float> J32;
   if (e == hipSuccess) {
     if (p.precision == PTHR_FP64) {
@@ -694,6 +701,18 @@ int pthr_read_pt(pthr_ctx* ctx, int32_t* clone_at, int32_t* er_head, uint8_t* pt
   return e == hipSuccess ? PTHR_OK : ctx->hip_fail(e, "read PT state");
 }
 
+int pthr_read_walkers(pthr_ctx* ctx, double* walker, void* stream) {
+  if (!ctx) return PTHR_EINVAL;
+  ctx->err.clear();
+  if (int rc = ctx->need_ready()) return rc;
+  if (!walker) return ctx->fail(PTHR_EINVAL, "walker must not be NULL");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = hipMemcpyAsync(walker, ctx->d_state + ctx->lay.walker, 8 * size_t(ctx->p.n_samples) * ctx->d.NPT,
+                                hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  return e == hipSuccess ? PTHR_OK : ctx->hip_fail(e, "read walkers");
+}
+
 int pthr_counters(const pthr_ctx* ctx, int64_t* t, int32_t* m_pt, int32_t* m_er) {
   if (!ctx) return PTHR_EINVAL;
   if (t) *t = ctx->t;
@@ -726,6 +745,18 @@ struct BlobHeader {
 };
 }  // namespace
 
+namespace {
+// Field by field: the struct's tail padding is not part of the parameters.
+bool same_params(const pthr_params& a, const pthr_params& b) {
+  return a.L == b.L && a.n_samples == b.n_samples && a.n_replicas == b.n_replicas && a.n_temps == b.n_temps &&
+         a.n_reservoir == b.n_reservoir && a.sweeps_per_emcs == b.sweeps_per_emcs &&
+         a.er_sweeps_per_emcs == b.er_sweeps_per_emcs && a.precision == b.precision &&
+         a.houdayer_mode == b.houdayer_mode && a.local_update == b.local_update &&
+         std::memcmp(&a.t_acu, &b.t_acu, sizeof a.t_acu) == 0 && a.seed == b.seed &&
+         a.micsa_refresh == b.micsa_refresh;
+}
+}  // namespace
+
 size_t pthr_blob_bytes(const pthr_ctx* ctx) { return ctx ? sizeof(BlobHeader) + ctx->lay.total : 0; }
 
 int pthr_get_state(pthr_ctx* ctx, void* blob, size_t bytes, void* stream) {
@@ -755,7 +786,7 @@ int pthr_set_state(pthr_ctx* ctx, const void* blob, size_t bytes, void* stream) 
   if (!blob || bytes < sizeof(BlobHeader)) return ctx->fail(PTHR_EINVAL, "blob too small");
   BlobHeader h{};
   std::memcpy(&h, blob, sizeof h);
-  if (h.magic != kBlobMagic || std::memcmp(&h.p, &ctx->p, sizeof h.p) != 0 || h.state_bytes != ctx->lay.total ||
+  if (h.magic != kBlobMagic || !same_params(h.p, ctx->p) || h.state_bytes != ctx->lay.total ||
       bytes < sizeof h + h.state_bytes)
     return ctx->fail(PTHR_EINVAL, "blob does not belong to a context with these parameters");
   hipStream_t s = static_cast<hipStream_t>(stream);

@@ -10,7 +10,11 @@
 namespace pthr {
 
 // Counter word 0 of every Philox block: site | sweep << 16 | purpose << 24.
-enum Purpose : uint32_t { kInit = 1, kMetro = 2, kAcu = 3, kHseed = 4, kPt = 5 };
+enum Purpose : uint32_t { kInit = 1, kMetro = 2, kAcu = 3, kHseed = 4, kPt = 5, kWalker = 6 };
+
+// Local update of the PT clones (the reservoir clones use Metropolis with
+// MicSA too).
+enum Update : int { kMetropolis = 0, kHeatBath = 1, kMicsa = 2 };
 
 enum Phase : uint32_t {
   kPhaseSweep = 1u,     // Metropolis sweeps of PT and/or ER clones
@@ -31,7 +35,8 @@ struct Geo {
   int NW, NWPT;      // 32-clone spin words per site: all, PT only
   int K_acu;         // number of temperatures with T_k < t_acu (a prefix)
   int mode;          // 0 all-cluster, 1 single negative cluster
-  int update;        // local update: 0 Metropolis, 1 heat bath
+  int update;        // local update of the PT clones (Update)
+  int micsa_refresh; // MicSA: PT sweeps between walker refreshes (>= 1)
   float exp_lo, exp_hi;  // FP64 Metropolis: factors of the float bounds on exp (set per launch:
                         // 1 -+ 2^-20, or 0 and +inf to take the FP64 polynomial for every test)
   uint32_t key0, key1;
@@ -56,6 +61,8 @@ struct State {
   const float* beta32;   // [NT] FP32 form's Metropolis factor (float)(beta log2 e)
   void* beta_clone;      // [S][C] Metropolis factor of every clone (FP64: beta; FP32: beta log2 e),
                          // kept by the PT kernel
+  const double* T64;     // [NT] temperatures as given
+  double* walker;        // [S][NPT] MicSA walker energy of every PT clone (FP32 form: float values)
 };
 
 struct Obs {

@@ -1676,6 +1676,118 @@ __device__ __forceinline__ void store_spins(const Geo& g, const Lds& s, const St
   store_spins(g, s.sp, st, sample);
 }
 
+// ------------------------------------------------------------------ MicSA
+// ln(u) for 0 < u <= 1 (u normal): u = 2^e m with m in [sqrt(1/2), sqrt(2))
+// (exact), f = m - 1 (exact), s = f / (2 + f) (correctly rounded division),
+// ln m = 2 atanh(s) = s (2 + 2 s^2/3 + 2 s^4/5 + ...) to s^23 by Horner in
+// z = s^2 with fused multiply-adds (|s| < 0.172: the first omitted term is
+// below 2^-60 of the sum), then e ln2 in two words (e times the head is
+// exact).  Coefficients 2/(2n+1) rounded to double.
+constexpr double kAtanhCoef[12] = {0x1.0000000000000p+1, 0x1.5555555555555p-1, 0x1.999999999999ap-2,
+                                   0x1.2492492492492p-2, 0x1.c71c71c71c71cp-3, 0x1.745d1745d1746p-3,
+                                   0x1.3b13b13b13b14p-3, 0x1.1111111111111p-3, 0x1.e1e1e1e1e1e1ep-4,
+                                   0x1.af286bca1af28p-4, 0x1.8618618618618p-4, 0x1.642c8590b2164p-4};
+__device__ __forceinline__ double log_unit64(double u) {
+  const unsigned long long b = static_cast<unsigned long long>(__double_as_longlong(u));
+  int e = static_cast<int>((b >> 52) & 0x7FFull) - 1022;
+  double m = __longlong_as_double(static_cast<long long>((b & 0x000FFFFFFFFFFFFFull) | 0x3FE0000000000000ull));
+  if (m < 0x1.6a09e667f3bcdp-1) {  // below sqrt(1/2): take m in [sqrt(1/2), 1)
+    m *= 2.0;
+    e -= 1;
+  }
+  const double f = m - 1.0;
+  const double s = f / (2.0 + f);
+  const double z = s * s;
+  double p = kAtanhCoef[11];
+#pragma unroll
+  for (int n = 10; n >= 0; --n) p = __builtin_fma(p, z, kAtanhCoef[n]);
+  const double lm = s * p;
+  const double de = static_cast<double>(e);
+  return __builtin_fma(de, 0x1.62e42feep-1, __builtin_fma(de, 0x1.a39ef35793c76p-33, lm));
+}
+
+// MicSA sweeps of the PT clones (App. A.1): each clone carries a walker
+// holding an energy W >= 0; a spin flips iff W >= dE, and the walker then
+// gives up dE.  The walker is redrawn from its Boltzmann law at the clone's
+// temperature, W = T_k (-ln u), at every sweep m with m % micsa_refresh == 0,
+// u = (b + 1) 2^-53 from 53 bits b of the block (WALKER, site 0, m, t, clone,
+// sample).  The walker makes one clone's sweep sequential, so a lane owns a
+// clone and walks its sites in the sweep order (colour 0 in increasing site
+// index, then colour 1); the lanes of one 32-clone word take the same site
+// at the same time and their flips enter the word through one ballot.  A
+// wave's 64 clones fill whole words that no other wave touches, so the
+// waves run without barriers.  dE is summed as the Metropolis sweep sums it:
+// terms J_d s_i s_j in the order ((+x, -x) + (+y, -y)) + (+z, -z), doubled.
+template <typename FP>
+__global__ __launch_bounds__(kMaxThreads) void micsa_kernel(Geo g, State st, Run run) {
+  const int sample = run.sample_begin + blockIdx.x;
+  if (sample >= g.S) return;
+  uint32_t* sp = reinterpret_cast<uint32_t*>(lds_raw);  // [NWPT][V]
+  int32_t* cat = reinterpret_cast<int32_t*>(lds_raw + align_up(sizeof(uint32_t) * size_t(g.NWPT) * g.V, 16));
+  int32_t* kof = cat + g.NR * g.NT;  // [NPT] temperature index of every clone
+  load_spins(g, sp, cat, st, sample, g.NWPT);
+  __syncthreads();
+  for (int x = threadIdx.x; x < g.NPT; x += blockDim.x) kof[cat[x]] = x % g.NT;
+  __syncthreads();
+  const FP* Js = static_cast<const FP*>(st.J) + size_t(sample) * 3 * g.V;
+  const uint32_t t = *st.t_dev;
+  const int L = g.L, L2 = L * L, V = g.V;
+  const int lane = lane_id();
+  // blockDim.x is a multiple of 64, so all lanes of a wave take the same trips
+  for (int base = 0; base < g.NPT; base += blockDim.x) {
+    const int c = base + static_cast<int>(threadIdx.x);
+    const bool active = c < g.NPT;
+    const int cw = active ? c : base;  // clone whose word and factors inactive lanes read
+    const uint32_t* plane = sp + size_t(cw >> 5) * V;
+    const int bit = cw & 31;
+    const int w_lo = (base + wave_id() * kWave) >> 5;  // words of lanes 0..31 and 32..63
+    const double Tk = st.T64[kof[cw]];
+    double* wslot = st.walker + size_t(sample) * g.NPT + cw;
+    FP W = static_cast<FP>(*wslot);
+    for (int mm = 0; mm < run.n_pt; ++mm) {
+      const int m = run.m_pt0 + mm;
+      if (m % g.micsa_refresh == 0) {
+        const Block blk = philox10(ctr_word(0, static_cast<uint32_t>(m), kWalker), t, static_cast<uint32_t>(cw),
+                                   static_cast<uint32_t>(sample), g.key0, g.key1);
+        const uint64_t b53 = ((static_cast<uint64_t>(blk.w1) << 32) | blk.w0) >> 11;
+        W = static_cast<FP>(Tk * -log_unit64(static_cast<double>(b53 + 1) * 0x1p-53));
+      }
+      for (int colour = 0; colour < 2; ++colour) {
+        for (int row = 0; row < L2; ++row) {
+          const int y = row % L, z = row / L;
+          for (int x = (y + z + colour) & 1; x < L; x += 2) {
+            const Site si{row * L + x, x, y, z};
+            const int j = colour * g.Vh + (si.i >> 1);
+            const uint32_t own = (plane[j] >> bit) & 1u;
+            FP term[6];
+#pragma unroll
+            for (int d = 0; d < 6; ++d) {
+              const int n = neighbour(si, d, L);
+              const FP Jd = Js[size_t(d >> 1) * V + ((d & 1) ? n : si.i)];
+              const uint32_t nbit = (plane[(colour ^ 1) * g.Vh + (n >> 1)] >> bit) & 1u;
+              term[d] = (own ^ nbit) ? -Jd : Jd;  // J_d s_i s_j
+            }
+            const FP dE = FP(2) * (((term[0] + term[1]) + (term[2] + term[3])) + (term[4] + term[5]));
+            const bool acc = active && W >= dE;
+            if (acc) W = W - dE;
+            const uint64_t flips = __builtin_amdgcn_ballot_w64(acc);
+            const uint32_t lo = static_cast<uint32_t>(flips), hi = static_cast<uint32_t>(flips >> 32);
+            if (lane == 0 && lo) sp[size_t(w_lo) * V + j] ^= lo;
+            if (lane == 32 && hi) sp[size_t(w_lo + 1) * V + j] ^= hi;
+          }
+        }
+      }
+    }
+    if (active) *wslot = static_cast<double>(W);
+  }
+  __syncthreads();
+  store_spins(g, sp, st, sample, g.NWPT);
+}
+
+size_t micsa_lds_bytes(const Geo& g) {
+  return align_up(sizeof(uint32_t) * size_t(g.NWPT) * g.V, 16) + sizeof(int32_t) * size_t(g.NR * g.NT + g.NPT);
+}
+
 template <typename FP, int CH, bool kSplit, bool kHB>
 __global__ __launch_bounds__(kMaxThreads) void sweep_kernel(Geo g, State st, Run run) {
   const int sample = run.sample_begin + blockIdx.x;
@@ -1790,6 +1902,7 @@ hipError_t prepare_t(size_t lds) {
   if ((e = set_lds(sweep_kernel<FP, CH, false, true>, lds)) != hipSuccess) return e;
   if ((e = set_lds(sweep_kernel<FP, CH, true, true>, lds)) != hipSuccess) return e;
   if ((e = set_lds(houdayer_kernel, lds)) != hipSuccess) return e;
+  if ((e = set_lds(micsa_kernel<FP>, lds)) != hipSuccess) return e;
   if ((e = set_lds(pt_kernel<FP, CH>, lds)) != hipSuccess) return e;
   return set_lds(measure_kernel<FP, CH>, lds);
 }
@@ -1802,10 +1915,22 @@ hipError_t launch_t(const Geo& g, const State& st, const Obs& ob, const Run& run
   if (run.phases & kPhaseSweep) {
     Run r = run;
     r.clone_split = split;
-    auto k = g.update ? (split > 1 ? sweep_kernel<FP, CH, true, true> : sweep_kernel<FP, CH, false, true>)
-                      : (split > 1 ? sweep_kernel<FP, CH, true, false> : sweep_kernel<FP, CH, false, false>);
-    hipLaunchKernelGGL(k, dim3(n_blocks), dim3(threads * split), lds, stream, g, st, r);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (g.update == kMicsa) {
+      // MicSA on the PT clones (one lane per clone), Metropolis on the reservoir
+      if (r.n_pt > 0) {
+        const int mt = g.NPT >= kMaxThreads ? kMaxThreads : (g.NPT + kWave - 1) / kWave * kWave;
+        hipLaunchKernelGGL(micsa_kernel<FP>, dim3(n_blocks), dim3(mt), micsa_lds_bytes(g), stream, g, st, r);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+      }
+      r.n_pt = 0;
+    }
+    if (r.n_pt > 0 || (r.n_er > 0 && g.NER > 0)) {
+      auto k = g.update == kHeatBath
+                   ? (split > 1 ? sweep_kernel<FP, CH, true, true> : sweep_kernel<FP, CH, false, true>)
+                   : (split > 1 ? sweep_kernel<FP, CH, true, false> : sweep_kernel<FP, CH, false, false>);
+      hipLaunchKernelGGL(k, dim3(n_blocks), dim3(threads * split), lds, stream, g, st, r);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
   }
   if (run.phases & (kPhaseHoudayer | kPhaseLabels | kPhaseClusterStats)) {
     Run r = run;

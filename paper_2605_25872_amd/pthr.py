@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(PKG, "libpthr.so")
 PTHR_OK, PTHR_EINVAL, PTHR_EUNSUPPORTED, PTHR_EHIP, PTHR_ESTATE, PTHR_EDEVICE = 0, -1, -2, -3, -4, -5
 FP64, FP32 = 0, 1
 ACU, SINGLE_NEG = 0, 1
-METROPOLIS, HEAT_BATH = 0, 1
+METROPOLIS, HEAT_BATH, MICSA = 0, 1, 2
 NOBS = 6
 OBS_NAMES = ("e", "e2", "q2", "q4", "ql", "sdy")
 
@@ -30,7 +30,7 @@ EXPORTED = (
     "pthr_blob_bytes", "pthr_get_state", "pthr_set_state", "pthr_get_schedule",
     "pthr_set_schedule", "pthr_autotune", "pthr_lds_bytes", "pthr_group_create",
     "pthr_group_destroy", "pthr_group_last_error", "pthr_group_run", "pthr_cluster_stats",
-    "pthr_write_spins",
+    "pthr_write_spins", "pthr_read_walkers",
 )
 
 
@@ -46,7 +46,8 @@ class Params(ctypes.Structure):
                 ("n_reservoir", ctypes.c_int32), ("sweeps_per_emcs", ctypes.c_int32),
                 ("er_sweeps_per_emcs", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("houdayer_mode", ctypes.c_int32), ("local_update", ctypes.c_int32),
-                ("t_acu", ctypes.c_double), ("seed", ctypes.c_uint64)]
+                ("t_acu", ctypes.c_double), ("seed", ctypes.c_uint64),
+                ("micsa_refresh", ctypes.c_int32)]
 
 
 class Schedule(ctypes.Structure):
@@ -92,6 +93,7 @@ def library() -> ctypes.CDLL:
         "pthr_cluster_stats": (i32, [vp, vp, vp]),
         "pthr_read_spins": (i32, [vp, vp, vp]),
         "pthr_write_spins": (i32, [vp, vp, vp]),
+        "pthr_read_walkers": (i32, [vp, vp, vp]),
         "pthr_read_pt": (i32, [vp, vp, vp, vp, vp, vp, vp, vp, vp]),
         "pthr_counters": (i32, [vp, vp, vp, vp]),
         "pthr_check": (i32, [vp, vp]),
@@ -121,15 +123,15 @@ def _np_ptr(a: np.ndarray) -> int:
 
 def make_params(L, n_samples, n_replicas, n_temps, n_reservoir, sweeps_per_emcs=10,
                 er_sweeps_per_emcs=240, precision=FP64, houdayer_mode=ACU, t_acu=1.0, seed=1,
-                local_update=METROPOLIS) -> Params:
+                local_update=METROPOLIS, micsa_refresh=0) -> Params:
     if isinstance(precision, str):
         precision = {"fp64": FP64, "fp32": FP32}[precision]
     if isinstance(houdayer_mode, str):
         houdayer_mode = {"acu": ACU, "single": SINGLE_NEG}[houdayer_mode]
     if isinstance(local_update, str):
-        local_update = {"metropolis": METROPOLIS, "heatbath": HEAT_BATH}[local_update]
+        local_update = {"metropolis": METROPOLIS, "heatbath": HEAT_BATH, "micsa": MICSA}[local_update]
     return Params(L, n_samples, n_replicas, n_temps, n_reservoir, sweeps_per_emcs,
-                  er_sweeps_per_emcs, precision, houdayer_mode, local_update, t_acu, seed)
+                  er_sweeps_per_emcs, precision, houdayer_mode, local_update, t_acu, seed, micsa_refresh)
 
 
 class Pthr:
@@ -138,13 +140,14 @@ class Pthr:
 
     def __init__(self, L, n_samples, n_replicas=4, n_temps=8, n_reservoir=4, sweeps_per_emcs=10,
                  er_sweeps_per_emcs=240, precision=FP64, houdayer_mode=ACU, t_acu=1.0, seed=1,
-                 device="cuda:0", local_update=METROPOLIS):
+                 device="cuda:0", local_update=METROPOLIS, micsa_refresh=0):
         import torch
 
         self.torch = torch
         self.lib = library()
         self.params = make_params(L, n_samples, n_replicas, n_temps, n_reservoir, sweeps_per_emcs,
-                                  er_sweeps_per_emcs, precision, houdayer_mode, t_acu, seed, local_update)
+                                  er_sweeps_per_emcs, precision, houdayer_mode, t_acu, seed, local_update,
+                                  micsa_refresh)
         ctx = ctypes.c_void_p()
         rc = self.lib.pthr_create(ctypes.byref(self.params), ctypes.byref(ctx))
         if rc != PTHR_OK:
@@ -237,6 +240,12 @@ class Pthr:
         """Replace every clone's spins: int8 [S][C][V] of +1/-1."""
         a = np.ascontiguousarray(spins, dtype=np.int8).reshape(self.S, self.C, self.V)
         self._check(self.lib.pthr_write_spins(self.ctx, _np_ptr(a), self._stream()))
+
+    def read_walkers(self) -> np.ndarray:
+        """MicSA walker energy of every PT clone, [S][N_r*N_T] by clone id."""
+        out = np.empty((self.S, self.NPT), dtype=np.float64)
+        self._check(self.lib.pthr_read_walkers(self.ctx, _np_ptr(out), self._stream()))
+        return out
 
     def read_pt(self) -> dict:
         S, NR, NT = self.S, self.NR, self.NT

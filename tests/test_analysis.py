@@ -138,3 +138,40 @@ def test_cluster_zoology_means():
     assert z["majority_mean"].shape == (3, 6)
     assert z["majority_mean"][1, 0] == 10.0 and z["majority_mean"][0, 0] == 0.0
     assert z["minority_mean"][2, 1] == 4.0
+
+
+def test_precision_statement_criteria_on_constructed_runs():
+    """The FP32-vs-FP64 statement's arithmetic on runs whose answers are
+    known: a constant energy offset shows up exactly as the mean paired
+    difference, and a shifted overlap histogram fails the P(q) criterion while
+    an identically distributed one passes it."""
+    rng = np.random.default_rng(3)
+    S, NT, B, n = 40, 3, 11, 4
+    base = [rng.normal(-1.2, 0.05, (S, NT)) for _ in range(n)]
+    noise = [rng.normal(0.0, 1e-5, (S, NT)) for _ in range(n)]
+    p = np.exp(-0.5 * ((np.arange(B) - 5.0) / 2.0) ** 2)
+    p /= p.sum()
+    hists = [rng.multinomial(200000, p, size=NT).astype(float) for _ in range(2 * n)]
+    fp64 = [analysis.FormRun(base[i], hists[i]) for i in range(n)]
+    fp32 = [analysis.FormRun(base[i] + 3e-5 + noise[i], hists[n + i]) for i in range(n)]
+    r = analysis.precision_statement(fp64, fp32)
+    d = np.concatenate(noise, axis=0)
+    assert np.allclose(r["e_diff_fp32_minus_fp64"], 3e-5 + d.mean(axis=0), atol=1e-15)
+    assert np.allclose(r["e_diff_sigma"], d.std(axis=0, ddof=1) / np.sqrt(n * S))
+    assert r["e_within_tolerance"] and not r["e_within_n_sigma"]
+    assert r["e_temperatures_beyond_n_sigma"] == NT
+    assert abs(r["e_z_bound_over_the_grid"] - 3.320) < 0.01  # 3 sigma over 3 temperatures
+    assert abs(r["e_diff_averaged_over_T"] - (3e-5 + d.mean())) < 1e-15
+    # one temperature: the grid bound is the plain 3 sigma
+    one = [analysis.FormRun(f.e[:, :1], f.hist[:1]) for f in fp64]
+    assert abs(analysis.precision_statement(one, [analysis.FormRun(f.e[:, :1], f.hist[:1]) for f in fp32])
+               ["e_z_bound_over_the_grid"] - 3.0) < 1e-9
+    assert r["pq_within_fp64_spread"]
+    # the leave-one-out pools: run i of either form against the FP64 runs j != i
+    pool0 = hists[1] + hists[2] + hists[3]
+    assert np.allclose(r["pq_tv_mean_over_T"]["fp32"][0], analysis.total_variation(hists[n], pool0).mean())
+    shifted = np.roll(p, 1) * 0.05 + p * 0.95
+    bad = [analysis.FormRun(f.e, rng.multinomial(200000, shifted, size=NT).astype(float)) for f in fp32]
+    assert not analysis.precision_statement(fp64, bad)["pq_within_fp64_spread"]
+    tv = analysis.total_variation(np.array([[1.0, 3.0]]), np.array([[3.0, 1.0]]))
+    assert np.allclose(tv, [0.5])

@@ -26,16 +26,20 @@ def _pthr():
     return pthr
 
 
+UPDATES = {"metropolis": oracle.METROPOLIS, "heatbath": oracle.HEAT_BATH, "micsa": oracle.MICSA}
+
+
 def make_pair(L, S, NR, NT, NER, precision="fp64", mode="acu", t_acu=1.0, sweeps=10, er_sweeps=240,
-              seed=1, jseed=1, T=None, t_range=(0.3, 1.6), update="metropolis"):
+              seed=1, jseed=1, T=None, t_range=(0.3, 1.6), update="metropolis", micsa_refresh=0):
     pthr = _pthr()
     J = inputs.couplings(L, S, seed=jseed)
     T = inputs.temperatures(*t_range, NT) if T is None else np.asarray(T, dtype=np.float64)
     prec_o = oracle.FP64 if precision == "fp64" else oracle.FP32
     mode_o = oracle.ACU if mode == "acu" else oracle.SINGLE_NEG
-    upd_o = oracle.METROPOLIS if update == "metropolis" else oracle.HEAT_BATH
-    o = oracle.Oracle(L, S, NR, NT, NER, sweeps, er_sweeps, prec_o, mode_o, t_acu, seed, local_update=upd_o)
-    g = pthr.Pthr(L, S, NR, NT, NER, sweeps, er_sweeps, precision, mode, t_acu, seed, local_update=update)
+    o = oracle.Oracle(L, S, NR, NT, NER, sweeps, er_sweeps, prec_o, mode_o, t_acu, seed, local_update=UPDATES[update],
+                      micsa_refresh=micsa_refresh)
+    g = pthr.Pthr(L, S, NR, NT, NER, sweeps, er_sweeps, precision, mode, t_acu, seed, local_update=update,
+                  micsa_refresh=micsa_refresh)
     o.init(J, T)
     g.init_samples(J, T)
     return o, g
@@ -56,6 +60,8 @@ def assert_same_state(o, g, what=""):
     assert np.array_equal(pt["rt_count"], o.rt_count), what
     t, mp, me = g.counters()
     assert (t, mp, me) == (o.t, o.m(oracle.SWEEP_PT), o.m(oracle.SWEEP_ER)), what
+    if o.params.local_update == oracle.MICSA:
+        assert np.array_equal(g.read_walkers().view(np.uint64), o.walker.view(np.uint64)), f"{what}: walkers differ"
 
 
 def assert_same_obs(o_obs, g, g_obs):
@@ -307,6 +313,62 @@ def test_group_at_the_mixed_batch_sizes():
         assert np.array_equal(pt["clone_at"][s], o.clone_at[0])
         assert np.array_equal(pt["pt_energy"][s].view(np.uint64), o.pt_energy[0].view(np.uint64))
         assert np.array_equal(g.obs_arrays(go)["acc"][s].view(np.uint64), oo.acc[0].view(np.uint64))
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_micsa_every_substep(precision):
+    """MicSA on the PT clones (walker per clone, flip iff the walker holds
+    dE), Metropolis on the reservoir: ragged clone words (2x7 PT clones, 3
+    reservoir clones), walker refreshes every 3 sweeps, the EMCS's PT sweeps
+    split over two launches (so that a launch starts between refreshes),
+    spins and walkers against the oracle after every sub-step."""
+    step(f"micsa ragged {precision}")
+    o, g = make_pair(6, 3, 2, 7, 3, precision=precision, er_sweeps=12, t_range=(0.2, 1.4), update="micsa",
+                     micsa_refresh=3)
+    for e in range(3):
+        o.sweep(4, oracle.SWEEP_PT)
+        g.sweep(4, 0)
+        assert_same_state(o, g, f"EMCS {e} after 4 PT sweeps")
+        o.sweep(6, oracle.SWEEP_PT)
+        o.sweep(12, oracle.SWEEP_ER)
+        g.sweep(6, 12)
+        assert_same_state(o, g, f"EMCS {e} after all sweeps")
+        o.houdayer()
+        g.houdayer()
+        o.pt_swap(True)
+        g.pt_swap(True)
+        assert_same_state(o, g, f"EMCS {e} after the PT/ER step")
+    g.check()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_micsa_fused_runs_and_tiles(precision):
+    """MicSA at L=8, 4x20 temperatures (80 PT clones: a full and a partial
+    wave of clones per sample), one refresh per EMCS: the step-wise calls,
+    the fused run, graph replays and one sample per launch all match the
+    oracle."""
+    step(f"micsa l8 {precision}")
+    o, g = make_pair(8, 3, 4, 20, 4, precision=precision, er_sweeps=20, update="micsa")
+    stepwise(o, g, 2)
+    oo, go = o.new_observables(), g.new_obs()
+    g.set_schedule(graph_window=2)
+    o.run(5, oo)
+    g.run(5, go)
+    assert_same_state(o, g, "fused run with graph replays")
+    assert_same_obs(oo, g, go)
+    g.set_schedule(samples_per_launch=1, graph_window=0)
+    o.run(1)
+    g.run(1)
+    assert_same_state(o, g, "one sample per launch")
+
+
+def test_micsa_many_waves_of_clones():
+    """8 replica groups x 100 temperatures: 800 PT clones, 25 words, so a
+    workgroup of 13 waves whose last wave has clones in one word only."""
+    step("micsa 800 clones")
+    o, g = make_pair(4, 2, 8, 100, 2, precision="fp32", sweeps=3, er_sweeps=5, t_range=(0.3, 1.6), update="micsa",
+                     micsa_refresh=2)
+    stepwise(o, g, 2)
 
 
 # ----------------------------------------------------------------------------- labels, run, schedules
@@ -589,13 +651,14 @@ def sampled_check(name, samples, n_emcs, mode="acu", update="metropolis"):
     spins = g.read_spins()
     pt = g.read_pt()
     acc = g.obs_arrays(go)["acc"]
+    walkers = g.read_walkers() if update == "micsa" else None
     prec = oracle.FP64 if w.precision == "fp64" else oracle.FP32
     for s in samples:
         step(f"  oracle sample {s}")
         o1 = oracle.Oracle(w.L, 1, w.n_replicas, w.n_temps, w.n_reservoir, w.sweeps_per_emcs,
                            w.er_sweeps_per_emcs, prec, oracle.ACU if mode == "acu" else oracle.SINGLE_NEG,
                            w.t_acu, w.seed, first_sample=s,
-                           local_update=oracle.METROPOLIS if update == "metropolis" else oracle.HEAT_BATH)
+                           local_update=UPDATES[update])
         o1.init(w.couplings(1, first_sample=s), T)
         oo = o1.new_observables()
         o1.run(n_emcs, oo)
@@ -603,6 +666,8 @@ def sampled_check(name, samples, n_emcs, mode="acu", update="metropolis"):
         assert np.array_equal(pt["clone_at"][s], o1.clone_at[0])
         assert np.array_equal(pt["pt_energy"][s].view(np.uint64), o1.pt_energy[0].view(np.uint64))
         assert np.array_equal(acc[s].view(np.uint64), oo.acc[0].view(np.uint64))
+        if update == "micsa":
+            assert np.array_equal(walkers[s].view(np.uint64), o1.walker[0].view(np.uint64))
 
 
 def test_full_l8_fp64_workload_sampled():
@@ -627,3 +692,11 @@ def test_full_l16_fp32_single_cluster_sampled():
 
 def test_full_l16_fp32_heat_bath_sampled():
     sampled_check("l16_fp32", [700], 1, update="heatbath")
+
+
+def test_full_l16_fp32_micsa_sampled():
+    sampled_check("l16_fp32", [5, 999], 1, update="micsa")
+
+
+def test_full_l12_fp64_micsa_sampled():
+    sampled_check("l12_fp64", [250], 1, update="micsa")

@@ -56,10 +56,13 @@ def test_validation(lib):
     assert _create(lib, n_samples=0)[0] == pthr.PTHR_EINVAL
     assert _create(lib, L=40)[0] == pthr.PTHR_EINVAL
     assert _create(lib, sweeps_per_emcs=257)[0] == pthr.PTHR_EINVAL
+    assert _create(lib, local_update="micsa")[0] == pthr.PTHR_OK
+    assert _create(lib, local_update="micsa", micsa_refresh=3)[0] == pthr.PTHR_OK
+    assert _create(lib, local_update="micsa", micsa_refresh=257)[0] == pthr.PTHR_EINVAL
     rc, msg, _ = _create(lib, L=16, n_temps=64, precision="fp32")
     assert rc == pthr.PTHR_EUNSUPPORTED and "LDS" in msg
     bad = pthr.make_params(8, 4, 4, 20, 4)
-    bad.local_update = 2
+    bad.local_update = 3
     ctx = ctypes.c_void_p()
     assert lib.pthr_create(ctypes.byref(bad), ctypes.byref(ctx)) == pthr.PTHR_EINVAL
     assert lib.pthr_state_bytes(ctypes.byref(bad)) == 0
