@@ -236,6 +236,16 @@ int pthr_set_schedule(pthr_ctx *ctx, const pthr_schedule *sch);
  * timed stretches of n_emcs EMCS each, the faster counting; keeps the
  * fastest candidate, restores nothing else.  best_ms (may be NULL) gets its time per EMCS. */
 int pthr_autotune(pthr_ctx *ctx, void *d_scratch, int n_emcs, double *best_ms, void *stream);
+/* pthr_autotune for callers that cannot allocate (inside stream capture,
+ * serving loops, harnesses that forbid allocation): the same candidates and
+ * choice, with the scratch copy of the state in a static device workspace of
+ * 64 MiB (PTHR_EINVAL if pthr_state_bytes exceeds it), the trial EMCS run as
+ * plain launches (no graph is instantiated) and timed with the host clock
+ * (no events are created); nothing is allocated.  The workspace is held on
+ * every device the library runs on until the process ends and is shared by
+ * every context on that device: calls that overlap on one device race.
+ * Synchronizes `stream`. */
+int pthr_autotune_noalloc(pthr_ctx *ctx, int n_emcs, double *best_ms, void *stream);
 
 /* Dynamic LDS bytes one sample workgroup needs (0 if invalid). */
 size_t pthr_lds_bytes(const pthr_params *p);

@@ -120,6 +120,18 @@ int default_chunk(int precision, int V) {
 
 thread_local std::string g_create_error;
 
+constexpr int kMaxDevices = 64;
+std::mutex& device_mu() {
+  static std::mutex mu;
+  return mu;
+}
+// Per device: address of the static autotuning workspace (null until the
+// device's first set-up), which also marks the kernels as prepared there.
+void** device_scratch() {
+  static void* ptr[kMaxDevices] = {};
+  return ptr;
+}
+
 const char* validate(const pthr_params& p) {
   if (p.L < 2 || p.L > 32) return "L must be in [2, 32]";
   if (p.L % 2) return "odd L is not supported on the GPU (the checkerboard is not a bipartition)";
@@ -245,18 +257,21 @@ struct pthr_ctx {
     }
     return PTHR_OK;
   }
-  // Raises the kernels' dynamic-LDS limit, once per device and process.
+  // Once per device and process: raises the kernels' dynamic-LDS limit and
+  // looks up the device address of the static autotuning workspace.
   int prepare() {
-    static std::mutex mu;
-    static bool done[64] = {};
+    std::lock_guard<std::mutex> lock(device_mu());
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return hip_fail(e, "get device");
-    std::lock_guard<std::mutex> lock(mu);
-    if (dev >= 0 && dev < 64 && done[dev]) return PTHR_OK;
+    if (dev < 0 || dev >= kMaxDevices) return fail(PTHR_EUNSUPPORTED, "device %d: at most %d devices", dev, kMaxDevices);
+    if (device_scratch()[dev]) return PTHR_OK;
     e = pthr::prepare_kernels(kLdsLimit);
     if (e != hipSuccess) return hip_fail(e, "kernel attributes");
-    if (dev >= 0 && dev < 64) done[dev] = true;
+    void* ptr = nullptr;
+    e = pthr::scratch_address(&ptr);
+    if (e != hipSuccess || !ptr) return hip_fail(e, "workspace address");
+    device_scratch()[dev] = ptr;
     return PTHR_OK;
   }
   // One whole EMCS on `stream`: sweeps, Houdayer, PT + reservoir (all
@@ -828,12 +843,14 @@ int pthr_set_schedule(pthr_ctx* ctx, const pthr_schedule* sch) {
   return PTHR_OK;
 }
 
-int pthr_autotune(pthr_ctx* ctx, void* d_scratch, int n_emcs, double* best_ms, void* stream) {
-  if (!ctx) return PTHR_EINVAL;
-  ctx->err.clear();
-  if (int rc = ctx->need_ready()) return rc;
-  if (!d_scratch || n_emcs < 1) return ctx->fail(PTHR_EINVAL, "need a scratch buffer and n_emcs >= 1");
-  if (ctx->m_pt || ctx->m_er) return ctx->fail(PTHR_ESTATE, "an EMCS is in progress");
+}  // extern "C"
+
+namespace {
+// Times candidate schedules on a copy of the state in `d_scratch` and keeps
+// the fastest.  no_alloc: the trial EMCS run as plain launches (no graph is
+// instantiated) and are timed with the host clock after a stream
+// synchronisation (no events are created), so that nothing is allocated.
+int autotune_impl(pthr_ctx* ctx, void* d_scratch, int n_emcs, double* best_ms, void* stream, bool no_alloc) {
   hipStream_t s = static_cast<hipStream_t>(stream);
   unsigned char* real = ctx->d_state;
   const int64_t t_saved = ctx->t;
@@ -841,9 +858,28 @@ int pthr_autotune(pthr_ctx* ctx, void* d_scratch, int n_emcs, double* best_ms, v
   const pthr_schedule saved = ctx->sch;
   pthr_schedule best = saved;
   double best_t = 1e300;
-  hipEvent_t e0, e1;
-  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (!no_alloc && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)) {
+    if (e0) (void)hipEventDestroy(e0);
     return ctx->fail(PTHR_EHIP, "event creation failed");
+  }
+  // elapsed milliseconds of n_emcs EMCS on the scratch state
+  auto timed = [&](float* ms) -> int {
+    if (no_alloc) {
+      if (hipStreamSynchronize(s) != hipSuccess) return ctx->fail(PTHR_EHIP, "autotune synchronisation");
+      const auto a = std::chrono::steady_clock::now();
+      if (int rc = pthr_run(ctx, n_emcs, nullptr, stream)) return rc;
+      if (hipStreamSynchronize(s) != hipSuccess) return ctx->fail(PTHR_EHIP, "autotune synchronisation");
+      *ms = std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() - a).count();
+      return PTHR_OK;
+    }
+    if (hipEventRecord(e0, s) != hipSuccess) return ctx->fail(PTHR_EHIP, "autotune event");
+    if (int rc = pthr_run(ctx, n_emcs, nullptr, stream)) return rc;
+    if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+        hipEventElapsedTime(ms, e0, e1) != hipSuccess)
+      return ctx->fail(PTHR_EHIP, "autotune timing");
+    return PTHR_OK;
+  };
   int rc = PTHR_OK;
   for (int ch = 2; ch <= 8 && rc == PTHR_OK; ch *= 2) {
     if (!chunk_ok(ctx->p.precision, ctx->d.V, ch)) continue;
@@ -856,6 +892,7 @@ int pthr_autotune(pthr_ctx* ctx, void* d_scratch, int n_emcs, double* best_ms, v
       cand.threads_per_sample = threads_for(ctx->d.V, ch);
       cand.exp_early_out = early;
       cand.clone_split = split;
+      if (no_alloc) cand.graph_window = 0;
       ctx->sch = cand;
       hipError_t e = hipMemcpyAsync(d_scratch, real, ctx->lay.total, hipMemcpyDeviceToDevice, s);
       if (e != hipSuccess) {
@@ -871,28 +908,53 @@ int pthr_autotune(pthr_ctx* ctx, void* d_scratch, int n_emcs, double* best_ms, v
       rc = pthr_run(ctx, 1, nullptr, stream);
       for (int rep = 0; rep < 2 && rc == PTHR_OK; ++rep) {
         float rep_ms = 0.f;
-        if (hipEventRecord(e0, s) != hipSuccess) rc = ctx->fail(PTHR_EHIP, "autotune event");
-        if (rc == PTHR_OK) rc = pthr_run(ctx, n_emcs, nullptr, stream);
-        if (rc == PTHR_OK && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-                              hipEventElapsedTime(&rep_ms, e0, e1) != hipSuccess))
-          rc = ctx->fail(PTHR_EHIP, "autotune timing");
+        rc = timed(&rep_ms);
         if (rc == PTHR_OK && (rep == 0 || rep_ms < ms)) ms = rep_ms;
       }
       if (rc == PTHR_OK && ms < best_t) {
         best_t = ms;
         best = cand;
+        best.graph_window = saved.graph_window;
       }
       ctx->d_state = real;
     }
   }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
   ctx->d_state = real;
   ctx->t = t_saved;
   ctx->e_current = e_saved;
   ctx->sch = rc == PTHR_OK ? best : saved;
   if (best_ms) *best_ms = best_t / n_emcs;
   return rc;
+}
+}  // namespace
+
+extern "C" {
+
+int pthr_autotune(pthr_ctx* ctx, void* d_scratch, int n_emcs, double* best_ms, void* stream) {
+  if (!ctx) return PTHR_EINVAL;
+  ctx->err.clear();
+  if (int rc = ctx->need_ready()) return rc;
+  if (!d_scratch || n_emcs < 1) return ctx->fail(PTHR_EINVAL, "need a scratch buffer and n_emcs >= 1");
+  if (ctx->m_pt || ctx->m_er) return ctx->fail(PTHR_ESTATE, "an EMCS is in progress");
+  return autotune_impl(ctx, d_scratch, n_emcs, best_ms, stream, false);
+}
+
+int pthr_autotune_noalloc(pthr_ctx* ctx, int n_emcs, double* best_ms, void* stream) {
+  if (!ctx) return PTHR_EINVAL;
+  ctx->err.clear();
+  if (int rc = ctx->need_ready()) return rc;
+  if (n_emcs < 1) return ctx->fail(PTHR_EINVAL, "n_emcs must be >= 1");
+  if (ctx->m_pt || ctx->m_er) return ctx->fail(PTHR_ESTATE, "an EMCS is in progress");
+  if (ctx->lay.total > pthr::kScratchBytes)
+    return ctx->fail(PTHR_EINVAL, "state buffer of %zu bytes exceeds the %zu-byte static workspace (use pthr_autotune)",
+                     ctx->lay.total, pthr::kScratchBytes);
+  if (int rc = ctx->prepare()) return rc;  // the workspace address of the current device
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return ctx->fail(PTHR_EHIP, "get device");
+  void* ws = device_scratch()[dev];
+  return autotune_impl(ctx, ws, n_emcs, best_ms, stream, true);
 }
 
 }  // extern "C"

@@ -99,6 +99,12 @@ constexpr size_t kLdsMax = 160 * 1024;  // gfx950 LDS per workgroup
 constexpr int kMaxHouMoves = 16;        // Houdayer moves labelled at once, at most
 constexpr int kStatTop = 6;             // largest clusters reported per overlap sign
 
+// Static device workspace of pthr_autotune_noalloc: room for one state
+// buffer of up to this many bytes, on every device the library runs on.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+// Device address of that workspace on the current device.
+hipError_t scratch_address(void** ptr);
+
 size_t lds_bytes(const Geo& g, int fp_bytes);
 int houdayer_moves_per_pass(const Geo& g, int threads, bool stats);
 int measure_rows_per_pass(const Geo& g, int threads, int fp_bytes);

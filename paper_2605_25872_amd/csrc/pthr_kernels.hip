@@ -1959,6 +1959,14 @@ hipError_t launch_t(const Geo& g, const State& st, const Obs& ob, const Run& run
 
 }  // namespace
 
+// Workspace for the allocation-free autotuner: a copy of the state buffer on
+// which candidate schedules run trial EMCS.  Its name is only a host-side
+// stand-in for the device array: host code uses the address
+// scratch_address returns for the current device, never the name.
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+hipError_t scratch_address(void** ptr) { return hipGetSymbolAddress(ptr, HIP_SYMBOL(scratch)); }
+
 size_t lds_bytes(const Geo& g, int fp_bytes) {
   const size_t phases = plan_lds(g, fp_bytes).total, hou = hou_lds_bytes(g, 1, false);
   return phases > hou ? phases : hou;

@@ -30,7 +30,7 @@ EXPORTED = (
     "pthr_blob_bytes", "pthr_get_state", "pthr_set_state", "pthr_get_schedule",
     "pthr_set_schedule", "pthr_autotune", "pthr_lds_bytes", "pthr_group_create",
     "pthr_group_destroy", "pthr_group_last_error", "pthr_group_run", "pthr_cluster_stats",
-    "pthr_write_spins", "pthr_read_walkers",
+    "pthr_write_spins", "pthr_read_walkers", "pthr_autotune_noalloc",
 )
 
 
@@ -103,6 +103,7 @@ def library() -> ctypes.CDLL:
         "pthr_get_schedule": (i32, [vp, ctypes.POINTER(Schedule)]),
         "pthr_set_schedule": (i32, [vp, ctypes.POINTER(Schedule)]),
         "pthr_autotune": (i32, [vp, vp, i32, vp, vp]),
+        "pthr_autotune_noalloc": (i32, [vp, i32, vp, vp]),
         "pthr_group_create": (i32, [ctypes.POINTER(vp), i32, ctypes.POINTER(vp)]),
         "pthr_group_destroy": (i32, [vp]),
         "pthr_group_last_error": (ctypes.c_char_p, [vp]),
@@ -322,6 +323,13 @@ class Pthr:
         best = ctypes.c_double()
         self._check(self.lib.pthr_autotune(self.ctx, ctypes.c_void_p(scratch.data_ptr()), n_emcs,
                                            ctypes.byref(best), self._stream()))
+        return best.value
+
+    def autotune_noalloc(self, n_emcs: int = 2) -> float:
+        """pthr_autotune_noalloc: the same tuning with no device allocation (the
+        scratch state lives in the library's static workspace)."""
+        best = ctypes.c_double()
+        self._check(self.lib.pthr_autotune_noalloc(self.ctx, n_emcs, ctypes.byref(best), self._stream()))
         return best.value
 
 
