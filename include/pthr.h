@@ -227,15 +227,26 @@ typedef struct pthr_schedule {
                            exp first and evaluates the FP64 polynomial only when u lies within
                            2^-20 of it; 0 evaluates the polynomial for every test.  Both give the
                            same decisions. */
+  int32_t sample_split; /* sweeps: 1, 2 or 4 workgroups per sample, each taking every
+                           sample_split-th group of clones of every word (the clones per
+                           workgroup of the sweep); the default fills the compute units when a
+                           batch has fewer samples than the GPU has CUs */
 } pthr_schedule;
 int pthr_get_schedule(const pthr_ctx *ctx, pthr_schedule *out);
 int pthr_set_schedule(pthr_ctx *ctx, const pthr_schedule *sch);
-/* Times candidate schedules (work-items per sample, clone_split, early-out
- * off or below T = 0.7) with pthr_run on a scratch copy of the state
- * (d_scratch: pthr_state_bytes bytes, device): after one untimed EMCS, two
- * timed stretches of n_emcs EMCS each, the faster counting; keeps the
- * fastest candidate, restores nothing else.  best_ms (may be NULL) gets its time per EMCS. */
+/* Times candidate schedules (work-items per sample, clone_split, and for
+ * batches of fewer than two samples per compute unit sample_split; early-out
+ * off or below T = 0.7 on the unsplit shapes) with pthr_run on a scratch
+ * copy of the state (d_scratch: pthr_state_bytes bytes, device): after one
+ * untimed EMCS, two timed stretches of n_emcs EMCS each, the faster
+ * counting; keeps the fastest candidate (graph_window and exp_filter as
+ * they were), restores nothing else.  best_ms (may be NULL) gets its time
+ * per EMCS. */
 int pthr_autotune(pthr_ctx *ctx, void *d_scratch, int n_emcs, double *best_ms, void *stream);
+/* The candidates the last autotuning timed and their ms per EMCS, in the
+ * order tried (at most `capacity` of each written; NULL arrays skipped);
+ * returns the number of candidates. */
+int pthr_autotune_results(const pthr_ctx *ctx, pthr_schedule *schedules, double *ms_per_emcs, int capacity);
 /* pthr_autotune for callers that cannot allocate (inside stream capture,
  * serving loops, harnesses that forbid allocation): the same candidates and
  * choice, with the scratch copy of the state in a static device workspace of

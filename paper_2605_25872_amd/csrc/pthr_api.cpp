@@ -167,6 +167,7 @@ struct pthr_ctx {
   int K_acu = 0;
   std::vector<double> T;
   pthr_schedule sch{};
+  std::vector<std::pair<pthr_schedule, double>> tune;  // last autotuning: candidate, ms per EMCS
   std::string err;
   // captured EMCS window for pthr_run
   hipStream_t cap_stream = nullptr;
@@ -231,6 +232,7 @@ struct pthr_ctx {
     pthr::Shape sh{};
     sh.threads = sch.threads_per_sample;
     sh.split = sch.clone_split;
+    sh.parts = sch.sample_split;
     sh.chunk = 2;  // smallest chunk giving this many work-items (checked by set_schedule)
     while (threads_for(d.V, sh.chunk) != sch.threads_per_sample && sh.chunk < 8) sh.chunk *= 2;
     return sh;
@@ -409,6 +411,10 @@ int pthr_create(const pthr_params* p, pthr_ctx** out) {
   while (c->sch.clone_split < 4 && c->sch.threads_per_sample * c->sch.clone_split * 2 <= 1024 &&
          waves * c->sch.clone_split * 2 <= int64_t(n_cu) * 16)
     c->sch.clone_split *= 2;
+  // Fewer sample workgroups than compute units (one GPU's share of a sharded
+  // batch): the sweep takes 2 or 4 workgroups per sample.
+  c->sch.sample_split = 1;
+  while (c->sch.sample_split < 4 && int64_t(p->n_samples) * c->sch.sample_split < n_cu) c->sch.sample_split *= 2;
   *out = c;
   g_create_error.clear();
   return PTHR_OK;
@@ -839,6 +845,8 @@ int pthr_set_schedule(pthr_ctx* ctx, const pthr_schedule* sch) {
     return ctx->fail(PTHR_EINVAL, "clone_split must be 1, 2 or 4");
   if (sch->threads_per_sample * sch->clone_split > 1024)
     return ctx->fail(PTHR_EINVAL, "threads_per_sample * clone_split must be <= 1024");
+  if (sch->sample_split != 1 && sch->sample_split != 2 && sch->sample_split != 4)
+    return ctx->fail(PTHR_EINVAL, "sample_split must be 1, 2 or 4");
   ctx->sch = *sch;
   return PTHR_OK;
 }
@@ -880,44 +888,64 @@ int autotune_impl(pthr_ctx* ctx, void* d_scratch, int n_emcs, double* best_ms, v
       return ctx->fail(PTHR_EHIP, "autotune timing");
     return PTHR_OK;
   };
-  int rc = PTHR_OK;
-  for (int ch = 2; ch <= 8 && rc == PTHR_OK; ch *= 2) {
+  int n_cu = 256, dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) !=
+                                               hipSuccess)
+    n_cu = 256;
+  // Candidates: work-items per sample (chunk size) x waves per chunk
+  // (clone_split) x workgroups per sample (sample_split, tried for batches of
+  // fewer than two samples per compute unit), and the exp early-out below
+  // T = 0.7 on the plain shapes.
+  std::vector<pthr_schedule> cands;
+  for (int ch = 2; ch <= 8; ch *= 2) {
     if (!chunk_ok(ctx->p.precision, ctx->d.V, ch)) continue;
     if (ch > 2 && threads_for(ctx->d.V, ch) == threads_for(ctx->d.V, ch / 2)) continue;
-    for (int cand_i = 0; cand_i < 6; ++cand_i) {
-      if (rc != PTHR_OK) break;
-      const int early = cand_i % 2 ? 700 : 0, split = 1 << (cand_i / 2);
-      if (threads_for(ctx->d.V, ch) * split > 1024) continue;
-      pthr_schedule cand = saved;
-      cand.threads_per_sample = threads_for(ctx->d.V, ch);
-      cand.exp_early_out = early;
-      cand.clone_split = split;
-      if (no_alloc) cand.graph_window = 0;
-      ctx->sch = cand;
-      hipError_t e = hipMemcpyAsync(d_scratch, real, ctx->lay.total, hipMemcpyDeviceToDevice, s);
-      if (e != hipSuccess) {
-        rc = ctx->hip_fail(e, "autotune copy");
-        break;
-      }
-      ctx->d_state = static_cast<unsigned char*>(d_scratch);
-      ctx->t = t_saved;
-      float ms = 0.f;
-      // one untimed EMCS first (caches, clocks), then two timed stretches of
-      // n_emcs EMCS; the faster one counts (a single stretch varies with the
-      // clocks and with work on other streams)
-      rc = pthr_run(ctx, 1, nullptr, stream);
-      for (int rep = 0; rep < 2 && rc == PTHR_OK; ++rep) {
-        float rep_ms = 0.f;
-        rc = timed(&rep_ms);
-        if (rc == PTHR_OK && (rep == 0 || rep_ms < ms)) ms = rep_ms;
-      }
-      if (rc == PTHR_OK && ms < best_t) {
+    for (int split = 1; split <= 4; split *= 2)
+      for (int parts = 1; parts <= 4; parts *= 2)
+        for (int early = 0; early <= 700; early += 700) {
+          if (threads_for(ctx->d.V, ch) * split > 1024) continue;
+          if (parts > 1 && int64_t(ctx->p.n_samples) >= 2 * int64_t(n_cu)) continue;
+          if (early && (split > 1 || parts > 1)) continue;
+          pthr_schedule cand = saved;
+          cand.threads_per_sample = threads_for(ctx->d.V, ch);
+          cand.exp_early_out = early;
+          cand.clone_split = split;
+          cand.sample_split = parts;
+          cands.push_back(cand);
+        }
+  }
+  ctx->tune.clear();
+  int rc = PTHR_OK;
+  for (pthr_schedule cand : cands) {
+    if (rc != PTHR_OK) break;
+    if (no_alloc) cand.graph_window = 0;
+    ctx->sch = cand;
+    hipError_t e = hipMemcpyAsync(d_scratch, real, ctx->lay.total, hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) {
+      rc = ctx->hip_fail(e, "autotune copy");
+      break;
+    }
+    ctx->d_state = static_cast<unsigned char*>(d_scratch);
+    ctx->t = t_saved;
+    float ms = 0.f;
+    // one untimed EMCS first (caches, clocks), then two timed stretches of
+    // n_emcs EMCS; the faster one counts (a single stretch varies with the
+    // clocks and with work on other streams)
+    rc = pthr_run(ctx, 1, nullptr, stream);
+    for (int rep = 0; rep < 2 && rc == PTHR_OK; ++rep) {
+      float rep_ms = 0.f;
+      rc = timed(&rep_ms);
+      if (rc == PTHR_OK && (rep == 0 || rep_ms < ms)) ms = rep_ms;
+    }
+    if (rc == PTHR_OK) {
+      cand.graph_window = saved.graph_window;
+      ctx->tune.push_back({cand, static_cast<double>(ms) / n_emcs});
+      if (ms < best_t) {
         best_t = ms;
         best = cand;
-        best.graph_window = saved.graph_window;
       }
-      ctx->d_state = real;
     }
+    ctx->d_state = real;
   }
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);
@@ -939,6 +967,16 @@ int pthr_autotune(pthr_ctx* ctx, void* d_scratch, int n_emcs, double* best_ms, v
   if (!d_scratch || n_emcs < 1) return ctx->fail(PTHR_EINVAL, "need a scratch buffer and n_emcs >= 1");
   if (ctx->m_pt || ctx->m_er) return ctx->fail(PTHR_ESTATE, "an EMCS is in progress");
   return autotune_impl(ctx, d_scratch, n_emcs, best_ms, stream, false);
+}
+
+int pthr_autotune_results(const pthr_ctx* ctx, pthr_schedule* schedules, double* ms_per_emcs, int capacity) {
+  if (!ctx) return PTHR_EINVAL;
+  const int n = static_cast<int>(ctx->tune.size());
+  for (int i = 0; i < n && i < capacity; ++i) {
+    if (schedules) schedules[i] = ctx->tune[i].first;
+    if (ms_per_emcs) ms_per_emcs[i] = ctx->tune[i].second;
+  }
+  return n;
 }
 
 int pthr_autotune_noalloc(pthr_ctx* ctx, int n_emcs, double* best_ms, void* stream) {

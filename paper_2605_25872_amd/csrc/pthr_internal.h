@@ -84,6 +84,7 @@ struct Run {
   int meas_k;         // temperatures per pass of the row-parallel overlaps (0: per-site form)
   int e_current;      // measure: e_now holds the energies of the current configurations
   int clone_split;    // sweep: work-items per chunk of sites (set by the launcher)
+  int sample_split;   // sweep: workgroups per sample, each taking every sample_split-th clone group
 };
 
 // Device status bits (per sample).
@@ -93,6 +94,7 @@ struct Shape {
   int chunk;       // sites per work-item: 2, 4 or 8
   int threads;     // work-items per sample workgroup (multiple of 64, <= 1024)
   int split;       // sweep only: work-items sharing each chunk's clone words (1, 2 or 4)
+  int parts;       // sweep only: workgroups sharing each sample's clone words (1, 2 or 4)
 };
 
 constexpr size_t kLdsMax = 160 * 1024;  // gfx950 LDS per workgroup

@@ -831,11 +831,14 @@ __device__ __forceinline__ void update_word(const Geo& g, const FP* __restrict__
 template <typename FP, int CH, bool kSplit, bool kHB>
 __device__ __forceinline__ void sweep_phase(const Geo& g, const Lds& s, const FP* Js, const FP* __restrict__ bc,
                                             int sample, uint32_t t, int m_pt0, int n_pt, int m_er0, int n_er,
-                                            float early_beta, float beta_cold, int F) {
+                                            float early_beta, float beta_cold, int F, int part, int P) {
   // kSplit: F waves share each wave-sized block of site chunks, wave f of the
-  // F taking every F-th clone group (wave-uniform, so no divergence)
+  // F taking every F-th clone group (wave-uniform, so no divergence); with P
+  // workgroups per sample (part = this one's index) the groups are dealt
+  // over all P F waves of the sample, part + P f taking every (P F)-th.
   const int wv = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) / kWave);
-  const int f = kSplit ? wv % F : 0;
+  const int f = kSplit ? part + P * (wv % F) : 0;
+  const int FP_ = P * F;
   const Own<CH> own(g.V, kSplit ? (wv / F) * kWave + lane_id() : static_cast<int>(threadIdx.x));
   // Couplings of own sites in the form the field uses (SiteJ).  FP32 (and
   // FP64 with 2 sites per work-item) keeps both colours in registers for all
@@ -905,11 +908,11 @@ __device__ __forceinline__ void sweep_phase(const Geo& g, const Lds& s, const FP
             if (!kHB && early)
               update_word<FP, !kHB, kSplit, kHB>(g, bc, s.sp + size_t(w) * g.V, self_idx, nb, sj[slot][q],
                                                  c0 | static_cast<uint32_t>(st.i), t, sample, clone0, n0, nbits,
-                                                 early_bits, f, F);
+                                                 early_bits, f, FP_);
             else
               update_word<FP, false, kSplit, kHB>(g, bc, s.sp + size_t(w) * g.V, self_idx, nb, sj[slot][q],
                                                   c0 | static_cast<uint32_t>(st.i), t, sample, clone0, n0, nbits,
-                                                  early_bits, f, F);
+                                                  early_bits, f, FP_);
           };
           if (pt_on)
             for (int w = 0; w < g.NWPT; ++w) word(pt_early, w, c0pt, 32 * w, 32 * w, min(32, g.NPT - 32 * w));
@@ -1788,9 +1791,31 @@ size_t micsa_lds_bytes(const Geo& g) {
   return align_up(sizeof(uint32_t) * size_t(g.NWPT) * g.V, 16) + sizeof(int32_t) * size_t(g.NR * g.NT + g.NPT);
 }
 
+// With P workgroups per sample, part p holds the clone groups j (Philox
+// blocks counted from the word's first clone) with j % P == p: the bits
+// ((b / G) % P == p) of every word, G clones per block.  Its sweeps touch no
+// other bit, and no other part touches these, so each part merges its result
+// into the sample's words with an atomic XOR of its own changed bits (the
+// global word still holds this part's bits as loaded).
+template <typename FP>
+__device__ __forceinline__ void store_part(const Geo& g, const uint32_t* sp, const State& st, int sample, int part,
+                                           int P) {
+  constexpr int G = sizeof(FP) == 8 ? 2 : 4;
+  uint32_t mask = 0;
+  for (int b = 0; b < 32; ++b) mask |= ((b / G) % P == part) ? 1u << b : 0u;
+  uint32_t* gsp = st.spins + size_t(sample) * g.NW * g.V;
+  const int words = g.NW * g.V;
+  for (int x = threadIdx.x; x < words; x += blockDim.x) {
+    const uint32_t change = (sp[x] ^ gsp[x]) & mask;
+    if (change) atomicXor(&gsp[x], change);
+  }
+}
+
 template <typename FP, int CH, bool kSplit, bool kHB>
 __global__ __launch_bounds__(kMaxThreads) void sweep_kernel(Geo g, State st, Run run) {
-  const int sample = run.sample_begin + blockIdx.x;
+  const int P = run.sample_split;
+  const int sample = run.sample_begin + static_cast<int>(blockIdx.x) / P;
+  const int part = static_cast<int>(blockIdx.x) % P;
   if (sample >= g.S) return;  // the whole workgroup leaves together
   const Lds s = lds_view(g, sizeof(FP));
   load_spins(g, s, st, sample);
@@ -1801,8 +1826,13 @@ __global__ __launch_bounds__(kMaxThreads) void sweep_kernel(Geo g, State st, Run
   // beta of the coldest temperature in the units the clone table holds
   const float beta_cold = sizeof(FP) == 8 ? static_cast<float>(st.beta64[0]) : st.beta32[0];
   sweep_phase<FP, CH, kSplit, kHB>(g, s, Js, bc, sample, t, run.m_pt0, run.n_pt, run.m_er0, run.n_er,
-                                   run.early_beta, beta_cold, run.clone_split);
-  store_spins(g, s, st, sample);
+                                   run.early_beta, beta_cold, run.clone_split, part, P);
+  if (P == 1) {
+    store_spins(g, s, st, sample);
+  } else {
+    __syncthreads();  // every wave's flips are in LDS
+    store_part<FP>(g, s.sp, st, sample, part, P);
+  }
 }
 
 // Houdayer moves (or cluster labels) of one sample per workgroup; the LDS
@@ -1909,7 +1939,7 @@ hipError_t prepare_t(size_t lds) {
 
 template <typename FP, int CH>
 hipError_t launch_t(const Geo& g, const State& st, const Obs& ob, const Run& run, int threads, int split,
-                    int n_blocks, hipStream_t stream) {
+                    int parts, int n_blocks, hipStream_t stream) {
   const size_t lds = plan_lds(g, sizeof(FP)).total;
   hipError_t e = hipSuccess;
   if (run.phases & kPhaseSweep) {
@@ -1925,10 +1955,12 @@ hipError_t launch_t(const Geo& g, const State& st, const Obs& ob, const Run& run
       r.n_pt = 0;
     }
     if (r.n_pt > 0 || (r.n_er > 0 && g.NER > 0)) {
+      r.sample_split = parts;
+      const bool shared = split > 1 || parts > 1;  // clone words shared by several waves
       auto k = g.update == kHeatBath
-                   ? (split > 1 ? sweep_kernel<FP, CH, true, true> : sweep_kernel<FP, CH, false, true>)
-                   : (split > 1 ? sweep_kernel<FP, CH, true, false> : sweep_kernel<FP, CH, false, false>);
-      hipLaunchKernelGGL(k, dim3(n_blocks), dim3(threads * split), lds, stream, g, st, r);
+                   ? (shared ? sweep_kernel<FP, CH, true, true> : sweep_kernel<FP, CH, false, true>)
+                   : (shared ? sweep_kernel<FP, CH, true, false> : sweep_kernel<FP, CH, false, false>);
+      hipLaunchKernelGGL(k, dim3(n_blocks * parts), dim3(threads * split), lds, stream, g, st, r);
       if ((e = hipGetLastError()) != hipSuccess) return e;
     }
   }
@@ -1997,7 +2029,8 @@ int houdayer_moves_per_pass(const Geo& g, int threads, bool stats) {
 
 hipError_t launch_emcs(int precision, const Geo& g, const State& st, const Obs& ob, const Run& run,
                        const Shape& sh, int n_blocks, hipStream_t stream) {
-#define PTHR_LAUNCH(FP, CH) return launch_t<FP, CH>(g, st, ob, run, sh.threads, sh.split, n_blocks, stream)
+#define PTHR_LAUNCH(FP, CH) \
+  return launch_t<FP, CH>(g, st, ob, run, sh.threads, sh.split, sh.parts, n_blocks, stream)
   if (precision == 0) {
     switch (sh.chunk) {
       case 2: PTHR_LAUNCH(double, 2);

@@ -30,7 +30,7 @@ EXPORTED = (
     "pthr_blob_bytes", "pthr_get_state", "pthr_set_state", "pthr_get_schedule",
     "pthr_set_schedule", "pthr_autotune", "pthr_lds_bytes", "pthr_group_create",
     "pthr_group_destroy", "pthr_group_last_error", "pthr_group_run", "pthr_cluster_stats",
-    "pthr_write_spins", "pthr_read_walkers", "pthr_autotune_noalloc",
+    "pthr_write_spins", "pthr_read_walkers", "pthr_autotune_noalloc", "pthr_autotune_results",
 )
 
 
@@ -53,7 +53,8 @@ class Params(ctypes.Structure):
 class Schedule(ctypes.Structure):
     _fields_ = [("threads_per_sample", ctypes.c_int32), ("samples_per_launch", ctypes.c_int32),
                 ("exp_early_out", ctypes.c_int32), ("graph_window", ctypes.c_int32),
-                ("clone_split", ctypes.c_int32), ("exp_filter", ctypes.c_int32)]
+                ("clone_split", ctypes.c_int32), ("exp_filter", ctypes.c_int32),
+                ("sample_split", ctypes.c_int32)]
 
 
 _lib = None
@@ -104,6 +105,7 @@ def library() -> ctypes.CDLL:
         "pthr_set_schedule": (i32, [vp, ctypes.POINTER(Schedule)]),
         "pthr_autotune": (i32, [vp, vp, i32, vp, vp]),
         "pthr_autotune_noalloc": (i32, [vp, i32, vp, vp]),
+        "pthr_autotune_results": (i32, [vp, ctypes.POINTER(Schedule), vp, i32]),
         "pthr_group_create": (i32, [ctypes.POINTER(vp), i32, ctypes.POINTER(vp)]),
         "pthr_group_destroy": (i32, [vp]),
         "pthr_group_last_error": (ctypes.c_char_p, [vp]),
@@ -302,8 +304,10 @@ class Pthr:
         return sch
 
     def set_schedule(self, threads_per_sample=None, samples_per_launch=None, exp_early_out=None,
-                     graph_window=None, clone_split=None, exp_filter=None) -> None:
+                     graph_window=None, clone_split=None, exp_filter=None, sample_split=None) -> None:
         sch = self.schedule()
+        if sample_split is not None:
+            sch.sample_split = sample_split
         if exp_filter is not None:
             sch.exp_filter = int(exp_filter)
         if clone_split is not None:
@@ -324,6 +328,14 @@ class Pthr:
         self._check(self.lib.pthr_autotune(self.ctx, ctypes.c_void_p(scratch.data_ptr()), n_emcs,
                                            ctypes.byref(best), self._stream()))
         return best.value
+
+    def autotune_results(self) -> list[tuple[Schedule, float]]:
+        """(candidate schedule, ms per EMCS) of every candidate the last autotuning timed."""
+        n = self.lib.pthr_autotune_results(self.ctx, None, None, 0)
+        sch = (Schedule * max(n, 1))()
+        ms = np.zeros(max(n, 1), dtype=np.float64)
+        self.lib.pthr_autotune_results(self.ctx, sch, _np_ptr(ms), n)
+        return [(sch[i], float(ms[i])) for i in range(n)]
 
     def autotune_noalloc(self, n_emcs: int = 2) -> float:
         """pthr_autotune_noalloc: the same tuning with no device allocation (the

@@ -134,10 +134,16 @@ def test_l6_ragged_words_and_single_cluster(precision):
     16; 6 ER clones) and Houdayer's single-cluster mode."""
     step(f"l6 ragged single {precision}")
     o, g = make_pair(6, 3, 2, 7, 3, precision=precision, mode="single", er_sweeps=12, t_range=(0.2, 1.4))
-    assert g.schedule().clone_split == 4  # 128 work-items: the default shares clone words among 4 waves
+    sch = g.schedule()
+    assert sch.clone_split == 4  # 128 work-items: the default shares clone words among 4 waves
+    assert sch.sample_split == 4  # 3 samples: 4 workgroups per sample in the sweep
     stepwise(o, g, 2)
-    g.set_schedule(clone_split=2)
+    g.set_schedule(clone_split=2, sample_split=2)
     stepwise(o, g, 2)
+    g.set_schedule(clone_split=1, sample_split=1)
+    stepwise(o, g, 1)
+    g.set_schedule(clone_split=1, sample_split=4)
+    stepwise(o, g, 1)
 
 
 def test_l2_smallest_lattice_and_two_temperatures():
@@ -518,12 +524,14 @@ def test_every_schedule_gives_the_same_bits(precision):
     step(f"schedules {precision}")
     pthr = _pthr()
     ref = None
-    for threads, early, per, split, filt in ((256, 700, 0, 1, 1), (128, 100000, 0, 1, 1), (256, 0, 1, 1, 1),
-                                             (128, 1000, 2, 1, 1), (256, 0, 0, 4, 1), (128, 700, 0, 2, 1),
-                                             (128, 0, 2, 8 // 2, 1), (256, 0, 0, 1, 0), (128, 0, 0, 2, 0)):
+    for threads, early, per, split, filt, parts in (
+            (256, 700, 0, 1, 1, 1), (128, 100000, 0, 1, 1, 1), (256, 0, 1, 1, 1, 1), (128, 1000, 2, 1, 1, 1),
+            (256, 0, 0, 4, 1, 1), (128, 700, 0, 2, 1, 1), (128, 0, 2, 8 // 2, 1, 1), (256, 0, 0, 1, 0, 1),
+            (128, 0, 0, 2, 0, 1), (256, 0, 0, 1, 1, 2), (128, 0, 0, 2, 1, 4), (128, 700, 2, 1, 1, 2),
+            (256, 0, 0, 1, 0, 4), (128, 0, 1, 4, 0, 2)):
         _, g = make_pair(8, 3, 4, 10, 4, precision=precision, er_sweeps=20)
         g.set_schedule(threads_per_sample=threads, exp_early_out=early, samples_per_launch=per, clone_split=split,
-                       exp_filter=filt)
+                       exp_filter=filt, sample_split=parts)
         go = g.new_obs()
         g.run(2, go)
         got = (g.read_spins(), g.read_pt(), g.obs_arrays(go))
@@ -577,8 +585,8 @@ def test_heat_bath_schedules_and_tiles(precision):
     step(f"heat bath l8 schedules {precision}")
     o, g = make_pair(8, 3, 4, 10, 4, precision=precision, er_sweeps=20, update="heatbath")
     stepwise(o, g, 1)
-    for threads, split in ((128, 1), (256, 2), (128, 4)):
-        g.set_schedule(threads_per_sample=threads, clone_split=split)
+    for threads, split, parts in ((128, 1, 1), (256, 2, 1), (128, 4, 2), (256, 1, 4)):
+        g.set_schedule(threads_per_sample=threads, clone_split=split, sample_split=parts)
         stepwise(o, g, 1, check_each=False)
 
 
@@ -599,11 +607,26 @@ def test_checkpoint_resume_is_bit_identical():
         c.set_state(blob)
 
 
-def test_autotune_keeps_the_state_and_picks_a_valid_schedule():
+def test_autotune_picks_its_fastest_candidate_and_keeps_the_state():
+    """The autotuner times every candidate shape (work-items per sample,
+    waves per chunk, workgroups per sample for a small batch, early-out) and
+    keeps the fastest: its choice is the minimum of its own timing table, the
+    table holds only valid shapes and includes split samples, and the state
+    is untouched (the run that follows matches the oracle)."""
     step("autotune")
     o, g = make_pair(8, 4, 4, 10, 4, er_sweeps=20)
     ms = g.autotune(1)
     assert ms > 0
+    table = g.autotune_results()
+    assert len(table) >= 10
+    best_sch, best_ms = min(table, key=lambda c: c[1])
+    chosen = g.schedule()
+    assert abs(best_ms - ms) <= 1e-9 * ms
+    for f in ("threads_per_sample", "clone_split", "sample_split", "exp_early_out"):
+        assert getattr(chosen, f) == getattr(best_sch, f), f
+    assert {c.sample_split for c, _ in table} == {1, 2, 4}
+    for c, t in table:
+        assert t > 0 and c.threads_per_sample * c.clone_split <= 1024 and c.clone_split in (1, 2, 4)
     stepwise(o, g, 1, with_obs=False, check_each=False)
 
 
