@@ -946,12 +946,18 @@ __device__ __forceinline__ void sweep_phase(const Geo& g, const Lds& s, const FP
 struct HouLds {
   uint32_t* sp;    // [NWPT][V] spin words of the PT clones
   int32_t* cat;    // [NR][NT]
-  uint32_t* lab;   // [M][V] union-find parents (entries of run starts only)
+  uint32_t* lab;   // [M][Vp] union-find parents (entries of run starts only), padded site indices
   uint32_t* qrow;  // [M][L^2] overlap bits of every row
-  uint32_t* eta;   // [M][ceil(V/32)] ACU: the root drew eta = -1
+  uint32_t* eta;   // [M][ceil(Vp/32)] ACU: the root drew eta = -1
   int32_t* misc;   // [kHouMisc] scan scratch, per-move single-cluster data
-  uint32_t* size;  // cluster statistics only: [M][V] cluster size at its root
+  uint32_t* size;  // cluster statistics only: [M][Vp] cluster size at its root
 };
+// The union-find works on padded site indices: site x + L row is entry
+// x + (L + 1) row, so the rows of consecutive work-items start in different
+// LDS banks (their run starts are otherwise L words apart, a multiple of the
+// bank count for L = 16 or 32).  Padding keeps the order of sites, so the
+// smallest padded index of a cluster is that of its smallest site.
+__host__ __device__ inline int hou_vp(const Geo& g) { return g.L * g.L * (g.L + 1); }
 constexpr int kHouMisc = 32 + 3 * kMaxHouMoves + 7 * kMaxHouMoves;
 // misc layout: [0, 32) block scan; 32 + m: single-cluster first count of move m;
 // 32 + kMaxHouMoves: total; 33 + kMaxHouMoves + m: chosen root of move m;
@@ -966,11 +972,11 @@ __host__ __device__ inline size_t hou_lds_bytes(const Geo& g, int M, bool stats 
   size_t o = 0;
   o = align_up(o + sizeof(uint32_t) * size_t(g.NWPT) * g.V, 16);
   o = align_up(o + sizeof(int32_t) * size_t(g.NR) * g.NT, 16);
-  o = align_up(o + sizeof(uint32_t) * size_t(M) * g.V, 16);
+  o = align_up(o + sizeof(uint32_t) * size_t(M) * hou_vp(g), 16);
   o = align_up(o + sizeof(uint32_t) * size_t(M) * g.L * g.L, 16);
-  o = align_up(o + sizeof(uint32_t) * size_t(M) * ((g.V + 31) / 32), 16);
+  o = align_up(o + sizeof(uint32_t) * size_t(M) * ((hou_vp(g) + 31) / 32), 16);
   o = align_up(o + sizeof(int32_t) * kHouMisc, 16);
-  if (stats) o = align_up(o + sizeof(uint32_t) * size_t(M) * g.V, 16);
+  if (stats) o = align_up(o + sizeof(uint32_t) * size_t(M) * hou_vp(g), 16);
   return o;
 }
 __device__ __forceinline__ HouLds hou_view(const Geo& g, int M) {
@@ -981,11 +987,11 @@ __device__ __forceinline__ HouLds hou_view(const Geo& g, int M) {
   s.cat = reinterpret_cast<int32_t*>(lds_raw + o);
   o = align_up(o + sizeof(int32_t) * size_t(g.NR) * g.NT, 16);
   s.lab = reinterpret_cast<uint32_t*>(lds_raw + o);
-  o = align_up(o + sizeof(uint32_t) * size_t(M) * g.V, 16);
+  o = align_up(o + sizeof(uint32_t) * size_t(M) * hou_vp(g), 16);
   s.qrow = reinterpret_cast<uint32_t*>(lds_raw + o);
   o = align_up(o + sizeof(uint32_t) * size_t(M) * g.L * g.L, 16);
   s.eta = reinterpret_cast<uint32_t*>(lds_raw + o);
-  o = align_up(o + sizeof(uint32_t) * size_t(M) * ((g.V + 31) / 32), 16);
+  o = align_up(o + sizeof(uint32_t) * size_t(M) * ((hou_vp(g) + 31) / 32), 16);
   s.misc = reinterpret_cast<int32_t*>(lds_raw + o);
   o = align_up(o + sizeof(int32_t) * kHouMisc, 16);
   s.size = reinterpret_cast<uint32_t*>(lds_raw + o);  // valid only when laid out with stats
@@ -1044,7 +1050,7 @@ __device__ __forceinline__ uint32_t join_points(uint32_t q, uint32_t rs, uint32_
 // rounds as its busiest work-item, not the sum of three such maxima).
 __device__ __forceinline__ void join_row(const Geo& g, uint32_t* lab, uint32_t q, uint32_t rs, int row, uint32_t qy,
                                          int ry, uint32_t qz, int rz, uint32_t full, bool* bad) {
-  const int L = g.L;
+  const int L = g.L, Lp = g.L + 1;
   const uint32_t rsy = run_starts(qy, full), rsz = run_starts(qz, full);
   uint32_t uy = join_points(q, rs, qy, rsy, full), uz = join_points(q, rs, qz, rsz, full);
   const int xl = 31 - __builtin_clz(rs);
@@ -1052,22 +1058,31 @@ __device__ __forceinline__ void join_row(const Geo& g, uint32_t* lab, uint32_t q
   while (ux || (uy | uz)) {
     int a, b;
     if (ux) {
-      a = L * row;
-      b = L * row + xl;
+      a = Lp * row;
+      b = Lp * row + xl;
       ux = false;
     } else if (uy) {
       const int x = __builtin_ctz(uy);
       uy &= uy - 1u;
-      a = start_at(rs, x) + L * row;
-      b = start_at(rsy, x) + L * ry;
+      a = start_at(rs, x) + Lp * row;
+      b = start_at(rsy, x) + Lp * ry;
     } else {
       const int x = __builtin_ctz(uz);
       uz &= uz - 1u;
-      a = start_at(rs, x) + L * row;
-      b = start_at(rsz, x) + L * rz;
+      a = start_at(rs, x) + Lp * row;
+      b = start_at(rsz, x) + Lp * rz;
     }
-    unite(lab, a, b, g.V, bad);
+    unite(lab, a, b, hou_vp(g), bad);
   }
+}
+
+// Order in which a row visits the sites of its flip mask: from x = rot up,
+// wrapping around, with rot different for rows 8 apart.  The rows of one
+// wave keep their spin words L/2 apart, so rows 8 apart (L = 16) meet in the
+// same LDS bank whenever they flip the same x in the same step.
+__device__ __forceinline__ int flip_rotation(int row, int L) { return (2 * (row >> 3)) % L; }
+__device__ __forceinline__ uint32_t rotate_mask(uint32_t fl, int rot, int L, uint32_t full) {
+  return rot ? ((fl >> rot) | (fl << (L - rot))) & full : fl;
 }
 
 // Flips clones a and b at plane index j; several moves may touch one word at
@@ -1085,22 +1100,23 @@ __device__ __forceinline__ void flip_pair_atomic(const Geo& g, uint32_t* sp, int
 
 // Sizes of the kStatTop largest clusters of the majority (clusters whose
 // overlap sign is that of the whole lattice, q >= 0 counting as +1) and of the
-// minority, after the roots are final (lab of every run start = its root).
+// minority, after the roots are final (lab of every run start = its root);
+// ip0: the row's first entry in the padded union-find arrays.
 // Sizes accumulate at the roots; then kStatTop rounds each take the largest
 // remaining (size, smaller root) key per move and sign with LDS atomicMax.
 // out: [2][kStatTop] sizes, descending, 0 where there are fewer clusters.
 // Called by every work-item of the workgroup (it synchronizes).
 __device__ void cluster_stats(const Geo& g, const HouLds& s, bool active, int m, int M, uint32_t q, uint32_t rs,
-                              int i0, int32_t* out) {
-  const int L = g.L, V = g.V;
-  uint32_t* size = s.size + size_t(active ? m : 0) * V;
-  const uint32_t* lab = s.lab + size_t(active ? m : 0) * V;
+                              int ip0, int32_t* out) {
+  const int L = g.L, Vp = hou_vp(g);
+  uint32_t* size = s.size + size_t(active ? m : 0) * Vp;
+  const uint32_t* lab = s.lab + size_t(active ? m : 0) * Vp;
   if (active) {
     for (uint32_t r = rs; r; r &= r - 1u) {
       const int xs = __builtin_ctz(r);
       const uint32_t rest = r & (r - 1u);
       const int xe = rest ? __builtin_ctz(rest) : L;
-      atomicAdd(&size[lab[i0 + xs]], static_cast<uint32_t>(xe - xs));
+      atomicAdd(&size[lab[ip0 + xs]], static_cast<uint32_t>(xe - xs));
     }
     atomicAdd(&s.misc[kStatQ + m], L - 2 * __builtin_popcount(q));
   }
@@ -1114,7 +1130,7 @@ __device__ void cluster_stats(const Geo& g, const HouLds& s, bool active, int m,
       uint32_t best[2] = {0u, 0u};
       for (uint32_t r = rs; r; r &= r - 1u) {
         const int xs = __builtin_ctz(r);
-        const int i = i0 + xs;
+        const int i = ip0 + xs;
         if (static_cast<int>(lab[i]) != i || ((taken >> xs) & 1u)) continue;
         const uint32_t k = (size[i] << 16) | (0xFFFFu - static_cast<uint32_t>(i));
         const int sign = ((q >> xs) & 1u) == maj ? 0 : 1;
@@ -1126,18 +1142,18 @@ __device__ void cluster_stats(const Geo& g, const HouLds& s, bool active, int m,
     __syncthreads();
     if (active) {
       const uint32_t k0 = static_cast<uint32_t>(key[0]), k1 = static_cast<uint32_t>(key[1]);
-      if (i0 == 0) {
+      if (ip0 == 0) {
         out[round] = static_cast<int32_t>(k0 >> 16);
         out[kStatTop + round] = static_cast<int32_t>(k1 >> 16);
       }
       for (uint32_t r = rs; r; r &= r - 1u) {
         const int xs = __builtin_ctz(r);
-        const uint32_t tag = 0xFFFFu - static_cast<uint32_t>(i0 + xs);
+        const uint32_t tag = 0xFFFFu - static_cast<uint32_t>(ip0 + xs);
         if ((k0 && (k0 & 0xFFFFu) == tag) || (k1 && (k1 & 0xFFFFu) == tag)) taken |= 1u << xs;
       }
       // clear the buffer of round + 2 (last read in round - 1, before this barrier)
       int32_t* ahead = s.misc + kStatKey + 6 * m + 2 * ((round + 2) % 3);
-      if (i0 == 0) ahead[0] = ahead[1] = 0;
+      if (ip0 == 0) ahead[0] = ahead[1] = 0;
     }
   }
 }
@@ -1148,12 +1164,13 @@ __device__ void cluster_stats(const Geo& g, const HouLds& s, bool active, int m,
 __device__ bool houdayer_moves(const Geo& g, const HouLds& s, int M, int sample, uint32_t t, int32_t* labels,
                                int32_t* stats) {
   const bool flips = !labels && !stats;
-  const int L = g.L, L2 = L * L, V = g.V;
+  const int L = g.L, L2 = L * L, V = g.V, Vp = hou_vp(g);
   const uint32_t full = L == 32 ? 0xFFFFFFFFu : (1u << L) - 1u;
   const int n_moves = (g.NR / 2) * g.K_acu;
-  const int eta_words = (V + 31) / 32;
+  const int eta_words = (Vp + 31) / 32;
   const int m = threadIdx.x / L2, row = threadIdx.x % L2;
-  const int y = row % L, z = row / L, i0 = row * L;
+  // i0: the row's first site; ip0: its entry in the padded union-find arrays
+  const int y = row % L, z = row / L, i0 = row * L, ip0 = row * (L + 1);
   bool bad = false;
   for (int base = 0; base < n_moves; base += M) {
     const int mv = base + m;
@@ -1161,12 +1178,12 @@ __device__ bool houdayer_moves(const Geo& g, const HouLds& s, int M, int sample,
     const int p = active ? mv / g.K_acu : 0, k = active ? mv % g.K_acu : 0;
     const int a = s.cat[(2 * p) * g.NT + k], b = s.cat[(2 * p + 1) * g.NT + k];
     const uint32_t slot = static_cast<uint32_t>(p * g.NT + k);
-    uint32_t* lab = s.lab + size_t(active ? m : 0) * V;
+    uint32_t* lab = s.lab + size_t(active ? m : 0) * Vp;
     uint32_t* eta = s.eta + size_t(active ? m : 0) * eta_words;
     // overlap bits of the row; run starts become singleton roots
     for (int x = threadIdx.x; x < M * eta_words; x += blockDim.x) s.eta[x] = 0u;
     if (stats) {
-      for (int x = threadIdx.x; x < M * V; x += blockDim.x) s.size[x] = 0u;
+      for (int x = threadIdx.x; x < M * Vp; x += blockDim.x) s.size[x] = 0u;
       for (int x = threadIdx.x; x < M; x += blockDim.x) s.misc[kStatQ + x] = 0;
       for (int x = threadIdx.x; x < 6 * M; x += blockDim.x) s.misc[kStatKey + x] = 0;
     }
@@ -1176,8 +1193,8 @@ __device__ bool houdayer_moves(const Geo& g, const HouLds& s, int M, int sample,
       s.qrow[m * L2 + row] = q;
       rs = run_starts(q, full);
       for (uint32_t r = rs; r; r &= r - 1u) {
-        const int i = i0 + __builtin_ctz(r);
-        lab[i] = static_cast<uint32_t>(i);
+        const int ip = ip0 + __builtin_ctz(r);
+        lab[ip] = static_cast<uint32_t>(ip);
       }
     }
     __syncthreads();
@@ -1192,20 +1209,22 @@ __device__ bool houdayer_moves(const Geo& g, const HouLds& s, int M, int sample,
       uint32_t own_roots = 0;  // run starts that are the roots of their clusters
       for (uint32_t r = rs; r; r &= r - 1u) {
         const int x = __builtin_ctz(r);
-        const int root = find_root_readonly(lab, i0 + x);
-        lab[i0 + x] = static_cast<uint32_t>(root);
-        own_roots |= root == i0 + x ? 1u << x : 0u;
+        const int root = find_root_readonly(lab, ip0 + x);
+        lab[ip0 + x] = static_cast<uint32_t>(root);
+        own_roots |= root == ip0 + x ? 1u << x : 0u;
       }
+      // the coin of a root is keyed by its site index; eta by its padded entry
       if (flips && g.mode == 0)
         for (; own_roots; own_roots &= own_roots - 1u) {
-          const int i = i0 + __builtin_ctz(own_roots);
-          const Block blk = philox10(ctr_word(i, 0, kAcu), t, slot, sample, g.key0, g.key1);
-          if (blk.w0 >> 31) atomicOr(&eta[i >> 5], 1u << (i & 31));
+          const int x = __builtin_ctz(own_roots);
+          const Block blk = philox10(ctr_word(i0 + x, 0, kAcu), t, slot, sample, g.key0, g.key1);
+          const int ip = ip0 + x;
+          if (blk.w0 >> 31) atomicOr(&eta[ip >> 5], 1u << (ip & 31));
         }
     }
     if (stats) {
       __syncthreads();
-      cluster_stats(g, s, active, m, M, q, rs, i0,
+      cluster_stats(g, s, active, m, M, q, rs, ip0,
                     active ? stats + ((size_t(sample) * (g.NR / 2) + p) * g.K_acu + k) * 2 * kStatTop : nullptr);
     } else if (flips && g.mode != 0) {
       // single cluster: the q = -1 cluster of the target-th q = -1 site in
@@ -1228,7 +1247,7 @@ __device__ bool houdayer_moves(const Geo& g, const HouLds& s, int M, int sample,
             uint32_t bits = q;
             for (; rank > 0; --rank) bits &= bits - 1u;
             const int x = __builtin_ctz(bits);
-            s.misc[32 + kMaxHouMoves + 1 + m] = static_cast<int32_t>(lab[i0 + start_at(rs, x)]);
+            s.misc[32 + kMaxHouMoves + 1 + m] = static_cast<int32_t>(lab[ip0 + start_at(rs, x)]);
           }
         }
       }
@@ -1243,10 +1262,11 @@ __device__ bool houdayer_moves(const Geo& g, const HouLds& s, int M, int sample,
             const int xs = __builtin_ctz(r);
             const uint32_t rest = r & (r - 1u);
             const uint32_t run = (rest ? (rest & (0u - rest)) : (full + 1u)) - (1u << xs);  // bits xs .. xe-1
-            fl |= lab[i0 + xs] == root ? run : 0u;
+            fl |= lab[ip0 + xs] == root ? run : 0u;
           }
-          for (; fl; fl &= fl - 1u) {
-            const int x = __builtin_ctz(fl);
+          const int rot = flip_rotation(row, L);
+          for (fl = rotate_mask(fl, rot, L, full); fl; fl &= fl - 1u) {
+            const int xr = __builtin_ctz(fl) + rot, x = xr >= L ? xr - L : xr;
             flip_pair_atomic(g, s.sp, a, b, plane_idx(i0 + x, (x + y + z) & 1, g.Vh));
           }
         }
@@ -1256,20 +1276,24 @@ __device__ bool houdayer_moves(const Geo& g, const HouLds& s, int M, int sample,
       if (active) {
         if (labels) {
           int32_t* out = labels + ((size_t(sample) * (g.NR / 2) + p) * g.K_acu + k) * V;
-          for (int x = 0; x < L; ++x) out[i0 + x] = static_cast<int32_t>(lab[i0 + start_at(rs, x)]);
+          for (int x = 0; x < L; ++x) {
+            const int rp = static_cast<int>(lab[ip0 + start_at(rs, x)]);
+            out[i0 + x] = rp - rp / (L + 1);  // the root's site index
+          }
         } else {
           // all-cluster update: flip both replicas on clusters whose root drew
           // eta = -1; the row's sites to flip are gathered into one mask first
           uint32_t fl = 0;
           for (uint32_t r = rs; r; r &= r - 1u) {
             const int xs = __builtin_ctz(r);
-            const uint32_t root = lab[i0 + xs];
+            const uint32_t root = lab[ip0 + xs];
             const uint32_t rest = r & (r - 1u);
             const uint32_t run = (rest ? (rest & (0u - rest)) : (full + 1u)) - (1u << xs);  // bits xs .. xe-1
             fl |= (eta[root >> 5] >> (root & 31)) & 1u ? run : 0u;
           }
-          for (; fl; fl &= fl - 1u) {
-            const int x = __builtin_ctz(fl);
+          const int rot = flip_rotation(row, L);
+          for (fl = rotate_mask(fl, rot, L, full); fl; fl &= fl - 1u) {
+            const int xr = __builtin_ctz(fl) + rot, x = xr >= L ? xr - L : xr;
             flip_pair_atomic(g, s.sp, a, b, plane_idx(i0 + x, (x + y + z) & 1, g.Vh));
           }
         }
