@@ -161,7 +161,7 @@ def cpu_baseline(w, n_samples: int, mode: str, update: str = "metropolis") -> di
     o = oracle.Oracle(w.L, n_samples, w.n_replicas, w.n_temps, w.n_reservoir, w.sweeps_per_emcs,
                       w.er_sweeps_per_emcs, prec, oracle.SINGLE_NEG if mode == "single" else oracle.ACU,
                       w.t_acu, w.seed,
-                      local_update=oracle.HEAT_BATH if update == "heatbath" else oracle.METROPOLIS)
+                      local_update={"heatbath": oracle.HEAT_BATH, "micsa": oracle.MICSA}.get(update, oracle.METROPOLIS))
     o.init(w.couplings(n_samples), T)
     t0 = time.perf_counter()
     o.run(1)
@@ -324,8 +324,8 @@ def main() -> int:
                     help="'mixed': L = 8..16 side by side, one graph launch per EMCS")
     ap.add_argument("--mode", default="acu", choices=["acu", "single", "plain"],
                     help="Houdayer all-cluster (paper), single cluster, or plain PT (no Houdayer, no reservoir)")
-    ap.add_argument("--update", default="metropolis", choices=["metropolis", "heatbath"],
-                    help="local update: Metropolis (paper) or heat bath")
+    ap.add_argument("--update", default="metropolis", choices=["metropolis", "heatbath", "micsa"],
+                    help="local update of the PT clones: Metropolis (paper), heat bath, or MicSA (PTHR*)")
     ap.add_argument("--cpu-samples", type=int, default=192)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--compare-fp64-samples", type=int, default=16,
@@ -423,9 +423,19 @@ def main() -> int:
     # stream, HIP events around the sweep and Houdayer kernels (the sweep's
     # roofline is taken from these launches: the same kernel, launch shape and
     # data as in the graph).
+    micsa = args.update == "micsa"
+
     def step(ev):
-        ev[0].record(stream)
-        g.sweep(w.sweeps_per_emcs, n_er)
+        if micsa:
+            # PTHR*: MicSA on the PT clones (micsa_kernel), then Metropolis on
+            # the reservoir clones (sweep_kernel); the two classes are independent
+            ev[4].record(stream)
+            g.sweep(w.sweeps_per_emcs, 0)
+            ev[0].record(stream)
+            g.sweep(0, n_er)
+        else:
+            ev[0].record(stream)
+            g.sweep(w.sweeps_per_emcs, n_er)
         ev[1].record(stream)
         g.houdayer()
         ev[2].record(stream)
@@ -433,7 +443,7 @@ def main() -> int:
         g.measure(obs)
         ev[3].record(stream)
 
-    evs = [tuple(torch.cuda.Event(enable_timing=True) for _ in range(4)) for _ in range(args.steps)]
+    evs = [tuple(torch.cuda.Event(enable_timing=True) for _ in range(5)) for _ in range(args.steps)]
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     for ev in evs:
@@ -442,13 +452,19 @@ def main() -> int:
     eager_elapsed = time.perf_counter() - t1
     g.check()
     sweep_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in evs]))
+    micsa_ms = float(np.mean([e[4].elapsed_time(e[0]) for e in evs])) if micsa else None
     houdayer_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in evs]))
     pt_measure_ms = float(np.mean([e[2].elapsed_time(e[3]) for e in evs]))
     log(f"eager per-phase EMCS: {att * args.steps / (eager_elapsed * 1e9):.1f} attempts/ns; "
         f"sweep kernel {sweep_ms:.2f} ms, Houdayer {houdayer_ms:.3f} ms, PT + observables {pt_measure_ms:.3f} ms")
 
-    peak_ops, ops_per_attempt = valu_peak(args.update, w.precision)
-    ops = ops_per_attempt * att
+    # the roofline of the Metropolis sweep kernel: all attempts, or with MicSA
+    # the reservoir clones' (the PT clones' MicSA kernel is reported beside it)
+    rule = "metropolis" if micsa else args.update
+    peak_ops, ops_per_attempt = valu_peak(rule, w.precision)
+    pt_att = float(w.V * w.sweeps_per_emcs * w.n_replicas * w.n_temps) * w.n_samples
+    sweep_att = att - pt_att if micsa else att
+    ops = ops_per_attempt * sweep_att
     achieved = ops / (sweep_ms * 1e-3)
     out = {
         "metric": METRIC,
@@ -488,9 +504,14 @@ def main() -> int:
                      "traffic": sweep_traffic_bytes(w.name) if args.update == "metropolis" else None,
                      "traffic_unit": "HBM bytes per launch",
                      "ops_per_attempt": ops_per_attempt,
-                     "ops_by_issue_class": OPS_BY_CLASS[(args.update, w.precision)],
+                     "ops_by_issue_class": OPS_BY_CLASS[(rule, w.precision)],
+                     "attempts_per_launch": sweep_att,
                      "sweep_ms_per_launch": sweep_ms},
     }
+    if micsa:
+        out["micsa_kernel"] = {"ms_per_launch": micsa_ms, "attempts_per_launch": pt_att,
+                               "attempts_per_ns": pt_att / (micsa_ms * 1e6)}
+        log(f"micsa kernel {micsa_ms:.2f} ms per launch: {pt_att / (micsa_ms * 1e6):.1f} attempts/ns")
 
     if args.shard_samples > 0 and args.shard_samples < w.n_samples:
         # One GPU's share of the batch sharded over 8 GPUs (samples are

@@ -1743,22 +1743,34 @@ __device__ __forceinline__ double log_unit64(double u) {
 // index, then colour 1); the lanes of one 32-clone word take the same site
 // at the same time and their flips enter the word through one ballot.  A
 // wave's 64 clones fill whole words that no other wave touches, so the
-// waves run without barriers.  dE is summed as the Metropolis sweep sums it:
-// terms J_d s_i s_j in the order ((+x, -x) + (+y, -y)) + (+z, -z), doubled.
-template <typename FP>
+// waves run without barriers.  Sites of one colour are not neighbours, so
+// within a half-sweep dE of a site does not depend on the decisions before
+// it: the dE of up to 8 sites of a row are formed side by side (independent
+// loads and adds), and only the walker's compare-and-subtract runs in
+// sequence.  dE is summed as the Metropolis sweep sums it: terms J_d s_i s_j
+// in the order ((+x, -x) + (+y, -y)) + (+z, -z), doubled.  kJLds: the
+// sample's couplings are staged in LDS (when they fit beside the spins).
+constexpr int kMicsaBatch = 8;
+template <typename FP, bool kJLds>
 __global__ __launch_bounds__(kMaxThreads) void micsa_kernel(Geo g, State st, Run run) {
   const int sample = run.sample_begin + blockIdx.x;
   if (sample >= g.S) return;
   uint32_t* sp = reinterpret_cast<uint32_t*>(lds_raw);  // [NWPT][V]
-  int32_t* cat = reinterpret_cast<int32_t*>(lds_raw + align_up(sizeof(uint32_t) * size_t(g.NWPT) * g.V, 16));
-  int32_t* kof = cat + g.NR * g.NT;  // [NPT] temperature index of every clone
+  size_t o = align_up(sizeof(uint32_t) * size_t(g.NWPT) * g.V, 16);
+  int32_t* cat = reinterpret_cast<int32_t*>(lds_raw + o);  // [NR][NT]
+  int32_t* kof = cat + g.NR * g.NT;                         // [NPT] temperature index of every clone
+  o = align_up(o + sizeof(int32_t) * size_t(g.NR * g.NT + g.NPT), 16);
+  const FP* Jg = static_cast<const FP*>(st.J) + size_t(sample) * 3 * g.V;
+  FP* Jl = reinterpret_cast<FP*>(lds_raw + o);  // [3][V] when kJLds
   load_spins(g, sp, cat, st, sample, g.NWPT);
+  if constexpr (kJLds)
+    for (int x = threadIdx.x; x < 3 * g.V; x += blockDim.x) Jl[x] = Jg[x];
   __syncthreads();
   for (int x = threadIdx.x; x < g.NPT; x += blockDim.x) kof[cat[x]] = x % g.NT;
   __syncthreads();
-  const FP* Js = static_cast<const FP*>(st.J) + size_t(sample) * 3 * g.V;
+  const FP* Js = kJLds ? Jl : Jg;
   const uint32_t t = *st.t_dev;
-  const int L = g.L, L2 = L * L, V = g.V;
+  const int L = g.L, L2 = L * L, V = g.V, half = L / 2;
   const int lane = lane_id();
   // blockDim.x is a multiple of 64, so all lanes of a wave take the same trips
   for (int base = 0; base < g.NPT; base += blockDim.x) {
@@ -1782,25 +1794,44 @@ __global__ __launch_bounds__(kMaxThreads) void micsa_kernel(Geo g, State st, Run
       for (int colour = 0; colour < 2; ++colour) {
         for (int row = 0; row < L2; ++row) {
           const int y = row % L, z = row / L;
-          for (int x = (y + z + colour) & 1; x < L; x += 2) {
-            const Site si{row * L + x, x, y, z};
-            const int j = colour * g.Vh + (si.i >> 1);
-            const uint32_t own = (plane[j] >> bit) & 1u;
-            FP term[6];
+          const int x0 = (y + z + colour) & 1;
+          for (int s0 = 0; s0 < half; s0 += kMicsaBatch) {
+            FP dE[kMicsaBatch];
 #pragma unroll
-            for (int d = 0; d < 6; ++d) {
-              const int n = neighbour(si, d, L);
-              const FP Jd = Js[size_t(d >> 1) * V + ((d & 1) ? n : si.i)];
-              const uint32_t nbit = (plane[(colour ^ 1) * g.Vh + (n >> 1)] >> bit) & 1u;
-              term[d] = (own ^ nbit) ? -Jd : Jd;  // J_d s_i s_j
+            for (int k = 0; k < kMicsaBatch; ++k) {
+              const int x = x0 + 2 * (s0 + k);
+              dE[k] = FP(0);
+              if (s0 + k < half) {
+                const Site si{row * L + x, x, y, z};
+                const uint32_t own = (plane[colour * g.Vh + (si.i >> 1)] >> bit) & 1u;
+                FP term[6];
+#pragma unroll
+                for (int d = 0; d < 6; ++d) {
+                  const int n = neighbour(si, d, L);
+                  const FP Jd = Js[size_t(d >> 1) * V + ((d & 1) ? n : si.i)];
+                  const uint32_t nbit = (plane[(colour ^ 1) * g.Vh + (n >> 1)] >> bit) & 1u;
+                  term[d] = (own ^ nbit) ? -Jd : Jd;  // J_d s_i s_j
+                }
+                dE[k] = FP(2) * (((term[0] + term[1]) + (term[2] + term[3])) + (term[4] + term[5]));
+              }
             }
-            const FP dE = FP(2) * (((term[0] + term[1]) + (term[2] + term[3])) + (term[4] + term[5]));
-            const bool acc = active && W >= dE;
-            if (acc) W = W - dE;
-            const uint64_t flips = __builtin_amdgcn_ballot_w64(acc);
-            const uint32_t lo = static_cast<uint32_t>(flips), hi = static_cast<uint32_t>(flips >> 32);
-            if (lane == 0 && lo) sp[size_t(w_lo) * V + j] ^= lo;
-            if (lane == 32 && hi) sp[size_t(w_lo + 1) * V + j] ^= hi;
+            // the walker, site after site
+            uint32_t acc = 0;
+#pragma unroll
+            for (int k = 0; k < kMicsaBatch; ++k) {
+              const bool a = s0 + k < half && active && W >= dE[k];
+              if (a) W = W - dE[k];
+              acc |= static_cast<uint32_t>(a) << k;
+            }
+#pragma unroll
+            for (int k = 0; k < kMicsaBatch; ++k) {
+              if (s0 + k >= half) break;
+              const uint64_t flips = __builtin_amdgcn_ballot_w64((acc >> k) & 1u);
+              const uint32_t lo = static_cast<uint32_t>(flips), hi = static_cast<uint32_t>(flips >> 32);
+              const int j = colour * g.Vh + ((row * L + x0 + 2 * (s0 + k)) >> 1);
+              if (lane == 0 && lo) sp[size_t(w_lo) * V + j] ^= lo;
+              if (lane == 32 && hi) sp[size_t(w_lo + 1) * V + j] ^= hi;
+            }
           }
         }
       }
@@ -1811,8 +1842,201 @@ __global__ __launch_bounds__(kMaxThreads) void micsa_kernel(Geo g, State st, Run
   store_spins(g, sp, st, sample, g.NWPT);
 }
 
-size_t micsa_lds_bytes(const Geo& g) {
-  return align_up(sizeof(uint32_t) * size_t(g.NWPT) * g.V, 16) + sizeof(int32_t) * size_t(g.NR * g.NT + g.NPT);
+// Row-wise MicSA for L = 2H, 2 <= H <= 8, couplings in LDS.  The same
+// sweep, walker and sums as micsa_kernel, reorganised around the lattice
+// rows (fixed y, z) of one colour: the couplings are staged in checkerboard
+// order (J_d of site i at d V + colour(i) V/2 + i/2, as the spin words), so
+// that a row's own words, the other colour's words of the same row and of
+// the rows at y -+ 1 and z -+ 1, and the six coupling rows it needs are
+// twelve contiguous vectors of H values, read with 8- or 16-byte LDS loads.
+// Within a row x = x0 + 2k; its +x neighbour is the other colour's word
+// k + x0 and its -x neighbour (and coupling) word k + x0 - 1, both modulo H.
+// Each coupling takes the sign of the neighbour spin (bit 31 of the word
+// shifted left by 31 - bit is 1 for a down spin) and the sum of the six takes
+// the sign of the updated spin: negation is exact and (-a) + (-b) = -(a + b)
+// under round-to-nearest, so dE equals micsa_kernel's sum of the products
+// J s_i s_j in the same order bit for bit (a zero dE can differ in its sign,
+// which neither W >= dE nor W - dE can tell).  The flips of a site enter the
+// row's own words in registers; each row is written back once.
+constexpr int kMicsaRowThreads = 512;
+
+template <int N>
+__device__ __forceinline__ void lds_words(const uint32_t* p, uint32_t (&v)[N]) {
+  if constexpr (N % 4 == 0) {
+#pragma unroll
+    for (int j = 0; j < N / 4; ++j) {
+      const uint4 q = reinterpret_cast<const uint4*>(p)[j];
+      v[4 * j] = q.x, v[4 * j + 1] = q.y, v[4 * j + 2] = q.z, v[4 * j + 3] = q.w;
+    }
+  } else if constexpr (N % 2 == 0) {
+#pragma unroll
+    for (int j = 0; j < N / 2; ++j) {
+      const uint2 q = reinterpret_cast<const uint2*>(p)[j];
+      v[2 * j] = q.x, v[2 * j + 1] = q.y;
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < N; ++j) v[j] = p[j];
+  }
+}
+template <int N>
+__device__ __forceinline__ void lds_store_words(uint32_t* p, const uint32_t (&v)[N]) {
+  if constexpr (N % 4 == 0) {
+#pragma unroll
+    for (int j = 0; j < N / 4; ++j) reinterpret_cast<uint4*>(p)[j] = make_uint4(v[4 * j], v[4 * j + 1], v[4 * j + 2], v[4 * j + 3]);
+  } else if constexpr (N % 2 == 0) {
+#pragma unroll
+    for (int j = 0; j < N / 2; ++j) reinterpret_cast<uint2*>(p)[j] = make_uint2(v[2 * j], v[2 * j + 1]);
+  } else {
+#pragma unroll
+    for (int j = 0; j < N; ++j) p[j] = v[j];
+  }
+}
+template <int H>
+__device__ __forceinline__ void lds_row(const float* p, float (&v)[H]) {
+  uint32_t w[H];
+  lds_words<H>(reinterpret_cast<const uint32_t*>(p), w);
+#pragma unroll
+  for (int k = 0; k < H; ++k) v[k] = __uint_as_float(w[k]);
+}
+template <int H>
+__device__ __forceinline__ void lds_row(const double* p, double (&v)[H]) {
+  uint32_t w[2 * H];
+  lds_words<2 * H>(reinterpret_cast<const uint32_t*>(p), w);
+#pragma unroll
+  for (int k = 0; k < H; ++k)
+    v[k] = __longlong_as_double(static_cast<long long>((static_cast<unsigned long long>(w[2 * k + 1]) << 32) | w[2 * k]));
+}
+// J with its sign flipped where bit 31 of s is set (s has no other bit set).
+__device__ __forceinline__ float flip31(float J, uint32_t s) { return __uint_as_float(__float_as_uint(J) ^ s); }
+__device__ __forceinline__ double flip31(double J, uint32_t s) {
+  return __longlong_as_double(
+      static_cast<long long>(static_cast<unsigned long long>(__double_as_longlong(J)) ^ (static_cast<unsigned long long>(s) << 32)));
+}
+
+// One row of one colour: the pointers address the row's first word (or
+// coupling) in each of the twelve vectors; own is read from Pc and, if
+// write, written back there.
+template <typename FP, int H, int X0>
+__device__ __forceinline__ void micsa_row(const uint32_t* Pc, const uint32_t* Px, const uint32_t* Pyp,
+                                          const uint32_t* Pym, const uint32_t* Pzp, const uint32_t* Pzm, const FP* Jxp,
+                                          const FP* Jxm, const FP* Jyp, const FP* Jym, const FP* Jzp, const FP* Jzm,
+                                          uint32_t* Pw, int sh, int hi_shift, bool active, bool write, FP& W) {
+  constexpr uint32_t kSign = 0x80000000u;
+  uint32_t own[H], xo[H], yp[H], ym[H], zp[H], zm[H];
+  FP jxp[H], jxm[H], jyp[H], jym[H], jzp[H], jzm[H];
+  lds_words<H>(Pc, own);
+  lds_words<H>(Px, xo);
+  lds_words<H>(Pyp, yp);
+  lds_words<H>(Pym, ym);
+  lds_words<H>(Pzp, zp);
+  lds_words<H>(Pzm, zm);
+  lds_row<H>(Jxp, jxp);
+  lds_row<H>(Jxm, jxm);
+  lds_row<H>(Jyp, jyp);
+  lds_row<H>(Jym, jym);
+  lds_row<H>(Jzp, jzp);
+  lds_row<H>(Jzm, jzm);
+  FP dE[H];
+#pragma unroll
+  for (int k = 0; k < H; ++k) {
+    const int kp = (k + X0) % H, km = (k + X0 + H - 1) % H;
+    const FP u0 = flip31(jxp[k], (xo[kp] << sh) & kSign);
+    const FP u1 = flip31(jxm[km], (xo[km] << sh) & kSign);
+    const FP u2 = flip31(jyp[k], (yp[k] << sh) & kSign);
+    const FP u3 = flip31(jym[k], (ym[k] << sh) & kSign);
+    const FP u4 = flip31(jzp[k], (zp[k] << sh) & kSign);
+    const FP u5 = flip31(jzm[k], (zm[k] << sh) & kSign);
+    dE[k] = FP(2) * flip31(((u0 + u1) + (u2 + u3)) + (u4 + u5), (own[k] << sh) & kSign);
+  }
+  // the walker, site after site
+#pragma unroll
+  for (int k = 0; k < H; ++k) {
+    const bool a = active && W >= dE[k];
+    if (a) W = W - dE[k];
+    own[k] ^= static_cast<uint32_t>(__builtin_amdgcn_ballot_w64(a) >> hi_shift);
+  }
+  if (write) lds_store_words<H>(Pw, own);
+}
+
+template <typename FP, int H>
+__global__ __launch_bounds__(kMicsaRowThreads) void micsa_row_kernel(Geo g, State st, Run run) {
+  constexpr int L = 2 * H, L2 = L * L, V = L2 * L, Vh = V / 2;
+  const int sample = run.sample_begin + blockIdx.x;
+  if (sample >= g.S) return;
+  uint32_t* sp = reinterpret_cast<uint32_t*>(lds_raw);  // [NWPT][V]
+  size_t o = align_up(sizeof(uint32_t) * size_t(g.NWPT) * V, 16);
+  int32_t* cat = reinterpret_cast<int32_t*>(lds_raw + o);  // [NR][NT]
+  int32_t* kof = cat + g.NR * g.NT;                         // [NPT] temperature index of every clone
+  o = align_up(o + sizeof(int32_t) * size_t(g.NR * g.NT + g.NPT), 16);
+  FP* Jc = reinterpret_cast<FP*>(lds_raw + o);  // [3][V], checkerboard order
+  load_spins(g, sp, cat, st, sample, g.NWPT);
+  const FP* Jg = static_cast<const FP*>(st.J) + size_t(sample) * 3 * V;
+  for (int x = threadIdx.x; x < 3 * V; x += blockDim.x) {
+    const int d = x / V, i = x - d * V;
+    const Site s = site_of(i, L);
+    Jc[d * V + plane_idx(i, colour_of(s), Vh)] = Jg[x];
+  }
+  __syncthreads();
+  for (int x = threadIdx.x; x < g.NPT; x += blockDim.x) kof[cat[x]] = x % g.NT;
+  __syncthreads();
+  const uint32_t t = *st.t_dev;
+  const int lane = lane_id();
+  const int sh = 31 - (lane & 31), hi_shift = lane & 32;
+  // blockDim.x is a multiple of 64, so all lanes of a wave take the same trips
+  for (int base = 0; base < g.NPT; base += blockDim.x) {
+    const int c = base + static_cast<int>(threadIdx.x);
+    const bool active = c < g.NPT;
+    const int word = c >> 5;              // this lane's 32-clone word
+    const bool write = word < g.NWPT;     // lanes past the last PT word read word base/32 and write nothing
+    const uint32_t* P = sp + size_t(write ? word : base >> 5) * V;
+    uint32_t* Pw = sp + size_t(write ? word : base >> 5) * V;
+    const int cw = active ? c : base;
+    const double Tk = st.T64[kof[cw]];
+    double* wslot = st.walker + size_t(sample) * g.NPT + cw;
+    FP W = static_cast<FP>(*wslot);
+    for (int mm = 0; mm < run.n_pt; ++mm) {
+      const int m = run.m_pt0 + mm;
+      if (m % g.micsa_refresh == 0) {
+        const Block blk = philox10(ctr_word(0, static_cast<uint32_t>(m), kWalker), t, static_cast<uint32_t>(cw),
+                                   static_cast<uint32_t>(sample), g.key0, g.key1);
+        const uint64_t b53 = ((static_cast<uint64_t>(blk.w1) << 32) | blk.w0) >> 11;
+        W = static_cast<FP>(Tk * -log_unit64(static_cast<double>(b53 + 1) * 0x1p-53));
+      }
+      for (int colour = 0; colour < 2; ++colour) {
+        const int oc = (colour ^ 1) * Vh, cc = colour * Vh;
+        for (int z = 0; z < L; ++z) {
+          const int zp = z + 1 < L ? z + 1 : 0, zm = z > 0 ? z - 1 : L - 1;
+          for (int y = 0; y < L; ++y) {
+            const int yp = y + 1 < L ? y + 1 : 0, ym = y > 0 ? y - 1 : L - 1;
+            const int row = (y + z * L) * H, ryp = (yp + z * L) * H, rym = (ym + z * L) * H;
+            const int rzp = (y + zp * L) * H, rzm = (y + zm * L) * H;
+            if ((y + z + colour) & 1)
+              micsa_row<FP, H, 1>(P + cc + row, P + oc + row, P + oc + ryp, P + oc + rym, P + oc + rzp, P + oc + rzm,
+                                  Jc + cc + row, Jc + oc + row, Jc + V + cc + row, Jc + V + oc + rym,
+                                  Jc + 2 * V + cc + row, Jc + 2 * V + oc + rzm, Pw + cc + row, sh, hi_shift, active,
+                                  write, W);
+            else
+              micsa_row<FP, H, 0>(P + cc + row, P + oc + row, P + oc + ryp, P + oc + rym, P + oc + rzp, P + oc + rzm,
+                                  Jc + cc + row, Jc + oc + row, Jc + V + cc + row, Jc + V + oc + rym,
+                                  Jc + 2 * V + cc + row, Jc + 2 * V + oc + rzm, Pw + cc + row, sh, hi_shift, active,
+                                  write, W);
+          }
+        }
+      }
+    }
+    if (active) *wslot = static_cast<double>(W);
+  }
+  __syncthreads();
+  store_spins(g, sp, st, sample, g.NWPT);
+}
+
+// LDS of the MicSA kernel: spins and permutation, plus the couplings when
+// with_j.
+size_t micsa_lds_bytes(const Geo& g, int fp_bytes, bool with_j) {
+  const size_t base = align_up(align_up(sizeof(uint32_t) * size_t(g.NWPT) * g.V, 16) +
+                                   sizeof(int32_t) * size_t(g.NR * g.NT + g.NPT), 16);
+  return base + (with_j ? size_t(fp_bytes) * 3 * g.V : 0);
 }
 
 // With P workgroups per sample, part p holds the clone groups j (Philox
@@ -1956,7 +2180,15 @@ hipError_t prepare_t(size_t lds) {
   if ((e = set_lds(sweep_kernel<FP, CH, false, true>, lds)) != hipSuccess) return e;
   if ((e = set_lds(sweep_kernel<FP, CH, true, true>, lds)) != hipSuccess) return e;
   if ((e = set_lds(houdayer_kernel, lds)) != hipSuccess) return e;
-  if ((e = set_lds(micsa_kernel<FP>, lds)) != hipSuccess) return e;
+  if ((e = set_lds(micsa_kernel<FP, true>, lds)) != hipSuccess) return e;
+  if ((e = set_lds(micsa_kernel<FP, false>, lds)) != hipSuccess) return e;
+  if ((e = set_lds(micsa_row_kernel<FP, 2>, lds)) != hipSuccess) return e;
+  if ((e = set_lds(micsa_row_kernel<FP, 3>, lds)) != hipSuccess) return e;
+  if ((e = set_lds(micsa_row_kernel<FP, 4>, lds)) != hipSuccess) return e;
+  if ((e = set_lds(micsa_row_kernel<FP, 5>, lds)) != hipSuccess) return e;
+  if ((e = set_lds(micsa_row_kernel<FP, 6>, lds)) != hipSuccess) return e;
+  if ((e = set_lds(micsa_row_kernel<FP, 7>, lds)) != hipSuccess) return e;
+  if ((e = set_lds(micsa_row_kernel<FP, 8>, lds)) != hipSuccess) return e;
   if ((e = set_lds(pt_kernel<FP, CH>, lds)) != hipSuccess) return e;
   return set_lds(measure_kernel<FP, CH>, lds);
 }
@@ -1973,7 +2205,23 @@ hipError_t launch_t(const Geo& g, const State& st, const Obs& ob, const Run& run
       // MicSA on the PT clones (one lane per clone), Metropolis on the reservoir
       if (r.n_pt > 0) {
         const int mt = g.NPT >= kMaxThreads ? kMaxThreads : (g.NPT + kWave - 1) / kWave * kWave;
-        hipLaunchKernelGGL(micsa_kernel<FP>, dim3(n_blocks), dim3(mt), micsa_lds_bytes(g), stream, g, st, r);
+        const bool jl = micsa_lds_bytes(g, sizeof(FP), true) <= kLdsMax;
+        auto mk = jl ? micsa_kernel<FP, true> : micsa_kernel<FP, false>;
+        int bt = mt;
+        if (jl && g.L >= 4 && g.L <= 16) {
+          // the row-wise form (same result)
+          bt = mt < kMicsaRowThreads ? mt : kMicsaRowThreads;
+          switch (g.L / 2) {
+            case 2: mk = micsa_row_kernel<FP, 2>; break;
+            case 3: mk = micsa_row_kernel<FP, 3>; break;
+            case 4: mk = micsa_row_kernel<FP, 4>; break;
+            case 5: mk = micsa_row_kernel<FP, 5>; break;
+            case 6: mk = micsa_row_kernel<FP, 6>; break;
+            case 7: mk = micsa_row_kernel<FP, 7>; break;
+            default: mk = micsa_row_kernel<FP, 8>; break;
+          }
+        }
+        hipLaunchKernelGGL(mk, dim3(n_blocks), dim3(bt), micsa_lds_bytes(g, sizeof(FP), jl), stream, g, st, r);
         if ((e = hipGetLastError()) != hipSuccess) return e;
       }
       r.n_pt = 0;

@@ -377,6 +377,31 @@ def test_micsa_many_waves_of_clones():
     stepwise(o, g, 2)
 
 
+@pytest.mark.parametrize("L", [4, 6, 8, 10, 12, 14, 16])
+def test_micsa_row_form_every_lattice_side(L):
+    """The row-wise MicSA kernel is compiled per half side H = L/2 (2..8);
+    each one, in both precisions (odd H reads rows with 4- and 8-byte loads,
+    H = 4, 8 with 16-byte loads), matches the oracle over two EMCS with a
+    refresh every 3 sweeps."""
+    for precision in ("fp64", "fp32"):
+        step(f"micsa row form L={L} {precision}")
+        o, g = make_pair(L, 2, 2, 5, 2, precision=precision, sweeps=4, er_sweeps=6, t_range=(0.3, 1.4),
+                         update="micsa", micsa_refresh=3)
+        stepwise(o, g, 2)
+
+
+@pytest.mark.parametrize("L, precision, NR, NT", [(2, "fp64", 2, 3), (18, "fp32", 2, 3), (16, "fp64", 4, 25)])
+def test_micsa_generic_form(L, precision, NR, NT):
+    """Cases outside the row-wise kernel's range take the site-by-site
+    kernel: L=2 (every neighbour pair is doubled), L=18 in FP32 (couplings in
+    LDS) and L=16 in FP64 with 100 PT clones (couplings read from HBM: 96 KiB
+    of them do not fit beside 64 KiB of spin words)."""
+    step(f"micsa generic form L={L} {precision} {NR}x{NT}")
+    o, g = make_pair(L, 2, NR, NT, 2, precision=precision, sweeps=3, er_sweeps=4, t_range=(0.4, 1.4),
+                     update="micsa", micsa_refresh=2)
+    stepwise(o, g, 2)
+
+
 # ----------------------------------------------------------------------------- labels, run, schedules
 def test_cluster_labels_match_oracle():
     step("labels")
