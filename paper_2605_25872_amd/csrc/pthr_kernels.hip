@@ -1858,7 +1858,7 @@ __global__ __launch_bounds__(kMaxThreads) void micsa_kernel(Geo g, State st, Run
 // J s_i s_j in the same order bit for bit (a zero dE can differ in its sign,
 // which neither W >= dE nor W - dE can tell).  The flips of a site enter the
 // row's own words in registers; each row is written back once.
-constexpr int kMicsaRowThreads = 512;
+constexpr int kMicsaRowThreads = 256;
 
 template <int N>
 __device__ __forceinline__ void lds_words(const uint32_t* p, uint32_t (&v)[N]) {
@@ -1914,54 +1914,127 @@ __device__ __forceinline__ double flip31(double J, uint32_t s) {
       static_cast<long long>(static_cast<unsigned long long>(__double_as_longlong(J)) ^ (static_cast<unsigned long long>(s) << 32)));
 }
 
-// One row of one colour: the pointers address the row's first word (or
-// coupling) in each of the twelve vectors; own is read from Pc and, if
-// write, written back there.
-template <typename FP, int H, int X0>
-__device__ __forceinline__ void micsa_row(const uint32_t* Pc, const uint32_t* Px, const uint32_t* Pyp,
-                                          const uint32_t* Pym, const uint32_t* Pzp, const uint32_t* Pzm, const FP* Jxp,
-                                          const FP* Jxm, const FP* Jyp, const FP* Jym, const FP* Jzp, const FP* Jzm,
-                                          uint32_t* Pw, int sh, int hi_shift, bool active, bool write, FP& W) {
-  constexpr uint32_t kSign = 0x80000000u;
+// Words shifted left by sh (the clone's bit to bit 31), two at a time: bit
+// 31 of either half of a 64-bit shift comes from that half.
+template <int H>
+__device__ __forceinline__ void to_bit31(const uint32_t (&v)[H], uint32_t (&out)[H], int sh) {
+#pragma unroll
+  for (int j = 0; j + 1 < H; j += 2) {
+    const uint64_t p = ((static_cast<uint64_t>(v[j + 1]) << 32) | v[j]) << sh;
+    out[j] = static_cast<uint32_t>(p);
+    out[j + 1] = static_cast<uint32_t>(p >> 32);
+  }
+  if constexpr (H % 2) out[H - 1] = v[H - 1] << sh;
+}
+
+// The twelve row vectors of one row of one colour.
+template <typename FP, int H>
+struct MicsaRow {
   uint32_t own[H], xo[H], yp[H], ym[H], zp[H], zm[H];
   FP jxp[H], jxm[H], jyp[H], jym[H], jzp[H], jzm[H];
-  lds_words<H>(Pc, own);
-  lds_words<H>(Px, xo);
-  lds_words<H>(Pyp, yp);
-  lds_words<H>(Pym, ym);
-  lds_words<H>(Pzp, zp);
-  lds_words<H>(Pzm, zm);
-  lds_row<H>(Jxp, jxp);
-  lds_row<H>(Jxm, jxm);
-  lds_row<H>(Jyp, jyp);
-  lds_row<H>(Jym, jym);
-  lds_row<H>(Jzp, jzp);
-  lds_row<H>(Jzm, jzm);
-  FP dE[H];
+};
+
+// Row (y, z) of colour C: P is the clone word's plane, Jc the couplings in
+// checkerboard order.
+template <typename FP, int H, int C>
+__device__ __forceinline__ void micsa_load(MicsaRow<FP, H>& r, const uint32_t* P, const FP* Jc, int y, int z) {
+  constexpr int L = 2 * H, V = L * L * L, Vh = V / 2, oc = (C ^ 1) * Vh, cc = C * Vh;
+  const int yp = y + 1 < L ? y + 1 : 0, ym = y > 0 ? y - 1 : L - 1;
+  const int zp = z + 1 < L ? z + 1 : 0, zm = z > 0 ? z - 1 : L - 1;
+  const int row = (y + z * L) * H, ryp = (yp + z * L) * H, rym = (ym + z * L) * H;
+  const int rzp = (y + zp * L) * H, rzm = (y + zm * L) * H;
+  lds_words<H>(P + cc + row, r.own);
+  lds_words<H>(P + oc + row, r.xo);
+  lds_words<H>(P + oc + ryp, r.yp);
+  lds_words<H>(P + oc + rym, r.ym);
+  lds_words<H>(P + oc + rzp, r.zp);
+  lds_words<H>(P + oc + rzm, r.zm);
+  lds_row<H>(Jc + cc + row, r.jxp);
+  lds_row<H>(Jc + oc + row, r.jxm);
+  lds_row<H>(Jc + V + cc + row, r.jyp);
+  lds_row<H>(Jc + V + oc + rym, r.jym);
+  lds_row<H>(Jc + 2 * V + cc + row, r.jzp);
+  lds_row<H>(Jc + 2 * V + oc + rzm, r.jzm);
+}
+
+// The walker over one row, x = X0, X0 + 2, ...: the flips enter r.own.  W is
+// -inf on lanes without a clone, so that they never accept.  W - dE =
+// fma(-2, U, W) with dE = 2U exact, rounded once as the difference is; with
+// FP32 denormals kept, the rounded difference is >= 0 exactly when W >= dE.
+template <typename FP, int H, int X0>
+__device__ __forceinline__ void micsa_update(MicsaRow<FP, H>& r, int sh, int hi_shift, FP& W) {
+  constexpr uint32_t kSign = 0x80000000u;
+  uint32_t os[H], xs[H], yps[H], yms[H], zps[H], zms[H];
+  to_bit31<H>(r.own, os, sh);
+  to_bit31<H>(r.xo, xs, sh);
+  to_bit31<H>(r.yp, yps, sh);
+  to_bit31<H>(r.ym, yms, sh);
+  to_bit31<H>(r.zp, zps, sh);
+  to_bit31<H>(r.zm, zms, sh);
+  FP U[H];
 #pragma unroll
   for (int k = 0; k < H; ++k) {
     const int kp = (k + X0) % H, km = (k + X0 + H - 1) % H;
-    const FP u0 = flip31(jxp[k], (xo[kp] << sh) & kSign);
-    const FP u1 = flip31(jxm[km], (xo[km] << sh) & kSign);
-    const FP u2 = flip31(jyp[k], (yp[k] << sh) & kSign);
-    const FP u3 = flip31(jym[k], (ym[k] << sh) & kSign);
-    const FP u4 = flip31(jzp[k], (zp[k] << sh) & kSign);
-    const FP u5 = flip31(jzm[k], (zm[k] << sh) & kSign);
-    dE[k] = FP(2) * flip31(((u0 + u1) + (u2 + u3)) + (u4 + u5), (own[k] << sh) & kSign);
+    const FP u0 = flip31(r.jxp[k], xs[kp] & kSign);
+    const FP u1 = flip31(r.jxm[km], xs[km] & kSign);
+    const FP u2 = flip31(r.jyp[k], yps[k] & kSign);
+    const FP u3 = flip31(r.jym[k], yms[k] & kSign);
+    const FP u4 = flip31(r.jzp[k], zps[k] & kSign);
+    const FP u5 = flip31(r.jzm[k], zms[k] & kSign);
+    U[k] = flip31(((u0 + u1) + (u2 + u3)) + (u4 + u5), os[k] & kSign);
   }
   // the walker, site after site
 #pragma unroll
   for (int k = 0; k < H; ++k) {
-    const bool a = active && W >= dE[k];
-    if (a) W = W - dE[k];
-    own[k] ^= static_cast<uint32_t>(__builtin_amdgcn_ballot_w64(a) >> hi_shift);
+    const FP rest = fma(FP(-2), U[k], W);
+    const bool a = rest >= FP(0);
+    W = a ? rest : W;
+    r.own[k] ^= static_cast<uint32_t>(__builtin_amdgcn_ballot_w64(a) >> hi_shift);
   }
-  if (write) lds_store_words<H>(Pw, own);
+}
+
+// Row (y, z) of colour C from cur, with the rows of (ny, nz) of colour NC
+// loaded into nxt meanwhile: a row never reads a row of its own colour other
+// than its own, and the first row of either colour reads none of the rows
+// the last row of the other colour writes.
+template <typename FP, int H, int C, int NC>
+__device__ __forceinline__ void micsa_step(MicsaRow<FP, H>& cur, MicsaRow<FP, H>& nxt, const uint32_t* P,
+                                           uint32_t* Pw, const FP* Jc, int y, int z, int ny, int nz, int sh,
+                                           int hi_shift, bool write, FP& W) {
+  constexpr int L = 2 * H, Vh = L * L * L / 2;
+  micsa_load<FP, H, NC>(nxt, P, Jc, ny, nz);
+  if ((y + z + C) & 1)
+    micsa_update<FP, H, 1>(cur, sh, hi_shift, W);
+  else
+    micsa_update<FP, H, 0>(cur, sh, hi_shift, W);
+  if (write) lds_store_words<H>(Pw + C * Vh + (y + z * L) * H, cur.own);
+}
+
+// One colour's half-sweep, rows in increasing site order, two rows per trip
+// so that the buffers alternate without copies (L is even); ends with the
+// first row of the other colour loaded into ra.
+template <typename FP, int H, int C>
+__device__ __forceinline__ void micsa_half_sweep(MicsaRow<FP, H>& ra, MicsaRow<FP, H>& rb, const uint32_t* P,
+                                                 uint32_t* Pw, const FP* Jc, int sh, int hi_shift, bool write,
+                                                 FP& W) {
+  constexpr int L = 2 * H;
+  for (int z = 0; z < L; ++z) {
+    for (int y = 0; y < L; y += 2) {
+      micsa_step<FP, H, C, C>(ra, rb, P, Pw, Jc, y, z, y + 1, z, sh, hi_shift, write, W);
+      if (y + 2 < L)
+        micsa_step<FP, H, C, C>(rb, ra, P, Pw, Jc, y + 1, z, y + 2, z, sh, hi_shift, write, W);
+      else if (z + 1 < L)
+        micsa_step<FP, H, C, C>(rb, ra, P, Pw, Jc, y + 1, z, 0, z + 1, sh, hi_shift, write, W);
+      else
+        micsa_step<FP, H, C, C ^ 1>(rb, ra, P, Pw, Jc, y + 1, z, 0, 0, sh, hi_shift, write, W);
+    }
+  }
 }
 
 template <typename FP, int H>
 __global__ __launch_bounds__(kMicsaRowThreads) void micsa_row_kernel(Geo g, State st, Run run) {
-  constexpr int L = 2 * H, L2 = L * L, V = L2 * L, Vh = V / 2;
+  static_assert(H >= 2, "the prefetch needs distinct boundary rows");
+  constexpr int L = 2 * H, V = L * L * L, Vh = V / 2;
   const int sample = run.sample_begin + blockIdx.x;
   if (sample >= g.S) return;
   uint32_t* sp = reinterpret_cast<uint32_t*>(lds_raw);  // [NWPT][V]
@@ -1983,47 +2056,32 @@ __global__ __launch_bounds__(kMicsaRowThreads) void micsa_row_kernel(Geo g, Stat
   const uint32_t t = *st.t_dev;
   const int lane = lane_id();
   const int sh = 31 - (lane & 31), hi_shift = lane & 32;
+  const FP kNoClone = -__builtin_huge_val();
   // blockDim.x is a multiple of 64, so all lanes of a wave take the same trips
   for (int base = 0; base < g.NPT; base += blockDim.x) {
     const int c = base + static_cast<int>(threadIdx.x);
     const bool active = c < g.NPT;
-    const int word = c >> 5;              // this lane's 32-clone word
-    const bool write = word < g.NWPT;     // lanes past the last PT word read word base/32 and write nothing
+    const int word = c >> 5;           // this lane's 32-clone word
+    const bool write = word < g.NWPT;  // lanes past the last PT word read word base/32 and write nothing
     const uint32_t* P = sp + size_t(write ? word : base >> 5) * V;
     uint32_t* Pw = sp + size_t(write ? word : base >> 5) * V;
     const int cw = active ? c : base;
     const double Tk = st.T64[kof[cw]];
     double* wslot = st.walker + size_t(sample) * g.NPT + cw;
-    FP W = static_cast<FP>(*wslot);
+    FP W = active ? static_cast<FP>(*wslot) : kNoClone;
+    MicsaRow<FP, H> ra, rb;
+    micsa_load<FP, H, 0>(ra, P, Jc, 0, 0);
     for (int mm = 0; mm < run.n_pt; ++mm) {
       const int m = run.m_pt0 + mm;
       if (m % g.micsa_refresh == 0) {
         const Block blk = philox10(ctr_word(0, static_cast<uint32_t>(m), kWalker), t, static_cast<uint32_t>(cw),
                                    static_cast<uint32_t>(sample), g.key0, g.key1);
         const uint64_t b53 = ((static_cast<uint64_t>(blk.w1) << 32) | blk.w0) >> 11;
-        W = static_cast<FP>(Tk * -log_unit64(static_cast<double>(b53 + 1) * 0x1p-53));
+        const FP w = static_cast<FP>(Tk * -log_unit64(static_cast<double>(b53 + 1) * 0x1p-53));
+        W = active ? w : kNoClone;
       }
-      for (int colour = 0; colour < 2; ++colour) {
-        const int oc = (colour ^ 1) * Vh, cc = colour * Vh;
-        for (int z = 0; z < L; ++z) {
-          const int zp = z + 1 < L ? z + 1 : 0, zm = z > 0 ? z - 1 : L - 1;
-          for (int y = 0; y < L; ++y) {
-            const int yp = y + 1 < L ? y + 1 : 0, ym = y > 0 ? y - 1 : L - 1;
-            const int row = (y + z * L) * H, ryp = (yp + z * L) * H, rym = (ym + z * L) * H;
-            const int rzp = (y + zp * L) * H, rzm = (y + zm * L) * H;
-            if ((y + z + colour) & 1)
-              micsa_row<FP, H, 1>(P + cc + row, P + oc + row, P + oc + ryp, P + oc + rym, P + oc + rzp, P + oc + rzm,
-                                  Jc + cc + row, Jc + oc + row, Jc + V + cc + row, Jc + V + oc + rym,
-                                  Jc + 2 * V + cc + row, Jc + 2 * V + oc + rzm, Pw + cc + row, sh, hi_shift, active,
-                                  write, W);
-            else
-              micsa_row<FP, H, 0>(P + cc + row, P + oc + row, P + oc + ryp, P + oc + rym, P + oc + rzp, P + oc + rzm,
-                                  Jc + cc + row, Jc + oc + row, Jc + V + cc + row, Jc + V + oc + rym,
-                                  Jc + 2 * V + cc + row, Jc + 2 * V + oc + rzm, Pw + cc + row, sh, hi_shift, active,
-                                  write, W);
-          }
-        }
-      }
+      micsa_half_sweep<FP, H, 0>(ra, rb, P, Pw, Jc, sh, hi_shift, write, W);
+      micsa_half_sweep<FP, H, 1>(ra, rb, P, Pw, Jc, sh, hi_shift, write, W);
     }
     if (active) *wslot = static_cast<double>(W);
   }
