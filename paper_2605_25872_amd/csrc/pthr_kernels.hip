@@ -1927,86 +1927,122 @@ __device__ __forceinline__ void to_bit31(const uint32_t (&v)[H], uint32_t (&out)
   if constexpr (H % 2) out[H - 1] = v[H - 1] << sh;
 }
 
-// The twelve row vectors of one row of one colour.
-template <typename FP, int H>
+// The six spin-word row vectors of one row of one colour, and the six
+// coupling row vectors.
+template <int H>
 struct MicsaRow {
   uint32_t own[H], xo[H], yp[H], ym[H], zp[H], zm[H];
-  FP jxp[H], jxm[H], jyp[H], jym[H], jzp[H], jzm[H];
+};
+template <typename FP, int H>
+struct MicsaJ {
+  FP xp[H], xm[H], yp[H], ym[H], zp[H], zm[H];
 };
 
-// Row (y, z) of colour C: P is the clone word's plane, Jc the couplings in
-// checkerboard order.
-template <typename FP, int H, int C>
-__device__ __forceinline__ void micsa_load(MicsaRow<FP, H>& r, const uint32_t* P, const FP* Jc, int y, int z) {
-  constexpr int L = 2 * H, V = L * L * L, Vh = V / 2, oc = (C ^ 1) * Vh, cc = C * Vh;
-  const int yp = y + 1 < L ? y + 1 : 0, ym = y > 0 ? y - 1 : L - 1;
-  const int zp = z + 1 < L ? z + 1 : 0, zm = z > 0 ? z - 1 : L - 1;
-  const int row = (y + z * L) * H, ryp = (yp + z * L) * H, rym = (ym + z * L) * H;
-  const int rzp = (y + zp * L) * H, rzm = (y + zm * L) * H;
+__device__ __forceinline__ int wrap_up(int v, int L) { return v + 1 < L ? v + 1 : 0; }
+__device__ __forceinline__ int wrap_down(int v, int L) { return v > 0 ? v - 1 : L - 1; }
+
+// Spin words of row (y, z) of colour C from the clone word's plane P.
+template <int H, int C>
+__device__ __forceinline__ void micsa_load(MicsaRow<H>& r, const uint32_t* P, int y, int z) {
+  constexpr int L = 2 * H, Vh = L * L * L / 2, oc = (C ^ 1) * Vh, cc = C * Vh;
+  const int row = (y + z * L) * H;
   lds_words<H>(P + cc + row, r.own);
   lds_words<H>(P + oc + row, r.xo);
-  lds_words<H>(P + oc + ryp, r.yp);
-  lds_words<H>(P + oc + rym, r.ym);
-  lds_words<H>(P + oc + rzp, r.zp);
-  lds_words<H>(P + oc + rzm, r.zm);
-  lds_row<H>(Jc + cc + row, r.jxp);
-  lds_row<H>(Jc + oc + row, r.jxm);
-  lds_row<H>(Jc + V + cc + row, r.jyp);
-  lds_row<H>(Jc + V + oc + rym, r.jym);
-  lds_row<H>(Jc + 2 * V + cc + row, r.jzp);
-  lds_row<H>(Jc + 2 * V + oc + rzm, r.jzm);
+  lds_words<H>(P + oc + (wrap_up(y, L) + z * L) * H, r.yp);
+  lds_words<H>(P + oc + (wrap_down(y, L) + z * L) * H, r.ym);
+  lds_words<H>(P + oc + (y + wrap_up(z, L) * L) * H, r.zp);
+  lds_words<H>(P + oc + (y + wrap_down(z, L) * L) * H, r.zm);
+}
+// Couplings of row (y, z) of colour C from Jc (checkerboard order).
+template <typename FP, int H, int C>
+__device__ __forceinline__ void micsa_load_j(MicsaJ<FP, H>& j, const FP* Jc, int y, int z) {
+  constexpr int L = 2 * H, V = L * L * L, Vh = V / 2, oc = (C ^ 1) * Vh, cc = C * Vh;
+  const int row = (y + z * L) * H;
+  lds_row<H>(Jc + cc + row, j.xp);
+  lds_row<H>(Jc + oc + row, j.xm);
+  lds_row<H>(Jc + V + cc + row, j.yp);
+  lds_row<H>(Jc + V + oc + (wrap_down(y, L) + z * L) * H, j.ym);
+  lds_row<H>(Jc + 2 * V + cc + row, j.zp);
+  lds_row<H>(Jc + 2 * V + oc + (y + wrap_down(z, L) * L) * H, j.zm);
 }
 
-// The walker over one row, x = X0, X0 + 2, ...: the flips enter r.own.  W is
-// -inf on lanes without a clone, so that they never accept.  W - dE =
+// dE / 2 of the row's sites with the sign of the updated spin, U[k] for
+// x = X0 + 2k: each coupling takes the sign of its neighbour spin, the sum
+// that of the updated spin.
+template <typename FP, int H, int X0>
+__device__ __forceinline__ void micsa_fields(const MicsaRow<H>& r, const MicsaJ<FP, H>& J, int sh, FP (&U)[H]) {
+  constexpr uint32_t kSign = 0x80000000u;
+  uint32_t xs[H];
+  to_bit31<H>(r.xo, xs, sh);
+  // two sites at a time, so that only their shifted words are live
+#pragma unroll
+  for (int j = 0; j < H; j += 2) {
+    uint32_t os[2], yps[2], yms[2], zps[2], zms[2];
+    const auto pair = [&](const uint32_t(&v)[H], uint32_t(&out)[2]) {
+      if (j + 1 < H) {
+        const uint64_t q = ((static_cast<uint64_t>(v[j + 1]) << 32) | v[j]) << sh;
+        out[0] = static_cast<uint32_t>(q);
+        out[1] = static_cast<uint32_t>(q >> 32);
+      } else {
+        out[0] = v[j] << sh;
+        out[1] = 0;
+      }
+    };
+    pair(r.own, os);
+    pair(r.yp, yps);
+    pair(r.ym, yms);
+    pair(r.zp, zps);
+    pair(r.zm, zms);
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const int k = j + i;
+      if (k >= H) break;
+      const int kp = (k + X0) % H, km = (k + X0 + H - 1) % H;
+      const FP u0 = flip31(J.xp[k], xs[kp] & kSign);
+      const FP u1 = flip31(J.xm[km], xs[km] & kSign);
+      const FP u2 = flip31(J.yp[k], yps[i] & kSign);
+      const FP u3 = flip31(J.ym[k], yms[i] & kSign);
+      const FP u4 = flip31(J.zp[k], zps[i] & kSign);
+      const FP u5 = flip31(J.zm[k], zms[i] & kSign);
+      U[k] = flip31(((u0 + u1) + (u2 + u3)) + (u4 + u5), os[i] & kSign);
+    }
+  }
+}
+
+// The walker over one row, site after site; the flips enter own.  W is -inf
+// on lanes without a clone, so that they never accept.  W - dE =
 // fma(-2, U, W) with dE = 2U exact, rounded once as the difference is; with
 // FP32 denormals kept, the rounded difference is >= 0 exactly when W >= dE.
-template <typename FP, int H, int X0>
-__device__ __forceinline__ void micsa_update(MicsaRow<FP, H>& r, int sh, int hi_shift, FP& W) {
-  constexpr uint32_t kSign = 0x80000000u;
-  uint32_t os[H], xs[H], yps[H], yms[H], zps[H], zms[H];
-  to_bit31<H>(r.own, os, sh);
-  to_bit31<H>(r.xo, xs, sh);
-  to_bit31<H>(r.yp, yps, sh);
-  to_bit31<H>(r.ym, yms, sh);
-  to_bit31<H>(r.zp, zps, sh);
-  to_bit31<H>(r.zm, zms, sh);
-  FP U[H];
-#pragma unroll
-  for (int k = 0; k < H; ++k) {
-    const int kp = (k + X0) % H, km = (k + X0 + H - 1) % H;
-    const FP u0 = flip31(r.jxp[k], xs[kp] & kSign);
-    const FP u1 = flip31(r.jxm[km], xs[km] & kSign);
-    const FP u2 = flip31(r.jyp[k], yps[k] & kSign);
-    const FP u3 = flip31(r.jym[k], yms[k] & kSign);
-    const FP u4 = flip31(r.jzp[k], zps[k] & kSign);
-    const FP u5 = flip31(r.jzm[k], zms[k] & kSign);
-    U[k] = flip31(((u0 + u1) + (u2 + u3)) + (u4 + u5), os[k] & kSign);
-  }
-  // the walker, site after site
+template <typename FP, int H>
+__device__ __forceinline__ void micsa_walk(uint32_t (&own)[H], const FP (&U)[H], int hi_shift, FP& W) {
 #pragma unroll
   for (int k = 0; k < H; ++k) {
     const FP rest = fma(FP(-2), U[k], W);
     const bool a = rest >= FP(0);
     W = a ? rest : W;
-    r.own[k] ^= static_cast<uint32_t>(__builtin_amdgcn_ballot_w64(a) >> hi_shift);
+    own[k] ^= static_cast<uint32_t>(__builtin_amdgcn_ballot_w64(a) >> hi_shift);
   }
 }
 
-// Row (y, z) of colour C from cur, with the rows of (ny, nz) of colour NC
-// loaded into nxt meanwhile: a row never reads a row of its own colour other
+// Row (y, z) of colour C from cur and J; meanwhile the spin words of row
+// (ny, nz) of colour NC load into nxt and, once this row's sums are formed,
+// its couplings into J.  A row never reads a row of its own colour other
 // than its own, and the first row of either colour reads none of the rows
-// the last row of the other colour writes.
+// the last row of the other colour writes, so the early loads see final
+// words.
 template <typename FP, int H, int C, int NC>
-__device__ __forceinline__ void micsa_step(MicsaRow<FP, H>& cur, MicsaRow<FP, H>& nxt, const uint32_t* P,
+__device__ __forceinline__ void micsa_step(MicsaRow<H>& cur, MicsaRow<H>& nxt, MicsaJ<FP, H>& J, const uint32_t* P,
                                            uint32_t* Pw, const FP* Jc, int y, int z, int ny, int nz, int sh,
                                            int hi_shift, bool write, FP& W) {
   constexpr int L = 2 * H, Vh = L * L * L / 2;
-  micsa_load<FP, H, NC>(nxt, P, Jc, ny, nz);
+  micsa_load<H, NC>(nxt, P, ny, nz);
+  FP U[H];
   if ((y + z + C) & 1)
-    micsa_update<FP, H, 1>(cur, sh, hi_shift, W);
+    micsa_fields<FP, H, 1>(cur, J, sh, U);
   else
-    micsa_update<FP, H, 0>(cur, sh, hi_shift, W);
+    micsa_fields<FP, H, 0>(cur, J, sh, U);
+  micsa_load_j<FP, H, NC>(J, Jc, ny, nz);
+  micsa_walk<FP, H>(cur.own, U, hi_shift, W);
   if (write) lds_store_words<H>(Pw + C * Vh + (y + z * L) * H, cur.own);
 }
 
@@ -2014,19 +2050,19 @@ __device__ __forceinline__ void micsa_step(MicsaRow<FP, H>& cur, MicsaRow<FP, H>
 // so that the buffers alternate without copies (L is even); ends with the
 // first row of the other colour loaded into ra.
 template <typename FP, int H, int C>
-__device__ __forceinline__ void micsa_half_sweep(MicsaRow<FP, H>& ra, MicsaRow<FP, H>& rb, const uint32_t* P,
-                                                 uint32_t* Pw, const FP* Jc, int sh, int hi_shift, bool write,
-                                                 FP& W) {
+__device__ __forceinline__ void micsa_half_sweep(MicsaRow<H>& ra, MicsaRow<H>& rb, MicsaJ<FP, H>& J,
+                                                 const uint32_t* P, uint32_t* Pw, const FP* Jc, int sh, int hi_shift,
+                                                 bool write, FP& W) {
   constexpr int L = 2 * H;
   for (int z = 0; z < L; ++z) {
     for (int y = 0; y < L; y += 2) {
-      micsa_step<FP, H, C, C>(ra, rb, P, Pw, Jc, y, z, y + 1, z, sh, hi_shift, write, W);
+      micsa_step<FP, H, C, C>(ra, rb, J, P, Pw, Jc, y, z, y + 1, z, sh, hi_shift, write, W);
       if (y + 2 < L)
-        micsa_step<FP, H, C, C>(rb, ra, P, Pw, Jc, y + 1, z, y + 2, z, sh, hi_shift, write, W);
+        micsa_step<FP, H, C, C>(rb, ra, J, P, Pw, Jc, y + 1, z, y + 2, z, sh, hi_shift, write, W);
       else if (z + 1 < L)
-        micsa_step<FP, H, C, C>(rb, ra, P, Pw, Jc, y + 1, z, 0, z + 1, sh, hi_shift, write, W);
+        micsa_step<FP, H, C, C>(rb, ra, J, P, Pw, Jc, y + 1, z, 0, z + 1, sh, hi_shift, write, W);
       else
-        micsa_step<FP, H, C, C ^ 1>(rb, ra, P, Pw, Jc, y + 1, z, 0, 0, sh, hi_shift, write, W);
+        micsa_step<FP, H, C, C ^ 1>(rb, ra, J, P, Pw, Jc, y + 1, z, 0, 0, sh, hi_shift, write, W);
     }
   }
 }
@@ -2069,8 +2105,10 @@ __global__ __launch_bounds__(kMicsaRowThreads) void micsa_row_kernel(Geo g, Stat
     const double Tk = st.T64[kof[cw]];
     double* wslot = st.walker + size_t(sample) * g.NPT + cw;
     FP W = active ? static_cast<FP>(*wslot) : kNoClone;
-    MicsaRow<FP, H> ra, rb;
-    micsa_load<FP, H, 0>(ra, P, Jc, 0, 0);
+    MicsaRow<H> ra, rb;
+    MicsaJ<FP, H> J;
+    micsa_load<H, 0>(ra, P, 0, 0);
+    micsa_load_j<FP, H, 0>(J, Jc, 0, 0);
     for (int mm = 0; mm < run.n_pt; ++mm) {
       const int m = run.m_pt0 + mm;
       if (m % g.micsa_refresh == 0) {
@@ -2080,8 +2118,8 @@ __global__ __launch_bounds__(kMicsaRowThreads) void micsa_row_kernel(Geo g, Stat
         const FP w = static_cast<FP>(Tk * -log_unit64(static_cast<double>(b53 + 1) * 0x1p-53));
         W = active ? w : kNoClone;
       }
-      micsa_half_sweep<FP, H, 0>(ra, rb, P, Pw, Jc, sh, hi_shift, write, W);
-      micsa_half_sweep<FP, H, 1>(ra, rb, P, Pw, Jc, sh, hi_shift, write, W);
+      micsa_half_sweep<FP, H, 0>(ra, rb, J, P, Pw, Jc, sh, hi_shift, write, W);
+      micsa_half_sweep<FP, H, 1>(ra, rb, J, P, Pw, Jc, sh, hi_shift, write, W);
     }
     if (active) *wslot = static_cast<double>(W);
   }
