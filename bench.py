@@ -92,8 +92,8 @@ def valu_peak(update: str, precision: str) -> tuple[float, int]:
 # SHA-256 is recorded here; any other source reports null.
 SWEEP_TRAFFIC = {
     "workload": "l16_fp32",
-    "sources_sha256": "dd7338e22f58498d9f4ba1852d7bbec178076a07002b52e0642661f36256abc8",
-    "fetch_kib": 75000.0625,
+    "sources_sha256": "b1dca5285d17da92bb87956a9c3a0d45ec015baae29575e1623d89c1ecff6307",
+    "fetch_kib": 75029.54,
     "write_kib": 98304.0,
 }
 # Utilisation of the Houdayer kernel in the same counter runs (L=16 FP32, all-
@@ -104,8 +104,8 @@ SWEEP_TRAFFIC = {
 HOUDAYER_COUNTERS = {
     "workload": "l16_fp32",
     "sources_sha256": SWEEP_TRAFFIC["sources_sha256"],
-    "valu_issue": 0.528,
-    "lds_pipe_busy": 0.487,
+    "valu_issue": 0.568,
+    "lds_pipe_busy": 0.333,
 }
 KERNEL_SOURCES = ("paper_2605_25872_amd/csrc/pthr_kernels.hip", "paper_2605_25872_amd/csrc/pthr_internal.h")
 
@@ -536,7 +536,8 @@ def main() -> int:
         out["per_gpu_shard"] = {
             "samples": n, "value": attempts_per_emcs(sub) * args.steps / (dt * 1e9),
             "unit": "spin-flip attempts/ns", "ms_per_step": dt / args.steps * 1e3,
-            "threads_per_sample": sch.threads_per_sample, "clone_split": sch.clone_split}
+            "threads_per_sample": sch.threads_per_sample, "clone_split": sch.clone_split,
+            "sample_split": sch.sample_split}
         log(f"per-GPU shard of {n} samples: {out['per_gpu_shard']['value']:.1f} attempts/ns")
         del h
 
