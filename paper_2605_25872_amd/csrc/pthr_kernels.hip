@@ -1941,29 +1941,49 @@ struct MicsaJ {
 __device__ __forceinline__ int wrap_up(int v, int L) { return v + 1 < L ? v + 1 : 0; }
 __device__ __forceinline__ int wrap_down(int v, int L) { return v > 0 ? v - 1 : L - 1; }
 
-// Spin words of row (y, z) of colour C from the clone word's plane P.
-template <int H, int C>
-__device__ __forceinline__ void micsa_load(MicsaRow<H>& r, const uint32_t* P, int y, int z) {
-  constexpr int L = 2 * H, Vh = L * L * L / 2, oc = (C ^ 1) * Vh, cc = C * Vh;
-  const int row = (y + z * L) * H;
-  lds_words<H>(P + cc + row, r.own);
-  lds_words<H>(P + oc + row, r.xo);
-  lds_words<H>(P + oc + (wrap_up(y, L) + z * L) * H, r.yp);
-  lds_words<H>(P + oc + (wrap_down(y, L) + z * L) * H, r.ym);
-  lds_words<H>(P + oc + (y + wrap_up(z, L) * L) * H, r.zp);
-  lds_words<H>(P + oc + (y + wrap_down(z, L) * L) * H, r.zm);
+// Word offsets (within a plane) of a row of one colour and of the other
+// colour's rows it reads: own and xo are the row itself, yp/ym/zp/zm its
+// neighbour rows.
+struct RowOff {
+  int own, xo, yp, ym, zp, zm;
+};
+// Row y of plane z, colour c; zb, zpb, zmb: the word offsets of planes z,
+// z + 1, z - 1 (periodic).
+template <int H>
+__device__ __forceinline__ RowOff row_off(int y, int zb, int zpb, int zmb, int c) {
+  constexpr int L = 2 * H, Vh = L * L * L / 2;
+  const int oc = (c ^ 1) * Vh, cc = c * Vh, yh = y * H;
+  RowOff o;
+  o.own = cc + zb + yh;
+  o.xo = oc + zb + yh;
+  o.yp = oc + zb + (y + 1 < L ? yh + H : 0);
+  o.ym = oc + zb + (y > 0 ? yh - H : (L - 1) * H);
+  o.zp = oc + zpb + yh;
+  o.zm = oc + zmb + yh;
+  return o;
 }
-// Couplings of row (y, z) of colour C from Jc (checkerboard order).
-template <typename FP, int H, int C>
-__device__ __forceinline__ void micsa_load_j(MicsaJ<FP, H>& j, const FP* Jc, int y, int z) {
-  constexpr int L = 2 * H, V = L * L * L, Vh = V / 2, oc = (C ^ 1) * Vh, cc = C * Vh;
-  const int row = (y + z * L) * H;
-  lds_row<H>(Jc + cc + row, j.xp);
-  lds_row<H>(Jc + oc + row, j.xm);
-  lds_row<H>(Jc + V + cc + row, j.yp);
-  lds_row<H>(Jc + V + oc + (wrap_down(y, L) + z * L) * H, j.ym);
-  lds_row<H>(Jc + 2 * V + cc + row, j.zp);
-  lds_row<H>(Jc + 2 * V + oc + (y + wrap_down(z, L) * L) * H, j.zm);
+// Spin words of a row from the clone word's plane P.
+template <int H>
+__device__ __forceinline__ void micsa_load(MicsaRow<H>& r, const uint32_t* P, const RowOff& o) {
+  lds_words<H>(P + o.own, r.own);
+  lds_words<H>(P + o.xo, r.xo);
+  lds_words<H>(P + o.yp, r.yp);
+  lds_words<H>(P + o.ym, r.ym);
+  lds_words<H>(P + o.zp, r.zp);
+  lds_words<H>(P + o.zm, r.zm);
+}
+// Couplings of a row from Jc (checkerboard order): J_x of the row's sites
+// and of the other colour's sites of the row (the -x bonds), J_y of the row
+// and of the row at y - 1, J_z of the row and of the row at z - 1.
+template <typename FP, int H>
+__device__ __forceinline__ void micsa_load_j(MicsaJ<FP, H>& j, const FP* Jc, const RowOff& o) {
+  constexpr int L = 2 * H, V = L * L * L;
+  lds_row<H>(Jc + o.own, j.xp);
+  lds_row<H>(Jc + o.xo, j.xm);
+  lds_row<H>(Jc + V + o.own, j.yp);
+  lds_row<H>(Jc + V + o.ym, j.ym);
+  lds_row<H>(Jc + 2 * V + o.own, j.zp);
+  lds_row<H>(Jc + 2 * V + o.zm, j.zm);
 }
 
 // dE / 2 of the row's sites with the sign of the updated spin, U[k] for
@@ -2024,46 +2044,59 @@ __device__ __forceinline__ void micsa_walk(uint32_t (&own)[H], const FP (&U)[H],
   }
 }
 
-// Row (y, z) of colour C from cur and J; meanwhile the spin words of row
-// (ny, nz) of colour NC load into nxt and, once this row's sums are formed,
-// its couplings into J.  A row never reads a row of its own colour other
-// than its own, and the first row of either colour reads none of the rows
-// the last row of the other colour writes, so the early loads see final
-// words.
-template <typename FP, int H, int C, int NC>
+// Row (y, z) of colour C, whose sites sit at x = X0 + 2k, from cur and J;
+// meanwhile the spin words of row (ny, nz) of colour nc load into nxt and,
+// once this row's sums are formed, its couplings into J.  A row never reads a
+// row of its own colour other than its own, and the first row of either
+// colour reads none of the rows the last row of the other colour writes, so
+// the early loads see final words.
+template <typename FP, int H, int C, int X0>
 __device__ __forceinline__ void micsa_step(MicsaRow<H>& cur, MicsaRow<H>& nxt, MicsaJ<FP, H>& J, const uint32_t* P,
-                                           uint32_t* Pw, const FP* Jc, int y, int z, int ny, int nz, int sh,
+                                           uint32_t* Pw, const FP* Jc, int own, const RowOff& next, int sh,
                                            int hi_shift, bool write, FP& W) {
-  constexpr int L = 2 * H, Vh = L * L * L / 2;
-  micsa_load<H, NC>(nxt, P, ny, nz);
+  micsa_load<H>(nxt, P, next);
   FP U[H];
-  if ((y + z + C) & 1)
-    micsa_fields<FP, H, 1>(cur, J, sh, U);
-  else
-    micsa_fields<FP, H, 0>(cur, J, sh, U);
-  micsa_load_j<FP, H, NC>(J, Jc, ny, nz);
+  micsa_fields<FP, H, X0>(cur, J, sh, U);
+  micsa_load_j<FP, H>(J, Jc, next);
   micsa_walk<FP, H>(cur.own, U, hi_shift, W);
-  if (write) lds_store_words<H>(Pw + C * Vh + (y + z * L) * H, cur.own);
+  if (write) lds_store_words<H>(Pw + own, cur.own);
 }
 
-// One colour's half-sweep, rows in increasing site order, two rows per trip
-// so that the buffers alternate without copies (L is even); ends with the
-// first row of the other colour loaded into ra.
+// The rows of plane z of colour C, two per trip so that the buffers
+// alternate without copies (L is even); rows with even y have their sites at
+// x = XE + 2k, rows with odd y at x = 1 - XE + 2k.  The last row loads the
+// first row of the next plane, or of the other colour after the last plane.
+template <typename FP, int H, int C, int XE>
+__device__ __forceinline__ void micsa_plane(MicsaRow<H>& ra, MicsaRow<H>& rb, MicsaJ<FP, H>& J, const uint32_t* P,
+                                            uint32_t* Pw, const FP* Jc, int z, int sh, int hi_shift, bool write,
+                                            FP& W) {
+  constexpr int L = 2 * H, LH = L * H, Vh = L * L * L / 2;
+  const int zb = z * LH, zpb = wrap_up(z, L) * LH, zmb = wrap_down(z, L) * LH;
+  // the row after this plane's last: the next plane's first, or the other
+  // colour's first after the last plane
+  const bool end = z + 1 == L;
+  const int nz = end ? 0 : z + 1, nc = end ? C ^ 1 : C;
+  const RowOff after = row_off<H>(0, nz * LH, wrap_up(nz, L) * LH, wrap_down(nz, L) * LH, nc);
+  for (int y = 0; y < L; y += 2) {
+    micsa_step<FP, H, C, XE>(ra, rb, J, P, Pw, Jc, C * Vh + zb + y * H, row_off<H>(y + 1, zb, zpb, zmb, C), sh,
+                             hi_shift, write, W);
+    micsa_step<FP, H, C, XE ^ 1>(rb, ra, J, P, Pw, Jc, C * Vh + zb + (y + 1) * H,
+                                 y + 2 < L ? row_off<H>(y + 2, zb, zpb, zmb, C) : after, sh, hi_shift, write, W);
+  }
+}
+
+// One colour's half-sweep, rows in increasing site order; on entry ra and J
+// hold its first row, on exit the first row of the other colour.
 template <typename FP, int H, int C>
 __device__ __forceinline__ void micsa_half_sweep(MicsaRow<H>& ra, MicsaRow<H>& rb, MicsaJ<FP, H>& J,
                                                  const uint32_t* P, uint32_t* Pw, const FP* Jc, int sh, int hi_shift,
                                                  bool write, FP& W) {
   constexpr int L = 2 * H;
   for (int z = 0; z < L; ++z) {
-    for (int y = 0; y < L; y += 2) {
-      micsa_step<FP, H, C, C>(ra, rb, J, P, Pw, Jc, y, z, y + 1, z, sh, hi_shift, write, W);
-      if (y + 2 < L)
-        micsa_step<FP, H, C, C>(rb, ra, J, P, Pw, Jc, y + 1, z, y + 2, z, sh, hi_shift, write, W);
-      else if (z + 1 < L)
-        micsa_step<FP, H, C, C>(rb, ra, J, P, Pw, Jc, y + 1, z, 0, z + 1, sh, hi_shift, write, W);
-      else
-        micsa_step<FP, H, C, C ^ 1>(rb, ra, J, P, Pw, Jc, y + 1, z, 0, 0, sh, hi_shift, write, W);
-    }
+    if ((z + C) & 1)
+      micsa_plane<FP, H, C, 1>(ra, rb, J, P, Pw, Jc, z, sh, hi_shift, write, W);
+    else
+      micsa_plane<FP, H, C, 0>(ra, rb, J, P, Pw, Jc, z, sh, hi_shift, write, W);
   }
 }
 
@@ -2107,8 +2140,9 @@ __global__ __launch_bounds__(kMicsaRowThreads) void micsa_row_kernel(Geo g, Stat
     FP W = active ? static_cast<FP>(*wslot) : kNoClone;
     MicsaRow<H> ra, rb;
     MicsaJ<FP, H> J;
-    micsa_load<H, 0>(ra, P, 0, 0);
-    micsa_load_j<FP, H, 0>(J, Jc, 0, 0);
+    const RowOff first = row_off<H>(0, 0, L * H, (L - 1) * L * H, 0);  // row 0 of plane 0, colour 0
+    micsa_load<H>(ra, P, first);
+    micsa_load_j<FP, H>(J, Jc, first);
     for (int mm = 0; mm < run.n_pt; ++mm) {
       const int m = run.m_pt0 + mm;
       if (m % g.micsa_refresh == 0) {
