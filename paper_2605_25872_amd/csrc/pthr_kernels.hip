@@ -45,6 +45,12 @@ struct Floats4 {
 __device__ __forceinline__ Floats4 to_floats(const Block& b) {
   return {{static_cast<float>(b.w0), static_cast<float>(b.w1), static_cast<float>(b.w2), static_cast<float>(b.w3)}};
 }
+// FP64 tests: the float of the 53 random bits of each word pair (u[0]: w0,
+// w1; u[1]: w2, w3), formed as bits53 does.
+__device__ __forceinline__ Floats4 to_bits53(const Block& b) {
+  return {{__builtin_fmaf(static_cast<float>(b.w1), 0x1p21f, static_cast<float>(b.w0 >> 11)),
+           __builtin_fmaf(static_cast<float>(b.w3), 0x1p21f, static_cast<float>(b.w2 >> 11)), 0.0f, 0.0f}};
+}
 
 // a ^ b ^ k in one VALU operation (three-input bitwise function, truth table
 // 0x96); k is wave-uniform and read from a scalar register.
@@ -214,16 +220,20 @@ struct Prec<double> {
     uint64_t sure;  // lanes whose test the bound proves accepted
     uint64_t open;  // lanes in range the bound leaves undecided
   };
-  static __device__ __forceinline__ Bound bound_lanes(uint32_t lo, uint32_t hi, double x, float f_lo, float f_hi) {
+  // The 53 random bits hi 2^21 + (lo >> 11) of u = (bits) 2^-53 in float:
+  // float(hi) and the fused multiply-add round once each (the low part is
+  // exact), so the result is within 2^-23 of the bits, relative.
+  static __device__ __forceinline__ float bits53(uint32_t lo, uint32_t hi) {
+    return __builtin_fmaf(static_cast<float>(hi), 0x1p21f, static_cast<float>(lo >> 11));
+  }
+  // hb: bits53 of the test's random words.
+  static __device__ __forceinline__ Bound bound_lanes(float hb, double x, float f_lo, float f_hi) {
     const double k = __builtin_rint(x * 0x1.71547652b82fep+0);
     double r = __builtin_fma(-k, 0x1.62e42feep-1, x);
     r = __builtin_fma(-k, 0x1.a39ef35793c76p-33, r);
     const float q = exp2_frac32(static_cast<float>(r) * 0x1.715476p+0f);
-    // u 2^-k in float, from the 53 random bits hi 2^21 + (lo >> 11): float(hi)
-    // and the fused multiply-add round once each (the low part is exact), so
-    // d is within 2^-23 of u 2^-k relative (or is 0 or subnormal where
-    // u 2^-k is far below q, or +inf where it is far above)
-    const float hb = __builtin_fmaf(static_cast<float>(hi), 0x1p21f, static_cast<float>(lo >> 11));
+    // u 2^-k in float: d is within 2^-23 of u 2^-k relative (or is 0 or
+    // subnormal where u 2^-k is far below q, or +inf where it is far above)
     const float d = __builtin_ldexpf(hb, -53 - static_cast<int>(k));
     const uint64_t in_range = __builtin_amdgcn_ballot_w64(x >= -708.0);
     const uint64_t below = __builtin_amdgcn_ballot_w64(d < q * f_lo);
@@ -705,11 +715,13 @@ __device__ __forceinline__ void attempt_group(const Geo& g, const FP* __restrict
         if constexpr (kExact) {
           acc_lanes = nonpos | Prec<double>::exact_lanes(lo, hi, x, __builtin_rint(x * 0x1.71547652b82fep+0));
         } else if constexpr (kDefer) {
-          const typename Prec<double>::Bound b = Prec<double>::bound_lanes(lo, hi, x, g.exp_lo, g.exp_hi);
+          // fw holds the floats of the block's random bits (to_bits53)
+          const typename Prec<double>::Bound b = Prec<double>::bound_lanes(fw.u[j & 1], x, g.exp_lo, g.exp_hi);
           acc_lanes = nonpos | b.sure;
           open |= b.open & ~nonpos;
         } else {
-          const typename Prec<double>::Bound b = Prec<double>::bound_lanes(lo, hi, x, g.exp_lo, g.exp_hi);
+          const typename Prec<double>::Bound b =
+              Prec<double>::bound_lanes(Prec<double>::bits53(lo, hi), x, g.exp_lo, g.exp_hi);
           acc_lanes = nonpos | (b.open == 0 ? b.sure
                                             : Prec<double>::exact_lanes(lo, hi, x,
                                                                         __builtin_rint(x * 0x1.71547652b82fep+0)));
@@ -773,15 +785,19 @@ __device__ __forceinline__ void update_word(const Geo& g, const FP* __restrict__
       // groups run from the highest clone down, one clone per doubling
       RunSigns rs = run_signs<FP>(ws, g_hi * G + G - 1 - n0);
       Block blk = philox10(c0w, t, static_cast<uint32_t>(grp), static_cast<uint32_t>(sample), g.key0, g.key1);
+      // the block's words are converted as it is taken up (float(w), or the
+      // floats of the FP64 tests' random bits in the deferred pass), so that
+      // the next block is produced in their registers
+      constexpr bool kBits53 = kRedo && !kExact;
       for (; grp > g_lo; --grp) {
-        const Floats4 fw = kUsesFloats ? to_floats(blk) : Floats4{};
+        const Floats4 fw = kUsesFloats ? to_floats(blk) : kBits53 ? to_bits53(blk) : Floats4{};
         const Block next =
             philox10(c0w, t, static_cast<uint32_t>(grp - 1), static_cast<uint32_t>(sample), g.key0, g.key1);
         attempt_group<FP, kMaybeEarly, kHB, kExact, kRedo>(g, bc, rs, sj, blk, fw, grp, n0, clone0, nbits,
                                                            early_beta_bits, fl, open);
         blk = next;
       }
-      const Floats4 fw = kUsesFloats ? to_floats(blk) : Floats4{};
+      const Floats4 fw = kUsesFloats ? to_floats(blk) : kBits53 ? to_bits53(blk) : Floats4{};
       attempt_group<FP, kMaybeEarly, kHB, kExact, kRedo>(g, bc, rs, sj, blk, fw, g_lo, n0, clone0, nbits,
                                                          early_beta_bits, fl, open);
       return fl;
