@@ -333,6 +333,9 @@ def main() -> int:
     ap.add_argument("--shard-samples", type=int, default=128,
                     help="also time one GPU's share of the batch sharded over 8 GPUs (0 = skip)")
     ap.add_argument("--autotune", action="store_true")
+    ap.add_argument("--overlap-reservoir", action="store_true",
+                    help="reservoir sweeps on a second stream beside the Houdayer step (plain launches)")
+    ap.add_argument("--plain-launches", action="store_true", help="time pthr_run as plain launches, no graph")
     ap.add_argument("--no-autotune", action="store_true", help="mixed batch: keep the default schedules")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy a MIB-MiB device buffer 3 times (HBM counter calibration)")
@@ -396,7 +399,10 @@ def main() -> int:
         best = g.autotune(max(1, math.ceil(1.5e10 / attempts_per_emcs(w))))
         sch = g.schedule()
         log(f"autotune: {best:.2f} ms/EMCS with {sch.threads_per_sample} work-items per sample, "
-            f"clone split {sch.clone_split}, exp early-out below T = {sch.exp_early_out / 1000:g}")
+            f"clone split {sch.clone_split}, sample split {sch.sample_split}, "
+            f"exp early-out below T = {sch.exp_early_out / 1000:g}, reservoir overlap {sch.overlap_reservoir}")
+    if args.overlap_reservoir:
+        g.set_schedule(overlap_reservoir=1)
     stream = torch.cuda.current_stream(dev)
     n_er = w.er_sweeps_per_emcs if w.n_reservoir else 0
     att = attempts_per_emcs(w)
@@ -405,7 +411,8 @@ def main() -> int:
     # Timed region: the persistent form the L=16 workload names, K EMCS as
     # replays of a captured graph of the phase kernels (pthr_run), with the
     # observables accumulated every EMCS.  The warm-up captures the graph.
-    window = max(1, min(args.steps, 32))
+    # (the reservoir overlap runs as plain launches)
+    window = 0 if args.overlap_reservoir or args.plain_launches else max(1, min(args.steps, 32))
     g.set_schedule(graph_window=window)
     g.run(max(args.warmup, window), obs)
     torch.cuda.synchronize()
@@ -417,7 +424,8 @@ def main() -> int:
     g.check()
     ms_per_step = elapsed / args.steps * 1e3
     value = att * args.steps / (elapsed * 1e9)
-    log(f"timed {args.steps} EMCS (graph replays) in {elapsed:.3f} s: {value:.1f} attempts/ns")
+    log(f"timed {args.steps} EMCS ({'graph replays' if window else 'plain launches'}) in {elapsed:.3f} s: "
+        f"{value:.1f} attempts/ns")
 
     # Kernel breakdown: the same EMCS as eager per-phase launches on the same
     # stream, HIP events around the sweep and Houdayer kernels (the sweep's
@@ -487,7 +495,10 @@ def main() -> int:
                    "threads_per_sample": g.schedule().threads_per_sample,
                    "exp_early_out_below_T": g.schedule().exp_early_out / 1000,
                    "clone_split": g.schedule().clone_split,
-                   "timed_form": f"pthr_run replaying a captured graph of {window} EMCS, observables every EMCS"},
+                   "sample_split": g.schedule().sample_split,
+                   "overlap_reservoir": g.schedule().overlap_reservoir,
+                   "timed_form": (f"pthr_run replaying a captured graph of {window} EMCS, observables every EMCS"
+                                  if window else "pthr_run as plain launches, observables every EMCS")},
         "houdayer_moves_per_s": moves * args.steps / elapsed,
         "eager_per_phase": {"value": att * args.steps / (eager_elapsed * 1e9),
                             "ms_per_step": eager_elapsed / args.steps * 1e3,

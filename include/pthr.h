@@ -231,16 +231,26 @@ typedef struct pthr_schedule {
                            sample_split-th group of clones of every word (the clones per
                            workgroup of the sweep); the default fills the compute units when a
                            batch has fewer samples than the GPU has CUs */
+  int32_t overlap_reservoir; /* pthr_run as plain launches (graph_window = 0): 0 (default) sweeps
+                                PT and reservoir clones in one launch before the Houdayer step; 1
+                                runs the reservoir sweeps of each EMCS on a second stream beside
+                                the PT sweeps and the Houdayer step, joined before the PT step (the
+                                reservoir clones are untouched by both until the exchange, Sec. 3).
+                                The library creates that stream and two events once per context.
+                                pthr_run with a captured window and pthr_group_run return
+                                PTHR_EUNSUPPORTED for a context with 1. */
 } pthr_schedule;
 int pthr_get_schedule(const pthr_ctx *ctx, pthr_schedule *out);
 int pthr_set_schedule(pthr_ctx *ctx, const pthr_schedule *sch);
 /* Times candidate schedules (work-items per sample, clone_split, and for
  * batches of fewer than two samples per compute unit sample_split; early-out
- * off or below T = 0.7 on the unsplit shapes) with pthr_run on a scratch
- * copy of the state (d_scratch: pthr_state_bytes bytes, device): after one
- * untimed EMCS, two timed stretches of n_emcs EMCS each, the faster
- * counting; keeps the fastest candidate (graph_window and exp_filter as
- * they were), restores nothing else.  best_ms (may be NULL) gets its time
+ * off or below T = 0.7 on the unsplit shapes; then the fastest of these with
+ * overlap_reservoir = 1, for contexts with a reservoir whose schedule runs
+ * plain launches) with pthr_run on a
+ * scratch copy of the state (d_scratch: pthr_state_bytes bytes, device):
+ * after one untimed EMCS, two timed stretches of n_emcs EMCS each, the
+ * faster counting; keeps the fastest candidate (graph_window and exp_filter
+ * as they were), restores nothing else.  best_ms (may be NULL) gets its time
  * per EMCS. */
 int pthr_autotune(pthr_ctx *ctx, void *d_scratch, int n_emcs, double *best_ms, void *stream);
 /* The candidates the last autotuning timed and their ms per EMCS, in the
@@ -249,7 +259,8 @@ int pthr_autotune(pthr_ctx *ctx, void *d_scratch, int n_emcs, double *best_ms, v
 int pthr_autotune_results(const pthr_ctx *ctx, pthr_schedule *schedules, double *ms_per_emcs, int capacity);
 /* pthr_autotune for callers that cannot allocate (inside stream capture,
  * serving loops, harnesses that forbid allocation): the same candidates and
- * choice, with the scratch copy of the state in a static device workspace of
+ * choice except overlap_reservoir = 1 (which needs a second stream), with the
+ * scratch copy of the state in a static device workspace of
  * 64 MiB (PTHR_EINVAL if pthr_state_bytes exceeds it), the trial EMCS run as
  * plain launches (no graph is instantiated) and timed with the host clock
  * (no events are created); nothing is allocated.  The workspace is held on

@@ -177,7 +177,29 @@ struct pthr_ctx {
   unsigned char* g_state = nullptr;
   pthr_schedule g_sch{};
 
-  ~pthr_ctx() { drop_graph(); if (cap_stream) (void)hipStreamDestroy(cap_stream); }
+  // overlap_reservoir: the second stream and the fork / join events
+  hipStream_t side_stream = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+
+  ~pthr_ctx() {
+    drop_graph();
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
+    if (side_stream) (void)hipStreamDestroy(side_stream);
+    if (ev_fork) (void)hipEventDestroy(ev_fork);
+    if (ev_join) (void)hipEventDestroy(ev_join);
+  }
+  bool overlapping() const { return sch.overlap_reservoir && d.NER > 0 && p.er_sweeps_per_emcs > 0; }
+  // Creates the second stream and its events (once; never inside a capture).
+  int make_side() {
+    hipError_t e = hipSuccess;
+    if (!side_stream && (e = hipStreamCreateWithFlags(&side_stream, hipStreamNonBlocking)) != hipSuccess)
+      return hip_fail(e, "second stream");
+    if (!ev_fork && (e = hipEventCreateWithFlags(&ev_fork, hipEventDisableTiming)) != hipSuccess)
+      return hip_fail(e, "fork event");
+    if (!ev_join && (e = hipEventCreateWithFlags(&ev_join, hipEventDisableTiming)) != hipSuccess)
+      return hip_fail(e, "join event");
+    return PTHR_OK;
+  }
   void drop_graph() {
     if (gexec) (void)hipGraphExecDestroy(gexec);
     gexec = nullptr;
@@ -284,8 +306,33 @@ struct pthr_ctx {
     run.n_pt = p.sweeps_per_emcs;
     run.n_er = d.NER > 0 ? p.er_sweeps_per_emcs : 0;
     run.do_reservoir = 1;
-    if (int rc = launch(run, nullptr, stream)) return rc;
-    hipError_t e = pthr::launch_advance_t(state(), stream);
+    hipError_t e = hipSuccess;
+    if (overlapping()) {
+      // reservoir sweeps on the second stream, PT sweeps and the Houdayer step
+      // on this one (disjoint spin words), joined before the PT step
+      if (!side_stream || !ev_fork || !ev_join) return fail(PTHR_ESTATE, "second stream not created");
+      if ((e = hipEventRecord(ev_fork, stream)) != hipSuccess ||
+          (e = hipStreamWaitEvent(side_stream, ev_fork, 0)) != hipSuccess)
+        return hip_fail(e, "fork");
+      pthr::Run er{};
+      er.phases = pthr::kPhaseSweep;
+      er.n_er = run.n_er;
+      if (int rc = launch(er, nullptr, side_stream)) return rc;
+      pthr::Run pt = run;
+      pt.phases &= ~pthr::kPhasePT;
+      pt.n_er = 0;
+      if (int rc = launch(pt, nullptr, stream)) return rc;
+      if ((e = hipEventRecord(ev_join, side_stream)) != hipSuccess ||
+          (e = hipStreamWaitEvent(stream, ev_join, 0)) != hipSuccess)
+        return hip_fail(e, "join");
+      pthr::Run ps{};
+      ps.phases = pthr::kPhasePT;
+      ps.do_reservoir = 1;
+      if (int rc = launch(ps, nullptr, stream)) return rc;
+    } else {
+      if (int rc = launch(run, nullptr, stream)) return rc;
+    }
+    e = pthr::launch_advance_t(state(), stream);
     if (e != hipSuccess) return hip_fail(e, "advance t");
     if (d_obs) {
       pthr::Run m{};
@@ -306,6 +353,7 @@ struct pthr_ctx {
     hipError_t e = hipSuccess;
     if (!cap_stream) e = hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking);
     if (e != hipSuccess) return hip_fail(e, "capture stream");
+    if (overlapping()) return fail(PTHR_EUNSUPPORTED, "overlap_reservoir runs as plain launches (graph_window = 0)");
     if ((e = hipStreamBeginCapture(cap_stream, hipStreamCaptureModeThreadLocal)) != hipSuccess)
       return hip_fail(e, "begin capture");
     int rc = PTHR_OK;
@@ -594,6 +642,11 @@ int pthr_run(pthr_ctx* ctx, int64_t n_emcs, void* d_obs, void* stream) {
   if (ctx->t + n_emcs > 0xFFFFFFFFll) return ctx->fail(PTHR_ESTATE, "EMCS counter would pass 2^32");
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int W = ctx->sch.graph_window;
+  if (ctx->overlapping()) {
+    if (W > 0 && n_emcs >= W)
+      return ctx->fail(PTHR_EUNSUPPORTED, "overlap_reservoir runs as plain launches (graph_window = 0)");
+    if (int rc = ctx->make_side()) return rc;
+  }
   int64_t done = 0;
   if (W > 0 && n_emcs >= W) {
     if (int rc = ctx->graph(W, d_obs)) return rc;
@@ -847,6 +900,8 @@ int pthr_set_schedule(pthr_ctx* ctx, const pthr_schedule* sch) {
     return ctx->fail(PTHR_EINVAL, "threads_per_sample * clone_split must be <= 1024");
   if (sch->sample_split != 1 && sch->sample_split != 2 && sch->sample_split != 4)
     return ctx->fail(PTHR_EINVAL, "sample_split must be 1, 2 or 4");
+  if (sch->overlap_reservoir != 0 && sch->overlap_reservoir != 1)
+    return ctx->fail(PTHR_EINVAL, "overlap_reservoir must be 0 or 1");
   ctx->sch = *sch;
   return PTHR_OK;
 }
@@ -911,13 +966,27 @@ int autotune_impl(pthr_ctx* ctx, void* d_scratch, int n_emcs, double* best_ms, v
           cand.exp_early_out = early;
           cand.clone_split = split;
           cand.sample_split = parts;
+          cand.overlap_reservoir = 0;
           cands.push_back(cand);
         }
   }
   ctx->tune.clear();
   int rc = PTHR_OK;
-  for (pthr_schedule cand : cands) {
+  // then the fastest of them with the reservoir sweeps beside the Houdayer
+  // step, for schedules that run plain launches (a second stream: not in the
+  // allocation-free form)
+  const bool try_overlap =
+      !no_alloc && saved.graph_window == 0 && ctx->d.NER > 0 && ctx->p.er_sweeps_per_emcs > 0;
+  const size_t n_base = cands.size();
+  for (size_t ci = 0; ci <= n_base; ++ci) {
     if (rc != PTHR_OK) break;
+    if (ci == n_base && !try_overlap) break;
+    pthr_schedule cand = ci < n_base ? cands[ci] : best;
+    if (ci == n_base) {
+      cand.overlap_reservoir = 1;
+      ctx->sch = cand;
+      if ((rc = ctx->make_side()) != PTHR_OK) break;
+    }
     if (no_alloc) cand.graph_window = 0;
     ctx->sch = cand;
     hipError_t e = hipMemcpyAsync(d_scratch, real, ctx->lay.total, hipMemcpyDeviceToDevice, s);
@@ -1189,6 +1258,8 @@ int pthr_group_run(pthr_group* grp, int64_t n_emcs, void* const* d_obs, int grap
     if (!c->ready) return grp->fail(PTHR_ESTATE, "context %zu: state buffer not initialised", i);
     if (c->m_pt || c->m_er) return grp->fail(PTHR_ESTATE, "context %zu: an EMCS is in progress", i);
     if (c->t + n_emcs > 0xFFFFFFFFll) return grp->fail(PTHR_ESTATE, "context %zu: EMCS counter would pass 2^32", i);
+    if (c->overlapping())
+      return grp->fail(PTHR_EUNSUPPORTED, "context %zu: overlap_reservoir is not supported in groups", i);
   }
   hipStream_t s = static_cast<hipStream_t>(stream);
   int64_t done = 0;

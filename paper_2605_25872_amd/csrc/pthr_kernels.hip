@@ -2193,13 +2193,13 @@ size_t micsa_lds_bytes(const Geo& g, int fp_bytes, bool with_j) {
 // global word still holds this part's bits as loaded).
 template <typename FP>
 __device__ __forceinline__ void store_part(const Geo& g, const uint32_t* sp, const State& st, int sample, int part,
-                                           int P) {
+                                           int P, int w_begin, int w_end) {
   constexpr int G = sizeof(FP) == 8 ? 2 : 4;
   uint32_t mask = 0;
   for (int b = 0; b < 32; ++b) mask |= ((b / G) % P == part) ? 1u << b : 0u;
   uint32_t* gsp = st.spins + size_t(sample) * g.NW * g.V;
-  const int words = g.NW * g.V;
-  for (int x = threadIdx.x; x < words; x += blockDim.x) {
+  const int end = w_end * g.V;
+  for (int x = w_begin * g.V + static_cast<int>(threadIdx.x); x < end; x += blockDim.x) {
     const uint32_t change = (sp[x] ^ gsp[x]) & mask;
     if (change) atomicXor(&gsp[x], change);
   }
@@ -2221,11 +2221,26 @@ __global__ __launch_bounds__(kMaxThreads) void sweep_kernel(Geo g, State st, Run
   const float beta_cold = sizeof(FP) == 8 ? static_cast<float>(st.beta64[0]) : st.beta32[0];
   sweep_phase<FP, CH, kSplit, kHB>(g, s, Js, bc, sample, t, run.m_pt0, run.n_pt, run.m_er0, run.n_er,
                                    run.early_beta, beta_cold, run.clone_split, part, P);
+  // only the words of the clone classes swept here go back: a launch of
+  // reservoir sweeps alone may run beside the Houdayer step, which writes the
+  // PT words meanwhile (and a launch of PT sweeps alone beside the reservoir's)
+  const int w_begin = run.n_pt > 0 ? 0 : g.NWPT;
+  const int w_end = run.n_er > 0 && g.NER > 0 ? g.NW : g.NWPT;
   if (P == 1) {
-    store_spins(g, s, st, sample);
+    __syncthreads();
+    const size_t stride = size_t(g.NW) * g.V;
+    uint32_t* gsp = st.spins + size_t(sample) * stride;
+    const size_t b = size_t(w_begin) * g.V, e = size_t(w_end) * g.V;
+    if (b % 4 == 0 && e % 4 == 0) {
+      const uint4* src = reinterpret_cast<const uint4*>(s.sp + b);
+      uint4* dst = reinterpret_cast<uint4*>(gsp + b);
+      for (size_t x = threadIdx.x; x < (e - b) / 4; x += blockDim.x) dst[x] = src[x];
+    } else {
+      for (size_t x = b + threadIdx.x; x < e; x += blockDim.x) gsp[x] = s.sp[x];
+    }
   } else {
     __syncthreads();  // every wave's flips are in LDS
-    store_part<FP>(g, s.sp, st, sample, part, P);
+    store_part<FP>(g, s.sp, st, sample, part, P, w_begin, w_end);
   }
 }
 

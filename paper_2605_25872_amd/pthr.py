@@ -54,7 +54,7 @@ class Schedule(ctypes.Structure):
     _fields_ = [("threads_per_sample", ctypes.c_int32), ("samples_per_launch", ctypes.c_int32),
                 ("exp_early_out", ctypes.c_int32), ("graph_window", ctypes.c_int32),
                 ("clone_split", ctypes.c_int32), ("exp_filter", ctypes.c_int32),
-                ("sample_split", ctypes.c_int32)]
+                ("sample_split", ctypes.c_int32), ("overlap_reservoir", ctypes.c_int32)]
 
 
 _lib = None
@@ -304,8 +304,11 @@ class Pthr:
         return sch
 
     def set_schedule(self, threads_per_sample=None, samples_per_launch=None, exp_early_out=None,
-                     graph_window=None, clone_split=None, exp_filter=None, sample_split=None) -> None:
+                     graph_window=None, clone_split=None, exp_filter=None, sample_split=None,
+                     overlap_reservoir=None) -> None:
         sch = self.schedule()
+        if overlap_reservoir is not None:
+            sch.overlap_reservoir = int(overlap_reservoir)
         if sample_split is not None:
             sch.sample_split = sample_split
         if exp_filter is not None:

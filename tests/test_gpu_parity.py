@@ -549,14 +549,15 @@ def test_every_schedule_gives_the_same_bits(precision):
     step(f"schedules {precision}")
     pthr = _pthr()
     ref = None
-    for threads, early, per, split, filt, parts in (
-            (256, 700, 0, 1, 1, 1), (128, 100000, 0, 1, 1, 1), (256, 0, 1, 1, 1, 1), (128, 1000, 2, 1, 1, 1),
-            (256, 0, 0, 4, 1, 1), (128, 700, 0, 2, 1, 1), (128, 0, 2, 8 // 2, 1, 1), (256, 0, 0, 1, 0, 1),
-            (128, 0, 0, 2, 0, 1), (256, 0, 0, 1, 1, 2), (128, 0, 0, 2, 1, 4), (128, 700, 2, 1, 1, 2),
-            (256, 0, 0, 1, 0, 4), (128, 0, 1, 4, 0, 2)):
+    for threads, early, per, split, filt, parts, over in (
+            (256, 700, 0, 1, 1, 1, 0), (128, 100000, 0, 1, 1, 1, 0), (256, 0, 1, 1, 1, 1, 0),
+            (128, 1000, 2, 1, 1, 1, 0), (256, 0, 0, 4, 1, 1, 0), (128, 700, 0, 2, 1, 1, 0), (128, 0, 2, 8 // 2, 1, 1, 0),
+            (256, 0, 0, 1, 0, 1, 0), (128, 0, 0, 2, 0, 1, 0), (256, 0, 0, 1, 1, 2, 0), (128, 0, 0, 2, 1, 4, 0),
+            (128, 700, 2, 1, 1, 2, 0), (256, 0, 0, 1, 0, 4, 0), (128, 0, 1, 4, 0, 2, 0), (256, 0, 0, 1, 1, 1, 1),
+            (128, 0, 1, 2, 1, 2, 1), (256, 700, 2, 1, 0, 1, 1), (128, 0, 0, 1, 1, 4, 1)):
         _, g = make_pair(8, 3, 4, 10, 4, precision=precision, er_sweeps=20)
         g.set_schedule(threads_per_sample=threads, exp_early_out=early, samples_per_launch=per, clone_split=split,
-                       exp_filter=filt, sample_split=parts)
+                       exp_filter=filt, sample_split=parts, overlap_reservoir=over)
         go = g.new_obs()
         g.run(2, go)
         got = (g.read_spins(), g.read_pt(), g.obs_arrays(go))
@@ -569,6 +570,35 @@ def test_every_schedule_gives_the_same_bits(precision):
         assert np.array_equal(got[2]["acc"], ref[2]["acc"])
         assert np.array_equal(got[2]["hist"], ref[2]["hist"])
     del pthr
+
+
+@pytest.mark.parametrize("update, precision", [("metropolis", "fp32"), ("metropolis", "fp64"), ("heatbath", "fp32"),
+                                               ("micsa", "fp64"), ("micsa", "fp32")])
+def test_reservoir_overlap_matches_oracle(update, precision):
+    """overlap_reservoir = 1 with plain launches: the reservoir sweeps of
+    every EMCS run on a second stream beside the PT sweeps and the Houdayer
+    step, joined before the PT step; spins, PT state and observables match
+    the oracle bit for bit.  A captured window and a group refuse the
+    schedule."""
+    step(f"reservoir overlap {update} {precision}")
+    pthr = _pthr()
+    o, g = make_pair(8, 3, 4, 10, 4, precision=precision, er_sweeps=20, update=update)
+    g.set_schedule(overlap_reservoir=1, graph_window=0)
+    oo, go = o.new_observables(), g.new_obs()
+    o.run(3, oo)
+    g.run(3, go)
+    assert_same_state(o, g, "overlapped run")
+    assert_same_obs(oo, g, go)
+    g.set_schedule(graph_window=2)
+    with pytest.raises(pthr.PthrError, match="plain launches"):
+        g.run(2)
+    _, g2 = make_pair(6, 2, 2, 7, 3, precision=precision, er_sweeps=12, update=update, seed=5)
+    with pytest.raises(pthr.PthrError, match="not supported in groups"):
+        pthr.Group([g, g2]).run(1, graph_window=0)
+    g.set_schedule(overlap_reservoir=0)
+    o.run(2)
+    g.run(2)
+    assert_same_state(o, g, "plain run after the refusals")
 
 
 def test_fp64_exact_exponential_every_test():
@@ -650,8 +680,21 @@ def test_autotune_picks_its_fastest_candidate_and_keeps_the_state():
     for f in ("threads_per_sample", "clone_split", "sample_split", "exp_early_out"):
         assert getattr(chosen, f) == getattr(best_sch, f), f
     assert {c.sample_split for c, _ in table} == {1, 2, 4}
+    # graph replays (the default window): no reservoir-overlap candidate
+    assert not any(c.overlap_reservoir for c, _ in table)
+    assert chosen.overlap_reservoir == 0
     for c, t in table:
         assert t > 0 and c.threads_per_sample * c.clone_split <= 1024 and c.clone_split in (1, 2, 4)
+    stepwise(o, g, 1, with_obs=False, check_each=False)
+    # plain launches: the fastest candidate is timed once more with the
+    # reservoir sweeps beside the Houdayer step
+    g.set_schedule(graph_window=0)
+    ms = g.autotune(1)
+    table = g.autotune_results()
+    assert [c.overlap_reservoir for c, _ in table] == [0] * (len(table) - 1) + [1]
+    best_sch, best_ms = min(table, key=lambda c: c[1])
+    assert abs(best_ms - ms) <= 1e-9 * ms and g.schedule().overlap_reservoir == best_sch.overlap_reservoir
+    g.set_schedule(overlap_reservoir=0, graph_window=16)
     stepwise(o, g, 1, with_obs=False, check_each=False)
 
 

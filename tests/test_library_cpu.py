@@ -130,5 +130,12 @@ def test_schedule_defaults_and_checks(lib):
         back = pthr.Schedule()
         assert lib.pthr_get_schedule(ctx, ctypes.byref(back)) == 0
         assert back.exp_filter == 0
+        # the reservoir sweeps beside the Houdayer step: off by default, 0 or 1
+        assert back.overlap_reservoir == 0
+        back.overlap_reservoir = 1
+        assert lib.pthr_set_schedule(ctx, ctypes.byref(back)) == 0
+        back.overlap_reservoir = 2
+        assert lib.pthr_set_schedule(ctx, ctypes.byref(back)) == pthr.PTHR_EINVAL
+        assert b"overlap_reservoir" in lib.pthr_last_error(ctx)
     finally:
         lib.pthr_destroy(ctx)
