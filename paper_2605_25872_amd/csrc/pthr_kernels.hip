@@ -1864,7 +1864,9 @@ __global__ __launch_bounds__(kMaxThreads) void micsa_kernel(Geo g, State st, Run
 // order (J_d of site i at d V + colour(i) V/2 + i/2, as the spin words), so
 // that a row's own words, the other colour's words of the same row and of
 // the rows at y -+ 1 and z -+ 1, and the six coupling rows it needs are
-// twelve contiguous vectors of H values, read with 8- or 16-byte LDS loads.
+// twelve contiguous vectors of H values, read with the widest LDS loads their
+// alignment allows (16 bytes when a row holds a multiple of 4 words, else 8
+// or 4).
 // Within a row x = x0 + 2k; its +x neighbour is the other colour's word
 // k + x0 and its -x neighbour (and coupling) word k + x0 - 1, both modulo H.
 // Each coupling takes the sign of the neighbour spin (bit 31 of the word
@@ -2060,12 +2062,13 @@ __device__ __forceinline__ void micsa_walk(uint32_t (&own)[H], const FP (&U)[H],
   }
 }
 
-// Row (y, z) of colour C, whose sites sit at x = X0 + 2k, from cur and J;
-// meanwhile the spin words of row (ny, nz) of colour nc load into nxt and,
-// once this row's sums are formed, its couplings into J.  A row never reads a
-// row of its own colour other than its own, and the first row of either
-// colour reads none of the rows the last row of the other colour writes, so
-// the early loads see final words.
+// One row of colour C, whose sites sit at x = X0 + 2k and whose own words
+// start at word `own` of the plane, from cur and J; meanwhile the spin words
+// of the row at `next` load into nxt and, once this row's sums are formed,
+// its couplings into J.  A row never reads a row of its own colour other
+// than its own, and the first row of either colour reads none of the rows
+// the last row of the other colour writes, so the early loads see final
+// words.
 template <typename FP, int H, int C, int X0>
 __device__ __forceinline__ void micsa_step(MicsaRow<H>& cur, MicsaRow<H>& nxt, MicsaJ<FP, H>& J, const uint32_t* P,
                                            uint32_t* Pw, const FP* Jc, int own, const RowOff& next, int sh,
