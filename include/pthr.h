@@ -237,7 +237,7 @@ typedef struct pthr_schedule {
                                 the PT sweeps and the Houdayer step, joined before the PT step (the
                                 reservoir clones are untouched by both until the exchange, Sec. 3).
                                 The library creates that stream and two events once per context.
-                                pthr_run with a captured window and pthr_group_run return
+                                pthr_run with graph_window > 0 and pthr_group_run return
                                 PTHR_EUNSUPPORTED for a context with 1. */
 } pthr_schedule;
 int pthr_get_schedule(const pthr_ctx *ctx, pthr_schedule *out);

@@ -643,8 +643,7 @@ int pthr_run(pthr_ctx* ctx, int64_t n_emcs, void* d_obs, void* stream) {
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int W = ctx->sch.graph_window;
   if (ctx->overlapping()) {
-    if (W > 0 && n_emcs >= W)
-      return ctx->fail(PTHR_EUNSUPPORTED, "overlap_reservoir runs as plain launches (graph_window = 0)");
+    if (W > 0) return ctx->fail(PTHR_EUNSUPPORTED, "overlap_reservoir runs as plain launches (graph_window = 0)");
     if (int rc = ctx->make_side()) return rc;
   }
   int64_t done = 0;

@@ -557,7 +557,7 @@ def test_every_schedule_gives_the_same_bits(precision):
             (128, 0, 1, 2, 1, 2, 1), (256, 700, 2, 1, 0, 1, 1), (128, 0, 0, 1, 1, 4, 1)):
         _, g = make_pair(8, 3, 4, 10, 4, precision=precision, er_sweeps=20)
         g.set_schedule(threads_per_sample=threads, exp_early_out=early, samples_per_launch=per, clone_split=split,
-                       exp_filter=filt, sample_split=parts, overlap_reservoir=over)
+                       exp_filter=filt, sample_split=parts, overlap_reservoir=over, graph_window=0)
         go = g.new_obs()
         g.run(2, go)
         got = (g.read_spins(), g.read_pt(), g.obs_arrays(go))
