@@ -251,9 +251,18 @@ def bench_mixed(args) -> dict:
             # each candidate timed over >= ~1.5e10 attempts, so that small lattices are not timed on one EMCS
             best = g.autotune(max(1, math.ceil(1.5e10 / attempts_per_emcs(w))))
             log(f"autotune L={w.L}: {best:.2f} ms/EMCS, {g.schedule().threads_per_sample} work-items, "
-                f"clone split {g.schedule().clone_split}, "
+                f"clone split {g.schedule().clone_split}, sample split {g.schedule().sample_split}, "
                 f"early-out below T = {g.schedule().exp_early_out / 1000:g}")
         members.append(g)
+    # each size's own sample split, for the run of one size after the other
+    alone_split = [g.schedule().sample_split for g in members]
+    if not args.split_group_samples:
+        # the sizes run side by side and fill the GPU together: splitting a
+        # size's samples over several workgroups (which pays when it runs
+        # alone, as the autotuner times it) only repeats per-word work here
+        for g in members:
+            g.set_schedule(sample_split=1)
+    group_split = [g.schedule().sample_split for g in members]
     group = pthr.Group(members)
     obs = [g.new_obs() for g in members]
     # one graph launch runs `window` EMCS of every size as parallel branches
@@ -266,9 +275,10 @@ def bench_mixed(args) -> dict:
     group.run(args.steps, obs, graph_window=window)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    # the same contexts one after the other, each with its own graph of the same window
-    for g, o in zip(members, obs):
-        g.set_schedule(graph_window=window)
+    # the same contexts one after the other, each with its own graph of the
+    # same window and the sample split it takes alone
+    for g, o, split in zip(members, obs, alone_split):
+        g.set_schedule(graph_window=window, sample_split=split)
         g.run(window, o)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
@@ -300,8 +310,9 @@ def bench_mixed(args) -> dict:
                    "members": [{"L": w.L, "samples": w.n_samples, "temperatures": w.n_temps,
                                 "threads_per_sample": g.schedule().threads_per_sample,
                                 "exp_early_out_below_T": g.schedule().exp_early_out / 1000,
-                                "clone_split": g.schedule().clone_split}
-                               for w, g in zip(batch, members)],
+                                "clone_split": g.schedule().clone_split,
+                                "sample_split_in_group": gs, "sample_split_alone": als}
+                               for w, g, gs, als in zip(batch, members, group_split, alone_split)],
                    "replicas": 4, "reservoir_clones": 4, "houdayer": args.mode},
         "attempts_per_emcs": att,
         "houdayer_moves_per_s": moves * args.steps / elapsed,
@@ -337,6 +348,8 @@ def main() -> int:
                     help="reservoir sweeps on a second stream beside the Houdayer step (plain launches)")
     ap.add_argument("--plain-launches", action="store_true", help="time pthr_run as plain launches, no graph")
     ap.add_argument("--no-autotune", action="store_true", help="mixed batch: keep the default schedules")
+    ap.add_argument("--split-group-samples", action="store_true",
+                    help="mixed batch: keep the sample split the schedules pick for each size alone")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy a MIB-MiB device buffer 3 times (HBM counter calibration)")
     ap.add_argument("--reservoir-decorrelation", action="store_true",
