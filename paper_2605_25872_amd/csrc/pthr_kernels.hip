@@ -185,7 +185,7 @@ __device__ __forceinline__ uint32_t shift_in(uint32_t f, uint64_t lanes) {
 // "u <= 2^t", t = -(beta log2 e) dE.  With `early` the binade bracket
 // 2^(k-1) < value < 2^(k+1) decides it without the polynomial unless u falls
 // inside the bracket; both forms return the same decision.
-// with_sign(J, s) is |J| carrying the sign bit of s (bit 31): one v_bfi_b32.
+// flip_sign(v, s) is v with its sign flipped where bit 31 of s is set.
 template <typename FP>
 struct Prec;
 template <>
@@ -252,14 +252,9 @@ struct Prec<double> {
     const double a = x >= -708.0 ? p : 0.0;
     return __builtin_amdgcn_ballot_w64(__builtin_fma(u, a, u) < (dE > 0.0 ? a : 1.0));
   }
-  static __device__ __forceinline__ bool negative(double J) { return __double2hiint(J) < 0; }
-  static __device__ __forceinline__ double magnitude(double J) {
-    return __hiloint2double(__double2hiint(J) & 0x7FFFFFFF, __double2loint(J));
-  }
-  // |J| (sign bit clear) with the sign bit of s
-  static __device__ __forceinline__ double with_sign(double Jabs, uint32_t s) {
-    return __hiloint2double(static_cast<int>((s & 0x80000000u) | static_cast<uint32_t>(__double2hiint(Jabs))),
-                            __double2loint(Jabs));
+  static __device__ __forceinline__ double flip_sign(double v, uint32_t s) {
+    return __hiloint2double(static_cast<int>((s & 0x80000000u) ^ static_cast<uint32_t>(__double2hiint(v))),
+                            __double2loint(v));
   }
 };
 template <>
@@ -304,11 +299,8 @@ struct Prec<float> {
     const float u = fw * 0x1p-32f;
     return __builtin_amdgcn_ballot_w64(__builtin_fmaf(u, a, u) < (dE > 0.0f ? a : 1.0f));
   }
-  static __device__ __forceinline__ bool negative(float J) { return __float_as_int(J) < 0; }
-  static __device__ __forceinline__ float magnitude(float J) { return __uint_as_float(__float_as_uint(J) & 0x7FFFFFFFu); }
-  // |J| (sign bit clear) with the sign bit of s
-  static __device__ __forceinline__ float with_sign(float Jabs, uint32_t s) {
-    return __uint_as_float((s & 0x80000000u) | __float_as_uint(Jabs));
+  static __device__ __forceinline__ float flip_sign(float v, uint32_t s) {
+    return __uint_as_float((s & 0x80000000u) ^ __float_as_uint(v));
   }
 };
 
@@ -517,44 +509,39 @@ __device__ void rebuild_beta(const Geo& g, const Lds& s, const FP* beta) {
 // ------------------------------------------------------------------ Metropolis
 // Couplings of one site as the sweep uses them.  The local field is summed
 // axis by axis, h = ((t[+x] + t[-x]) + (t[+y] + t[-y])) + (t[+z] + t[-z]) with
-// t[d] = J_d s_i s_j(d) (the s_i factor makes dE = 2h).  For an axis with
-// couplings A = J[+], B = J[-]: if the two terms have the same sign their sum
-// is that sign times P = |A| + |B|, otherwise it is the sign of the + term times
-// M = |A| - |B|; both are rounded once, exactly like the sum of the two signed
-// terms.  FP32 stores P and |M| per axis; FP64 stores |J| per direction.
-// Every stored magnitude is doubled (exact), so the same sum yields dE = 2h
-// with identical rounding.
+// t[d] = J_d s_i s_j(d) (the s_i factor makes dE = 2h).  With r_d = s_i s_j(d)
+// and the couplings A = J[+], B = J[-] of an axis, the axis sum is r_+ (A + B)
+// where r_+ = r_-, and r_+ (A - B) where they differ; rounding is symmetric,
+// so the signed sum rounded once equals r_+ times the rounded A + B or A - B.
+// FP32 stores A + B and A - B per axis; FP64 stores J_d per direction.  Every
+// stored value is doubled (exact), so the same sums yield dE = 2h with
+// identical rounding.  The signs of the couplings live in these values, so
+// the sign words of a word are built from the spin words alone.
 template <typename FP>
 struct SiteJ {
-  FP v[6];        // FP32: 2P_x, 2|M_x|, 2P_y, ...; FP64: 2|J_d| for d = 0..5
-  uint32_t sign;  // bits 0..5: J_d < 0; bits 8..10: M_axis < 0 (FP32)
+  FP v[6];  // FP32: 2(A_x + B_x), 2(A_x - B_x), 2(A_y + B_y), ...; FP64: 2 J_d for d = 0..5
 };
 
 template <typename FP>
 __device__ __forceinline__ SiteJ<FP> make_site_j(const FP (&J)[6]) {
   SiteJ<FP> r;
-  r.sign = 0;
-#pragma unroll
-  for (int d = 0; d < 6; ++d) r.sign |= static_cast<uint32_t>(Prec<FP>::negative(J[d])) << d;
   if constexpr (sizeof(FP) == 4) {
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-      const float A = Prec<float>::magnitude(J[2 * a]), B = Prec<float>::magnitude(J[2 * a + 1]);
-      const float M = A - B;
-      r.v[2 * a] = 2.0f * (A + B);
-      r.v[2 * a + 1] = 2.0f * Prec<float>::magnitude(M);
-      r.sign |= static_cast<uint32_t>(Prec<float>::negative(M)) << (8 + a);
+      r.v[2 * a] = 2.0f * (J[2 * a] + J[2 * a + 1]);
+      r.v[2 * a + 1] = 2.0f * (J[2 * a] - J[2 * a + 1]);
     }
   } else {
 #pragma unroll
-    for (int d = 0; d < 6; ++d) r.v[d] = FP(2) * Prec<FP>::magnitude(J[d]);
+    for (int d = 0; d < 6; ++d) r.v[d] = FP(2) * J[d];
   }
   return r;
 }
 
-// Sign words of one 32-clone word at one site: bit b of x[d] is the sign bit
-// of t[d] for clone clone0+b; FP32 also keeps, per axis, y (the two terms have
-// unlike signs) and z (sign bit of the axis sum).
+// Sign words of one 32-clone word at one site: bit b concerns clone clone0+b.
+// FP64: x[d] is set where r_d = -1 (own spin and neighbour d differ).  FP32:
+// per axis, y where r_+ and r_- differ (the two neighbours differ: the own
+// spin cancels) and z where r_+ = -1.
 struct WordSigns {
   uint32_t x[6], y[3], z[3];
 };
@@ -634,7 +621,7 @@ __device__ __forceinline__ void attempt_group(const Geo& g, const FP* __restrict
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
         const uint32_t pick = static_cast<uint32_t>(static_cast<int32_t>(rs.s[a]) >> 31);
-        ax[a] = Prec<float>::with_sign(__uint_as_float(bitfield_insert(pick, __float_as_uint(sj.v[2 * a + 1]),
+        ax[a] = Prec<float>::flip_sign(__uint_as_float(bitfield_insert(pick, __float_as_uint(sj.v[2 * a + 1]),
                                                                        __float_as_uint(sj.v[2 * a]))),
                                        rs.s[3 + a]);
       }
@@ -668,9 +655,9 @@ __device__ __forceinline__ void attempt_group(const Geo& g, const FP* __restrict
       float ax[3];
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
-        // all ones where the axis' two terms have unlike signs: take |M|, else P
+        // all ones where r_+ and r_- differ: take A - B, else A + B
         const uint32_t pick = static_cast<uint32_t>(static_cast<int32_t>(rs.s[a]) >> 31);
-        ax[a] = Prec<float>::with_sign(__uint_as_float(bitfield_insert(pick, __float_as_uint(sj.v[2 * a + 1]),
+        ax[a] = Prec<float>::flip_sign(__uint_as_float(bitfield_insert(pick, __float_as_uint(sj.v[2 * a + 1]),
                                                                        __float_as_uint(sj.v[2 * a]))),
                                        rs.s[3 + a]);
       }
@@ -678,7 +665,7 @@ __device__ __forceinline__ void attempt_group(const Geo& g, const FP* __restrict
     } else {
       FP tt[6];
 #pragma unroll
-      for (int d = 0; d < 6; ++d) tt[d] = Prec<FP>::with_sign(sj.v[d], rs.s[d]);
+      for (int d = 0; d < 6; ++d) tt[d] = Prec<FP>::flip_sign(sj.v[d], rs.s[d]);
       dE = ((tt[0] + tt[1]) + (tt[2] + tt[3])) + (tt[4] + tt[5]);
     }
 #pragma unroll
@@ -745,28 +732,36 @@ __device__ __forceinline__ void attempt_group(const Geo& g, const FP* __restrict
   }
 }
 
+// The word `b` bytes into a word plane.
+__device__ __forceinline__ uint32_t* word_at(uint32_t* plane, int b) {
+  return reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(plane) + b);
+}
+
 // All attempts of one word (clones clone0 .. clone0+nbits-1, random-number
-// indices n0 .. n0+nbits-1 with n0 a multiple of 4) at one site.  beta per
+// indices n0 .. n0+nbits-1 with n0 a multiple of 4) at one site (own word and
+// neighbour words at byte offsets self_b and nb[d] of the plane).  beta per
 // clone comes from uniform (scalar) loads.  Blocks are visited from the last
 // to the first, so clone clone0+b ends at bit b of the flip mask; the bits of
 // a partial last block's surplus indices land above bit nbits-1 and are
 // masked off.
 template <typename FP, bool kMaybeEarly, bool kSplit, bool kHB>
-__device__ __forceinline__ void update_word(const Geo& g, const FP* __restrict__ bc, uint32_t* plane, int self_idx,
+__device__ __forceinline__ void update_word(const Geo& g, const FP* __restrict__ bc, uint32_t* plane, int self_b,
                                             const int (&nb)[6], const SiteJ<FP>& sj, uint32_t c0w, uint32_t t,
                                             int sample, int clone0, int n0, int nbits, int early_beta_bits,
                                             int f, int F) {
   constexpr int G = sizeof(FP) == 8 ? 2 : 4;
-  const uint32_t self = plane[self_idx];
+  const uint32_t self = *word_at(plane, self_b);
   WordSigns ws;
-#pragma unroll
-  for (int d = 0; d < 6; ++d) ws.x[d] = self ^ plane[nb[d]] ^ (0u - ((sj.sign >> d) & 1u));
   if constexpr (sizeof(FP) == 4) {
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-      ws.y[a] = ws.x[2 * a] ^ ws.x[2 * a + 1];
-      ws.z[a] = ws.x[2 * a] ^ (ws.y[a] & (0u - ((sj.sign >> (8 + a)) & 1u)));
+      const uint32_t np = *word_at(plane, nb[2 * a]);
+      ws.y[a] = np ^ *word_at(plane, nb[2 * a + 1]);
+      ws.z[a] = self ^ np;
     }
+  } else {
+#pragma unroll
+    for (int d = 0; d < 6; ++d) ws.x[d] = self ^ *word_at(plane, nb[d]);
   }
   const int g_lo = n0 / G, g_hi = (n0 + nbits - 1) / G;
   // FP64 Metropolis words whose float bounds left a lane open are redone with
@@ -808,7 +803,7 @@ __device__ __forceinline__ void update_word(const Geo& g, const FP* __restrict__
     }
     if constexpr (kRejectBits<FP, kMaybeEarly, kHB>) flips = ~flips;
     if (nbits < 32) flips &= (1u << nbits) - 1u;
-    plane[self_idx] = self ^ flips;
+    *word_at(plane, self_b) = self ^ flips;
   } else {
     // F waves share the word: this one takes groups g_lo + f, g_lo + f + F, ...;
     // each group's decisions land at their own bits, and the flips of the F
@@ -838,8 +833,57 @@ __device__ __forceinline__ void update_word(const Geo& g, const FP* __restrict__
     if constexpr (kRejectBits<FP, kMaybeEarly, kHB>) part = ~part & ((1u << G) - 1u);
     flips |= part << (G * (first - g_lo));
     if (nbits < 32) flips &= (1u << nbits) - 1u;
-    if (flips) atomicXor(&plane[self_idx], flips);
+    if (flips) atomicXor(word_at(plane, self_b), flips);
   }
+}
+
+// All attempts of two 16-clone words at two sites a and b of one colour, in
+// one 32-clone pass (FP32): the spin words of a fill bits 0..15 of the words
+// the pass works on, those of b bits 16..31, so the pass pays once for what a
+// word costs besides its attempts (sign words, pipeline fill and drain).  The
+// clones of b are visited first, with b's couplings and Philox counter (c0_b),
+// then those of a; the next block is produced beside the current group
+// throughout, also across the change of site.  Both words hold clones
+// clone0 .. clone0+15 with random-number indices n0 .. n0+15 (n0 a multiple
+// of 4); decisions and results are those of two update_word calls.
+template <typename FP, bool kMaybeEarly, bool kHB>
+__device__ __forceinline__ void update_pair16(const Geo& g, const FP* __restrict__ bc, uint32_t* plane, int self_a,
+                                              const int (&nb_a)[6], const SiteJ<FP>& sj_a, uint32_t c0_a, int self_b,
+                                              const int (&nb_b)[6], const SiteJ<FP>& sj_b, uint32_t c0_b,
+                                              uint32_t t, int sample, int clone0, int n0, int early_beta_bits) {
+  static_assert(sizeof(FP) == 4, "two 16-clone words per pass: FP32 forms");
+  constexpr int G = 4;
+  constexpr bool kUsesFloats = kRejectBits<FP, kMaybeEarly, kHB> || kHB;
+  // low half of lo in bits 0..15, low half of hi in bits 16..31
+  auto merge = [](uint32_t lo, uint32_t hi) { return __builtin_amdgcn_perm(hi, lo, 0x05040100u); };
+  const uint32_t wa = *word_at(plane, self_a), wb = *word_at(plane, self_b);
+  const uint32_t self = merge(wa, wb);
+  RunSigns rs;  // as run_signs: y[0..2] then z[0..2], bit 31 = the first clone visited
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const uint32_t np = merge(*word_at(plane, nb_a[2 * a]), *word_at(plane, nb_b[2 * a]));
+    rs.s[a] = np ^ merge(*word_at(plane, nb_a[2 * a + 1]), *word_at(plane, nb_b[2 * a + 1]));
+    rs.s[3 + a] = self ^ np;
+  }
+  const int g_lo = n0 / G, g_hi = g_lo + 16 / G - 1;
+  uint32_t fl = 0;
+  uint64_t open = 0;
+  Block blk = philox10(c0_b, t, static_cast<uint32_t>(g_hi), static_cast<uint32_t>(sample), g.key0, g.key1);
+  auto group = [&](const SiteJ<FP>& sj, int grp, uint32_t c_next, int grp_next, bool last) {
+    const Floats4 fw = kUsesFloats ? to_floats(blk) : Floats4{};
+    Block next{};
+    if (!last)
+      next = philox10(c_next, t, static_cast<uint32_t>(grp_next), static_cast<uint32_t>(sample), g.key0, g.key1);
+    attempt_group<FP, kMaybeEarly, kHB>(g, bc, rs, sj, blk, fw, grp, n0, clone0, 16, early_beta_bits, fl, open);
+    blk = next;
+  };
+  for (int grp = g_hi; grp > g_lo; --grp) group(sj_b, grp, c0_b, grp - 1, false);
+  group(sj_b, g_lo, c0_a, g_hi, false);
+  for (int grp = g_hi; grp > g_lo; --grp) group(sj_a, grp, c0_a, grp - 1, false);
+  group(sj_a, g_lo, 0u, 0, true);
+  if constexpr (kRejectBits<FP, kMaybeEarly, kHB>) fl = ~fl;
+  *word_at(plane, self_a) = wa ^ (fl & 0xFFFFu);
+  *word_at(plane, self_b) = wb ^ (fl >> 16);
 }
 
 // n_pt sweeps of the PT clones and n_er sweeps of the ER clones, interleaved
@@ -898,6 +942,10 @@ __device__ __forceinline__ void sweep_phase(const Geo& g, const Lds& s, const FP
   // random-number index of the first reservoir clone: the first multiple of 4
   // at or above N_PT (PT clones use their own ids)
   const int n_er0 = (g.NPT + 3) / 4 * 4;
+  // FP32 with two or more sites of a colour per work-item: a last reservoir
+  // word of 16 clones is swept two sites per pass (update_pair16)
+  constexpr bool kPairs = sizeof(FP) == 4 && CH >= 4 && !kSplit;
+  const int er_pair_words = kPairs && g.NER % 32 == 16 ? 1 : 0;
   for (int mm = 0; mm < n_m; ++mm) {
     const bool pt_on = mm < n_pt, er_on = mm < n_er && g.NER > 0;
     const uint32_t c0pt = ctr_word(0, static_cast<uint32_t>(m_pt0 + mm), kMetro);
@@ -909,35 +957,63 @@ __device__ __forceinline__ void sweep_phase(const Geo& g, const Lds& s, const FP
       constexpr int slot = kAllInRegs ? colour : 0;
       if constexpr (!kAllInRegs) load_couplings(0, colour);
       if (own.owns) {
+        // own sites of this colour: natural index, byte offsets of the own
+        // and neighbour words within a word plane (one add per address)
+        int site_i[CH / 2], self_bq[CH / 2], nbq[CH / 2][6];
 #pragma unroll
         for (int q = 0; q < CH / 2; ++q) {
           const int i0 = own.first + 2 * q;  // x even
           const int x0 = pq[q] & 1023, y = (pq[q] >> 10) & 1023, z = pq[q] >> 20;
           const int sel = (y + z + colour) & 1;
           const Site st{i0 + sel, x0 + sel, y, z};
-          int nb[6];
+          site_i[q] = st.i;
 #pragma unroll
-          for (int d = 0; d < 6; ++d) nb[d] = plane_idx(neighbour(st, d, g.L), colour ^ 1, g.Vh);
-          const int self_idx = colour * g.Vh + (i0 >> 1);
+          for (int d = 0; d < 6; ++d) nbq[q][d] = 4 * plane_idx(neighbour(st, d, g.L), colour ^ 1, g.Vh);
+          self_bq[q] = 4 * (colour * g.Vh + (i0 >> 1));
+        }
+#pragma unroll
+        for (int q = 0; q < CH / 2; ++q) {
+          const int(&nb)[6] = nbq[q];
+          const int self_b = self_bq[q];
           // one word of clones: early-out form or not (a uniform choice per word; never for heat bath)
           auto word = [&](bool early, int w, uint32_t c0, int clone0, int n0, int nbits) {
             if (!kHB && early)
-              update_word<FP, !kHB, kSplit, kHB>(g, bc, s.sp + size_t(w) * g.V, self_idx, nb, sj[slot][q],
-                                                 c0 | static_cast<uint32_t>(st.i), t, sample, clone0, n0, nbits,
+              update_word<FP, !kHB, kSplit, kHB>(g, bc, s.sp + size_t(w) * g.V, self_b, nb, sj[slot][q],
+                                                 c0 | static_cast<uint32_t>(site_i[q]), t, sample, clone0, n0, nbits,
                                                  early_bits, f, FP_);
             else
-              update_word<FP, false, kSplit, kHB>(g, bc, s.sp + size_t(w) * g.V, self_idx, nb, sj[slot][q],
-                                                  c0 | static_cast<uint32_t>(st.i), t, sample, clone0, n0, nbits,
-                                                  early_bits, f, FP_);
+              update_word<FP, false, kSplit, kHB>(g, bc, s.sp + size_t(w) * g.V, self_b, nb, sj[slot][q],
+                                                  c0 | static_cast<uint32_t>(site_i[q]), t, sample, clone0, n0,
+                                                  nbits, early_bits, f, FP_);
           };
           if (pt_on)
             for (int w = 0; w < g.NWPT; ++w) word(pt_early, w, c0pt, 32 * w, 32 * w, min(32, g.NPT - 32 * w));
           if (er_on)
-            for (int w = g.NWPT; w < g.NW; ++w) {
+            for (int w = g.NWPT; w < g.NW - er_pair_words; ++w) {
               const int e0 = 32 * (w - g.NWPT);
               // every reservoir clone sits at T_max: one uniform choice of path per word
               word(er_early, w, c0er, g.NPT + e0, n_er0 + e0, min(32, g.NER - e0));
             }
+        }
+        if constexpr (kPairs) {
+          // the last reservoir word, 16 clones per site: two sites per pass
+          if (er_on && er_pair_words) {
+            const int w = g.NW - 1, e0 = 32 * (w - g.NWPT);
+            uint32_t* plane = s.sp + size_t(w) * g.V;
+#pragma unroll
+            for (int q = 0; q + 1 < CH / 2; q += 2) {
+              const uint32_t ca = c0er | static_cast<uint32_t>(site_i[q]);
+              const uint32_t cb = c0er | static_cast<uint32_t>(site_i[q + 1]);
+              if (!kHB && er_early)
+                update_pair16<FP, !kHB, kHB>(g, bc, plane, self_bq[q], nbq[q], sj[slot][q], ca, self_bq[q + 1],
+                                             nbq[q + 1], sj[slot][q + 1], cb, t, sample, g.NPT + e0, n_er0 + e0,
+                                             early_bits);
+              else
+                update_pair16<FP, false, kHB>(g, bc, plane, self_bq[q], nbq[q], sj[slot][q], ca, self_bq[q + 1],
+                                              nbq[q + 1], sj[slot][q + 1], cb, t, sample, g.NPT + e0, n_er0 + e0,
+                                              early_bits);
+            }
+          }
         }
       }
     };

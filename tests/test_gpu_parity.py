@@ -554,7 +554,10 @@ def test_every_schedule_gives_the_same_bits(precision):
             (128, 1000, 2, 1, 1, 1, 0), (256, 0, 0, 4, 1, 1, 0), (128, 700, 0, 2, 1, 1, 0), (128, 0, 2, 8 // 2, 1, 1, 0),
             (256, 0, 0, 1, 0, 1, 0), (128, 0, 0, 2, 0, 1, 0), (256, 0, 0, 1, 1, 2, 0), (128, 0, 0, 2, 1, 4, 0),
             (128, 700, 2, 1, 1, 2, 0), (256, 0, 0, 1, 0, 4, 0), (128, 0, 1, 4, 0, 2, 0), (256, 0, 0, 1, 1, 1, 1),
-            (128, 0, 1, 2, 1, 2, 1), (256, 700, 2, 1, 0, 1, 1), (128, 0, 0, 1, 1, 4, 1)):
+            (128, 0, 1, 2, 1, 2, 1), (256, 700, 2, 1, 0, 1, 1), (128, 0, 0, 1, 1, 4, 1),
+            (128, 0, 0, 1, 1, 1, 0), (64, 700, 0, 1, 1, 1, 0), (64, 0, 2, 1, 1, 1, 0)):
+        if threads == 64 and precision == "fp64":
+            continue  # 8 sites per work-item: FP32 only
         _, g = make_pair(8, 3, 4, 10, 4, precision=precision, er_sweeps=20)
         g.set_schedule(threads_per_sample=threads, exp_early_out=early, samples_per_launch=per, clone_split=split,
                        exp_filter=filt, sample_split=parts, overlap_reservoir=over, graph_window=0)
@@ -612,6 +615,31 @@ def test_fp64_exact_exponential_every_test():
     stepwise(o, g, 2)
     g.set_schedule(clone_split=4)
     stepwise(o, g, 2)
+
+
+@pytest.mark.parametrize("L, NR, NERG, threads, update, early", [
+    (10, 4, 4, 256, "metropolis", None),  # 4 sites per work-item (one pair per colour), rows split across chunks
+    (10, 2, 8, 128, "heatbath", None),    # 8 sites per work-item: two pairs per colour
+    (6, 4, 12, 64, "metropolis", None),   # 48 reservoir clones: a full word, then a 16-clone word in pairs
+    (10, 4, 4, 256, "metropolis", 0),     # every clone on the exp early-out path
+    (8, 4, 4, 64, "heatbath", None),
+])
+def test_reservoir_words_two_sites_per_pass(L, NR, NERG, threads, update, early):
+    """FP32 sweeps a last reservoir word of 16 clones two sites at a time (one
+    32-clone pass over both sites' words) when a work-item owns two or more
+    sites of a colour; every sub-step against the oracle, then a fused run."""
+    step(f"reservoir pairs L={L} NR={NR} NERG={NERG} threads={threads} {update} early={early}")
+    o, g = make_pair(L, 3, NR, 8, NERG, precision="fp32", er_sweeps=24, t_range=(0.3, 1.6), update=update)
+    g.set_schedule(threads_per_sample=threads, clone_split=1, sample_split=1)
+    if early is not None:
+        g.set_schedule(exp_early_out=early)
+    stepwise(o, g, 2)
+    oo, go = o.new_observables(), g.new_obs()
+    o.run(2, oo)
+    g.run(2, go)
+    g.check()
+    assert_same_state(o, g, "fused run")
+    assert_same_obs(oo, g, go)
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
