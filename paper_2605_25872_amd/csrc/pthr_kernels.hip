@@ -575,20 +575,39 @@ __device__ __forceinline__ RunSigns run_signs(const WordSigns& ws, int b_top) {
   return r;
 }
 
-// The Metropolis attempts of random-number indices n = grp*G + j (j from G-1
-// down to 0) of one word, all drawing on Philox block grp.  The word's clones
-// are clone0 + (n - n0), n0 = the index of clone0 (a multiple of G); indices
-// past the word's last clone (a partial last block) run on the next entries of
-// the clone-factor table and are discarded by the caller.  Accept iff dE <= 0 or u < exp(-beta dE).
-// kMaybeEarly: clones colder than the early-out threshold may decide from the
-// binade of exp(x).  kHB: heat-bath test instead of Metropolis (no early-out).
-// Each decision is shifted in at bit 0 of `flips`.  `rs` holds the sign words
-// positioned for the group's first (highest) clone and is advanced past the
-// group.
+// attempt_group: the Metropolis attempts of the G clones that draw on one
+// Philox block (random-number indices n = grp*G + j, j from G-1 down to 0),
+// with their clone factors; in a partial last block of a word the surplus
+// attempts are discarded by the caller.  Accept iff dE <= 0 or
+// u < exp(-beta dE).  kMaybeEarly: clones colder than the early-out threshold
+// may decide from the binade of exp(x).  kHB: heat-bath test instead of
+// Metropolis (no early-out).  Each decision is shifted in at bit 0 of
+// `flips`.  `rs` holds the sign words positioned for the group's first
+// (highest) clone and is advanced past the group.
 // attempt_group shifts in reject bits instead of accept bits (FP32 Metropolis
 // without early-out).
 template <typename FP, bool kMaybeEarly, bool kHB>
 constexpr bool kRejectBits = sizeof(FP) == 4 && !kMaybeEarly && !kHB;
+
+// The clone factors (beta, or beta log2 e) of the G clones of one Philox
+// block.
+template <typename FP>
+struct Betas {
+  FP b[sizeof(FP) == 8 ? 2 : 4];
+};
+// Those of block grp of a word (clone0, n0 as for update_word), one
+// contiguous (scalar) load; in a partial last block the surplus entries belong
+// to the next clones or to the table's padding, and their decisions are
+// discarded.
+template <typename FP>
+__device__ __forceinline__ Betas<FP> group_betas(const FP* __restrict__ bc, int clone0, int grp, int n0) {
+  constexpr int G = sizeof(FP) == 8 ? 2 : 4;
+  const FP* __restrict__ bg = bc + (clone0 + grp * G - n0);
+  Betas<FP> r;
+#pragma unroll
+  for (int j = 0; j < G; ++j) r.b[j] = bg[j];
+  return r;
+}
 
 // FP64 Metropolis (branch-free form): decisions come from the float bound
 // on exp.  With kDefer the lanes it leaves open are added to `open` and the
@@ -597,18 +616,11 @@ constexpr bool kRejectBits = sizeof(FP) == 4 && !kMaybeEarly && !kHB;
 // once.  fw: float(w) of the block's words, read by the FP32 Metropolis test
 // without early-out and by the FP32 heat-bath test (the other forms read blk).
 template <typename FP, bool kMaybeEarly, bool kHB, bool kExact = false, bool kDefer = false>
-__device__ __forceinline__ void attempt_group(const Geo& g, const FP* __restrict__ bc, RunSigns& rs,
-                                              const SiteJ<FP>& sj, const Block& blk, const Floats4& fw, int grp,
-                                              int n0, int clone0, int nbits, int early_beta_bits, uint32_t& flips,
-                                              uint64_t& open) {
+__device__ __forceinline__ void attempt_group(const Geo& g, const Betas<FP>& betas, RunSigns& rs,
+                                              const SiteJ<FP>& sj, const Block& blk, const Floats4& fw,
+                                              int early_beta_bits, uint32_t& flips, uint64_t& open) {
   constexpr int G = sizeof(FP) == 8 ? 2 : 4;  // clones per Philox block
-  // the factors of the block's G clones, one contiguous (scalar) load; in a
-  // partial last block the surplus entries belong to the next clones or to
-  // the table's padding, and their decisions are discarded
-  const FP* __restrict__ bg = bc + (clone0 + grp * G - n0);
-  FP beta[G];
-#pragma unroll
-  for (int j = 0; j < G; ++j) beta[j] = bg[j];
+  const FP(&beta)[G] = betas.b;
   if constexpr (kRejectBits<FP, kMaybeEarly, kHB>) {
     // FP32 Metropolis, branch-free: the same steps as reject_sign, taken for
     // the group's clones side by side so that every step offers the SIMD G
@@ -788,12 +800,12 @@ __device__ __forceinline__ void update_word(const Geo& g, const FP* __restrict__
         const Floats4 fw = kUsesFloats ? to_floats(blk) : kBits53 ? to_bits53(blk) : Floats4{};
         const Block next =
             philox10(c0w, t, static_cast<uint32_t>(grp - 1), static_cast<uint32_t>(sample), g.key0, g.key1);
-        attempt_group<FP, kMaybeEarly, kHB, kExact, kRedo>(g, bc, rs, sj, blk, fw, grp, n0, clone0, nbits,
+        attempt_group<FP, kMaybeEarly, kHB, kExact, kRedo>(g, group_betas(bc, clone0, grp, n0), rs, sj, blk, fw,
                                                            early_beta_bits, fl, open);
         blk = next;
       }
       const Floats4 fw = kUsesFloats ? to_floats(blk) : kBits53 ? to_bits53(blk) : Floats4{};
-      attempt_group<FP, kMaybeEarly, kHB, kExact, kRedo>(g, bc, rs, sj, blk, fw, g_lo, n0, clone0, nbits,
+      attempt_group<FP, kMaybeEarly, kHB, kExact, kRedo>(g, group_betas(bc, clone0, g_lo, n0), rs, sj, blk, fw,
                                                          early_beta_bits, fl, open);
       return fl;
     };
@@ -819,8 +831,8 @@ __device__ __forceinline__ void update_word(const Geo& g, const FP* __restrict__
           philox10(c0w, t, static_cast<uint32_t>(grp - F), static_cast<uint32_t>(sample), g.key0, g.key1);
       uint32_t part = 0;
       RunSigns rs = run_signs<FP>(ws, grp * G + G - 1 - n0);
-      attempt_group<FP, kMaybeEarly, kHB>(g, bc, rs, sj, blk, fw, grp, n0, clone0, nbits, early_beta_bits, part,
-                                          open);
+      attempt_group<FP, kMaybeEarly, kHB>(g, group_betas(bc, clone0, grp, n0), rs, sj, blk, fw, early_beta_bits,
+                                          part, open);
       if constexpr (kRejectBits<FP, kMaybeEarly, kHB>) part = ~part & ((1u << G) - 1u);
       flips |= part << (G * (grp - g_lo));
       blk = next;
@@ -828,8 +840,8 @@ __device__ __forceinline__ void update_word(const Geo& g, const FP* __restrict__
     uint32_t part = 0;
     RunSigns rs = run_signs<FP>(ws, first * G + G - 1 - n0);
     const Floats4 fw = kUsesFloats ? to_floats(blk) : Floats4{};
-    attempt_group<FP, kMaybeEarly, kHB>(g, bc, rs, sj, blk, fw, first, n0, clone0, nbits, early_beta_bits, part,
-                                        open);
+    attempt_group<FP, kMaybeEarly, kHB>(g, group_betas(bc, clone0, first, n0), rs, sj, blk, fw, early_beta_bits,
+                                        part, open);
     if constexpr (kRejectBits<FP, kMaybeEarly, kHB>) part = ~part & ((1u << G) - 1u);
     flips |= part << (G * (first - g_lo));
     if (nbits < 32) flips &= (1u << nbits) - 1u;
@@ -865,22 +877,36 @@ __device__ __forceinline__ void update_pair16(const Geo& g, const FP* __restrict
     rs.s[a] = np ^ merge(*word_at(plane, nb_a[2 * a + 1]), *word_at(plane, nb_b[2 * a + 1]));
     rs.s[3 + a] = self ^ np;
   }
-  const int g_lo = n0 / G, g_hi = g_lo + 16 / G - 1;
+  const int g_lo = n0 / G;
+  // every reservoir clone sits at T_max: one clone factor for the pass
+  const FP b = bc[clone0];
+  const Betas<FP> betas{{b, b, b, b}};
   uint32_t fl = 0;
   uint64_t open = 0;
-  Block blk = philox10(c0_b, t, static_cast<uint32_t>(g_hi), static_cast<uint32_t>(sample), g.key0, g.key1);
-  auto group = [&](const SiteJ<FP>& sj, int grp, uint32_t c_next, int grp_next, bool last) {
+  const uint32_t smp = static_cast<uint32_t>(sample);
+  Block blk = philox10(c0_b, t, static_cast<uint32_t>(g_lo + 3), smp, g.key0, g.key1);
+  for (int grp = g_lo + 3; grp > g_lo; --grp) {
     const Floats4 fw = kUsesFloats ? to_floats(blk) : Floats4{};
-    Block next{};
-    if (!last)
-      next = philox10(c_next, t, static_cast<uint32_t>(grp_next), static_cast<uint32_t>(sample), g.key0, g.key1);
-    attempt_group<FP, kMaybeEarly, kHB>(g, bc, rs, sj, blk, fw, grp, n0, clone0, 16, early_beta_bits, fl, open);
+    const Block next = philox10(c0_b, t, static_cast<uint32_t>(grp - 1), smp, g.key0, g.key1);
+    attempt_group<FP, kMaybeEarly, kHB>(g, betas, rs, sj_b, blk, fw, early_beta_bits, fl, open);
     blk = next;
-  };
-  for (int grp = g_hi; grp > g_lo; --grp) group(sj_b, grp, c0_b, grp - 1, false);
-  group(sj_b, g_lo, c0_a, g_hi, false);
-  for (int grp = g_hi; grp > g_lo; --grp) group(sj_a, grp, c0_a, grp - 1, false);
-  group(sj_a, g_lo, 0u, 0, true);
+  }
+  {
+    const Floats4 fw = kUsesFloats ? to_floats(blk) : Floats4{};
+    const Block next = philox10(c0_a, t, static_cast<uint32_t>(g_lo + 3), smp, g.key0, g.key1);
+    attempt_group<FP, kMaybeEarly, kHB>(g, betas, rs, sj_b, blk, fw, early_beta_bits, fl, open);
+    blk = next;
+  }
+  for (int grp = g_lo + 3; grp > g_lo; --grp) {
+    const Floats4 fw = kUsesFloats ? to_floats(blk) : Floats4{};
+    const Block next = philox10(c0_a, t, static_cast<uint32_t>(grp - 1), smp, g.key0, g.key1);
+    attempt_group<FP, kMaybeEarly, kHB>(g, betas, rs, sj_a, blk, fw, early_beta_bits, fl, open);
+    blk = next;
+  }
+  {
+    const Floats4 fw = kUsesFloats ? to_floats(blk) : Floats4{};
+    attempt_group<FP, kMaybeEarly, kHB>(g, betas, rs, sj_a, blk, fw, early_beta_bits, fl, open);
+  }
   if constexpr (kRejectBits<FP, kMaybeEarly, kHB>) fl = ~fl;
   *word_at(plane, self_a) = wa ^ (fl & 0xFFFFu);
   *word_at(plane, self_b) = wb ^ (fl >> 16);
