@@ -208,7 +208,11 @@ int pthr_get_state(pthr_ctx *ctx, void *blob, size_t bytes, void *stream);
 int pthr_set_state(pthr_ctx *ctx, const void *blob, size_t bytes, void *stream);
 
 /* Launch schedule.  threads_per_sample: work-items per sample workgroup (each
- * owns V/threads consecutive sites: 2, 4 or 8 of them); samples_per_launch:
+ * owns V/threads consecutive sites: 2, 4 or 8 of them; the default is the
+ * smallest count with a compiled kernel, except that FP32 batches of two or
+ * more samples per CU whose reservoir ends in a word of 16 clones take 4
+ * sites per work-item when that still gives 256 or more work-items);
+ * samples_per_launch:
  * 0 = all samples in one launch, 1 = one sample per launch (the unbatched
  * form); exp_early_out: clones with 1000/T above this value (i.e. colder than
  * T = exp_early_out/1000) decide a Metropolis test from the binade of exp(x)

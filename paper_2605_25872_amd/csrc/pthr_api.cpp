@@ -439,7 +439,20 @@ int pthr_create(const pthr_params* p, pthr_ctx** out) {
   c->d = d;
   c->lay = layout_of(*p);
   c->g = geo_of(*p, 0);
-  const int ch = default_chunk(p->precision, d.V);
+  int n_cu = 256, dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n_cu < 1) {
+    n_cu = 256;                // no device visible here: size for an MI355X
+    (void)hipGetLastError();   // and leave no error behind for later calls
+  }
+  int ch = default_chunk(p->precision, d.V);
+  // FP32 sweeps a last reservoir word of 16 clones two sites at a time when a
+  // work-item owns two sites of a colour: for batches of at least two samples
+  // per CU, 4 sites per work-item is then the faster default wherever it
+  // still gives a sample 4 or more waves
+  if (p->precision == PTHR_FP32 && ch == 2 && d.NER % 32 == 16 && chunk_ok(PTHR_FP32, d.V, 4) &&
+      threads_for(d.V, 4) >= 256 && int64_t(p->n_samples) >= 2 * int64_t(n_cu))
+    ch = 4;
   c->sch.threads_per_sample = threads_for(d.V, ch);
   c->sch.samples_per_launch = 0;
   c->sch.exp_early_out = 0;  // the branch-free exponential for every clone (fastest on gfx950)
@@ -448,12 +461,6 @@ int pthr_create(const pthr_params* p, pthr_ctx** out) {
   // Batches too small to fill the GPU with waves (4 per SIMD at the sweep's
   // register use): share each chunk's clone words among 2 or 4 waves, up to
   // 1024 work-items per workgroup and one GPU's worth of waves.
-  int n_cu = 256, dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess ||
-      hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n_cu < 1) {
-    n_cu = 256;                // no device visible here: size for an MI355X
-    (void)hipGetLastError();   // and leave no error behind for later calls
-  }
   const int64_t waves = int64_t(p->n_samples) * (c->sch.threads_per_sample / 64);
   c->sch.clone_split = 1;
   while (c->sch.clone_split < 4 && c->sch.threads_per_sample * c->sch.clone_split * 2 <= 1024 &&

@@ -111,6 +111,31 @@ def test_group_argument_checks(lib):
         lib.pthr_destroy(ctx)
 
 
+def test_default_sites_per_work_item(lib):
+    """FP32 batches of two or more samples per CU (512 on an MI355X, also the
+    size assumed where no device is visible) whose reservoir ends in a
+    16-clone word default to 4 sites per work-item (two sites of a colour
+    share one pass over that word) where that leaves 256 or more work-items;
+    other contexts take the smallest chunk with a compiled kernel."""
+    def threads(L, S, NERG, precision):
+        p = pthr.make_params(L, S, 4, 10, NERG, precision=precision)
+        ctx = ctypes.c_void_p()
+        assert lib.pthr_create(ctypes.byref(p), ctypes.byref(ctx)) == 0
+        try:
+            sch = pthr.Schedule()
+            assert lib.pthr_get_schedule(ctx, ctypes.byref(sch)) == 0
+            return sch.threads_per_sample
+        finally:
+            lib.pthr_destroy(ctx)
+    assert threads(12, 512, 4, "fp32") == 448   # 1728 sites, 16 reservoir clones: 4 per work-item
+    assert threads(12, 128, 4, "fp32") == 896   # small batch: more waves per sample
+    assert threads(12, 512, 3, "fp32") == 896   # 12 reservoir clones: 2 per work-item
+    assert threads(12, 512, 4, "fp64") == 896
+    assert threads(10, 512, 4, "fp32") == 256   # 250 work-items of 4 sites: 4 waves
+    assert threads(8, 512, 4, "fp32") == 256    # 128 work-items of 4 would be 2 waves
+    assert threads(16, 512, 4, "fp32") == 1024
+
+
 def test_schedule_defaults_and_checks(lib):
     """The default schedule decides FP64 tests against the float bound first
     (exp_filter = 1); set_schedule accepts 0 and refuses other values, and a
