@@ -92,8 +92,8 @@ def valu_peak(update: str, precision: str) -> tuple[float, int]:
 # SHA-256 is recorded here; any other source reports null.
 SWEEP_TRAFFIC = {
     "workload": "l16_fp32",
-    "sources_sha256": "a77082701fe4d3e9721faca94642004e02d0f2a2240a10a51ff63de27966308b",
-    "fetch_kib": 75013.92,
+    "sources_sha256": "b27bf92381ac34296b0b541cc6205bfca6c6b42d7c74de697635a45e004edba2",
+    "fetch_kib": 75110.6,
     "write_kib": 98304.0,
 }
 # Utilisation of the Houdayer kernel in the same counter runs (L=16 FP32, all-
@@ -104,8 +104,8 @@ SWEEP_TRAFFIC = {
 HOUDAYER_COUNTERS = {
     "workload": "l16_fp32",
     "sources_sha256": SWEEP_TRAFFIC["sources_sha256"],
-    "valu_issue": 0.568,
-    "lds_pipe_busy": 0.332,
+    "valu_issue": 0.566,
+    "lds_pipe_busy": 0.331,
 }
 KERNEL_SOURCES = ("paper_2605_25872_amd/csrc/pthr_kernels.hip", "paper_2605_25872_amd/csrc/pthr_internal.h")
 
