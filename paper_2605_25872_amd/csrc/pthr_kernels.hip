@@ -752,16 +752,28 @@ __device__ __forceinline__ uint32_t* word_at(uint32_t* plane, int b) {
 // All attempts of one word (clones clone0 .. clone0+nbits-1, random-number
 // indices n0 .. n0+nbits-1 with n0 a multiple of 4) at one site (own word and
 // neighbour words at byte offsets self_b and nb[d] of the plane).  beta per
-// clone comes from uniform (scalar) loads.  Blocks are visited from the last
-// to the first, so clone clone0+b ends at bit b of the flip mask; the bits of
-// a partial last block's surplus indices land above bit nbits-1 and are
-// masked off.
-template <typename FP, bool kMaybeEarly, bool kSplit, bool kHB>
+// clone comes from uniform (scalar) loads, or with kOneBeta (a word of
+// reservoir clones, all at T_max) is bc[clone0] for every clone, read once.
+// Blocks are visited from the last to the first, so clone clone0+b ends at
+// bit b of the flip mask; the bits of a partial last block's surplus indices
+// land above bit nbits-1 and are masked off.
+template <typename FP, bool kMaybeEarly, bool kSplit, bool kHB, bool kOneBeta = false>
 __device__ __forceinline__ void update_word(const Geo& g, const FP* __restrict__ bc, uint32_t* plane, int self_b,
                                             const int (&nb)[6], const SiteJ<FP>& sj, uint32_t c0w, uint32_t t,
                                             int sample, int clone0, int n0, int nbits, int early_beta_bits,
                                             int f, int F) {
   constexpr int G = sizeof(FP) == 8 ? 2 : 4;
+  const FP b_one = kOneBeta ? bc[clone0] : FP(0);
+  auto betas = [&](int grp) {
+    if constexpr (kOneBeta) {
+      Betas<FP> r;
+#pragma unroll
+      for (int j = 0; j < G; ++j) r.b[j] = b_one;
+      return r;
+    } else {
+      return group_betas(bc, clone0, grp, n0);
+    }
+  };
   const uint32_t self = *word_at(plane, self_b);
   WordSigns ws;
   if constexpr (sizeof(FP) == 4) {
@@ -800,12 +812,12 @@ __device__ __forceinline__ void update_word(const Geo& g, const FP* __restrict__
         const Floats4 fw = kUsesFloats ? to_floats(blk) : kBits53 ? to_bits53(blk) : Floats4{};
         const Block next =
             philox10(c0w, t, static_cast<uint32_t>(grp - 1), static_cast<uint32_t>(sample), g.key0, g.key1);
-        attempt_group<FP, kMaybeEarly, kHB, kExact, kRedo>(g, group_betas(bc, clone0, grp, n0), rs, sj, blk, fw,
+        attempt_group<FP, kMaybeEarly, kHB, kExact, kRedo>(g, betas(grp), rs, sj, blk, fw,
                                                            early_beta_bits, fl, open);
         blk = next;
       }
       const Floats4 fw = kUsesFloats ? to_floats(blk) : kBits53 ? to_bits53(blk) : Floats4{};
-      attempt_group<FP, kMaybeEarly, kHB, kExact, kRedo>(g, group_betas(bc, clone0, g_lo, n0), rs, sj, blk, fw,
+      attempt_group<FP, kMaybeEarly, kHB, kExact, kRedo>(g, betas(g_lo), rs, sj, blk, fw,
                                                          early_beta_bits, fl, open);
       return fl;
     };
@@ -831,7 +843,7 @@ __device__ __forceinline__ void update_word(const Geo& g, const FP* __restrict__
           philox10(c0w, t, static_cast<uint32_t>(grp - F), static_cast<uint32_t>(sample), g.key0, g.key1);
       uint32_t part = 0;
       RunSigns rs = run_signs<FP>(ws, grp * G + G - 1 - n0);
-      attempt_group<FP, kMaybeEarly, kHB>(g, group_betas(bc, clone0, grp, n0), rs, sj, blk, fw, early_beta_bits,
+      attempt_group<FP, kMaybeEarly, kHB>(g, betas(grp), rs, sj, blk, fw, early_beta_bits,
                                           part, open);
       if constexpr (kRejectBits<FP, kMaybeEarly, kHB>) part = ~part & ((1u << G) - 1u);
       flips |= part << (G * (grp - g_lo));
@@ -840,7 +852,7 @@ __device__ __forceinline__ void update_word(const Geo& g, const FP* __restrict__
     uint32_t part = 0;
     RunSigns rs = run_signs<FP>(ws, first * G + G - 1 - n0);
     const Floats4 fw = kUsesFloats ? to_floats(blk) : Floats4{};
-    attempt_group<FP, kMaybeEarly, kHB>(g, group_betas(bc, clone0, first, n0), rs, sj, blk, fw, early_beta_bits,
+    attempt_group<FP, kMaybeEarly, kHB>(g, betas(first), rs, sj, blk, fw, early_beta_bits,
                                         part, open);
     if constexpr (kRejectBits<FP, kMaybeEarly, kHB>) part = ~part & ((1u << G) - 1u);
     flips |= part << (G * (first - g_lo));
@@ -1002,23 +1014,30 @@ __device__ __forceinline__ void sweep_phase(const Geo& g, const Lds& s, const FP
           const int(&nb)[6] = nbq[q];
           const int self_b = self_bq[q];
           // one word of clones: early-out form or not (a uniform choice per word; never for heat bath)
-          auto word = [&](bool early, int w, uint32_t c0, int clone0, int n0, int nbits) {
+          // kOne: one clone factor for the whole word (update_word's kOneBeta)
+          auto word = [&](auto one_tag, bool early, int w, uint32_t c0, int clone0, int n0, int nbits) {
+            constexpr bool kOne = decltype(one_tag)::value;
             if (!kHB && early)
-              update_word<FP, !kHB, kSplit, kHB>(g, bc, s.sp + size_t(w) * g.V, self_b, nb, sj[slot][q],
-                                                 c0 | static_cast<uint32_t>(site_i[q]), t, sample, clone0, n0, nbits,
-                                                 early_bits, f, FP_);
+              update_word<FP, !kHB, kSplit, kHB, kOne>(g, bc, s.sp + size_t(w) * g.V, self_b, nb, sj[slot][q],
+                                                       c0 | static_cast<uint32_t>(site_i[q]), t, sample, clone0, n0,
+                                                       nbits, early_bits, f, FP_);
             else
-              update_word<FP, false, kSplit, kHB>(g, bc, s.sp + size_t(w) * g.V, self_b, nb, sj[slot][q],
-                                                  c0 | static_cast<uint32_t>(site_i[q]), t, sample, clone0, n0,
-                                                  nbits, early_bits, f, FP_);
+              update_word<FP, false, kSplit, kHB, kOne>(g, bc, s.sp + size_t(w) * g.V, self_b, nb, sj[slot][q],
+                                                        c0 | static_cast<uint32_t>(site_i[q]), t, sample, clone0, n0,
+                                                        nbits, early_bits, f, FP_);
           };
           if (pt_on)
-            for (int w = 0; w < g.NWPT; ++w) word(pt_early, w, c0pt, 32 * w, 32 * w, min(32, g.NPT - 32 * w));
+            for (int w = 0; w < g.NWPT; ++w)
+              word(std::false_type{}, pt_early, w, c0pt, 32 * w, 32 * w, min(32, g.NPT - 32 * w));
           if (er_on)
             for (int w = g.NWPT; w < g.NW - er_pair_words; ++w) {
               const int e0 = 32 * (w - g.NWPT);
-              // every reservoir clone sits at T_max: one uniform choice of path per word
-              word(er_early, w, c0er, g.NPT + e0, n_er0 + e0, min(32, g.NER - e0));
+              // every reservoir clone sits at T_max: one uniform choice of path
+              // per word, and one clone factor where a work-item owns its words
+              // and there is no two-site pass (with it, such words are rare;
+              // shared words measured no faster with it)
+              word(std::integral_constant<bool, !kPairs && !kSplit>{}, er_early, w, c0er, g.NPT + e0, n_er0 + e0,
+                   min(32, g.NER - e0));
             }
         }
         if constexpr (kPairs) {
