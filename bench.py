@@ -92,8 +92,8 @@ def valu_peak(update: str, precision: str) -> tuple[float, int]:
 # SHA-256 is recorded here; any other source reports null.
 SWEEP_TRAFFIC = {
     "workload": "l16_fp32",
-    "sources_sha256": "b27bf92381ac34296b0b541cc6205bfca6c6b42d7c74de697635a45e004edba2",
-    "fetch_kib": 75110.6,
+    "sources_sha256": "58cb63bc40dd9cb5233554e56bc27f83d44aac3e76addc7c8be281ab539236ce",
+    "fetch_kib": 75093.75,
     "write_kib": 98304.0,
 }
 # Utilisation of the Houdayer kernel in the same counter runs (L=16 FP32, all-
