@@ -676,7 +676,7 @@ int pthr_cluster_stats(pthr_ctx* ctx, void* d_sizes, void* stream) {
   if (int rc = ctx->need_ready()) return rc;
   if (!d_sizes) return ctx->fail(PTHR_EINVAL, "d_sizes must not be NULL");
   if (ctx->K_acu == 0) return PTHR_OK;
-  if (pthr::houdayer_moves_per_pass(ctx->g, ctx->sch.threads_per_sample, true) < 1)
+  if (pthr::houdayer_plan(ctx->g, ctx->sch.threads_per_sample, true, false).M < 1)
     return ctx->fail(PTHR_EUNSUPPORTED, "cluster statistics need more LDS than one workgroup has at this size");
   pthr::Run run{};
   run.phases = pthr::kPhaseClusterStats;

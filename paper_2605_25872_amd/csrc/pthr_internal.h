@@ -81,6 +81,8 @@ struct Run {
   int32_t* labels;    // kPhaseLabels output [S][NR/2][K_acu][V]; kPhaseClusterStats output
                       // [S][NR/2][K_acu][2][kStatTop]
   int hou_moves;      // Houdayer moves labelled at once (set by the launcher)
+  int hou_chunk;      // Houdayer moves whose flips are collected before they are applied (a
+                      // multiple of hou_moves; set by the launcher)
   int meas_k;         // temperatures per pass of the row-parallel overlaps (0: per-site form)
   int e_current;      // measure: e_now holds the energies of the current configurations
   int clone_split;    // sweep: work-items per chunk of sites (set by the launcher)
@@ -108,7 +110,14 @@ constexpr size_t kScratchBytes = size_t(64) << 20;
 hipError_t scratch_address(void** ptr);
 
 size_t lds_bytes(const Geo& g, int fp_bytes);
-int houdayer_moves_per_pass(const Geo& g, int threads, bool stats);
+// Houdayer moves labelled at once; lds_rows: the PT spin words in LDS, else
+// rows read from global memory with the flips of C moves collected before
+// they are applied; M = 0 if one move does not fit.
+struct HouPlan {
+  int M, C;
+  bool lds_rows;
+};
+HouPlan houdayer_plan(const Geo& g, int threads, bool stats, bool flips);
 int measure_rows_per_pass(const Geo& g, int threads, int fp_bytes);
 hipError_t launch_emcs(int precision, const Geo& g, const State& st, const Obs& ob, const Run& run,
                        const Shape& sh, int n_blocks, hipStream_t stream);

@@ -1081,13 +1081,18 @@ __device__ __forceinline__ void sweep_phase(const Geo& g, const Lds& s, const FP
 // is always a run start: the canonical root.
 
 struct HouLds {
-  uint32_t* sp;    // [NWPT][V] spin words of the PT clones
+  uint32_t* sp;    // the sample's PT spin words [NWPT][V]: in LDS, or (rows read from
+                   // global memory, flips collected) the words in global memory
   int32_t* cat;    // [NR][NT]
   uint32_t* lab;   // [M][Vp] union-find parents (entries of run starts only), padded site indices
   uint32_t* qrow;  // [M][L^2] overlap bits of every row
   uint32_t* eta;   // [M][ceil(Vp/32)] ACU: the root drew eta = -1
   int32_t* misc;   // [kHouMisc] scan scratch, per-move single-cluster data
   uint32_t* size;  // cluster statistics only: [M][Vp] cluster size at its root
+  void* flipm;     // moves only: [C][L^2] sites to flip per move of the chunk and
+                   // row (uint16 for L <= 16, else uint32)
+  int32_t* wlist;  // moves only: [NWPT + 1] offsets, then [2 C] entries
+                   // (move in the chunk | bit << 16) of the clones of each PT word
 };
 // The union-find works on padded site indices: site x + L row is entry
 // x + (L + 1) row, so the rows of consecutive work-items start in different
@@ -1105,22 +1110,31 @@ constexpr int kHouMisc = 32 + 3 * kMaxHouMoves + 7 * kMaxHouMoves;
 
 constexpr int kStatQ = 32 + 3 * kMaxHouMoves, kStatKey = kStatQ + kMaxHouMoves;
 
-__host__ __device__ inline size_t hou_lds_bytes(const Geo& g, int M, bool stats = false) {
+__host__ __device__ inline int hou_moves(const Geo& g) { return (g.NR / 2) * g.K_acu; }
+__host__ __device__ inline size_t hou_mask_bytes(const Geo& g) { return g.L <= 16 ? 2 : 4; }
+// LDS of the Houdayer kernel with M moves labelled at once; `lds_rows`: the
+// PT spin words in LDS; `stats`: the cluster-size arrays; C > 0 (rows from
+// global memory): the flip masks of C moves and the word lists.
+__host__ __device__ inline size_t hou_lds_bytes(const Geo& g, int M, bool lds_rows, bool stats = false, int C = 0) {
   size_t o = 0;
-  o = align_up(o + sizeof(uint32_t) * size_t(g.NWPT) * g.V, 16);
+  if (lds_rows) o = align_up(o + sizeof(uint32_t) * size_t(g.NWPT) * g.V, 16);
   o = align_up(o + sizeof(int32_t) * size_t(g.NR) * g.NT, 16);
   o = align_up(o + sizeof(uint32_t) * size_t(M) * hou_vp(g), 16);
   o = align_up(o + sizeof(uint32_t) * size_t(M) * g.L * g.L, 16);
   o = align_up(o + sizeof(uint32_t) * size_t(M) * ((hou_vp(g) + 31) / 32), 16);
   o = align_up(o + sizeof(int32_t) * kHouMisc, 16);
   if (stats) o = align_up(o + sizeof(uint32_t) * size_t(M) * hou_vp(g), 16);
+  if (C > 0) {
+    o = align_up(o + hou_mask_bytes(g) * size_t(C) * g.L * g.L, 16);
+    o = align_up(o + sizeof(int32_t) * (size_t(g.NWPT) + 1 + 2 * size_t(C)), 16);
+  }
   return o;
 }
-__device__ __forceinline__ HouLds hou_view(const Geo& g, int M) {
+__device__ __forceinline__ HouLds hou_view(const Geo& g, int M, bool lds_rows, bool stats, int C) {
   HouLds s;
   size_t o = 0;
   s.sp = reinterpret_cast<uint32_t*>(lds_raw + o);
-  o = align_up(o + sizeof(uint32_t) * size_t(g.NWPT) * g.V, 16);
+  if (lds_rows) o = align_up(o + sizeof(uint32_t) * size_t(g.NWPT) * g.V, 16);
   s.cat = reinterpret_cast<int32_t*>(lds_raw + o);
   o = align_up(o + sizeof(int32_t) * size_t(g.NR) * g.NT, 16);
   s.lab = reinterpret_cast<uint32_t*>(lds_raw + o);
@@ -1132,7 +1146,23 @@ __device__ __forceinline__ HouLds hou_view(const Geo& g, int M) {
   s.misc = reinterpret_cast<int32_t*>(lds_raw + o);
   o = align_up(o + sizeof(int32_t) * kHouMisc, 16);
   s.size = reinterpret_cast<uint32_t*>(lds_raw + o);  // valid only when laid out with stats
+  if (stats) o = align_up(o + sizeof(uint32_t) * size_t(M) * hou_vp(g), 16);
+  s.flipm = lds_raw + o;  // valid only when laid out with C > 0
+  if (C > 0) o = align_up(o + hou_mask_bytes(g) * size_t(C) * g.L * g.L, 16);
+  s.wlist = reinterpret_cast<int32_t*>(lds_raw + o);
   return s;
+}
+// The flip mask of the chunk's move mv at row `row` (bit x: flip both clones
+// at site x).
+__device__ __forceinline__ void hou_store_mask(const Geo& g, const HouLds& s, int mv, int row, uint32_t fl) {
+  const size_t i = size_t(mv) * g.L * g.L + row;
+  if (g.L <= 16) static_cast<uint16_t*>(s.flipm)[i] = static_cast<uint16_t>(fl);
+  else static_cast<uint32_t*>(s.flipm)[i] = fl;
+}
+__device__ __forceinline__ uint32_t hou_load_mask(const Geo& g, const HouLds& s, int mv, int row) {
+  const size_t i = size_t(mv) * g.L * g.L + row;
+  return g.L <= 16 ? static_cast<uint32_t>(static_cast<const uint16_t*>(s.flipm)[i])
+                   : static_cast<const uint32_t*>(s.flipm)[i];
 }
 
 // Bit x set where a run of the row mask q starts (x = 0 always).
@@ -1145,7 +1175,8 @@ __device__ __forceinline__ int start_at(uint32_t rs, int x) {
 // Spin bits of clone c at the sites (x, y, z), x = 0..L-1, of row y + L z
 // (bit x set: spin down).
 // The row's sites of each colour are L/2 consecutive plane words (x even:
-// colour (y+z)&1, x odd: the other), read four at a time when L % 8 == 0.
+// colour (y+z)&1, x odd: the other), read four at a time when L % 8 == 0 and
+// two at a time when L % 4 == 0.
 __device__ __forceinline__ uint32_t clone_row(const Geo& g, const uint32_t* sp, int c, int row) {
   const uint32_t* pl = sp + size_t(word_of(g, c)) * g.V;
   const int b = bit_of(g, c);
@@ -1161,6 +1192,16 @@ __device__ __forceinline__ uint32_t clone_row(const Geo& g, const uint32_t* sp, 
                             (((o.y >> b) & 1u) << 3) | (((e.z >> b) & 1u) << 4) | (((o.z >> b) & 1u) << 5) |
                             (((e.w >> b) & 1u) << 6) | (((o.w >> b) & 1u) << 7);
       m |= part << (8 * v);
+    }
+  } else if (g.L % 4 == 0) {
+    const int c0 = yz & 1;
+    const uint2* ev = reinterpret_cast<const uint2*>(pl + c0 * g.Vh + i0 / 2);        // x = 0, 2, 4, ...
+    const uint2* od = reinterpret_cast<const uint2*>(pl + (c0 ^ 1) * g.Vh + i0 / 2);  // x = 1, 3, 5, ...
+    for (int v = 0; v < g.L / 4; ++v) {
+      const uint2 e = ev[v], o = od[v];
+      const uint32_t part = ((e.x >> b) & 1u) | (((o.x >> b) & 1u) << 1) | (((e.y >> b) & 1u) << 2) |
+                            (((o.y >> b) & 1u) << 3);
+      m |= part << (4 * v);
     }
   } else {
     for (int x = 0; x < g.L; ++x) m |= ((pl[plane_idx(i0 + x, (x + yz) & 1, g.Vh)] >> b) & 1u) << x;
@@ -1210,28 +1251,6 @@ __device__ __forceinline__ void join_row(const Geo& g, uint32_t* lab, uint32_t q
       b = start_at(rsz, x) + Lp * rz;
     }
     unite(lab, a, b, hou_vp(g), bad);
-  }
-}
-
-// Order in which a row visits the sites of its flip mask: from x = rot up,
-// wrapping around, with rot different for rows 8 apart.  The rows of one
-// wave keep their spin words L/2 apart, so rows 8 apart (L = 16) meet in the
-// same LDS bank whenever they flip the same x in the same step.
-__device__ __forceinline__ int flip_rotation(int row, int L) { return (2 * (row >> 3)) % L; }
-__device__ __forceinline__ uint32_t rotate_mask(uint32_t fl, int rot, int L, uint32_t full) {
-  return rot ? ((fl >> rot) | (fl << (L - rot))) & full : fl;
-}
-
-// Flips clones a and b at plane index j; several moves may touch one word at
-// the same time, so the update is atomic.
-__device__ __forceinline__ void flip_pair_atomic(const Geo& g, uint32_t* sp, int a, int b, int j) {
-  const int wa = word_of(g, a), wb = word_of(g, b);
-  const uint32_t ma = 1u << bit_of(g, a), mb = 1u << bit_of(g, b);
-  if (wa == wb) {
-    atomicXor(&sp[size_t(wa) * g.V + j], ma | mb);
-  } else {
-    atomicXor(&sp[size_t(wa) * g.V + j], ma);
-    atomicXor(&sp[size_t(wb) * g.V + j], mb);
   }
 }
 
@@ -1295,12 +1314,133 @@ __device__ void cluster_stats(const Geo& g, const HouLds& s, bool active, int m,
   }
 }
 
+// LDS rows: the order in which a row visits the sites of its flip mask, from
+// x = rot up, wrapping around, with rot different for rows 8 apart.  The rows
+// of one wave keep their spin words L/2 apart, so rows 8 apart (L = 16) meet
+// in the same LDS bank whenever they flip the same x in the same step.
+__device__ __forceinline__ int flip_rotation(int row, int L) { return (2 * (row >> 3)) % L; }
+__device__ __forceinline__ uint32_t rotate_mask(uint32_t fl, int rot, int L, uint32_t full) {
+  return rot ? ((fl >> rot) | (fl << (L - rot))) & full : fl;
+}
+// LDS rows: flips clones a and b at plane index j; several moves may touch one
+// word at the same time, so the update is atomic.
+__device__ __forceinline__ void flip_pair_atomic(const Geo& g, uint32_t* sp, int a, int b, int j) {
+  const int wa = word_of(g, a), wb = word_of(g, b);
+  const uint32_t ma = 1u << bit_of(g, a), mb = 1u << bit_of(g, b);
+  if (wa == wb) {
+    atomicXor(&sp[size_t(wa) * g.V + j], ma | mb);
+  } else {
+    atomicXor(&sp[size_t(wa) * g.V + j], ma);
+    atomicXor(&sp[size_t(wb) * g.V + j], mb);
+  }
+}
+// The flips of a row's mask fl for move (a, b): on the LDS words at once, or
+// collected as the chunk's mask of the move.
+template <bool kLdsRows>
+__device__ __forceinline__ void hou_flip_row(const Geo& g, const HouLds& s, int a, int b, int row, uint32_t fl,
+                                             int chunk_move) {
+  if constexpr (kLdsRows) {
+    const int L = g.L, y = row % L, z = row / L, i0 = row * L;
+    const uint32_t full = L == 32 ? 0xFFFFFFFFu : (1u << L) - 1u;
+    const int rot = flip_rotation(row, L);
+    for (fl = rotate_mask(fl, rot, L, full); fl; fl &= fl - 1u) {
+      const int xr = __builtin_ctz(fl) + rot, x = xr >= L ? xr - L : xr;
+      flip_pair_atomic(g, s.sp, a, b, plane_idx(i0 + x, (x + y + z) & 1, g.Vh));
+    }
+  } else {
+    hou_store_mask(g, s, chunk_move, row, fl);
+  }
+}
+
+// The flips of moves m0 .. m1-1 (the moves of one step use disjoint clones,
+// so they commute and can wait until a chunk of them is labelled): for each
+// PT word, the list of (move, bit) of its clones, then every work-item XORs
+// into the words of its sites the bits whose move flipped that site (global
+// memory, one read-modify-write per word and site that changes).  Called by
+// every work-item; it synchronizes.
+__device__ void hou_apply_flips(const Geo& g, const HouLds& s, uint32_t* gsp, int m0, int m1) {
+  const int L = g.L;
+  int32_t* off = s.wlist;                // [NWPT + 1]
+  int32_t* ent = s.wlist + g.NWPT + 1;   // [2 (m1 - m0)]
+  auto clone_of = [&](int m, int side) {
+    const int p = m / g.K_acu, k = m - p * g.K_acu;
+    return s.cat[(2 * p + side) * g.NT + k];
+  };
+  for (int w = threadIdx.x; w < g.NWPT; w += blockDim.x) {
+    int n = 0;
+    for (int m = m0; m < m1; ++m)
+      n += (word_of(g, clone_of(m, 0)) == w ? 1 : 0) + (word_of(g, clone_of(m, 1)) == w ? 1 : 0);
+    off[w + 1] = n;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    off[0] = 0;
+    for (int w = 0; w < g.NWPT; ++w) off[w + 1] += off[w];
+  }
+  __syncthreads();
+  for (int w = threadIdx.x; w < g.NWPT; w += blockDim.x) {
+    int n = off[w];
+    for (int m = m0; m < m1; ++m)
+      for (int side = 0; side < 2; ++side) {
+        const int c = clone_of(m, side);
+        if (word_of(g, c) == w) ent[n++] = (m - m0) | (bit_of(g, c) << 16);
+      }
+  }
+  __syncthreads();
+  if (L <= 16) {
+    // one (word, row) per work-item: each entry's row mask is read once and
+    // spread over the row's L sites
+    const int L2 = L * L;
+    for (int item = threadIdx.x; item < g.NWPT * L2; item += blockDim.x) {
+      const int w = item / L2, row = item - w * L2;
+      const int e0 = off[w], e1 = off[w + 1];
+      uint32_t acc[16];
+#pragma unroll
+      for (int x = 0; x < 16; ++x) acc[x] = 0u;
+      for (int e = e0; e < e1; ++e) {
+        const int v = ent[e];
+        const uint32_t msk = hou_load_mask(g, s, v & 0xFFFF, row);
+        const uint32_t b = static_cast<uint32_t>(v) >> 16;
+#pragma unroll
+        for (int x = 0; x < 16; ++x) acc[x] |= ((msk >> x) & 1u) << b;
+      }
+      // site x of the row: colour (x + y + z) & 1, plane word row L/2 + x/2
+      uint32_t* plane = gsp + size_t(w) * g.V + size_t(row) * (L / 2);
+      const int c0 = (row % L + row / L) & 1;
+#pragma unroll
+      for (int x = 0; x < 16; ++x)
+        if (x < L && acc[x]) plane[size_t(c0 ^ (x & 1)) * g.Vh + (x >> 1)] ^= acc[x];
+    }
+    __syncthreads();
+    return;
+  }
+  for (int w = 0; w < g.NWPT; ++w) {
+    const int e0 = off[w], e1 = off[w + 1];
+    uint32_t* plane = gsp + size_t(w) * g.V;
+    for (int j = threadIdx.x; e1 > e0 && j < g.V; j += blockDim.x) {
+      // plane index j holds the site of colour j / Vh at x = x0 or x0 + 1 of a row
+      const int col = j >= g.Vh ? 1 : 0, i0 = 2 * (j - col * g.Vh);
+      const int row = i0 / L, x0 = i0 - row * L;
+      const int x = x0 + ((row % L + row / L + col) & 1);
+      uint32_t acc = 0;
+      for (int e = e0; e < e1; ++e) {
+        const int v = ent[e];
+        acc |= ((hou_load_mask(g, s, v & 0xFFFF, row) >> x) & 1u) << (v >> 16);
+      }
+      if (acc) plane[j] ^= acc;
+    }
+  }
+  __syncthreads();
+}
+
 // One Houdayer move for every pair p and every k < K_acu (or, with `labels`,
 // the canonical labels of every such pair into labels [S][NR/2][K_acu][V]),
 // hou_moves moves per pass.
-__device__ bool houdayer_moves(const Geo& g, const HouLds& s, int M, int sample, uint32_t t, int32_t* labels,
+template <bool kLdsRows>
+__device__ bool houdayer_moves(const Geo& g, const HouLds& s, int M, int C, int sample, uint32_t t, int32_t* labels,
                                int32_t* stats) {
   const bool flips = !labels && !stats;
+  const bool collect = flips && !kLdsRows;  // flips collected per chunk, then applied to global memory
   const int L = g.L, L2 = L * L, V = g.V, Vp = hou_vp(g);
   const uint32_t full = L == 32 ? 0xFFFFFFFFu : (1u << L) - 1u;
   const int n_moves = (g.NR / 2) * g.K_acu;
@@ -1317,6 +1457,10 @@ __device__ bool houdayer_moves(const Geo& g, const HouLds& s, int M, int sample,
     const uint32_t slot = static_cast<uint32_t>(p * g.NT + k);
     uint32_t* lab = s.lab + size_t(active ? m : 0) * Vp;
     uint32_t* eta = s.eta + size_t(active ? m : 0) * eta_words;
+    // the first move of the current chunk of collected flips (C a multiple of M)
+    const int cb = collect ? base - base % C : 0;
+    if (collect && cb == base)
+      for (int x = threadIdx.x; x < C * L2; x += blockDim.x) hou_store_mask(g, s, x / L2, x % L2, 0u);
     // overlap bits of the row; run starts become singleton roots
     for (int x = threadIdx.x; x < M * eta_words; x += blockDim.x) s.eta[x] = 0u;
     if (stats) {
@@ -1401,11 +1545,7 @@ __device__ bool houdayer_moves(const Geo& g, const HouLds& s, int M, int sample,
             const uint32_t run = (rest ? (rest & (0u - rest)) : (full + 1u)) - (1u << xs);  // bits xs .. xe-1
             fl |= lab[ip0 + xs] == root ? run : 0u;
           }
-          const int rot = flip_rotation(row, L);
-          for (fl = rotate_mask(fl, rot, L, full); fl; fl &= fl - 1u) {
-            const int xr = __builtin_ctz(fl) + rot, x = xr >= L ? xr - L : xr;
-            flip_pair_atomic(g, s.sp, a, b, plane_idx(i0 + x, (x + y + z) & 1, g.Vh));
-          }
+          hou_flip_row<kLdsRows>(g, s, a, b, row, fl, mv - cb);
         }
       }
     } else {
@@ -1428,15 +1568,13 @@ __device__ bool houdayer_moves(const Geo& g, const HouLds& s, int M, int sample,
             const uint32_t run = (rest ? (rest & (0u - rest)) : (full + 1u)) - (1u << xs);  // bits xs .. xe-1
             fl |= (eta[root >> 5] >> (root & 31)) & 1u ? run : 0u;
           }
-          const int rot = flip_rotation(row, L);
-          for (fl = rotate_mask(fl, rot, L, full); fl; fl &= fl - 1u) {
-            const int xr = __builtin_ctz(fl) + rot, x = xr >= L ? xr - L : xr;
-            flip_pair_atomic(g, s.sp, a, b, plane_idx(i0 + x, (x + y + z) & 1, g.Vh));
-          }
+          hou_flip_row<kLdsRows>(g, s, a, b, row, fl, mv - cb);
         }
       }
     }
     __syncthreads();
+    // a full chunk (or the last moves): flip the spins
+    if (collect && (base + M - cb >= C || base + M >= n_moves)) hou_apply_flips(g, s, s.sp, cb, min(cb + C, n_moves));
   }
   return bad;
 }
@@ -2370,17 +2508,31 @@ __global__ __launch_bounds__(kMaxThreads) void sweep_kernel(Geo g, State st, Run
 
 // Houdayer moves (or cluster labels) of one sample per workgroup; the LDS
 // layout depends on run.hou_moves, the number of moves labelled at once.
+// kLdsRows: the PT spin words are loaded into LDS, read there and flipped
+// there; otherwise (for samples whose words would keep a CU to one
+// workgroup) the overlap rows come from global memory and the flips are
+// collected as masks and applied in chunks of run.hou_chunk moves.
+template <bool kLdsRows>
 __global__ __launch_bounds__(kMaxThreads) void houdayer_kernel(Geo g, State st, Run run) {
   const int sample = run.sample_begin + blockIdx.x;
   if (sample >= g.S) return;
-  const HouLds s = hou_view(g, run.hou_moves);
-  load_spins(g, s.sp, s.cat, st, sample, g.NWPT);  // Houdayer pairs are PT clones
-  __syncthreads();
   const bool labels = (run.phases & kPhaseLabels) != 0;
   const bool stats = (run.phases & kPhaseClusterStats) != 0;
-  const bool bad = houdayer_moves(g, s, run.hou_moves, sample, *st.t_dev, labels ? run.labels : nullptr,
-                                  stats ? run.labels : nullptr);
-  if (!labels && !stats) store_spins(g, s.sp, st, sample, g.NWPT);
+  const bool flips = !labels && !stats;
+  const int C = flips && !kLdsRows ? run.hou_chunk : 0;
+  HouLds s = hou_view(g, run.hou_moves, kLdsRows, stats, C);
+  if constexpr (kLdsRows) {
+    load_spins(g, s.sp, s.cat, st, sample, g.NWPT);  // Houdayer pairs are PT clones
+  } else {
+    s.sp = st.spins + size_t(sample) * g.NW * g.V;  // words 0 .. NWPT-1: the PT clones
+    for (int x = threadIdx.x; x < g.NR * g.NT; x += blockDim.x) s.cat[x] = st.clone_at[size_t(sample) * g.NR * g.NT + x];
+  }
+  __syncthreads();
+  const bool bad = houdayer_moves<kLdsRows>(g, s, run.hou_moves, C, sample, *st.t_dev, labels ? run.labels : nullptr,
+                                            stats ? run.labels : nullptr);
+  if constexpr (kLdsRows) {
+    if (flips) store_spins(g, s.sp, st, sample, g.NWPT);
+  }
   if (bad) atomicOr(&st.status[sample], kStatusUnionBound);
 }
 
@@ -2464,7 +2616,8 @@ hipError_t prepare_t(size_t lds) {
   if ((e = set_lds(sweep_kernel<FP, CH, true, false>, lds)) != hipSuccess) return e;
   if ((e = set_lds(sweep_kernel<FP, CH, false, true>, lds)) != hipSuccess) return e;
   if ((e = set_lds(sweep_kernel<FP, CH, true, true>, lds)) != hipSuccess) return e;
-  if ((e = set_lds(houdayer_kernel, lds)) != hipSuccess) return e;
+  if ((e = set_lds(houdayer_kernel<true>, lds)) != hipSuccess) return e;
+  if ((e = set_lds(houdayer_kernel<false>, lds)) != hipSuccess) return e;
   if ((e = set_lds(micsa_kernel<FP, true>, lds)) != hipSuccess) return e;
   if ((e = set_lds(micsa_kernel<FP, false>, lds)) != hipSuccess) return e;
   if ((e = set_lds(micsa_row_kernel<FP, 2>, lds)) != hipSuccess) return e;
@@ -2524,10 +2677,20 @@ hipError_t launch_t(const Geo& g, const State& st, const Obs& ob, const Run& run
   if (run.phases & (kPhaseHoudayer | kPhaseLabels | kPhaseClusterStats)) {
     Run r = run;
     const bool stats = (run.phases & kPhaseClusterStats) != 0;
-    r.hou_moves = houdayer_moves_per_pass(g, threads, stats);
-    if (r.hou_moves < 1) return hipErrorInvalidConfiguration;
-    hipLaunchKernelGGL(houdayer_kernel, dim3(n_blocks), dim3(threads), hou_lds_bytes(g, r.hou_moves, stats), stream,
-                       g, st, r);
+    const bool flips = (run.phases & (kPhaseLabels | kPhaseClusterStats)) == 0;
+    const HouPlan hp = houdayer_plan(g, threads, stats, flips);
+    if (hp.M < 1) return hipErrorInvalidConfiguration;
+    r.hou_moves = hp.M;
+    r.hou_chunk = hp.C;
+    if (hp.lds_rows) {
+      hipLaunchKernelGGL(houdayer_kernel<true>, dim3(n_blocks), dim3(threads), hou_lds_bytes(g, hp.M, true, stats),
+                         stream, g, st, r);
+    } else {
+      // one work-item per row of each move labelled at once
+      const int ht = (hp.M * g.L * g.L + kWave - 1) / kWave * kWave;
+      hipLaunchKernelGGL(houdayer_kernel<false>, dim3(n_blocks), dim3(ht), hou_lds_bytes(g, hp.M, false, stats, hp.C),
+                         stream, g, st, r);
+    }
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   if (run.phases & kPhasePT) {
@@ -2557,13 +2720,10 @@ static __device__ __align__(256) unsigned char scratch[kScratchBytes];
 hipError_t scratch_address(void** ptr) { return hipGetSymbolAddress(ptr, HIP_SYMBOL(scratch)); }
 
 size_t lds_bytes(const Geo& g, int fp_bytes) {
-  const size_t phases = plan_lds(g, fp_bytes).total, hou = hou_lds_bytes(g, 1, false);
+  const size_t phases = plan_lds(g, fp_bytes).total, hou = hou_lds_bytes(g, 1, true);
   return phases > hou ? phases : hou;
 }
 
-// Houdayer moves labelled at once: one x-row per work-item, as many moves as
-// the workgroup has rows for and LDS holds (at least one: a workgroup has at
-// least V/8 >= L^2 work-items, rounded up to whole waves).
 // Temperatures whose overlaps are taken at once by the row-parallel form: one
 // x-row per work-item and the clones' row masks in LDS after the phase plan;
 // 0 selects the per-site form.
@@ -2575,13 +2735,30 @@ int measure_rows_per_pass(const Geo& g, int threads, int fp_bytes) {
   return KC;
 }
 
-int houdayer_moves_per_pass(const Geo& g, int threads, bool stats) {
-  const int n_moves = (g.NR / 2) * g.K_acu;
-  int M = threads / (g.L * g.L);
-  if (M > n_moves) M = n_moves;
-  if (M > kMaxHouMoves) M = kMaxHouMoves;
-  while (M > 0 && hou_lds_bytes(g, M, stats) > kLdsMax) --M;
-  return M;
+// Houdayer moves labelled at once: one x-row per work-item, as many moves as
+// the workgroup has rows for and LDS holds (at least one: a workgroup has at
+// least V/8 >= L^2 work-items, rounded up to whole waves); the launch takes
+// M L^2 work-items.
+HouPlan houdayer_plan(const Geo& g, int threads, bool stats, bool flips) {
+  const int n_moves = hou_moves(g);
+  int cap = threads / (g.L * g.L);
+  if (cap > n_moves) cap = n_moves;
+  if (cap > kMaxHouMoves) cap = kMaxHouMoves;
+  // spin words in LDS: as many moves as the workgroup has rows for and LDS holds
+  int M = cap;
+  while (M > 0 && hou_lds_bytes(g, M, true, stats) > kLdsMax) --M;
+  if (M == 0 || !flips || g.L % 8 != 0 || 2 * hou_lds_bytes(g, M, true, stats) <= kLdsMax)
+    return HouPlan{M, 0, true};
+  // The words keep a CU to one workgroup: with the rows read from global
+  // memory (four words at a time) and every flip collected before one
+  // application, two workgroups share a CU where LDS allows it and they label
+  // at least as many moves together (the kernel waits on LDS latency, so more
+  // waves per CU pay).
+  int M2 = cap;
+  auto all = [&](int m) { return (n_moves + m - 1) / m * m; };
+  while (M2 > 0 && hou_lds_bytes(g, M2, false, stats, all(M2)) > kLdsMax / 2) --M2;
+  if (M2 > 0 && 2 * M2 >= M) return HouPlan{M2, all(M2), false};
+  return HouPlan{M, 0, true};
 }
 
 hipError_t launch_emcs(int precision, const Geo& g, const State& st, const Obs& ob, const Run& run,
