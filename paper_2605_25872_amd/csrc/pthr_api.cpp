@@ -177,6 +177,7 @@ struct pthr_ctx {
   unsigned char* g_state = nullptr;
   pthr_schedule g_sch{};
 
+  int n_cu = 256;  // compute units of the device the context was made on
   // overlap_reservoir: the second stream and the fork / join events
   hipStream_t side_stream = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
@@ -259,8 +260,9 @@ struct pthr_ctx {
     while (threads_for(d.V, sh.chunk) != sch.threads_per_sample && sh.chunk < 8) sh.chunk *= 2;
     return sh;
   }
-  // Launches `run` over all samples, split by samples_per_launch.
-  int launch(pthr::Run run, void* d_obs, hipStream_t stream) {
+  // Launches `run` over all samples, split by samples_per_launch;
+  // `shared_gpu`: other contexts' kernels run beside these (a group).
+  int launch(pthr::Run run, void* d_obs, hipStream_t stream, bool shared_gpu = false) {
     const pthr::State st = state();
     const pthr::Obs ob = obs(d_obs);
     const int per = sch.samples_per_launch > 0 ? sch.samples_per_launch : p.n_samples;
@@ -276,7 +278,11 @@ struct pthr_ctx {
         gl.exp_lo = 0.0f;
         gl.exp_hi = INFINITY;
       }
-      hipError_t e = pthr::launch_emcs(p.precision, gl, st, ob, run, shape(), nb, stream);
+      pthr::Shape sh = shape();
+      // more sample workgroups than CUs, or other work beside them: the
+      // Houdayer kernel may take fewer moves at once for more workgroups per CU
+      sh.hou_occupancy = shared_gpu || nb > n_cu;
+      hipError_t e = pthr::launch_emcs(p.precision, gl, st, ob, run, sh, nb, stream);
       if (e != hipSuccess) return hip_fail(e, "EMCS kernel launch");
     }
     return PTHR_OK;
@@ -300,7 +306,7 @@ struct pthr_ctx {
   }
   // One whole EMCS on `stream`: sweeps, Houdayer, PT + reservoir (all
   // samples), t += 1, then the observables if d_obs is set.
-  int emcs(void* d_obs, hipStream_t stream) {
+  int emcs(void* d_obs, hipStream_t stream, bool shared_gpu = false) {
     pthr::Run run{};
     run.phases = pthr::kPhaseSweep | (K_acu ? pthr::kPhaseHoudayer : 0u) | pthr::kPhasePT;
     run.n_pt = p.sweeps_per_emcs;
@@ -317,20 +323,20 @@ struct pthr_ctx {
       pthr::Run er{};
       er.phases = pthr::kPhaseSweep;
       er.n_er = run.n_er;
-      if (int rc = launch(er, nullptr, side_stream)) return rc;
+      if (int rc = launch(er, nullptr, side_stream, shared_gpu)) return rc;
       pthr::Run pt = run;
       pt.phases &= ~pthr::kPhasePT;
       pt.n_er = 0;
-      if (int rc = launch(pt, nullptr, stream)) return rc;
+      if (int rc = launch(pt, nullptr, stream, shared_gpu)) return rc;
       if ((e = hipEventRecord(ev_join, side_stream)) != hipSuccess ||
           (e = hipStreamWaitEvent(stream, ev_join, 0)) != hipSuccess)
         return hip_fail(e, "join");
       pthr::Run ps{};
       ps.phases = pthr::kPhasePT;
       ps.do_reservoir = 1;
-      if (int rc = launch(ps, nullptr, stream)) return rc;
+      if (int rc = launch(ps, nullptr, stream, shared_gpu)) return rc;
     } else {
-      if (int rc = launch(run, nullptr, stream)) return rc;
+      if (int rc = launch(run, nullptr, stream, shared_gpu)) return rc;
     }
     e = pthr::launch_advance_t(state(), stream);
     if (e != hipSuccess) return hip_fail(e, "advance t");
@@ -338,7 +344,7 @@ struct pthr_ctx {
       pthr::Run m{};
       m.phases = pthr::kPhaseMeasure;
       m.e_current = 1;  // the PT step just left the current energies in e_now
-      if (int rc = launch(m, d_obs, stream)) return rc;
+      if (int rc = launch(m, d_obs, stream, shared_gpu)) return rc;
     }
     return PTHR_OK;
   }
@@ -445,6 +451,7 @@ int pthr_create(const pthr_params* p, pthr_ctx** out) {
     n_cu = 256;                // no device visible here: size for an MI355X
     (void)hipGetLastError();   // and leave no error behind for later calls
   }
+  c->n_cu = n_cu;
   int ch = default_chunk(p->precision, d.V);
   // FP32 sweeps a last reservoir word of 16 clones two sites at a time when a
   // work-item owns two sites of a colour: for batches of at least two samples
@@ -676,7 +683,7 @@ int pthr_cluster_stats(pthr_ctx* ctx, void* d_sizes, void* stream) {
   if (int rc = ctx->need_ready()) return rc;
   if (!d_sizes) return ctx->fail(PTHR_EINVAL, "d_sizes must not be NULL");
   if (ctx->K_acu == 0) return PTHR_OK;
-  if (pthr::houdayer_plan(ctx->g, ctx->sch.threads_per_sample, true, false).M < 1)
+  if (pthr::houdayer_plan(ctx->g, ctx->sch.threads_per_sample, true, false, false).M < 1)
     return ctx->fail(PTHR_EUNSUPPORTED, "cluster statistics need more LDS than one workgroup has at this size");
   pthr::Run run{};
   run.phases = pthr::kPhaseClusterStats;
@@ -1132,7 +1139,7 @@ struct pthr_group {
       for (size_t i = 0; i < ctx.size(); ++i) {
         if (lane[i] != static_cast<int>(s)) continue;
         for (int w = 0; w < n; ++w)
-          if (int rc = ctx[i]->emcs(d_obs ? d_obs[i] : nullptr, side[s]))
+          if (int rc = ctx[i]->emcs(d_obs ? d_obs[i] : nullptr, side[s], true))
             return fail(rc, "context %zu: %s", i, ctx[i]->err.c_str());
       }
       if ((e = hipEventRecord(join[s], side[s])) != hipSuccess ||

@@ -97,6 +97,8 @@ struct Shape {
   int threads;     // work-items per sample workgroup (multiple of 64, <= 1024)
   int split;       // sweep only: work-items sharing each chunk's clone words (1, 2 or 4)
   int parts;       // sweep only: workgroups sharing each sample's clone words (1, 2 or 4)
+  int hou_occupancy;  // Houdayer only: the launch has more samples than CUs or shares the GPU
+                      // with other work, so more workgroups per CU may pay over more moves at once
 };
 
 constexpr size_t kLdsMax = 160 * 1024;  // gfx950 LDS per workgroup
@@ -112,12 +114,12 @@ hipError_t scratch_address(void** ptr);
 size_t lds_bytes(const Geo& g, int fp_bytes);
 // Houdayer moves labelled at once; lds_rows: the PT spin words in LDS, else
 // rows read from global memory with the flips of C moves collected before
-// they are applied; M = 0 if one move does not fit.
+// they are applied (only with `occupancy`); M = 0 if one move does not fit.
 struct HouPlan {
   int M, C;
   bool lds_rows;
 };
-HouPlan houdayer_plan(const Geo& g, int threads, bool stats, bool flips);
+HouPlan houdayer_plan(const Geo& g, int threads, bool stats, bool flips, bool occupancy);
 int measure_rows_per_pass(const Geo& g, int threads, int fp_bytes);
 hipError_t launch_emcs(int precision, const Geo& g, const State& st, const Obs& ob, const Run& run,
                        const Shape& sh, int n_blocks, hipStream_t stream);

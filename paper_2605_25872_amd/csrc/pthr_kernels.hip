@@ -2632,8 +2632,9 @@ hipError_t prepare_t(size_t lds) {
 }
 
 template <typename FP, int CH>
-hipError_t launch_t(const Geo& g, const State& st, const Obs& ob, const Run& run, int threads, int split,
-                    int parts, int n_blocks, hipStream_t stream) {
+hipError_t launch_t(const Geo& g, const State& st, const Obs& ob, const Run& run, const Shape& sh, int n_blocks,
+                    hipStream_t stream) {
+  const int threads = sh.threads, split = sh.split, parts = sh.parts;
   const size_t lds = plan_lds(g, sizeof(FP)).total;
   hipError_t e = hipSuccess;
   if (run.phases & kPhaseSweep) {
@@ -2678,7 +2679,7 @@ hipError_t launch_t(const Geo& g, const State& st, const Obs& ob, const Run& run
     Run r = run;
     const bool stats = (run.phases & kPhaseClusterStats) != 0;
     const bool flips = (run.phases & (kPhaseLabels | kPhaseClusterStats)) == 0;
-    const HouPlan hp = houdayer_plan(g, threads, stats, flips);
+    const HouPlan hp = houdayer_plan(g, threads, stats, flips, sh.hou_occupancy != 0);
     if (hp.M < 1) return hipErrorInvalidConfiguration;
     r.hou_moves = hp.M;
     r.hou_chunk = hp.C;
@@ -2739,7 +2740,7 @@ int measure_rows_per_pass(const Geo& g, int threads, int fp_bytes) {
 // the workgroup has rows for and LDS holds (at least one: a workgroup has at
 // least V/8 >= L^2 work-items, rounded up to whole waves); the launch takes
 // M L^2 work-items.
-HouPlan houdayer_plan(const Geo& g, int threads, bool stats, bool flips) {
+HouPlan houdayer_plan(const Geo& g, int threads, bool stats, bool flips, bool occupancy) {
   const int n_moves = hou_moves(g);
   int cap = threads / (g.L * g.L);
   if (cap > n_moves) cap = n_moves;
@@ -2747,7 +2748,7 @@ HouPlan houdayer_plan(const Geo& g, int threads, bool stats, bool flips) {
   // spin words in LDS: as many moves as the workgroup has rows for and LDS holds
   int M = cap;
   while (M > 0 && hou_lds_bytes(g, M, true, stats) > kLdsMax) --M;
-  if (M == 0 || !flips || g.L % 8 != 0 || 2 * hou_lds_bytes(g, M, true, stats) <= kLdsMax)
+  if (M == 0 || !flips || !occupancy || g.L % 8 != 0 || 2 * hou_lds_bytes(g, M, true, stats) <= kLdsMax)
     return HouPlan{M, 0, true};
   // The words keep a CU to one workgroup: with the rows read from global
   // memory (four words at a time) and every flip collected before one
@@ -2764,7 +2765,7 @@ HouPlan houdayer_plan(const Geo& g, int threads, bool stats, bool flips) {
 hipError_t launch_emcs(int precision, const Geo& g, const State& st, const Obs& ob, const Run& run,
                        const Shape& sh, int n_blocks, hipStream_t stream) {
 #define PTHR_LAUNCH(FP, CH) \
-  return launch_t<FP, CH>(g, st, ob, run, sh.threads, sh.split, sh.parts, n_blocks, stream)
+  return launch_t<FP, CH>(g, st, ob, run, sh, n_blocks, stream)
   if (precision == 0) {
     switch (sh.chunk) {
       case 2: PTHR_LAUNCH(double, 2);
