@@ -245,6 +245,55 @@ def test_houdayer_roots_every_sample_l16():
 
 
 @pytest.mark.parametrize("mode", ["acu", "single"])
+def test_houdayer_both_kernel_forms_every_sample_l16(mode):
+    """The L=16 FP32 shape (4x36 on [0.2, 1.6], 4 reservoir clones) with more
+    samples than the GPU has CUs: the Houdayer step over all samples in one
+    launch (overlap rows read from global memory, every move's flips applied
+    in one pass after the last, two workgroups per CU) and in launches of 64
+    samples (spin words in LDS, flipped there) give the same spins on every
+    sample over several EMCS; two samples are recomputed by the oracle."""
+    import torch
+    pthr = _pthr()
+    w = inputs.WORKLOADS["l16_fp32"]
+    S = torch.cuda.get_device_properties(0).multi_processor_count + 64
+    T = w.temperatures()
+    step(f"houdayer kernel forms l16 {mode}: {S} samples")
+    J = w.couplings(S)
+    ctx = []
+    for per in (0, 64):
+        g = pthr.Pthr(w.L, S, w.n_replicas, w.n_temps, w.n_reservoir, 2, 4, "fp32", mode, w.t_acu, w.seed)
+        g.init_samples(J, T)
+        g.set_schedule(samples_per_launch=per)
+        ctx.append(g)
+    picks = [1, S - 2]
+    orc = []
+    for s in picks:
+        o1 = oracle.Oracle(w.L, 1, w.n_replicas, w.n_temps, w.n_reservoir, 2, 4, oracle.FP32,
+                           oracle.ACU if mode == "acu" else oracle.SINGLE_NEG, w.t_acu, w.seed, first_sample=s)
+        o1.init(w.couplings(1, first_sample=s), T)
+        orc.append(o1)
+    for e in range(3):
+        for g in ctx:
+            g.sweep(2, 4)
+            g.houdayer()
+        for o1 in orc:
+            o1.sweep(2, oracle.SWEEP_PT)
+            o1.sweep(4, oracle.SWEEP_ER)
+            o1.houdayer()
+        a, b = ctx[0].read_spins(), ctx[1].read_spins()
+        bad = [s for s in range(S) if not np.array_equal(a[s], b[s])]
+        assert not bad, f"EMCS {e}: the two forms differ on samples {bad[:8]}"
+        for s, o1 in zip(picks, orc):
+            assert np.array_equal(a[s], o1.spins[0]), f"EMCS {e}: sample {s} against the oracle"
+        for g in ctx:
+            g.pt_swap(True)
+        for o1 in orc:
+            o1.pt_swap(True)
+    for g in ctx:
+        g.check()
+
+
+@pytest.mark.parametrize("mode", ["acu", "single"])
 @pytest.mark.parametrize("L,precision", [(4, "fp64"), (16, "fp32")])
 def test_houdayer_on_identical_and_opposite_replicas(L, precision, mode):
     """Sec. 3's degenerate overlaps, written through pthr_write_spins: pair
