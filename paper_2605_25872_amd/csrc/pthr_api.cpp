@@ -31,7 +31,7 @@ size_t align256(size_t v) { return (v + 255) / 256 * 256; }
 // Byte offsets of every region of the caller's state buffer.
 struct Layout {
   size_t beta64, beta32, T64, spins, J, beta_clone, clone_at, er_head, pt_last, pt_count, pt_energy, e_now, rt_state,
-      rt_count, status, walker, total;
+      rt_count, status, walker, J_plane, total;
 };
 
 struct Derived {
@@ -74,6 +74,12 @@ Layout layout_of(const pthr_params& p) {
   l.rt_count = o;  o = align256(o + 8 * S);
   l.status = o;    o = align256(o + 4 * S);
   l.walker = o;    o = align256(o + 8 * S * d.NPT);
+  // FP32 MicSA whose row kernel reads the couplings through the scalar cache:
+  // the couplings again, in plane order
+  const bool j_plane = p.precision == PTHR_FP32 && p.local_update == PTHR_MICSA &&
+                       pthr::micsa_scalar_couplings(p.L, d.NWPT, int(NR * NT), d.NPT);
+  l.J_plane = j_plane ? o : 0;
+  if (j_plane) o = align256(o + 4 * S * 3 * d.V);
   l.total = o;
   return l;
 }
@@ -239,6 +245,7 @@ struct pthr_ctx {
     st.beta_clone = b + lay.beta_clone;
     st.T64 = reinterpret_cast<const double*>(b + lay.T64);
     st.walker = reinterpret_cast<double*>(b + lay.walker);
+    st.J_plane = lay.J_plane ? reinterpret_cast<float*>(b + lay.J_plane) : nullptr;
     return st;
   }
   pthr::Obs obs(void* d_obs) const {

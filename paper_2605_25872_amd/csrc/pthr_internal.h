@@ -63,6 +63,9 @@ struct State {
                          // kept by the PT kernel
   const double* T64;     // [NT] temperatures as given
   double* walker;        // [S][NPT] MicSA walker energy of every PT clone (FP32 form: float values)
+  float* J_plane;        // [S][3][V] FP32 couplings in the spin words' plane order (j = colour*Vh + i/2),
+                         // kept for the MicSA row kernel's scalar loads; null where that kernel
+                         // does not take them
 };
 
 struct Obs {
@@ -121,6 +124,12 @@ struct HouPlan {
 };
 HouPlan houdayer_plan(const Geo& g, int threads, bool stats, bool flips, bool occupancy);
 int measure_rows_per_pass(const Geo& g, int threads, int fp_bytes);
+// FP32 MicSA row kernel: reading the couplings through the scalar cache (from
+// a plane-order copy in the state buffer) leaves LDS to the spin words; worth
+// it where that fits two samples per CU and the LDS copy of the couplings
+// does not (the geometry: lattice side, PT spin words, permutation entries
+// NR NT, PT clones).
+bool micsa_scalar_couplings(int L, int NWPT, int n_cat, int NPT);
 hipError_t launch_emcs(int precision, const Geo& g, const State& st, const Obs& ob, const Run& run,
                        const Shape& sh, int n_blocks, hipStream_t stream);
 hipError_t launch_init(const Geo& g, const State& st, hipStream_t stream);

@@ -2252,15 +2252,27 @@ __device__ __forceinline__ void micsa_load(MicsaRow<H>& r, const uint32_t* P, co
 // Couplings of a row from Jc (checkerboard order): J_x of the row's sites
 // and of the other colour's sites of the row (the -x bonds), J_y of the row
 // and of the row at y - 1, J_z of the row and of the row at z - 1.
-template <typename FP, int H>
-__device__ __forceinline__ void micsa_load_j(MicsaJ<FP, H>& j, const FP* Jc, const RowOff& o) {
+// FP32 couplings read through the scalar data cache (wave-uniform
+// addresses; the kernel never writes them).
+using ScalarF32 = const __attribute__((address_space(4))) float;
+template <int H>
+__device__ __forceinline__ void j_row(const float* p, float (&v)[H]) { lds_row<H>(p, v); }
+template <int H>
+__device__ __forceinline__ void j_row(const double* p, double (&v)[H]) { lds_row<H>(p, v); }
+template <int H>
+__device__ __forceinline__ void j_row(ScalarF32* p, float (&v)[H]) {
+#pragma unroll
+  for (int k = 0; k < H; ++k) v[k] = p[k];
+}
+template <typename FP, int H, typename JP>
+__device__ __forceinline__ void micsa_load_j(MicsaJ<FP, H>& j, JP Jc, const RowOff& o) {
   constexpr int L = 2 * H, V = L * L * L;
-  lds_row<H>(Jc + o.own, j.xp);
-  lds_row<H>(Jc + o.xo, j.xm);
-  lds_row<H>(Jc + V + o.own, j.yp);
-  lds_row<H>(Jc + V + o.ym, j.ym);
-  lds_row<H>(Jc + 2 * V + o.own, j.zp);
-  lds_row<H>(Jc + 2 * V + o.zm, j.zm);
+  j_row<H>(Jc + o.own, j.xp);
+  j_row<H>(Jc + o.xo, j.xm);
+  j_row<H>(Jc + V + o.own, j.yp);
+  j_row<H>(Jc + V + o.ym, j.ym);
+  j_row<H>(Jc + 2 * V + o.own, j.zp);
+  j_row<H>(Jc + 2 * V + o.zm, j.zm);
 }
 
 // dE / 2 of the row's sites with the sign of the updated spin, U[k] for
@@ -2328,9 +2340,9 @@ __device__ __forceinline__ void micsa_walk(uint32_t (&own)[H], const FP (&U)[H],
 // than its own, and the first row of either colour reads none of the rows
 // the last row of the other colour writes, so the early loads see final
 // words.
-template <typename FP, int H, int C, int X0>
+template <typename FP, int H, int C, int X0, typename JP>
 __device__ __forceinline__ void micsa_step(MicsaRow<H>& cur, MicsaRow<H>& nxt, MicsaJ<FP, H>& J, const uint32_t* P,
-                                           uint32_t* Pw, const FP* Jc, int own, const RowOff& next, int sh,
+                                           uint32_t* Pw, JP Jc, int own, const RowOff& next, int sh,
                                            int hi_shift, bool write, FP& W) {
   micsa_load<H>(nxt, P, next);
   FP U[H];
@@ -2344,9 +2356,9 @@ __device__ __forceinline__ void micsa_step(MicsaRow<H>& cur, MicsaRow<H>& nxt, M
 // alternate without copies (L is even); rows with even y have their sites at
 // x = XE + 2k, rows with odd y at x = 1 - XE + 2k.  The last row loads the
 // first row of the next plane, or of the other colour after the last plane.
-template <typename FP, int H, int C, int XE>
+template <typename FP, int H, int C, int XE, typename JP>
 __device__ __forceinline__ void micsa_plane(MicsaRow<H>& ra, MicsaRow<H>& rb, MicsaJ<FP, H>& J, const uint32_t* P,
-                                            uint32_t* Pw, const FP* Jc, int z, int sh, int hi_shift, bool write,
+                                            uint32_t* Pw, JP Jc, int z, int sh, int hi_shift, bool write,
                                             FP& W) {
   constexpr int L = 2 * H, LH = L * H, Vh = L * L * L / 2;
   const int zb = z * LH, zpb = wrap_up(z, L) * LH, zmb = wrap_down(z, L) * LH;
@@ -2365,9 +2377,9 @@ __device__ __forceinline__ void micsa_plane(MicsaRow<H>& ra, MicsaRow<H>& rb, Mi
 
 // One colour's half-sweep, rows in increasing site order; on entry ra and J
 // hold its first row, on exit the first row of the other colour.
-template <typename FP, int H, int C>
+template <typename FP, int H, int C, typename JP>
 __device__ __forceinline__ void micsa_half_sweep(MicsaRow<H>& ra, MicsaRow<H>& rb, MicsaJ<FP, H>& J,
-                                                 const uint32_t* P, uint32_t* Pw, const FP* Jc, int sh, int hi_shift,
+                                                 const uint32_t* P, uint32_t* Pw, JP Jc, int sh, int hi_shift,
                                                  bool write, FP& W) {
   constexpr int L = 2 * H;
   for (int z = 0; z < L; ++z) {
@@ -2378,27 +2390,45 @@ __device__ __forceinline__ void micsa_half_sweep(MicsaRow<H>& ra, MicsaRow<H>& r
   }
 }
 
-template <typename FP, int H>
+// kScalarJ (FP32): the couplings are read in plane order from st.J_plane
+// through the scalar data cache and LDS holds only the spin words (at L=16
+// with 144 PT clones, 80 KiB: two samples per CU); otherwise LDS also holds
+// the permutation and the couplings, rearranged into plane order here.
+template <typename FP, int H, bool kScalarJ>
 __global__ __launch_bounds__(kMicsaRowThreads) void micsa_row_kernel(Geo g, State st, Run run) {
   static_assert(H >= 2, "the prefetch needs distinct boundary rows");
+  static_assert(!kScalarJ || sizeof(FP) == 4, "scalar couplings: FP32 form");
   constexpr int L = 2 * H, V = L * L * L, Vh = V / 2;
   const int sample = run.sample_begin + blockIdx.x;
   if (sample >= g.S) return;
   uint32_t* sp = reinterpret_cast<uint32_t*>(lds_raw);  // [NWPT][V]
   size_t o = align_up(sizeof(uint32_t) * size_t(g.NWPT) * V, 16);
-  int32_t* cat = reinterpret_cast<int32_t*>(lds_raw + o);  // [NR][NT]
+  const int32_t* cat_g = st.clone_at + size_t(sample) * g.NR * g.NT;
+  int32_t* cat = reinterpret_cast<int32_t*>(lds_raw + o);  // [NR][NT] (not with kScalarJ)
   int32_t* kof = cat + g.NR * g.NT;                         // [NPT] temperature index of every clone
   o = align_up(o + sizeof(int32_t) * size_t(g.NR * g.NT + g.NPT), 16);
-  FP* Jc = reinterpret_cast<FP*>(lds_raw + o);  // [3][V], checkerboard order
-  load_spins(g, sp, cat, st, sample, g.NWPT);
-  const FP* Jg = static_cast<const FP*>(st.J) + size_t(sample) * 3 * V;
-  for (int x = threadIdx.x; x < 3 * V; x += blockDim.x) {
-    const int d = x / V, i = x - d * V;
-    const Site s = site_of(i, L);
-    Jc[d * V + plane_idx(i, colour_of(s), Vh)] = Jg[x];
+  auto Jc = [&] {
+    if constexpr (kScalarJ) {
+      return (ScalarF32*)(st.J_plane + size_t(sample) * 3 * V);  // [3][V], plane order (address-space cast)
+    } else {
+      return reinterpret_cast<FP*>(lds_raw + o);  // [3][V], plane order
+    }
+  }();
+  if constexpr (kScalarJ) {
+    const size_t words = size_t(g.NWPT) * V;
+    const uint32_t* gsp = st.spins + size_t(sample) * g.NW * V;
+    for (size_t x = threadIdx.x; x < words; x += blockDim.x) sp[x] = gsp[x];
+  } else {
+    load_spins(g, sp, cat, st, sample, g.NWPT);
+    const FP* Jg = static_cast<const FP*>(st.J) + size_t(sample) * 3 * V;
+    for (int x = threadIdx.x; x < 3 * V; x += blockDim.x) {
+      const int d = x / V, i = x - d * V;
+      const Site s = site_of(i, L);
+      Jc[d * V + plane_idx(i, colour_of(s), Vh)] = Jg[x];
+    }
+    __syncthreads();
+    for (int x = threadIdx.x; x < g.NPT; x += blockDim.x) kof[cat[x]] = x % g.NT;
   }
-  __syncthreads();
-  for (int x = threadIdx.x; x < g.NPT; x += blockDim.x) kof[cat[x]] = x % g.NT;
   __syncthreads();
   const uint32_t t = *st.t_dev;
   const int lane = lane_id();
@@ -2413,7 +2443,13 @@ __global__ __launch_bounds__(kMicsaRowThreads) void micsa_row_kernel(Geo g, Stat
     const uint32_t* P = sp + size_t(write ? word : base >> 5) * V;
     uint32_t* Pw = sp + size_t(write ? word : base >> 5) * V;
     const int cw = active ? c : base;
-    const double Tk = st.T64[kof[cw]];
+    int k_cw = 0;  // temperature index of clone cw
+    if constexpr (kScalarJ) {
+      for (int x = 0; x < g.NPT; ++x) k_cw = cat_g[x] == cw ? x % g.NT : k_cw;
+    } else {
+      k_cw = kof[cw];
+    }
+    const double Tk = st.T64[k_cw];
     double* wslot = st.walker + size_t(sample) * g.NPT + cw;
     FP W = active ? static_cast<FP>(*wslot) : kNoClone;
     MicsaRow<H> ra, rb;
@@ -2596,6 +2632,18 @@ __global__ void init_kernel(Geo g, State st) {
   }
 }
 
+// The FP32 couplings again, in the spin words' plane order (the MicSA row
+// kernel reads them so through the scalar cache).
+__global__ void j_plane_kernel(Geo g, State st) {
+  const size_t total = size_t(g.S) * 3 * g.V;
+  const float* J = static_cast<const float*>(st.J);
+  for (size_t x = blockIdx.x * size_t(blockDim.x) + threadIdx.x; x < total; x += size_t(gridDim.x) * blockDim.x) {
+    const int i = static_cast<int>(x % g.V);
+    const size_t row = x / g.V;  // sample * 3 + direction
+    st.J_plane[row * g.V + plane_idx(i, colour_of(site_of(i, g.L)), g.Vh)] = J[x];
+  }
+}
+
 // Closes an EMCS: t += 1 (one work-item).
 __global__ void advance_t_kernel(uint32_t* t) { *t += 1u; }
 
@@ -2620,13 +2668,27 @@ hipError_t prepare_t(size_t lds) {
   if ((e = set_lds(houdayer_kernel<false>, lds)) != hipSuccess) return e;
   if ((e = set_lds(micsa_kernel<FP, true>, lds)) != hipSuccess) return e;
   if ((e = set_lds(micsa_kernel<FP, false>, lds)) != hipSuccess) return e;
-  if ((e = set_lds(micsa_row_kernel<FP, 2>, lds)) != hipSuccess) return e;
-  if ((e = set_lds(micsa_row_kernel<FP, 3>, lds)) != hipSuccess) return e;
-  if ((e = set_lds(micsa_row_kernel<FP, 4>, lds)) != hipSuccess) return e;
-  if ((e = set_lds(micsa_row_kernel<FP, 5>, lds)) != hipSuccess) return e;
-  if ((e = set_lds(micsa_row_kernel<FP, 6>, lds)) != hipSuccess) return e;
-  if ((e = set_lds(micsa_row_kernel<FP, 7>, lds)) != hipSuccess) return e;
-  if ((e = set_lds(micsa_row_kernel<FP, 8>, lds)) != hipSuccess) return e;
+  if ((e = set_lds(micsa_row_kernel<FP, 2, false>, lds)) != hipSuccess) return e;
+  if constexpr (sizeof(FP) == 4)
+    if ((e = set_lds(micsa_row_kernel<FP, 2, true>, lds)) != hipSuccess) return e;
+  if ((e = set_lds(micsa_row_kernel<FP, 3, false>, lds)) != hipSuccess) return e;
+  if constexpr (sizeof(FP) == 4)
+    if ((e = set_lds(micsa_row_kernel<FP, 3, true>, lds)) != hipSuccess) return e;
+  if ((e = set_lds(micsa_row_kernel<FP, 4, false>, lds)) != hipSuccess) return e;
+  if constexpr (sizeof(FP) == 4)
+    if ((e = set_lds(micsa_row_kernel<FP, 4, true>, lds)) != hipSuccess) return e;
+  if ((e = set_lds(micsa_row_kernel<FP, 5, false>, lds)) != hipSuccess) return e;
+  if constexpr (sizeof(FP) == 4)
+    if ((e = set_lds(micsa_row_kernel<FP, 5, true>, lds)) != hipSuccess) return e;
+  if ((e = set_lds(micsa_row_kernel<FP, 6, false>, lds)) != hipSuccess) return e;
+  if constexpr (sizeof(FP) == 4)
+    if ((e = set_lds(micsa_row_kernel<FP, 6, true>, lds)) != hipSuccess) return e;
+  if ((e = set_lds(micsa_row_kernel<FP, 7, false>, lds)) != hipSuccess) return e;
+  if constexpr (sizeof(FP) == 4)
+    if ((e = set_lds(micsa_row_kernel<FP, 7, true>, lds)) != hipSuccess) return e;
+  if ((e = set_lds(micsa_row_kernel<FP, 8, false>, lds)) != hipSuccess) return e;
+  if constexpr (sizeof(FP) == 4)
+    if ((e = set_lds(micsa_row_kernel<FP, 8, true>, lds)) != hipSuccess) return e;
   if ((e = set_lds(pt_kernel<FP, CH>, lds)) != hipSuccess) return e;
   return set_lds(measure_kernel<FP, CH>, lds);
 }
@@ -2647,20 +2709,27 @@ hipError_t launch_t(const Geo& g, const State& st, const Obs& ob, const Run& run
         const bool jl = micsa_lds_bytes(g, sizeof(FP), true) <= kLdsMax;
         auto mk = jl ? micsa_kernel<FP, true> : micsa_kernel<FP, false>;
         int bt = mt;
+        size_t lds_m = micsa_lds_bytes(g, sizeof(FP), jl);
         if (jl && g.L >= 4 && g.L <= 16) {
-          // the row-wise form (same result)
+          // the row-wise form (same result); FP32 with the plane-order copy of
+          // the couplings reads them through the scalar cache
           bt = mt < kMicsaRowThreads ? mt : kMicsaRowThreads;
+          constexpr bool kF32 = sizeof(FP) == 4;
+          const bool sj = kF32 && st.J_plane != nullptr;
+          if (sj) lds_m = align_up(sizeof(uint32_t) * size_t(g.NWPT) * g.V, 16);
+#define PTHR_ROW(HH) (sj ? micsa_row_kernel<FP, HH, kF32> : micsa_row_kernel<FP, HH, false>)
           switch (g.L / 2) {
-            case 2: mk = micsa_row_kernel<FP, 2>; break;
-            case 3: mk = micsa_row_kernel<FP, 3>; break;
-            case 4: mk = micsa_row_kernel<FP, 4>; break;
-            case 5: mk = micsa_row_kernel<FP, 5>; break;
-            case 6: mk = micsa_row_kernel<FP, 6>; break;
-            case 7: mk = micsa_row_kernel<FP, 7>; break;
-            default: mk = micsa_row_kernel<FP, 8>; break;
+            case 2: mk = PTHR_ROW(2); break;
+            case 3: mk = PTHR_ROW(3); break;
+            case 4: mk = PTHR_ROW(4); break;
+            case 5: mk = PTHR_ROW(5); break;
+            case 6: mk = PTHR_ROW(6); break;
+            case 7: mk = PTHR_ROW(7); break;
+            default: mk = PTHR_ROW(8); break;
           }
+#undef PTHR_ROW
         }
-        hipLaunchKernelGGL(mk, dim3(n_blocks), dim3(bt), micsa_lds_bytes(g, sizeof(FP), jl), stream, g, st, r);
+        hipLaunchKernelGGL(mk, dim3(n_blocks), dim3(bt), lds_m, stream, g, st, r);
         if ((e = hipGetLastError()) != hipSuccess) return e;
       }
       r.n_pt = 0;
@@ -2740,6 +2809,14 @@ int measure_rows_per_pass(const Geo& g, int threads, int fp_bytes) {
 // the workgroup has rows for and LDS holds (at least one: a workgroup has at
 // least V/8 >= L^2 work-items, rounded up to whole waves); the launch takes
 // M L^2 work-items.
+bool micsa_scalar_couplings(int L, int NWPT, int n_cat, int NPT) {
+  if (L < 4 || L > 16) return false;  // the row kernel's sizes
+  const size_t V = size_t(L) * L * L;
+  const size_t spins = align_up(sizeof(uint32_t) * size_t(NWPT) * V, 16);
+  const size_t full = align_up(spins + sizeof(int32_t) * size_t(n_cat + NPT), 16) + sizeof(float) * 3 * V;
+  return 2 * full > kLdsMax && 2 * spins <= kLdsMax;
+}
+
 HouPlan houdayer_plan(const Geo& g, int threads, bool stats, bool flips, bool occupancy) {
   const int n_moves = hou_moves(g);
   int cap = threads / (g.L * g.L);
@@ -2801,6 +2878,11 @@ hipError_t launch_init(const Geo& g, const State& st, hipStream_t stream) {
   const int threads = 256;
   const int blocks = static_cast<int>((total + threads - 1) / threads < 65536 ? (total + threads - 1) / threads : 65536);
   hipLaunchKernelGGL(init_kernel, dim3(blocks), dim3(threads), 0, stream, g, st);
+  if (st.J_plane) {
+    const size_t nj = size_t(g.S) * 3 * g.V;
+    const int bj = static_cast<int>((nj + threads - 1) / threads < 65536 ? (nj + threads - 1) / threads : 65536);
+    hipLaunchKernelGGL(j_plane_kernel, dim3(bj), dim3(threads), 0, stream, g, st);
+  }
   return hipGetLastError();
 }
 

@@ -439,6 +439,37 @@ def test_micsa_row_form_every_lattice_side(L):
         stepwise(o, g, 2)
 
 
+@pytest.mark.parametrize("NR, NT", [(4, 20), (4, 36)])
+def test_micsa_row_form_scalar_couplings_l16(NR, NT):
+    """FP32 MicSA at L=16 with enough PT clones (80 or 144: 3 or 5 words per
+    site) that the row kernel reads the couplings through the scalar cache
+    from their plane-order copy and keeps only the spin words in LDS: every
+    sub-step against the oracle over two EMCS, walker refreshes every 3
+    sweeps, a refresh falling between two launches, then a checkpoint taken
+    and restored into a context set up with other couplings (the plane-order
+    copy travels with the state)."""
+    step(f"micsa scalar couplings L=16 {NR}x{NT}")
+    o, g = make_pair(16, 2, NR, NT, 2, precision="fp32", sweeps=4, er_sweeps=6, t_range=(0.2, 1.6),
+                     update="micsa", micsa_refresh=3, jseed=41)
+    stepwise(o, g, 1)
+    o.sweep(2, oracle.SWEEP_PT)
+    g.sweep(2, 0)
+    assert_same_state(o, g, "2 PT sweeps")
+    blob = g.get_state()
+    # a context set up with other couplings takes the checkpoint's, both copies
+    _, h = make_pair(16, 2, NR, NT, 2, precision="fp32", sweeps=4, er_sweeps=6, t_range=(0.2, 1.6),
+                     update="micsa", micsa_refresh=3, jseed=42)
+    h.set_state(blob)
+    for x in (g, h):
+        x.sweep(2, 6)
+    o.sweep(2, oracle.SWEEP_PT)
+    o.sweep(6, oracle.SWEEP_ER)
+    assert_same_state(o, g, "2 more PT sweeps")
+    assert_same_state(o, h, "restored context")
+    g.check()
+    h.check()
+
+
 @pytest.mark.parametrize("L, precision, NR, NT", [(2, "fp64", 2, 3), (18, "fp32", 2, 3), (16, "fp64", 4, 25)])
 def test_micsa_generic_form(L, precision, NR, NT):
     """Cases outside the row-wise kernel's range take the site-by-site
