@@ -1387,48 +1387,28 @@ __device__ void hou_apply_flips(const Geo& g, const HouLds& s, uint32_t* gsp, in
       }
   }
   __syncthreads();
-  if (L <= 16) {
-    // one (word, row) per work-item: each entry's row mask is read once and
-    // spread over the row's L sites
-    const int L2 = L * L;
-    for (int item = threadIdx.x; item < g.NWPT * L2; item += blockDim.x) {
-      const int w = item / L2, row = item - w * L2;
-      const int e0 = off[w], e1 = off[w + 1];
-      uint32_t acc[16];
-#pragma unroll
-      for (int x = 0; x < 16; ++x) acc[x] = 0u;
-      for (int e = e0; e < e1; ++e) {
-        const int v = ent[e];
-        const uint32_t msk = hou_load_mask(g, s, v & 0xFFFF, row);
-        const uint32_t b = static_cast<uint32_t>(v) >> 16;
-#pragma unroll
-        for (int x = 0; x < 16; ++x) acc[x] |= ((msk >> x) & 1u) << b;
-      }
-      // site x of the row: colour (x + y + z) & 1, plane word row L/2 + x/2
-      uint32_t* plane = gsp + size_t(w) * g.V + size_t(row) * (L / 2);
-      const int c0 = (row % L + row / L) & 1;
-#pragma unroll
-      for (int x = 0; x < 16; ++x)
-        if (x < L && acc[x]) plane[size_t(c0 ^ (x & 1)) * g.Vh + (x >> 1)] ^= acc[x];
-    }
-    __syncthreads();
-    return;
-  }
-  for (int w = 0; w < g.NWPT; ++w) {
+  // one (word, row) per work-item (L <= 16, see houdayer_plan): each entry's
+  // row mask is read once and spread over the row's L sites
+  const int L2 = L * L;
+  for (int item = threadIdx.x; item < g.NWPT * L2; item += blockDim.x) {
+    const int w = item / L2, row = item - w * L2;
     const int e0 = off[w], e1 = off[w + 1];
-    uint32_t* plane = gsp + size_t(w) * g.V;
-    for (int j = threadIdx.x; e1 > e0 && j < g.V; j += blockDim.x) {
-      // plane index j holds the site of colour j / Vh at x = x0 or x0 + 1 of a row
-      const int col = j >= g.Vh ? 1 : 0, i0 = 2 * (j - col * g.Vh);
-      const int row = i0 / L, x0 = i0 - row * L;
-      const int x = x0 + ((row % L + row / L + col) & 1);
-      uint32_t acc = 0;
-      for (int e = e0; e < e1; ++e) {
-        const int v = ent[e];
-        acc |= ((hou_load_mask(g, s, v & 0xFFFF, row) >> x) & 1u) << (v >> 16);
-      }
-      if (acc) plane[j] ^= acc;
+    uint32_t acc[16];
+#pragma unroll
+    for (int x = 0; x < 16; ++x) acc[x] = 0u;
+    for (int e = e0; e < e1; ++e) {
+      const int v = ent[e];
+      const uint32_t msk = hou_load_mask(g, s, v & 0xFFFF, row);
+      const uint32_t b = static_cast<uint32_t>(v) >> 16;
+#pragma unroll
+      for (int x = 0; x < 16; ++x) acc[x] |= ((msk >> x) & 1u) << b;
     }
+    // site x of the row: colour (x + y + z) & 1, plane word row L/2 + x/2
+    uint32_t* plane = gsp + size_t(w) * g.V + size_t(row) * (L / 2);
+    const int c0 = (row % L + row / L) & 1;
+#pragma unroll
+    for (int x = 0; x < 16; ++x)
+      if (x < L && acc[x]) plane[size_t(c0 ^ (x & 1)) * g.Vh + (x >> 1)] ^= acc[x];
   }
   __syncthreads();
 }
@@ -2825,7 +2805,10 @@ HouPlan houdayer_plan(const Geo& g, int threads, bool stats, bool flips, bool oc
   // spin words in LDS: as many moves as the workgroup has rows for and LDS holds
   int M = cap;
   while (M > 0 && hou_lds_bytes(g, M, true, stats) > kLdsMax) --M;
-  if (M == 0 || !flips || !occupancy || g.L % 8 != 0 || 2 * hou_lds_bytes(g, M, true, stats) <= kLdsMax)
+  // (rows read four words at a time, L % 8 == 0; flips applied one row of
+  // at most 16 sites per work-item, L <= 16)
+  if (M == 0 || !flips || !occupancy || g.L % 8 != 0 || g.L > 16 ||
+      2 * hou_lds_bytes(g, M, true, stats) <= kLdsMax)
     return HouPlan{M, 0, true};
   // The words keep a CU to one workgroup: with the rows read from global
   // memory (four words at a time) and every flip collected before one
