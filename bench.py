@@ -92,8 +92,8 @@ def valu_peak(update: str, precision: str) -> tuple[float, int]:
 # SHA-256 is recorded here; any other source reports null.
 SWEEP_TRAFFIC = {
     "workload": "l16_fp32",
-    "sources_sha256": "ef8735d0e98be3e4a2895979a03385a7b29ad6fd8611598e2eefed2e51ee447c",
-    "fetch_kib": 75026.67,
+    "sources_sha256": "c3a941c99887cc45c9237f4883cfbfbbadcc43a46fc939bb0f264e7160612dfb",
+    "fetch_kib": 75038.44,
     "write_kib": 98304.0,
 }
 # Utilisation of the Houdayer kernel in the same counter runs (L=16 FP32, all-
@@ -104,8 +104,8 @@ SWEEP_TRAFFIC = {
 HOUDAYER_COUNTERS = {
     "workload": "l16_fp32",
     "sources_sha256": SWEEP_TRAFFIC["sources_sha256"],
-    "valu_issue": 0.646,
-    "lds_pipe_busy": 0.349,
+    "valu_issue": 0.643,
+    "lds_pipe_busy": 0.346,
 }
 KERNEL_SOURCES = ("paper_2605_25872_amd/csrc/pthr_kernels.hip", "paper_2605_25872_amd/csrc/pthr_internal.h")
 
