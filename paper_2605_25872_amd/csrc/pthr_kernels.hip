@@ -2525,9 +2525,10 @@ __global__ __launch_bounds__(kMaxThreads) void sweep_kernel(Geo g, State st, Run
 // Houdayer moves (or cluster labels) of one sample per workgroup; the LDS
 // layout depends on run.hou_moves, the number of moves labelled at once.
 // kLdsRows: the PT spin words are loaded into LDS, read there and flipped
-// there; otherwise (for samples whose words would keep a CU to one
-// workgroup) the overlap rows come from global memory and the flips are
-// collected as masks and applied in chunks of run.hou_chunk moves.
+// there; otherwise (samples whose words would keep a CU to one workgroup, in
+// launches with more samples than CUs or beside other work; houdayer_plan)
+// the overlap rows come from global memory and the flips are collected as
+// masks and applied in chunks of run.hou_chunk moves.
 template <bool kLdsRows>
 __global__ __launch_bounds__(kMaxThreads) void houdayer_kernel(Geo g, State st, Run run) {
   const int sample = run.sample_begin + blockIdx.x;
