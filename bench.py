@@ -92,8 +92,8 @@ def valu_peak(update: str, precision: str) -> tuple[float, int]:
 # SHA-256 is recorded here; any other source reports null.
 SWEEP_TRAFFIC = {
     "workload": "l16_fp32",
-    "sources_sha256": "c3a941c99887cc45c9237f4883cfbfbbadcc43a46fc939bb0f264e7160612dfb",
-    "fetch_kib": 75038.44,
+    "sources_sha256": "77095f4f2c1227a086aae1ebcf24747f7e3e91293e6b176ec8cd687c42c9a6a0",
+    "fetch_kib": 75041.04,
     "write_kib": 98304.0,
 }
 # Utilisation of the Houdayer kernel in the same counter runs (L=16 FP32, all-
