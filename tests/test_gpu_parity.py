@@ -447,7 +447,7 @@ def test_micsa_row_form_scalar_couplings_l16(NR, NT):
     sub-step against the oracle over two EMCS, walker refreshes every 3
     sweeps, a refresh falling between two launches, then a checkpoint taken
     and restored into a context set up with other couplings (the plane-order
-    copy travels with the state)."""
+    copy travels with the state), and an EMCS with one sample per launch."""
     step(f"micsa scalar couplings L=16 {NR}x{NT}")
     o, g = make_pair(16, 2, NR, NT, 2, precision="fp32", sweeps=4, er_sweeps=6, t_range=(0.2, 1.6),
                      update="micsa", micsa_refresh=3, jseed=41)
@@ -466,6 +466,16 @@ def test_micsa_row_form_scalar_couplings_l16(NR, NT):
     o.sweep(6, oracle.SWEEP_ER)
     assert_same_state(o, g, "2 more PT sweeps")
     assert_same_state(o, h, "restored context")
+    # close the EMCS, then one with one sample per launch: each launch reads
+    # its own sample's coupling copy
+    o.houdayer()
+    g.houdayer()
+    o.pt_swap(True)
+    g.pt_swap(True)
+    g.set_schedule(samples_per_launch=1, graph_window=0)
+    o.run(1)
+    g.run(1)
+    assert_same_state(o, g, "one sample per launch")
     g.check()
     h.check()
 
