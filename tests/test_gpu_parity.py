@@ -439,6 +439,29 @@ def test_micsa_row_form_every_lattice_side(L):
         stepwise(o, g, 2)
 
 
+def test_group_with_micsa_members_matches_oracle():
+    """PTHR* contexts in a group (their kernels run beside each other's): an
+    L=16 FP32 MicSA member with 80 PT clones (couplings through the scalar
+    cache from its plane-order copy), an L=6 FP64 MicSA member and an L=8
+    FP32 Metropolis member, replayed as one captured graph and as plain
+    launches; every member stays bit-identical to its own oracle."""
+    step("group with micsa members")
+    pthr = _pthr()
+    cases = [(16, 2, 4, 20, 2, "fp32", "micsa"), (6, 2, 2, 7, 3, "fp64", "micsa"), (8, 2, 4, 5, 1, "fp32", "metropolis")]
+    pairs = [make_pair(L, S, NR, NT, NER, precision=prec, sweeps=4, er_sweeps=6, jseed=50 + L, seed=5 + L,
+                       t_range=(0.2, 1.6), update=upd, micsa_refresh=3)
+             for L, S, NR, NT, NER, prec, upd in cases]
+    group = pthr.Group([g for _, g in pairs])
+    for stretch in (5, 2):  # 2 replays + 1 eager; eager
+        for o, _ in pairs:
+            o.run(stretch)
+        group.run(stretch, None, graph_window=2)
+        for i, (o, g) in enumerate(pairs):
+            assert_same_state(o, g, f"member {i} after a stretch of {stretch}")
+    for _, g in pairs:
+        g.check()
+
+
 @pytest.mark.parametrize("NR, NT", [(4, 20), (4, 36)])
 def test_micsa_row_form_scalar_couplings_l16(NR, NT):
     """FP32 MicSA at L=16 with enough PT clones (80 or 144: 3 or 5 words per
