@@ -293,6 +293,50 @@ def test_houdayer_both_kernel_forms_every_sample_l16(mode):
         g.check()
 
 
+def test_reservoir_overlap_beside_global_row_houdayer_l16():
+    """overlap_reservoir = 1 at the L=16 FP32 shape with more samples than
+    CUs: the reservoir sweeps (second stream) run beside the PT sweeps and
+    the Houdayer step in its global-row form, which reads and flips PT words
+    in global memory while the reservoir sweep writes back reservoir words of
+    the same samples.  Every sample matches the plain schedule, and two the
+    oracle, over several EMCS."""
+    import torch
+    pthr = _pthr()
+    w = inputs.WORKLOADS["l16_fp32"]
+    S = torch.cuda.get_device_properties(0).multi_processor_count + 64
+    T = w.temperatures()
+    step(f"reservoir overlap beside the global-row Houdayer form: {S} samples")
+    J = w.couplings(S)
+    ctx = []
+    for over in (0, 1):
+        g = pthr.Pthr(w.L, S, w.n_replicas, w.n_temps, w.n_reservoir, 2, 6, "fp32", "acu", w.t_acu, w.seed)
+        g.init_samples(J, T)
+        g.set_schedule(overlap_reservoir=over, graph_window=0)
+        ctx.append(g)
+    picks = [0, S - 1]
+    orc = []
+    for s in picks:
+        o1 = oracle.Oracle(w.L, 1, w.n_replicas, w.n_temps, w.n_reservoir, 2, 6, oracle.FP32, oracle.ACU, w.t_acu,
+                           w.seed, first_sample=s)
+        o1.init(w.couplings(1, first_sample=s), T)
+        orc.append(o1)
+    for e in range(3):
+        for g in ctx:
+            g.run(1)
+        for o1 in orc:
+            o1.run(1)
+        a, b = ctx[0].read_spins(), ctx[1].read_spins()
+        bad = [s for s in range(S) if not np.array_equal(a[s], b[s])]
+        assert not bad, f"EMCS {e}: the overlapped schedule differs on samples {bad[:8]}"
+        pa, pb = ctx[0].read_pt(), ctx[1].read_pt()
+        for key in pa:
+            assert np.array_equal(pa[key], pb[key]), (e, key)
+        for s, o1 in zip(picks, orc):
+            assert np.array_equal(a[s], o1.spins[0]), f"EMCS {e}: sample {s} against the oracle"
+    for g in ctx:
+        g.check()
+
+
 @pytest.mark.parametrize("mode", ["acu", "single"])
 @pytest.mark.parametrize("L,precision", [(4, "fp64"), (16, "fp32")])
 def test_houdayer_on_identical_and_opposite_replicas(L, precision, mode):
