@@ -2316,18 +2316,27 @@ __device__ __forceinline__ void micsa_walk(uint32_t (&own)[H], const FP (&U)[H],
 // One row of colour C, whose sites sit at x = X0 + 2k and whose own words
 // start at word `own` of the plane, from cur and J; meanwhile the spin words
 // of the row at `next` load into nxt and, once this row's sums are formed,
-// its couplings into J.  A row never reads a row of its own colour other
+// its couplings into J.  Couplings read through the scalar cache are instead
+// loaded for the row itself (at `at`) as it starts: held from one row to the
+// next they made the compiler move scalar registers into vector lanes and
+// back.  A row never reads a row of its own colour other
 // than its own, and the first row of either colour reads none of the rows
 // the last row of the other colour writes, so the early loads see final
 // words.
 template <typename FP, int H, int C, int X0, typename JP>
 __device__ __forceinline__ void micsa_step(MicsaRow<H>& cur, MicsaRow<H>& nxt, MicsaJ<FP, H>& J, const uint32_t* P,
-                                           uint32_t* Pw, JP Jc, int own, const RowOff& next, int sh,
-                                           int hi_shift, bool write, FP& W) {
+                                           uint32_t* Pw, JP Jc, int own, const RowOff& at, const RowOff& next,
+                                           int sh, int hi_shift, bool write, FP& W) {
   micsa_load<H>(nxt, P, next);
   FP U[H];
-  micsa_fields<FP, H, X0>(cur, J, sh, U);
-  micsa_load_j<FP, H>(J, Jc, next);
+  if constexpr (std::is_same_v<JP, ScalarF32*>) {
+    MicsaJ<FP, H> Jr;
+    micsa_load_j<FP, H>(Jr, Jc, at);
+    micsa_fields<FP, H, X0>(cur, Jr, sh, U);
+  } else {
+    micsa_fields<FP, H, X0>(cur, J, sh, U);
+    micsa_load_j<FP, H>(J, Jc, next);
+  }
   micsa_walk<FP, H>(cur.own, U, hi_shift, W);
   if (write) lds_store_words<H>(Pw + own, cur.own);
 }
@@ -2348,9 +2357,9 @@ __device__ __forceinline__ void micsa_plane(MicsaRow<H>& ra, MicsaRow<H>& rb, Mi
   const int nz = end ? 0 : z + 1, nc = end ? C ^ 1 : C;
   const RowOff after = row_off<H>(0, nz * LH, wrap_up(nz, L) * LH, wrap_down(nz, L) * LH, nc);
   for (int y = 0; y < L; y += 2) {
-    micsa_step<FP, H, C, XE>(ra, rb, J, P, Pw, Jc, C * Vh + zb + y * H, row_off<H>(y + 1, zb, zpb, zmb, C), sh,
-                             hi_shift, write, W);
-    micsa_step<FP, H, C, XE ^ 1>(rb, ra, J, P, Pw, Jc, C * Vh + zb + (y + 1) * H,
+    micsa_step<FP, H, C, XE>(ra, rb, J, P, Pw, Jc, C * Vh + zb + y * H, row_off<H>(y, zb, zpb, zmb, C),
+                             row_off<H>(y + 1, zb, zpb, zmb, C), sh, hi_shift, write, W);
+    micsa_step<FP, H, C, XE ^ 1>(rb, ra, J, P, Pw, Jc, C * Vh + zb + (y + 1) * H, row_off<H>(y + 1, zb, zpb, zmb, C),
                                  y + 2 < L ? row_off<H>(y + 2, zb, zpb, zmb, C) : after, sh, hi_shift, write, W);
   }
 }
@@ -2436,7 +2445,7 @@ __global__ __launch_bounds__(kMicsaRowThreads) void micsa_row_kernel(Geo g, Stat
     MicsaJ<FP, H> J;
     const RowOff first = row_off<H>(0, 0, L * H, (L - 1) * L * H, 0);  // row 0 of plane 0, colour 0
     micsa_load<H>(ra, P, first);
-    micsa_load_j<FP, H>(J, Jc, first);
+    if constexpr (!kScalarJ) micsa_load_j<FP, H>(J, Jc, first);
     for (int mm = 0; mm < run.n_pt; ++mm) {
       const int m = run.m_pt0 + mm;
       if (m % g.micsa_refresh == 0) {
