@@ -117,10 +117,10 @@ const char *pthr_last_error(const pthr_ctx *ctx); /* "" if none; valid until the
 const char *pthr_create_error(void);
 
 /* Bytes of device memory the caller must provide (0 if p is invalid).  For
- * PTHR_FP32 with PTHR_MICSA at sizes where LDS holds two samples' PT spin
- * words but not their couplings beside them (L=16 at the paper's grid), this
- * includes a second copy of the couplings in the spin words' site order,
- * written by pthr_init_samples and carried by pthr_get_state/pthr_set_state. */
+ * PTHR_FP32 with PTHR_MICSA at 4 <= L <= 16 where LDS holds two samples' PT
+ * spin words (every lattice of the paper's grids), this includes a second
+ * copy of the couplings in the spin words' site order, written by
+ * pthr_init_samples and carried by pthr_get_state/pthr_set_state. */
 size_t pthr_state_bytes(const pthr_params *p);
 /* Observable buffer: uint64 n_meas at offset 0; double acc[S][N_T][PTHR_NOBS]
  * at offset 256; then uint64 hist[N_T][V+1], hist[k][(Q+V)/2] counting the

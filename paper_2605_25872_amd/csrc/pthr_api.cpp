@@ -74,8 +74,9 @@ Layout layout_of(const pthr_params& p) {
   l.rt_count = o;  o = align256(o + 8 * S);
   l.status = o;    o = align256(o + 4 * S);
   l.walker = o;    o = align256(o + 8 * S * d.NPT);
-  // FP32 MicSA whose row kernel reads the couplings through the scalar cache:
-  // the couplings again, in plane order
+  // FP32 MicSA whose row kernel reads the couplings through the scalar cache
+  // (4 <= L <= 16, two samples' spin words fit in LDS): the couplings again,
+  // in plane order
   const bool j_plane = p.precision == PTHR_FP32 && p.local_update == PTHR_MICSA &&
                        pthr::micsa_scalar_couplings(p.L, d.NWPT, int(NR * NT), d.NPT);
   l.J_plane = j_plane ? o : 0;

@@ -125,10 +125,9 @@ struct HouPlan {
 HouPlan houdayer_plan(const Geo& g, int threads, bool stats, bool flips, bool occupancy);
 int measure_rows_per_pass(const Geo& g, int threads, int fp_bytes);
 // FP32 MicSA row kernel: reading the couplings through the scalar cache (from
-// a plane-order copy in the state buffer) leaves LDS to the spin words; worth
-// it where that fits two samples per CU and the LDS copy of the couplings
-// does not (the geometry: lattice side, PT spin words, permutation entries
-// NR NT, PT clones).
+// a plane-order copy in the state buffer) leaves LDS to the spin words; taken
+// wherever LDS then holds two samples' spin words (the geometry: lattice side,
+// PT spin words, permutation entries NR NT, PT clones).
 bool micsa_scalar_couplings(int L, int NWPT, int n_cat, int NPT);
 hipError_t launch_emcs(int precision, const Geo& g, const State& st, const Obs& ob, const Run& run,
                        const Shape& sh, int n_blocks, hipStream_t stream);

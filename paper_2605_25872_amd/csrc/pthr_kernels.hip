@@ -2800,11 +2800,12 @@ int measure_rows_per_pass(const Geo& g, int threads, int fp_bytes) {
 // least V/8 >= L^2 work-items, rounded up to whole waves); the launch takes
 // M L^2 work-items.
 bool micsa_scalar_couplings(int L, int NWPT, int n_cat, int NPT) {
+  (void)n_cat;
+  (void)NPT;
   if (L < 4 || L > 16) return false;  // the row kernel's sizes
   const size_t V = size_t(L) * L * L;
   const size_t spins = align_up(sizeof(uint32_t) * size_t(NWPT) * V, 16);
-  const size_t full = align_up(spins + sizeof(int32_t) * size_t(n_cat + NPT), 16) + sizeof(float) * 3 * V;
-  return 2 * full > kLdsMax && 2 * spins <= kLdsMax;
+  return 2 * spins <= kLdsMax;
 }
 
 HouPlan houdayer_plan(const Geo& g, int threads, bool stats, bool flips, bool occupancy) {

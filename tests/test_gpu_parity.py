@@ -506,16 +506,18 @@ def test_group_with_micsa_members_matches_oracle():
         g.check()
 
 
-@pytest.mark.parametrize("NR, NT", [(4, 20), (4, 36)])
-def test_micsa_row_form_scalar_couplings_l16(NR, NT):
-    """FP32 MicSA at L=16 with enough PT clones (80 or 144: 3 or 5 words per
-    site) that the row kernel reads the couplings through the scalar cache
-    from their plane-order copy and keeps only the spin words in LDS: every
+@pytest.mark.parametrize("NR, NT", [(4, 20), (4, 36), (4, 48)])
+def test_micsa_row_form_coupling_placement_l16(NR, NT):
+    """FP32 MicSA at L=16 with 80 or 144 PT clones (3 or 5 words per site),
+    where the row kernel reads the couplings through the scalar cache from
+    their plane-order copy and keeps only the spin words in LDS, and with 192
+    (6 words: two samples' words no longer fit in LDS, so the couplings are
+    staged in LDS beside the words): every
     sub-step against the oracle over two EMCS, walker refreshes every 3
     sweeps, a refresh falling between two launches, then a checkpoint taken
     and restored into a context set up with other couplings (the plane-order
     copy travels with the state), and an EMCS with one sample per launch."""
-    step(f"micsa scalar couplings L=16 {NR}x{NT}")
+    step(f"micsa row form L=16 {NR}x{NT}")
     o, g = make_pair(16, 2, NR, NT, 2, precision="fp32", sweeps=4, er_sweeps=6, t_range=(0.2, 1.6),
                      update="micsa", micsa_refresh=3, jseed=41)
     stepwise(o, g, 1)
