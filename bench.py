@@ -92,8 +92,8 @@ def valu_peak(update: str, precision: str) -> tuple[float, int]:
 # SHA-256 is recorded here; any other source reports null.
 SWEEP_TRAFFIC = {
     "workload": "l16_fp32",
-    "sources_sha256": "335bb4c55cd35dbb96ffa402eda32f3bebffb9463c42dae27ff3e36d810da83e",
-    "fetch_kib": 75035.69,
+    "sources_sha256": "a6018820b7b04cb522803854d02c34a6925ba69ba1af38cf77d0f0e47cf09753",
+    "fetch_kib": 75035.92,
     "write_kib": 98304.0,
 }
 # Utilisation of the Houdayer kernel in the same counter runs (L=16 FP32, all-
@@ -104,8 +104,8 @@ SWEEP_TRAFFIC = {
 HOUDAYER_COUNTERS = {
     "workload": "l16_fp32",
     "sources_sha256": SWEEP_TRAFFIC["sources_sha256"],
-    "valu_issue": 0.642,
-    "lds_pipe_busy": 0.346,
+    "valu_issue": 0.641,
+    "lds_pipe_busy": 0.345,
 }
 KERNEL_SOURCES = ("paper_2605_25872_amd/csrc/pthr_kernels.hip", "paper_2605_25872_amd/csrc/pthr_internal.h")
 
